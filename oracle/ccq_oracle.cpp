@@ -1,0 +1,379 @@
+/*
+ * ccq_oracle -- plain CPU reference for filter / group-by / aggregate queries
+ * over lightweight-encoded columns.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the bench's
+ * CPU-baseline leg load this library.  The GPU library shares no code,
+ * header, table or helper with it.
+ *
+ * What it computes is the plain relational definition (the paper's method is
+ * exact, so its answer must equal the uncompressed one):
+ *   1. every referenced column is decompressed to one int64 value per logical
+ *      row (Section 3.1 "Basic Encodings": RLE runs (value, start, end), Index
+ *      (value, position); Section 3.2 bit-width reduction with a global
+ *      reference value, value = base + code);
+ *   2. a row qualifies when every predicate holds on its values (selection,
+ *      Section 6);
+ *   3. qualifying rows are grouped by their key tuple and COUNT(*) / SUM(col)
+ *      are accumulated per group (Section 7, grouping and aggregating phases);
+ *   4. groups are emitted in ascending key order (torch.unique returns sorted
+ *      unique values, Section 2.2); an ungrouped query emits one row.
+ * No NULLs exist (Appendix "Query Optimization Rules").
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - run ends are stored exclusive: run i covers rows [run_ends[i-1], run_ends[i]),
+ *     i.e. the paper's inclusive end plus one; base columns have no gaps;
+ *   - an Index data column holds 0 at rows it does not list;
+ *   - range predicates are half open, lo <= v < hi; IN has set semantics;
+ *   - a group key is v >> shift and must lie in the declared [0, card);
+ *   - the bit-packed stream is LSB first in little-endian uint32 words;
+ *   - sums are exact int64; any overflow is reported as an error.
+ *
+ * Work is split into chunks of at most 2^20 rows handed to std::threads; each
+ * thread keeps its own std::map, and the maps are added together at the end
+ * (exact integer addition, so the thread count cannot change the answer).
+ */
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+extern "C" {
+
+enum { ORC_RLE = 1, ORC_INDEX = 2, ORC_BITPACKED = 3 };
+enum { ORC_I32 = 1, ORC_I64 = 2 };
+enum { ORC_RANGE = 1, ORC_IN = 2 };
+enum { ORC_COUNT = 1, ORC_SUM = 2 };
+
+typedef struct {
+    int32_t enc;
+    int32_t vtype;
+    int64_t n;                  /* runs | listed points | rows */
+    const void* values;         /* RLE / INDEX values */
+    const int64_t* run_ends;    /* RLE */
+    const void* positions;      /* INDEX, int32 or int64 per ptype */
+    const uint32_t* packed;     /* BITPACKED */
+    int32_t w;                  /* BITPACKED bit width */
+    int32_t ptype;              /* INDEX position type: ORC_I32 or ORC_I64 */
+    int64_t base;               /* BITPACKED: value = base + code */
+} orc_column;
+
+typedef struct {
+    int32_t col;
+    int32_t op;
+    int64_t lo, hi;             /* RANGE: lo <= v < hi */
+    const int64_t* in_list;     /* IN */
+    int64_t in_len;
+} orc_pred;
+
+typedef struct {
+    int32_t col;
+    int32_t shift;
+    int64_t card;
+} orc_key;
+
+typedef struct {
+    int32_t func;
+    int32_t col;
+} orc_agg;
+
+}  // extern "C"
+
+namespace {
+
+struct Acc {
+    int64_t count = 0;
+    std::vector<int64_t> vals;
+};
+
+struct Result {
+    std::string error;
+    int32_t n_keys = 0, n_aggs = 0;
+    std::vector<std::vector<int64_t>> keys;
+    std::vector<int64_t> counts;
+    std::vector<std::vector<int64_t>> aggs;
+};
+
+int64_t value_at(const orc_column& c, int64_t i) {
+    return c.vtype == ORC_I32 ? (int64_t)((const int32_t*)c.values)[i] : ((const int64_t*)c.values)[i];
+}
+
+int64_t position_at(const orc_column& c, int64_t i) {
+    return c.ptype == ORC_I32 ? (int64_t)((const int32_t*)c.positions)[i] : ((const int64_t*)c.positions)[i];
+}
+
+/* first listed point whose position is >= r (binary search over positions) */
+int64_t first_point_at_or_after(const orc_column& c, int64_t r) {
+    int64_t lo = 0, hi = c.n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (position_at(c, mid) < r) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+std::string validate_column(const orc_column& c, int64_t n_rows) {
+    if (c.enc == ORC_RLE) {
+        if (c.vtype != ORC_I32 && c.vtype != ORC_I64) return "RLE value type must be int32 or int64";
+        if (c.n <= 0 || !c.run_ends || !c.values) return "RLE column needs at least one run";
+        int64_t prev = 0;
+        for (int64_t i = 0; i < c.n; i++) {
+            if (c.run_ends[i] <= prev) return "RLE run ends must be strictly increasing and positive";
+            prev = c.run_ends[i];
+        }
+        if (prev != n_rows) return "last RLE run end must equal the row count";
+    } else if (c.enc == ORC_INDEX) {
+        if (c.vtype != ORC_I32 && c.vtype != ORC_I64) return "Index value type must be int32 or int64";
+        if (c.ptype != ORC_I32 && c.ptype != ORC_I64) return "Index position type must be int32 or int64";
+        if (c.n < 0 || (c.n > 0 && (!c.positions || !c.values))) return "Index column arrays missing";
+        int64_t prev = -1;
+        for (int64_t i = 0; i < c.n; i++) {
+            int64_t p = position_at(c, i);
+            if (p <= prev || p >= n_rows) return "Index positions must be strictly increasing in [0, rows)";
+            prev = p;
+        }
+    } else if (c.enc == ORC_BITPACKED) {
+        if (c.w < 1 || c.w > 32) return "bit width must be in 1..32";
+        if (!c.packed) return "packed stream missing";
+        if (c.n != n_rows) return "bit-packed column must hold one code per row";
+    } else {
+        return "unknown encoding";
+    }
+    return "";
+}
+
+/* Rows [r0, r1) of column c as int64 values. */
+void decode(const orc_column& c, int64_t r0, int64_t r1, int64_t* out) {
+    int64_t len = r1 - r0;
+    if (len <= 0) return;
+    if (c.enc == ORC_RLE) {
+        /* first run whose (exclusive) end lies beyond r0 is the run holding row r0 */
+        int64_t i = std::upper_bound(c.run_ends, c.run_ends + c.n, r0) - c.run_ends;
+        int64_t r = r0;
+        while (r < r1) {
+            int64_t stop = std::min(c.run_ends[i], r1);
+            int64_t v = value_at(c, i);
+            for (; r < stop; r++) out[r - r0] = v;
+            i++;
+        }
+    } else if (c.enc == ORC_INDEX) {
+        for (int64_t k = 0; k < len; k++) out[k] = 0;
+        for (int64_t i = first_point_at_or_after(c, r0); i < c.n && position_at(c, i) < r1; i++)
+            out[position_at(c, i) - r0] = value_at(c, i);
+    } else {
+        const uint64_t mask = c.w == 32 ? 0xFFFFFFFFull : ((1ull << c.w) - 1);
+        for (int64_t r = r0; r < r1; r++) {
+            uint64_t bit = (uint64_t)r * (uint64_t)c.w;
+            uint64_t word = bit / 32, sh = bit % 32;
+            uint64_t two = (uint64_t)c.packed[word] | ((uint64_t)c.packed[word + 1] << 32);
+            uint64_t code = (two >> sh) & mask;
+            out[r - r0] = c.base + (int64_t)code;
+        }
+    }
+}
+
+struct Query {
+    std::vector<orc_column> cols;
+    int64_t n_rows = 0;
+    std::vector<orc_pred> preds;
+    std::vector<std::set<int64_t>> in_sets;
+    std::vector<orc_key> keys;
+    std::vector<orc_agg> aggs;
+    int64_t row_begin = 0, row_end = 0;
+    std::vector<int> used;        /* referenced column ids */
+    std::vector<int> slot;        /* column id -> index into the decoded chunk */
+};
+
+struct ThreadState {
+    std::map<std::vector<int64_t>, Acc> groups;
+    std::string error;
+};
+
+void run_chunks(const Query& q, std::atomic<int64_t>& next_chunk, int64_t n_chunks, ThreadState& st) {
+    const int64_t CH = 1 << 20;
+    std::vector<std::vector<int64_t>> x(q.used.size());
+    std::vector<int64_t> key(q.keys.size());
+    std::vector<int64_t> last_key;
+    Acc* last = nullptr;
+    for (;;) {
+        int64_t ch = next_chunk.fetch_add(1);
+        if (ch >= n_chunks || !st.error.empty()) return;
+        int64_t c0 = q.row_begin + ch * CH;
+        int64_t c1 = std::min(c0 + CH, q.row_end);
+        for (size_t u = 0; u < q.used.size(); u++) {
+            x[u].resize(c1 - c0);
+            decode(q.cols[q.used[u]], c0, c1, x[u].data());
+        }
+        for (int64_t r = 0; r < c1 - c0; r++) {
+            bool pass = true;
+            for (size_t p = 0; p < q.preds.size() && pass; p++) {
+                int64_t v = x[q.slot[q.preds[p].col]][r];
+                if (q.preds[p].op == ORC_RANGE) pass = q.preds[p].lo <= v && v < q.preds[p].hi;
+                else pass = q.in_sets[p].count(v) != 0;
+            }
+            if (!pass) continue;
+            for (size_t k = 0; k < q.keys.size(); k++) {
+                int64_t v = x[q.slot[q.keys[k].col]][r] >> q.keys[k].shift;
+                if (v < 0 || v >= q.keys[k].card) {
+                    st.error = "group key outside its declared domain";
+                    return;
+                }
+                key[k] = v;
+            }
+            if (last == nullptr || key != last_key) {
+                auto it = st.groups.find(key);
+                if (it == st.groups.end()) {
+                    Acc a;
+                    a.vals.assign(q.aggs.size(), 0);
+                    it = st.groups.emplace(key, a).first;
+                }
+                last = &it->second;
+                last_key = key;
+            }
+            last->count += 1;
+            for (size_t a = 0; a < q.aggs.size(); a++) {
+                int64_t add = q.aggs[a].func == ORC_COUNT ? 1 : x[q.slot[q.aggs[a].col]][r];
+                if (__builtin_add_overflow(last->vals[a], add, &last->vals[a])) {
+                    st.error = "int64 overflow in an aggregate";
+                    return;
+                }
+            }
+        }
+    }
+}
+
+Result* execute(Query& q, int n_threads) {
+    Result* res = new Result();
+    res->n_keys = (int32_t)q.keys.size();
+    res->n_aggs = (int32_t)q.aggs.size();
+    for (auto& c : q.cols) {
+        std::string e = validate_column(c, q.n_rows);
+        if (!e.empty()) { res->error = e; return res; }
+    }
+    if (q.row_begin < 0 || q.row_end > q.n_rows || q.row_begin > q.row_end) {
+        res->error = "window outside the table";
+        return res;
+    }
+    q.slot.assign(q.cols.size(), -1);
+    auto use = [&](int c) -> bool {
+        if (c < 0 || c >= (int)q.cols.size()) return false;
+        if (q.slot[c] < 0) { q.slot[c] = (int)q.used.size(); q.used.push_back(c); }
+        return true;
+    };
+    q.in_sets.assign(q.preds.size(), {});
+    for (size_t p = 0; p < q.preds.size(); p++) {
+        if (!use(q.preds[p].col)) { res->error = "predicate column out of range"; return res; }
+        if (q.preds[p].op == ORC_IN) {
+            for (int64_t i = 0; i < q.preds[p].in_len; i++) q.in_sets[p].insert(q.preds[p].in_list[i]);
+        } else if (q.preds[p].op != ORC_RANGE) {
+            res->error = "unknown predicate";
+            return res;
+        }
+    }
+    for (auto& k : q.keys) {
+        if (!use(k.col)) { res->error = "key column out of range"; return res; }
+        if (k.card <= 0 || k.shift < 0 || k.shift > 62) { res->error = "bad key domain"; return res; }
+    }
+    for (auto& a : q.aggs) {
+        if (a.func == ORC_SUM) {
+            if (!use(a.col)) { res->error = "aggregate column out of range"; return res; }
+        } else if (a.func != ORC_COUNT) {
+            res->error = "unknown aggregate";
+            return res;
+        }
+    }
+
+    const int64_t CH = 1 << 20;
+    int64_t n_chunks = (q.row_end - q.row_begin + CH - 1) / CH;
+    if (n_threads < 1) n_threads = 1;
+    std::vector<ThreadState> st(n_threads);
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < n_threads; t++) th.emplace_back(run_chunks, std::cref(q), std::ref(next), n_chunks, std::ref(st[t]));
+    for (auto& t : th) t.join();
+
+    std::map<std::vector<int64_t>, Acc> all;
+    for (auto& s : st) {
+        if (!s.error.empty()) { res->error = s.error; return res; }
+        for (auto& kv : s.groups) {
+            auto it = all.find(kv.first);
+            if (it == all.end()) { all.emplace(kv.first, kv.second); continue; }
+            it->second.count += kv.second.count;
+            for (size_t a = 0; a < q.aggs.size(); a++)
+                if (__builtin_add_overflow(it->second.vals[a], kv.second.vals[a], &it->second.vals[a])) {
+                    res->error = "int64 overflow in an aggregate";
+                    return res;
+                }
+        }
+    }
+    if (q.keys.empty()) {
+        /* ungrouped: exactly one row, zero when nothing qualifies */
+        Acc a;
+        a.vals.assign(q.aggs.size(), 0);
+        auto it = all.find(std::vector<int64_t>{});
+        if (it != all.end()) a = it->second;
+        res->keys.push_back({});
+        res->counts.push_back(a.count);
+        res->aggs.push_back(a.vals);
+        return res;
+    }
+    for (auto& kv : all) {   /* std::map iterates in ascending lexicographic key order */
+        res->keys.push_back(kv.first);
+        res->counts.push_back(kv.second.count);
+        res->aggs.push_back(kv.second.vals);
+    }
+    return res;
+}
+
+}  // namespace
+
+extern "C" {
+
+/* Run one query; always returns a handle (check orc_error). */
+void* orc_query(const orc_column* cols, int32_t n_cols, int64_t n_rows, const orc_pred* preds, int32_t n_preds,
+                const orc_key* keys, int32_t n_keys, const orc_agg* aggs, int32_t n_aggs, int64_t row_begin,
+                int64_t row_end, int32_t n_threads) {
+    Query q;
+    q.cols.assign(cols, cols + n_cols);
+    q.n_rows = n_rows;
+    q.preds.assign(preds, preds + n_preds);
+    q.keys.assign(keys, keys + n_keys);
+    q.aggs.assign(aggs, aggs + n_aggs);
+    q.row_begin = row_begin;
+    q.row_end = row_end;
+    return execute(q, n_threads);
+}
+
+const char* orc_error(void* h) { return ((Result*)h)->error.c_str(); }
+
+int64_t orc_n_groups(void* h) { return (int64_t)((Result*)h)->counts.size(); }
+
+/* keys: [G][n_keys], counts: [G], aggs: [G][n_aggs] */
+void orc_copy(void* h, int64_t* keys, int64_t* counts, int64_t* aggs) {
+    Result* r = (Result*)h;
+    for (size_t g = 0; g < r->counts.size(); g++) {
+        for (int k = 0; k < r->n_keys; k++) keys[g * r->n_keys + k] = r->keys[g][k];
+        counts[g] = r->counts[g];
+        for (int a = 0; a < r->n_aggs; a++) aggs[g * r->n_aggs + a] = r->aggs[g][a];
+    }
+}
+
+void orc_free(void* h) { delete (Result*)h; }
+
+/* Decode rows [r0, r1) of one column; returns "" or a validation message. */
+const char* orc_decode(const orc_column* c, int64_t n_rows, int64_t r0, int64_t r1, int64_t* out) {
+    static thread_local std::string err;
+    err = validate_column(*c, n_rows);
+    if (!err.empty()) return err.c_str();
+    if (r0 < 0 || r1 > n_rows || r0 > r1) { err = "rows outside the column"; return err.c_str(); }
+    decode(*c, r0, r1, out);
+    return "";
+}
+
+}  // extern "C"

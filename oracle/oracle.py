@@ -1,0 +1,201 @@
+"""ctypes wrapper around the CPU oracle (``libccq_oracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+bench's CPU-baseline leg, never by the GPU library.  It converts the
+column / query dicts described in ``datagen`` into the oracle's own structs.
+
+Results are returned as plain Python values::
+
+    {"keys": [tuple, ...], "counts": [int, ...], "aggs": [tuple, ...]}
+
+in ascending key order; an ungrouped query returns exactly one row.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.environ.get("CCQ_ORACLE_LIB") or os.path.join(_HERE, "libccq_oracle.so")
+_lib = None
+
+RLE, INDEX, BITPACKED = 1, 2, 3
+I32, I64 = 1, 2
+RANGE, IN = 1, 2
+COUNT, SUM = 1, 2
+
+
+class OrcColumn(ctypes.Structure):
+    _fields_ = [("enc", ctypes.c_int32), ("vtype", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("values", ctypes.c_void_p), ("run_ends", ctypes.c_void_p), ("positions", ctypes.c_void_p),
+                ("packed", ctypes.c_void_p), ("w", ctypes.c_int32), ("ptype", ctypes.c_int32),
+                ("base", ctypes.c_int64)]
+
+
+class OrcPred(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
+                ("in_list", ctypes.c_void_p), ("in_len", ctypes.c_int64)]
+
+
+class OrcKey(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("shift", ctypes.c_int32), ("card", ctypes.c_int64)]
+
+
+class OrcAgg(ctypes.Structure):
+    _fields_ = [("func", ctypes.c_int32), ("col", ctypes.c_int32)]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ -O2 (no SIMD intrinsics)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                               os.path.join(_HERE, "ccq_oracle.cpp"), "-o", tmp, "-lpthread"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        L.orc_query.restype = ctypes.c_void_p
+        L.orc_query.argtypes = [ctypes.POINTER(OrcColumn), ctypes.c_int32, ctypes.c_int64,
+                                ctypes.POINTER(OrcPred), ctypes.c_int32, ctypes.POINTER(OrcKey), ctypes.c_int32,
+                                ctypes.POINTER(OrcAgg), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.c_int32]
+        L.orc_error.restype = ctypes.c_char_p
+        L.orc_error.argtypes = [ctypes.c_void_p]
+        L.orc_n_groups.restype = ctypes.c_int64
+        L.orc_n_groups.argtypes = [ctypes.c_void_p]
+        L.orc_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_free.argtypes = [ctypes.c_void_p]
+        L.orc_decode.restype = ctypes.c_char_p
+        L.orc_decode.argtypes = [ctypes.POINTER(OrcColumn), ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _vtype(a):
+    if a.dtype == np.int32:
+        return I32
+    if a.dtype == np.int64:
+        return I64
+    raise OracleError("values must be int32 or int64, got %s" % a.dtype)
+
+
+def _column(c, n_rows, keep):
+    """Build an OrcColumn; `keep` holds the arrays alive."""
+    oc = OrcColumn()
+    if c["enc"] == "rle":
+        v = np.ascontiguousarray(c["values"])
+        e = np.ascontiguousarray(c["run_ends"], dtype=np.int64)
+        if len(v) != len(e):
+            raise OracleError("RLE values and run_ends differ in length")
+        keep += [v, e]
+        oc.enc, oc.vtype, oc.n = RLE, _vtype(v), len(e)
+        oc.values, oc.run_ends = v.ctypes.data, e.ctypes.data
+    elif c["enc"] == "index":
+        v = np.ascontiguousarray(c["values"])
+        p = np.ascontiguousarray(c["positions"])
+        if len(v) != len(p):
+            raise OracleError("Index values and positions differ in length")
+        keep += [v, p]
+        oc.enc, oc.vtype, oc.n, oc.ptype = INDEX, _vtype(v), len(p), _vtype(p)
+        oc.values, oc.positions = v.ctypes.data, p.ctypes.data
+    elif c["enc"] == "bitpacked":
+        pk = np.ascontiguousarray(c["packed"], dtype=np.uint32)
+        w = int(c["w"])
+        if len(pk) < (n_rows * w + 31) // 32 + 2:
+            raise OracleError("packed stream shorter than ceil(rows*w/32) + 2 words")
+        keep.append(pk)
+        oc.enc, oc.n, oc.w, oc.base = BITPACKED, n_rows, w, int(c.get("base", 0))
+        oc.packed = pk.ctypes.data
+    else:
+        raise OracleError("unknown encoding %r" % (c["enc"],))
+    return oc
+
+
+def decode(column, n_rows, r0=0, r1=None):
+    """Decompress rows [r0, r1) of one column to int64 (the oracle's decoder)."""
+    r1 = n_rows if r1 is None else r1
+    keep = []
+    oc = _column(column, n_rows, keep)
+    out = np.empty(max(r1 - r0, 0), dtype=np.int64)
+    err = lib().orc_decode(ctypes.byref(oc), int(n_rows), int(r0), int(r1), out.ctypes.data)
+    if err:
+        raise OracleError(err.decode())
+    return out
+
+
+def run(table, query, n_threads=None):
+    """Execute `query` over `table` ({"n_rows", "columns"}) on the CPU."""
+    n_rows = int(table["n_rows"])
+    names = list(table["columns"].keys())
+    idx = {n: i for i, n in enumerate(names)}
+    keep = []
+    cols = (OrcColumn * max(len(names), 1))()
+    for i, n in enumerate(names):
+        cols[i] = _column(table["columns"][n], n_rows, keep)
+
+    def col_id(name):
+        if name not in idx:
+            raise OracleError("unknown column %r" % (name,))
+        return idx[name]
+
+    preds = (OrcPred * max(len(query["preds"]), 1))()
+    for i, p in enumerate(query["preds"]):
+        op = p[1]
+        preds[i].col = col_id(p[0])
+        if op == "range":
+            preds[i].op, preds[i].lo, preds[i].hi = RANGE, int(p[2]), int(p[3])
+        elif op == "in":
+            lst = np.ascontiguousarray(np.array(list(p[2]), dtype=np.int64))
+            keep.append(lst)
+            preds[i].op, preds[i].in_list, preds[i].in_len = IN, lst.ctypes.data, len(lst)
+        else:
+            raise OracleError("unknown predicate %r" % (op,))
+    keys = (OrcKey * max(len(query["keys"]), 1))()
+    for i, k in enumerate(query["keys"]):
+        keys[i].col, keys[i].shift, keys[i].card = col_id(k[0]), int(k[1]), int(k[2])
+    aggs = (OrcAgg * max(len(query["aggs"]), 1))()
+    for i, a in enumerate(query["aggs"]):
+        if a[0] == "count":
+            aggs[i].func, aggs[i].col = COUNT, -1
+        elif a[0] == "sum":
+            aggs[i].func, aggs[i].col = SUM, col_id(a[1])
+        else:
+            raise OracleError("unknown aggregate %r" % (a[0],))
+    rb, re_ = query.get("window", (0, n_rows))
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    L = lib()
+    h = L.orc_query(cols, len(names), n_rows, preds, len(query["preds"]), keys, len(query["keys"]), aggs,
+                    len(query["aggs"]), int(rb), int(re_), int(n_threads))
+    try:
+        err = L.orc_error(h)
+        if err:
+            raise OracleError(err.decode())
+        g = L.orc_n_groups(h)
+        nk, na = len(query["keys"]), len(query["aggs"])
+        kb = np.zeros(max(g * nk, 1), dtype=np.int64)
+        cb = np.zeros(max(g, 1), dtype=np.int64)
+        ab = np.zeros(max(g * na, 1), dtype=np.int64)
+        L.orc_copy(h, kb.ctypes.data, cb.ctypes.data, ab.ctypes.data)
+    finally:
+        L.orc_free(h)
+    return {
+        "keys": [tuple(int(x) for x in kb[i * nk:(i + 1) * nk]) for i in range(g)],
+        "counts": [int(x) for x in cb[:g]],
+        "aggs": [tuple(int(x) for x in ab[i * na:(i + 1) * na]) for i in range(g)],
+    }

@@ -1,0 +1,99 @@
+"""Pure-Python brute force for tiny tables (test helper, no C, no numpy math).
+
+Decodes every column row by row with its own decoder (the packed stream is
+read as one Python big integer, a different route from the oracle's two-word
+read), evaluates the query one row at a time and groups with a dict.  A
+second route loads the decoded rows into sqlite3 and lets SQL do the work.
+"""
+from __future__ import annotations
+
+import sqlite3
+
+
+def decode_rows(col, n_rows):
+    enc = col["enc"]
+    if enc == "rle":
+        out = []
+        start = 0
+        for v, e in zip(col["values"], col["run_ends"]):
+            out.extend([int(v)] * (int(e) - start))
+            start = int(e)
+        assert len(out) == n_rows
+        return out
+    if enc == "index":
+        out = [0] * n_rows
+        for p, v in zip(col["positions"], col["values"]):
+            out[int(p)] = int(v)
+        return out
+    if enc == "bitpacked":
+        w = int(col["w"])
+        big = 0
+        for i, word in enumerate(col["packed"]):
+            big |= int(word) << (32 * i)
+        mask = (1 << w) - 1
+        return [int(col.get("base", 0)) + ((big >> (r * w)) & mask) for r in range(n_rows)]
+    raise ValueError(enc)
+
+
+def run(table, query):
+    n = int(table["n_rows"])
+    rows = {name: decode_rows(c, n) for name, c in table["columns"].items()}
+    r0, r1 = query.get("window", (0, n))
+    groups = {}
+    for r in range(r0, r1):
+        ok = True
+        for p in query["preds"]:
+            v = rows[p[0]][r]
+            if p[1] == "range":
+                ok = p[2] <= v < p[3]
+            else:
+                ok = v in set(p[2])
+            if not ok:
+                break
+        if not ok:
+            continue
+        key = []
+        for (c, shift, card) in query["keys"]:
+            k = rows[c][r] >> shift
+            if not (0 <= k < card):
+                raise ValueError("key outside domain")
+            key.append(k)
+        key = tuple(key)
+        acc = groups.setdefault(key, [0] + [0] * len(query["aggs"]))
+        acc[0] += 1
+        for i, a in enumerate(query["aggs"]):
+            acc[1 + i] += 1 if a[0] == "count" else rows[a[1]][r]
+    if not query["keys"]:
+        acc = groups.get((), [0] + [0] * len(query["aggs"]))
+        return {"keys": [()], "counts": [acc[0]], "aggs": [tuple(acc[1:])]}
+    ks = sorted(groups)
+    return {"keys": ks, "counts": [groups[k][0] for k in ks], "aggs": [tuple(groups[k][1:]) for k in ks]}
+
+
+def run_sqlite(table, query):
+    """Same query through sqlite3 over the decoded rows."""
+    n = int(table["n_rows"])
+    names = list(table["columns"])
+    rows = {name: decode_rows(table["columns"][name], n) for name in names}
+    db = sqlite3.connect(":memory:")
+    cols = ", ".join('"%s" INTEGER' % c for c in names)
+    db.execute("CREATE TABLE t (rid INTEGER, %s)" % cols)
+    db.executemany("INSERT INTO t VALUES (%s)" % ", ".join("?" * (len(names) + 1)),
+                   [(r,) + tuple(rows[c][r] for c in names) for r in range(n)])
+    r0, r1 = query.get("window", (0, n))
+    where = ["rid >= %d" % r0, "rid < %d" % r1]
+    for p in query["preds"]:
+        if p[1] == "range":
+            where.append('"%s" >= %d AND "%s" < %d' % (p[0], p[2], p[0], p[3]))
+        else:
+            where.append('"%s" IN (%s)' % (p[0], ", ".join(str(int(x)) for x in p[2]) or "NULL"))
+    keys = ['("%s" >> %d)' % (c, s) for (c, s, _) in query["keys"]]
+    aggs = ["COUNT(*)"] + ["COUNT(*)" if a[0] == "count" else 'COALESCE(SUM("%s"), 0)' % a[1]
+                           for a in query["aggs"]]
+    sql = "SELECT %s FROM t WHERE %s" % (", ".join(keys + aggs), " AND ".join(where))
+    if keys:
+        sql += " GROUP BY %s ORDER BY %s" % (", ".join(keys), ", ".join(keys))
+    out = db.execute(sql).fetchall()
+    nk = len(keys)
+    return {"keys": [tuple(r[:nk]) for r in out], "counts": [r[nk] for r in out],
+            "aggs": [tuple(r[nk + 1:]) for r in out]}
