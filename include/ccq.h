@@ -1,0 +1,195 @@
+/*
+ * ccq.h -- filter / group-by / aggregate queries that run directly on
+ * lightweight-compressed columns on an MI355X (gfx950) GPU.
+ *
+ * The operation follows the paper's statement of the problem
+ * (arXiv 2506.10092, "GPU Acceleration of SQL Analytics on Compressed Data"):
+ *   - columns arrive encoded (Section 3.1: Plain, RLE, Index; Section 3.2:
+ *     bit-width reduction around a global reference value; dictionary codes
+ *     are plain integer codes, Section 2.1);
+ *   - a query is a conjunction of selection predicates (Sections 5.1 and 6),
+ *     a list of group-by keys and SUM / COUNT(*) aggregates (Section 7);
+ *   - the answer is the exact aggregate per non-empty group, in ascending key
+ *     order (torch.unique order, Section 2.2).  RLE runs contribute
+ *     value * run length to SUM and run length to COUNT (Section 7,
+ *     "Aggregating Phase"); runs of several RLE columns are first aligned to
+ *     their common refinement (Section 6, Alignment; Algorithm 1).
+ *
+ * Conventions (readings of the paper, see the design notes):
+ *   - an RLE column stores values[i] and an EXCLUSIVE run end run_ends[i]:
+ *     run i covers rows [run_ends[i-1], run_ends[i]) (run_ends[-1] = 0), i.e.
+ *     the paper's inclusive end plus one; base columns have no gaps;
+ *   - an Index column lists (position, value) pairs; rows it does not list
+ *     hold the value 0;
+ *   - a bit-packed column stores row r's code in bits [r*w, r*w + w) of an
+ *     LSB-first stream of little-endian uint32 words; value = base + code;
+ *   - RANGE predicates are half open, lo <= v < hi; IN has set semantics;
+ *   - a group key is v >> shift (arithmetic) and must lie in [0, card);
+ *   - all arithmetic is exact int64 (sums wrap only where int64 overflows,
+ *     which callers must rule out).
+ *
+ * Memory: every column buffer, workspace and result buffer is DEVICE memory
+ * owned by the caller (e.g. torch tensors); the library borrows column
+ * buffers for the lifetime of the table and plans built on them and never
+ * writes to them.  Host descriptors and IN-lists are copied at create time.
+ * The library allocates device memory only in ccq_plan_create (the compiled
+ * plan) -- never in ccq_execute.
+ *
+ * Errors: every call returns CCQ_OK (0) or a negative ccq_status; a
+ * thread-local message is available from ccq_last_error().  Errors that
+ * depend on data values (a group key outside its domain) are written to the
+ * result's device status word by the kernels and are readable after the
+ * stream is synchronised.  No C++ exception crosses this interface.
+ *
+ * Threading: a context, table or plan may be used from several host threads;
+ * a plan is immutable after creation and may run concurrently on different
+ * streams as long as each call has its own workspace and result buffers.
+ */
+#ifndef CCQ_H
+#define CCQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCQ_ABI_VERSION 1
+
+typedef int32_t ccq_status;
+enum {
+    CCQ_OK = 0,
+    CCQ_E_INVALID = -1,      /* malformed argument, descriptor or plan */
+    CCQ_E_UNSUPPORTED = -2,  /* well formed, but outside what the kernels implement */
+    CCQ_E_CAPACITY = -3,     /* workspace or result buffer too small */
+    CCQ_E_KEY_DOMAIN = -4,   /* (device status) a group key fell outside [0, card) */
+    CCQ_E_HIP = -5,          /* HIP runtime error (message has the detail) */
+    CCQ_E_BUDGET = -6,       /* server: the query does not fit the HBM budget */
+    CCQ_E_BUSY = -7,         /* server: queue full */
+    CCQ_E_NOMEM = -8         /* host or device allocation failed */
+};
+
+typedef struct ccq_context ccq_context;
+typedef struct ccq_table ccq_table;
+typedef struct ccq_plan ccq_plan;
+
+/* ---- encodings (Section 3.1 Basic Encodings; Section 3.2 bit widths) ---- */
+enum { CCQ_RLE = 1, CCQ_INDEX = 2, CCQ_BITPACKED = 3 };
+enum { CCQ_I32 = 1, CCQ_I64 = 2 };
+
+typedef struct {
+    int32_t encoding;          /* CCQ_RLE, CCQ_INDEX or CCQ_BITPACKED */
+    int32_t value_type;        /* RLE, INDEX: CCQ_I32 or CCQ_I64 */
+    int64_t n_entries;         /* RLE: runs; INDEX: listed points; BITPACKED: rows (== table rows) */
+    const void* values;        /* RLE, INDEX: device value_type[n_entries] */
+    const int64_t* run_ends;   /* RLE: device int64[n_entries], exclusive, strictly
+                                  increasing, first > 0, last == table rows */
+    const void* positions;     /* INDEX: device position_type[n_entries], strictly
+                                  increasing in [0, table rows) */
+    const uint32_t* packed;    /* BITPACKED: device stream of >= ceil(rows*w/32) + 2 words */
+    int32_t bit_width;         /* BITPACKED: 1..32 */
+    int32_t position_type;     /* INDEX: CCQ_I32 or CCQ_I64 */
+    int64_t base;              /* BITPACKED: value = base + code */
+} ccq_column_desc;
+
+/* ---- query (Sections 5-7) ---- */
+enum { CCQ_RANGE = 1, CCQ_IN = 2 };
+typedef struct {
+    int32_t col;               /* column index in the table */
+    int32_t op;                /* CCQ_RANGE: lo <= v < hi;  CCQ_IN: v in in_list */
+    int64_t lo, hi;
+    const int64_t* in_list;    /* CCQ_IN: HOST array, copied by ccq_plan_create */
+    int64_t in_len;
+} ccq_pred;
+
+typedef struct {
+    int32_t col;               /* RLE or BITPACKED column */
+    int32_t shift;             /* key = v >> shift, 0..62 */
+    int64_t card;              /* the key must lie in [0, card) */
+} ccq_key;
+
+enum { CCQ_COUNT_STAR = 1, CCQ_SUM = 2 };
+typedef struct {
+    int32_t func;              /* CCQ_COUNT_STAR or CCQ_SUM */
+    int32_t col;               /* CCQ_SUM: any column; ignored for COUNT(*) */
+} ccq_agg;
+
+typedef struct {
+    const ccq_pred* preds;  int32_t n_preds;   /* conjunction */
+    const ccq_key* keys;    int32_t n_keys;    /* GROUP BY, first key most significant */
+    const ccq_agg* aggs;    int32_t n_aggs;
+    int64_t row_begin, row_end;                /* logical window [row_begin, row_end) */
+} ccq_query_desc;
+
+/* Result buffers (DEVICE memory, caller owned).  After the stream is
+ * synchronised: *n_groups rows are valid; row g has keys[g*n_keys + k],
+ * counts[g] (= COUNT(*) of the group) and aggs[g*n_aggs + a] (COUNT(*)
+ * aggregates repeat counts[g]).  Grouped queries list only groups with
+ * count > 0, in ascending key order.  An ungrouped query always yields one
+ * row (count 0 and sums 0 when nothing qualifies).  *status is CCQ_OK or a
+ * data-dependent error (CCQ_E_KEY_DOMAIN), in which case the rows are not
+ * meaningful.  capacity must be >= the plan's max_groups (ccq_plan_info). */
+typedef struct {
+    int64_t* keys;
+    int64_t* counts;
+    int64_t* aggs;
+    int64_t* n_groups;
+    int32_t* status;
+    int64_t capacity;
+} ccq_result;
+
+/* ---- calls ---- */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ccq_last_error(void);
+int32_t ccq_abi_version(void);
+
+/* A context binds a HIP device (the device is made current on each call).
+ * device == CCQ_HOST_ONLY makes a context without a device: tables can be
+ * described and plans checked (ccq_plan_check), nothing can run. */
+#define CCQ_HOST_ONLY (-1)
+ccq_status ccq_context_create(int32_t device, ccq_context** out);
+void ccq_context_destroy(ccq_context* ctx);              /* NULL-safe */
+
+/* A table: n_rows logical rows and n_cols encoded columns.  Host-side checks
+ * only (counts, widths, pointer presence); see ccq_table_validate for the
+ * O(data) device check. */
+ccq_status ccq_table_create(ccq_context* ctx, int64_t n_rows, const ccq_column_desc* cols, int32_t n_cols,
+                            ccq_table** out);
+void ccq_table_destroy(ccq_table* t);                    /* NULL-safe; plans keep their own copy */
+
+/* Check on the device that run ends are strictly increasing with the last
+ * equal to n_rows and that positions are strictly increasing in range.
+ * Synchronises `stream`; returns CCQ_OK or CCQ_E_INVALID. */
+ccq_status ccq_table_validate(ccq_table* t, void* stream);
+
+/* Compile a query against a table: validates the query, folds predicates
+ * per column, builds code lookup tables, chooses tiles and allocates the
+ * plan's device descriptor.  CCQ_E_UNSUPPORTED for query shapes the kernels
+ * do not implement (predicates or keys on INDEX columns, more than 8 RLE or
+ * 4 bit-packed columns, more than 2^27 key combinations). */
+ccq_status ccq_plan_create(const ccq_table* t, const ccq_query_desc* q, ccq_plan** out);
+void ccq_plan_destroy(ccq_plan* p);                      /* NULL-safe */
+
+/* Validate and compile a query without allocating anything: the same
+ * checks and status codes as ccq_plan_create, plus the result bound and the
+ * workspace size a plan for it would report. */
+ccq_status ccq_plan_check(const ccq_table* t, const ccq_query_desc* q, int64_t* max_groups,
+                          size_t* workspace_bytes);
+
+/* Upper bound on result rows and the workspace size ccq_execute needs. */
+ccq_status ccq_plan_info(const ccq_plan* p, int64_t* max_groups, size_t* workspace_bytes);
+
+/* Run one query on `stream` (a hipStream_t, or NULL for the null stream).
+ * Asynchronous: returns after enqueueing.  workspace: device buffer of at
+ * least workspace_bytes, 256-byte aligned, not shared with a concurrent call.
+ * Result rows are written as described at ccq_result. */
+ccq_status ccq_execute(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
+                       const ccq_result* result);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCQ_H */

@@ -1,0 +1,317 @@
+"""ctypes binding for libccq (include/ccq.h): argument marshalling only.
+
+Device memory and streams come from torch; every step of a query runs in the
+library's HIP kernels.  The binding refuses to work when libccq.so is
+missing -- there is no CPU fallback.
+
+Column dicts follow the generator's format (see ``datagen``) but hold torch
+tensors on the GPU::
+
+    {"enc": "rle", "values": int32|int64, "run_ends": int64}
+    {"enc": "index", "positions": int32|int64, "values": int32|int64}
+    {"enc": "bitpacked", "packed": int32 (the uint32 words), "w": int, "base": int}
+
+A query names columns and uses the same dict layout as the generator::
+
+    {"preds": [(col, "range", lo, hi) | (col, "in", [...])],
+     "keys": [(col, shift, card)], "aggs": [("count",) | ("sum", col)],
+     "window": (row_begin, row_end)}
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccq.so")
+
+OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_KEY_DOMAIN, E_HIP, E_BUDGET, E_BUSY, E_NOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8
+RLE, INDEX, BITPACKED = 1, 2, 3
+I32, I64 = 1, 2
+RANGE, IN = 1, 2
+COUNT_STAR, SUM = 1, 2
+HOST_ONLY = -1
+
+_STATUS_NAMES = {0: "CCQ_OK", -1: "CCQ_E_INVALID", -2: "CCQ_E_UNSUPPORTED", -3: "CCQ_E_CAPACITY",
+                 -4: "CCQ_E_KEY_DOMAIN", -5: "CCQ_E_HIP", -6: "CCQ_E_BUDGET", -7: "CCQ_E_BUSY", -8: "CCQ_E_NOMEM"}
+
+
+class CcqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class ColumnDesc(ctypes.Structure):
+    _fields_ = [("encoding", ctypes.c_int32), ("value_type", ctypes.c_int32), ("n_entries", ctypes.c_int64),
+                ("values", ctypes.c_void_p), ("run_ends", ctypes.c_void_p), ("positions", ctypes.c_void_p),
+                ("packed", ctypes.c_void_p), ("bit_width", ctypes.c_int32), ("position_type", ctypes.c_int32),
+                ("base", ctypes.c_int64)]
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
+                ("in_list", ctypes.c_void_p), ("in_len", ctypes.c_int64)]
+
+
+class Key(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("shift", ctypes.c_int32), ("card", ctypes.c_int64)]
+
+
+class Agg(ctypes.Structure):
+    _fields_ = [("func", ctypes.c_int32), ("col", ctypes.c_int32)]
+
+
+class QueryDesc(ctypes.Structure):
+    _fields_ = [("preds", ctypes.POINTER(Pred)), ("n_preds", ctypes.c_int32),
+                ("keys", ctypes.POINTER(Key)), ("n_keys", ctypes.c_int32),
+                ("aggs", ctypes.POINTER(Agg)), ("n_aggs", ctypes.c_int32),
+                ("row_begin", ctypes.c_int64), ("row_end", ctypes.c_int64)]
+
+
+class ResultDesc(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("aggs", ctypes.c_void_p),
+                ("n_groups", ctypes.c_void_p), ("status", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+# every function include/ccq.h declares: name -> (restype, argtypes)
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+SIGNATURES = {
+    "ccq_last_error": (ctypes.c_char_p, []),
+    "ccq_abi_version": (_i32, []),
+    "ccq_context_create": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "ccq_context_destroy": (None, [_vp]),
+    "ccq_table_create": (_i32, [_vp, _i64, ctypes.POINTER(ColumnDesc), _i32, ctypes.POINTER(_vp)]),
+    "ccq_table_destroy": (None, [_vp]),
+    "ccq_table_validate": (_i32, [_vp, _vp]),
+    "ccq_plan_check": (_i32, [_vp, ctypes.POINTER(QueryDesc), ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
+    "ccq_plan_create": (_i32, [_vp, ctypes.POINTER(QueryDesc), ctypes.POINTER(_vp)]),
+    "ccq_plan_destroy": (None, [_vp]),
+    "ccq_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
+    "ccq_execute": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libccq.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CcqError(E_UNSUPPORTED, "libccq.so is not built (run __graft_entry__.build()); "
+                                          "there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise CcqError(status, lib().ccq_last_error().decode())
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.int32:
+        return I32
+    if t.dtype == torch.int64:
+        return I64
+    raise CcqError(E_INVALID, "values must be int32 or int64 tensors, got %s" % t.dtype)
+
+
+class Context:
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        _check(lib().ccq_context_create(int(device), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ccq_context_destroy(self.h)
+            self.h = None
+
+
+def _column_desc(c, n_rows):
+    d = ColumnDesc()
+    if c["enc"] == "rle":
+        d.encoding, d.value_type, d.n_entries = RLE, _dtype_code(c["values"]), c["run_ends"].numel()
+        d.values, d.run_ends = c["values"].data_ptr(), c["run_ends"].data_ptr()
+    elif c["enc"] == "index":
+        d.encoding, d.value_type, d.n_entries = INDEX, _dtype_code(c["values"]), c["positions"].numel()
+        d.position_type = _dtype_code(c["positions"])
+        d.values, d.positions = c["values"].data_ptr(), c["positions"].data_ptr()
+    elif c["enc"] == "bitpacked":
+        d.encoding, d.n_entries, d.bit_width, d.base = BITPACKED, n_rows, int(c["w"]), int(c.get("base", 0))
+        d.packed = c["packed"].data_ptr()
+    else:
+        raise CcqError(E_INVALID, "unknown encoding %r" % (c["enc"],))
+    return d
+
+
+class Table:
+    """Encoded columns (device tensors, borrowed) over n_rows logical rows."""
+
+    def __init__(self, ctx, n_rows, columns):
+        self.ctx = ctx
+        self.n_rows = int(n_rows)
+        self.names = list(columns)
+        self.columns = columns            # keeps the tensors alive
+        arr = (ColumnDesc * max(len(self.names), 1))()
+        for i, n in enumerate(self.names):
+            arr[i] = _column_desc(columns[n], self.n_rows)
+        h = ctypes.c_void_p()
+        _check(lib().ccq_table_create(ctx.h, self.n_rows, arr, len(self.names), ctypes.byref(h)))
+        self.h = h
+
+    def validate(self, stream=None):
+        _check(lib().ccq_table_validate(self.h, _stream_ptr(stream)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ccq_table_destroy(self.h)
+            self.h = None
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def query_desc(table, query):
+    """Marshal a query dict into a QueryDesc; returns (desc, keepalive)."""
+    idx = {n: i for i, n in enumerate(table.names)}
+
+    def col(name):
+        if name not in idx:
+            raise CcqError(E_INVALID, "unknown column %r" % (name,))
+        return idx[name]
+
+    keep = []
+    preds = (Pred * max(len(query["preds"]), 1))()
+    for i, p in enumerate(query["preds"]):
+        preds[i].col = col(p[0])
+        if p[1] == "range":
+            preds[i].op, preds[i].lo, preds[i].hi = RANGE, int(p[2]), int(p[3])
+        elif p[1] == "in":
+            lst = np.ascontiguousarray(np.array(list(p[2]), dtype=np.int64))
+            keep.append(lst)
+            preds[i].op, preds[i].in_list, preds[i].in_len = IN, lst.ctypes.data, len(lst)
+        else:
+            raise CcqError(E_INVALID, "unknown predicate %r" % (p[1],))
+    keys = (Key * max(len(query["keys"]), 1))()
+    for i, k in enumerate(query["keys"]):
+        keys[i].col, keys[i].shift, keys[i].card = col(k[0]), int(k[1]), int(k[2])
+    aggs = (Agg * max(len(query["aggs"]), 1))()
+    for i, a in enumerate(query["aggs"]):
+        if a[0] == "count":
+            aggs[i].func, aggs[i].col = COUNT_STAR, -1
+        elif a[0] == "sum":
+            aggs[i].func, aggs[i].col = SUM, col(a[1])
+        else:
+            raise CcqError(E_INVALID, "unknown aggregate %r" % (a[0],))
+    rb, re_ = query.get("window", (0, table.n_rows))
+    d = QueryDesc(preds, len(query["preds"]), keys, len(query["keys"]), aggs, len(query["aggs"]), int(rb), int(re_))
+    keep += [preds, keys, aggs]
+    return d, keep
+
+
+def plan_check(table, query):
+    """Validate and compile without allocating: (max_groups, workspace_bytes)."""
+    d, keep = query_desc(table, query)
+    g, w = ctypes.c_int64(), ctypes.c_size_t()
+    _check(lib().ccq_plan_check(table.h, ctypes.byref(d), ctypes.byref(g), ctypes.byref(w)))
+    return g.value, w.value
+
+
+class Result:
+    """Caller-owned device result buffers."""
+
+    def __init__(self, capacity, n_keys, n_aggs, device):
+        import torch
+        self.capacity = int(capacity)
+        self.n_keys, self.n_aggs = n_keys, n_aggs
+        self.keys = torch.zeros(max(self.capacity * n_keys, 1), dtype=torch.int64, device=device)
+        self.counts = torch.zeros(max(self.capacity, 1), dtype=torch.int64, device=device)
+        self.aggs = torch.zeros(max(self.capacity * n_aggs, 1), dtype=torch.int64, device=device)
+        self.n_groups = torch.zeros(1, dtype=torch.int64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.desc = ResultDesc(self.keys.data_ptr(), self.counts.data_ptr(), self.aggs.data_ptr(),
+                               self.n_groups.data_ptr(), self.status.data_ptr(), self.capacity)
+
+    def to_python(self):
+        """Copy to host (synchronises) and return {"keys", "counts", "aggs", "status"}."""
+        g = int(self.n_groups.item())
+        st = int(self.status.item())
+        nk, na = self.n_keys, self.n_aggs
+        k = self.keys[: g * nk].cpu().numpy().reshape(g, nk) if nk else np.zeros((g, 0), dtype=np.int64)
+        c = self.counts[:g].cpu().numpy()
+        a = self.aggs[: g * na].cpu().numpy().reshape(g, na) if na else np.zeros((g, 0), dtype=np.int64)
+        return {"keys": [tuple(int(x) for x in row) for row in k], "counts": [int(x) for x in c],
+                "aggs": [tuple(int(x) for x in row) for row in a], "status": st}
+
+
+class Plan:
+    def __init__(self, table, query):
+        self.table = table
+        self.query = query
+        d, keep = query_desc(table, query)
+        h = ctypes.c_void_p()
+        _check(lib().ccq_plan_create(table.h, ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+        g, w = ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib().ccq_plan_info(h, ctypes.byref(g), ctypes.byref(w)))
+        self.max_groups, self.workspace_bytes = g.value, w.value
+        self.n_keys, self.n_aggs = len(query["keys"]), len(query["aggs"])
+
+    def new_workspace(self):
+        import torch
+        # torch's caching allocator returns 512-byte aligned blocks
+        return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device="cuda:%d" % self.table.ctx.device)
+
+    def new_result(self):
+        return Result(self.max_groups, self.n_keys, self.n_aggs, "cuda:%d" % self.table.ctx.device)
+
+    def execute(self, workspace, result, stream=None):
+        """Enqueue the query on `stream` (torch stream, raw handle or None = current)."""
+        _check(lib().ccq_execute(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                 _stream_ptr(stream), ctypes.byref(result.desc)))
+
+    def run(self):
+        """Execute once and return the result on the host."""
+        ws, res = self.new_workspace(), self.new_result()
+        self.execute(ws, res)
+        return res.to_python()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ccq_plan_destroy(self.h)
+            self.h = None
+
+
+def to_device(columns, device="cuda:0"):
+    """Host column dicts (numpy) -> device column dicts (torch tensors)."""
+    import torch
+    out = {}
+    for name, c in columns.items():
+        d = {"enc": c["enc"]}
+        for k, v in c.items():
+            if isinstance(v, np.ndarray):
+                if v.dtype == np.uint32:
+                    v = v.view(np.int32)
+                d[k] = torch.from_numpy(np.ascontiguousarray(v)).to(device)
+            elif k != "enc":
+                d[k] = v
+        out[name] = d
+    return out

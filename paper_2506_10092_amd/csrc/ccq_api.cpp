@@ -1,0 +1,632 @@
+// Host side of the ccq C-ABI (include/ccq.h): validation, plan compilation
+// (predicate folding, code tables, tiling, LDS layout) and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/ccq.h"
+#include "ccq_plan.h"
+
+using namespace ccq;
+
+namespace {
+
+thread_local std::string g_err;
+
+ccq_status fail(ccq_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+ccq_status ok() {
+    g_err.clear();
+    return CCQ_OK;
+}
+
+ccq_status hip_fail(hipError_t e, const char* what) {
+    return fail(CCQ_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct ccq_context {
+    int device;
+    int cus;
+    size_t lds_per_block;
+};
+
+struct ccq_table {
+    ccq_context* ctx;
+    int64_t n_rows;
+    std::vector<ccq_column_desc> cols;
+};
+
+struct ccq_plan {
+    ccq_context* ctx;
+    DevPlan host;           // host copy (device pointers inside)
+    DevPlan* dev;           // device copy, inside `blob`
+    void* blob;             // one device allocation: plan, code tables, sets, slot keys
+    int grid_fused;
+    int64_t max_groups;
+    WsLayout ws;
+};
+
+extern "C" {
+
+const char* ccq_last_error(void) { return g_err.c_str(); }
+
+int32_t ccq_abi_version(void) { return CCQ_ABI_VERSION; }
+
+ccq_status ccq_context_create(int32_t device, ccq_context** out) {
+    if (!out) return fail(CCQ_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (device == CCQ_HOST_ONLY) {
+        ccq_context* c = new (std::nothrow) ccq_context;
+        if (!c) return fail(CCQ_E_NOMEM, "out of host memory");
+        c->device = -1;
+        c->cus = 256;
+        c->lds_per_block = 160 * 1024;
+        *out = c;
+        return ok();
+    }
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(CCQ_E_INVALID, "device %d out of range (%d devices)", device, n);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+        return fail(CCQ_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    ccq_context* c = new (std::nothrow) ccq_context;
+    if (!c) return fail(CCQ_E_NOMEM, "out of host memory");
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    *out = c;
+    return ok();
+}
+
+void ccq_context_destroy(ccq_context* ctx) { delete ctx; }
+
+ccq_status ccq_table_create(ccq_context* ctx, int64_t n_rows, const ccq_column_desc* cols, int32_t n_cols,
+                            ccq_table** out) {
+    if (!out) return fail(CCQ_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(CCQ_E_INVALID, "context is NULL");
+    if (n_rows < 0) return fail(CCQ_E_INVALID, "n_rows must be >= 0");
+    if (n_cols < 0 || (n_cols > 0 && !cols)) return fail(CCQ_E_INVALID, "bad column array");
+    for (int i = 0; i < n_cols; ++i) {
+        const ccq_column_desc& c = cols[i];
+        if (c.encoding == CCQ_RLE) {
+            if (c.value_type != CCQ_I32 && c.value_type != CCQ_I64)
+                return fail(CCQ_E_INVALID, "column %d: RLE value_type must be CCQ_I32 or CCQ_I64", i);
+            if (n_rows > 0 && c.n_entries < 1) return fail(CCQ_E_INVALID, "column %d: RLE column needs runs", i);
+            if (c.n_entries > n_rows) return fail(CCQ_E_INVALID, "column %d: more runs than rows", i);
+            if (c.n_entries > 0 && (!c.values || !c.run_ends))
+                return fail(CCQ_E_INVALID, "column %d: RLE values / run_ends missing", i);
+        } else if (c.encoding == CCQ_INDEX) {
+            if (c.value_type != CCQ_I32 && c.value_type != CCQ_I64)
+                return fail(CCQ_E_INVALID, "column %d: INDEX value_type must be CCQ_I32 or CCQ_I64", i);
+            if (c.position_type != CCQ_I32 && c.position_type != CCQ_I64)
+                return fail(CCQ_E_INVALID, "column %d: INDEX position_type must be CCQ_I32 or CCQ_I64", i);
+            if (c.n_entries < 0 || c.n_entries > n_rows)
+                return fail(CCQ_E_INVALID, "column %d: INDEX n_entries out of range", i);
+            if (c.position_type == CCQ_I32 && n_rows > (int64_t)INT32_MAX + 1)
+                return fail(CCQ_E_INVALID, "column %d: int32 positions cannot address %lld rows", i,
+                            (long long)n_rows);
+            if (c.n_entries > 0 && (!c.values || !c.positions))
+                return fail(CCQ_E_INVALID, "column %d: INDEX values / positions missing", i);
+        } else if (c.encoding == CCQ_BITPACKED) {
+            if (c.bit_width < 1 || c.bit_width > 32)
+                return fail(CCQ_E_INVALID, "column %d: bit_width must be in 1..32", i);
+            if (c.n_entries != n_rows) return fail(CCQ_E_INVALID, "column %d: BITPACKED n_entries must equal n_rows", i);
+            if (n_rows > 0 && !c.packed) return fail(CCQ_E_INVALID, "column %d: packed stream missing", i);
+        } else {
+            return fail(CCQ_E_INVALID, "column %d: unknown encoding %d", i, c.encoding);
+        }
+    }
+    ccq_table* t = new (std::nothrow) ccq_table;
+    if (!t) return fail(CCQ_E_NOMEM, "out of host memory");
+    t->ctx = ctx;
+    t->n_rows = n_rows;
+    t->cols.assign(cols, cols + n_cols);
+    *out = t;
+    return ok();
+}
+
+void ccq_table_destroy(ccq_table* t) { delete t; }
+
+ccq_status ccq_table_validate(ccq_table* t, void* stream) {
+    if (!t) return fail(CCQ_E_INVALID, "table is NULL");
+    if (t->ctx->device < 0) return fail(CCQ_E_UNSUPPORTED, "host-only context has no device");
+    hipError_t e = hipSetDevice(t->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* flag = nullptr;
+    e = hipMalloc(&flag, sizeof(int32_t) * 64);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    int32_t host[64] = {0};
+    e = hipMemcpyAsync(flag, host, sizeof host, hipMemcpyHostToDevice, s);
+    for (size_t i = 0; i < t->cols.size() && e == hipSuccess; ++i) {
+        const ccq_column_desc& c = t->cols[i];
+        if (c.encoding == CCQ_RLE && c.n_entries > 0) e = launch_validate_rle(c.run_ends, c.n_entries, t->n_rows, flag + (i % 64), s);
+        if (c.encoding == CCQ_INDEX && c.n_entries > 0)
+            e = launch_validate_idx(c.positions, c.position_type, c.n_entries, t->n_rows, flag + (i % 64), s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(host, flag, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(flag);
+    if (e != hipSuccess) return hip_fail(e, "table validation");
+    for (size_t i = 0; i < t->cols.size(); ++i)
+        if (host[i % 64]) return fail(CCQ_E_INVALID, "column %zu: run ends or positions are not valid", i);
+    return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plan compilation
+
+namespace {
+
+struct Fold {               // conjunction of predicates on one column
+    bool has_range = false, has_set = false, is_false = false;
+    int64_t lo = 0, hi = 0;   // [lo, hi) when has_range
+    std::set<int64_t> set;
+};
+
+bool fold_pass(const Fold& f, int64_t v) {
+    if (f.is_false) return false;
+    if (f.has_range && !(f.lo <= v && v < f.hi)) return false;
+    if (f.has_set && !f.set.count(v)) return false;
+    return true;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+struct Compiled {
+    DevPlan P;
+    std::vector<unsigned char> blob;        // DevPlan followed by tables, sets, slot keys
+    std::vector<std::pair<size_t, size_t>> fixes;   // (pointer field offset in DevPlan, data offset in blob)
+};
+
+ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& out) {
+    if (!t || !q) return fail(CCQ_E_INVALID, "table or query is NULL");
+    const int ncol = (int)t->cols.size();
+    if (q->n_preds < 0 || q->n_keys < 0 || q->n_aggs < 0) return fail(CCQ_E_INVALID, "negative counts");
+    if ((q->n_preds && !q->preds) || (q->n_keys && !q->keys) || (q->n_aggs && !q->aggs))
+        return fail(CCQ_E_INVALID, "query arrays missing");
+    if (q->row_begin < 0 || q->row_end > t->n_rows || q->row_begin > q->row_end)
+        return fail(CCQ_E_INVALID, "window [%lld, %lld) outside the table of %lld rows", (long long)q->row_begin,
+                    (long long)q->row_end, (long long)t->n_rows);
+    if (q->n_keys > kMaxKeys) return fail(CCQ_E_UNSUPPORTED, "at most %d group keys", kMaxKeys);
+    if (q->n_aggs > kMaxAggs) return fail(CCQ_E_UNSUPPORTED, "at most %d aggregates", kMaxAggs);
+
+    DevPlan& P = out.P;
+    memset(&P, 0, sizeof P);
+    P.row_begin = q->row_begin;
+    P.row_end = q->row_end;
+
+    // referenced columns, grouped by encoding, in order of first use
+    std::vector<int> kind_slot(ncol, -1);
+    std::vector<int> rle_cols, bp_cols, idx_cols;
+    auto use = [&](int c) -> ccq_status {
+        if (c < 0 || c >= ncol) return fail(CCQ_E_INVALID, "column index %d out of range", c);
+        if (kind_slot[c] >= 0) return CCQ_OK;
+        int enc = t->cols[c].encoding;
+        std::vector<int>& v = enc == CCQ_RLE ? rle_cols : enc == CCQ_BITPACKED ? bp_cols : idx_cols;
+        kind_slot[c] = (int)v.size();
+        v.push_back(c);
+        return CCQ_OK;
+    };
+    for (int i = 0; i < q->n_preds; ++i)
+        if (ccq_status s = use(q->preds[i].col)) return s;
+    for (int i = 0; i < q->n_keys; ++i)
+        if (ccq_status s = use(q->keys[i].col)) return s;
+    for (int i = 0; i < q->n_aggs; ++i) {
+        if (q->aggs[i].func == CCQ_SUM) {
+            if (ccq_status s = use(q->aggs[i].col)) return s;
+        } else if (q->aggs[i].func != CCQ_COUNT_STAR) {
+            return fail(CCQ_E_INVALID, "aggregate %d: unknown function %d", i, q->aggs[i].func);
+        }
+    }
+    if ((int)rle_cols.size() > kMaxRle) return fail(CCQ_E_UNSUPPORTED, "at most %d RLE columns per query", kMaxRle);
+    if ((int)bp_cols.size() > kMaxBp)
+        return fail(CCQ_E_UNSUPPORTED, "at most %d bit-packed columns per query", kMaxBp);
+    if ((int)idx_cols.size() > kMaxIdx) return fail(CCQ_E_UNSUPPORTED, "at most %d Index columns per query", kMaxIdx);
+
+    // fold the conjunction per column (composite predicates on one column
+    // become one range or one set)
+    std::vector<Fold> fold(ncol);
+    for (int i = 0; i < q->n_preds; ++i) {
+        const ccq_pred& p = q->preds[i];
+        if (t->cols[p.col].encoding == CCQ_INDEX)
+            return fail(CCQ_E_UNSUPPORTED, "predicate %d: predicates on INDEX columns are not supported", i);
+        Fold& f = fold[p.col];
+        if (p.op == CCQ_RANGE) {
+            if (!f.has_range) {
+                f.has_range = true;
+                f.lo = p.lo;
+                f.hi = p.hi;
+            } else {
+                f.lo = std::max(f.lo, p.lo);
+                f.hi = std::min(f.hi, p.hi);
+            }
+            if (f.lo >= f.hi) f.is_false = true;
+        } else if (p.op == CCQ_IN) {
+            if (p.in_len < 0 || (p.in_len > 0 && !p.in_list))
+                return fail(CCQ_E_INVALID, "predicate %d: bad IN list", i);
+            std::set<int64_t> s(p.in_list, p.in_list + p.in_len);
+            if (!f.has_set) {
+                f.has_set = true;
+                f.set = s;
+            } else {
+                std::set<int64_t> both;
+                for (int64_t v : f.set)
+                    if (s.count(v)) both.insert(v);
+                f.set = both;
+            }
+        } else {
+            return fail(CCQ_E_INVALID, "predicate %d: unknown op %d", i, p.op);
+        }
+    }
+    for (auto& f : fold) {
+        if (f.has_set && f.has_range) {
+            std::set<int64_t> kept;
+            for (int64_t v : f.set)
+                if (f.lo <= v && v < f.hi) kept.insert(v);
+            f.set = kept;
+            f.has_range = false;
+        }
+        if (f.has_set && f.set.empty()) f.is_false = true;
+    }
+
+    // device blob contents, laid out after the DevPlan
+    std::vector<unsigned char>& blob = out.blob;
+    blob.assign(align16(sizeof(DevPlan)), 0);
+    auto blob_put = [&](const void* data, size_t bytes) -> size_t {
+        size_t off = blob.size();
+        blob.resize(align16(off + bytes));
+        if (bytes) memcpy(blob.data() + off, data, bytes);
+        return off;
+    };
+    auto fix_ptr = [&](const void* field, size_t data_off) {
+        out.fixes.push_back({(size_t)((const unsigned char*)field - (const unsigned char*)&P), data_off});
+    };
+
+    P.k_rle = (int)rle_cols.size();
+    P.n_bp = (int)bp_cols.size();
+    P.n_idx = (int)idx_cols.size();
+    for (int s = 0; s < P.k_rle; ++s) {
+        const ccq_column_desc& c = t->cols[rle_cols[s]];
+        const Fold& f = fold[rle_cols[s]];
+        RleCol& r = P.rle[s];
+        r.sum_slot = -1;
+        r.ends = c.run_ends;
+        r.vals = c.values;
+        r.n_runs = c.n_entries;
+        r.vtype = c.value_type;
+        if (f.is_false) r.pred = kPredFalse;
+        else if (f.has_set) {
+            r.pred = kPredSet;
+            std::vector<int64_t> v(f.set.begin(), f.set.end());
+            r.set_len = (int32_t)v.size();
+            fix_ptr(&r.set, blob_put(v.data(), v.size() * 8));
+        } else if (f.has_range) {
+            r.pred = kPredRange;
+            r.lo = f.lo;
+            r.hi = f.hi;
+        } else r.pred = kPredNone;
+    }
+    for (int s = 0; s < P.n_idx; ++s) {
+        const ccq_column_desc& c = t->cols[idx_cols[s]];
+        IdxCol& x = P.idx[s];
+        x.pos = c.positions;
+        x.vals = c.values;
+        x.n = c.n_entries;
+        x.ptype = c.position_type;
+        x.vtype = c.value_type;
+        x.sum_slot = -1;
+    }
+
+    // keys: mixed radix; bit-packed keys up to kLutMaxBits bits get dense
+    // slots over the key values their passing codes can reach
+    P.n_keys = q->n_keys;
+    std::vector<std::vector<int64_t>> slot_keys(q->n_keys);
+    std::vector<int> bp_key(P.n_bp, -1);
+    for (int k = 0; k < q->n_keys; ++k) {
+        const ccq_key& key = q->keys[k];
+        const ccq_column_desc& c = t->cols[key.col];
+        if (key.shift < 0 || key.shift > 62) return fail(CCQ_E_INVALID, "key %d: shift must be in 0..62", k);
+        if (key.card < 1) return fail(CCQ_E_INVALID, "key %d: card must be >= 1", k);
+        KeyDesc& kd = P.keys[k];
+        kd.shift = key.shift;
+        kd.card = key.card;
+        kd.src = kind_slot[key.col];
+        if (c.encoding == CCQ_RLE) {
+            kd.src_kind = kKeyRle;
+            kd.radix = key.card;
+            RleCol& r = P.rle[kd.src];
+            if (r.key_on) return fail(CCQ_E_UNSUPPORTED, "key %d: an RLE column may be one group key only", k);
+            r.key_on = 1;
+            r.key_shift = key.shift;
+            r.key_card = key.card;
+        } else if (c.encoding == CCQ_BITPACKED) {
+            kd.src_kind = kKeyBp;
+            if (bp_key[kd.src] >= 0)
+                return fail(CCQ_E_UNSUPPORTED, "key %d: a bit-packed column may be one group key only", k);
+            bp_key[kd.src] = k;
+            if (c.bit_width <= kLutMaxBits) {
+                kd.via_lut = 1;
+                const Fold& f = fold[key.col];
+                std::set<int64_t> reach;
+                for (int64_t code = 0; code < (int64_t(1) << c.bit_width); ++code) {
+                    int64_t v = c.base + code;
+                    if (!fold_pass(f, v)) continue;
+                    int64_t kv = v >> key.shift;
+                    if (kv >= 0 && kv < key.card) reach.insert(kv);
+                }
+                slot_keys[k].assign(reach.begin(), reach.end());
+                kd.radix = std::max<int64_t>(1, (int64_t)slot_keys[k].size());
+                if (slot_keys[k].empty()) slot_keys[k].push_back(0);
+                fix_ptr(&kd.slot_keys, blob_put(slot_keys[k].data(), slot_keys[k].size() * 8));
+            } else {
+                kd.radix = key.card;
+            }
+        } else {
+            return fail(CCQ_E_UNSUPPORTED, "key %d: group keys on INDEX columns are not supported", k);
+        }
+    }
+    int64_t G = 1;
+    for (int k = q->n_keys - 1; k >= 0; --k) {
+        P.keys[k].stride = G;
+        if (P.keys[k].radix > kMaxGroups / G)
+            return fail(CCQ_E_UNSUPPORTED, "more than 2^27 key combinations (product of key domains)");
+        G *= P.keys[k].radix;
+    }
+    P.n_groups = G;
+    for (int k = 0; k < q->n_keys; ++k)
+        if (P.keys[k].src_kind == kKeyRle) P.rle[P.keys[k].src].key_stride = P.keys[k].stride;
+
+    // bit-packed columns: predicates and key slots folded into one code table
+    std::vector<bool> has_lut(P.n_bp, false);
+    for (int s = 0; s < P.n_bp; ++s) {
+        const ccq_column_desc& c = t->cols[bp_cols[s]];
+        const Fold& f = fold[bp_cols[s]];
+        BpCol& b = P.bp[s];
+        b.packed = c.packed;
+        b.base = c.base;
+        b.w = c.bit_width;
+        b.key = bp_key[s];
+        b.sum_slot = -1;
+        if (b.key >= 0) {
+            b.key_shift = P.keys[b.key].shift;
+            b.key_card = P.keys[b.key].card;
+            b.key_stride = P.keys[b.key].stride;
+        }
+        const bool has_pred = f.is_false || f.has_range || f.has_set;
+        if (c.bit_width <= kLutMaxBits && (has_pred || b.key >= 0)) {
+            const int64_t n = int64_t(1) << c.bit_width;
+            std::vector<uint16_t> lut(n);
+            std::map<int64_t, int64_t> rank;
+            if (b.key >= 0)
+                for (size_t i = 0; i < slot_keys[b.key].size(); ++i) rank[slot_keys[b.key][i]] = (int64_t)i;
+            for (int64_t code = 0; code < n; ++code) {
+                const int64_t v = c.base + code;
+                if (!fold_pass(f, v)) { lut[code] = kLutReject; continue; }
+                if (b.key < 0) { lut[code] = 0; continue; }
+                const KeyDesc& kd = P.keys[b.key];
+                const int64_t kv = v >> kd.shift;
+                lut[code] = (kv < 0 || kv >= kd.card) ? kLutDomain : (uint16_t)rank[kv];
+            }
+            fix_ptr(&b.lut, blob_put(lut.data(), lut.size() * 2));
+            has_lut[s] = true;
+        } else {
+            if (f.is_false) b.pred = kPredFalse;
+            else if (f.has_set) {
+                b.pred = kPredSet;
+                std::vector<int64_t> v(f.set.begin(), f.set.end());
+                b.set_len = (int32_t)v.size();
+                fix_ptr(&b.set, blob_put(v.data(), v.size() * 8));
+            } else if (f.has_range) {
+                b.pred = kPredRange;
+                b.lo = f.lo;
+                b.hi = f.hi;
+            } else b.pred = kPredNone;
+        }
+    }
+
+    // aggregates
+    P.n_aggs = q->n_aggs;
+    for (int a = 0; a < q->n_aggs; ++a) {
+        AggDesc& ad = P.aggs[a];
+        if (q->aggs[a].func == CCQ_COUNT_STAR) {
+            ad.kind = kAggCount;
+            ad.sum_slot = -1;
+            continue;
+        }
+        const int col = q->aggs[a].col;
+        const int enc = t->cols[col].encoding;
+        ad.kind = enc == CCQ_RLE ? kAggSumRle : enc == CCQ_BITPACKED ? kAggSumBp : kAggSumIdx;
+        ad.src = kind_slot[col];
+        // one accumulator per column: repeated SUMs of a column share it
+        int32_t& slot = enc == CCQ_RLE ? P.rle[ad.src].sum_slot
+                        : enc == CCQ_BITPACKED ? P.bp[ad.src].sum_slot : P.idx[ad.src].sum_slot;
+        if (slot < 0) slot = P.n_sums++;
+        ad.sum_slot = slot;
+    }
+
+    // mode and tiling
+    P.row_mode = P.n_bp > 0 ? 1 : 0;
+    P.any_rle_row = 0;
+    if (P.row_mode) {
+        for (int k = 0; k < P.n_keys; ++k)
+            if (P.keys[k].src_kind == kKeyRle) P.any_rle_row = 1;
+        for (int a = 0; a < P.n_aggs; ++a)
+            if (P.aggs[a].kind == kAggSumRle) P.any_rle_row = 1;
+    }
+    const int64_t window = P.row_end - P.row_begin;
+    if (P.row_mode) {
+        P.span = kRowSpan;
+        P.run_cap = std::max(64 * P.k_rle, 512);
+    } else {
+        // aim for about a quarter of a column's LDS share per tile, so tiles
+        // rarely end early
+        P.run_cap = std::max(64 * P.k_rle, 1024);
+        double dens = 0;
+        for (int s = 0; s < P.k_rle; ++s)
+            dens = std::max(dens, (double)P.rle[s].n_runs / (double)std::max<int64_t>(t->n_rows, 1));
+        const double cap = P.k_rle ? (double)(P.run_cap / P.k_rle) : 0;
+        int64_t span = 1 << 16;
+        if (dens > 0) {
+            double want = cap / 4.0 / dens / 64.0;
+            span = 1;
+            while (span * 2 <= want && span < (1 << 16)) span *= 2;
+        }
+        P.span = (int32_t)span;
+    }
+    P.tile_rows = (int64_t)64 * P.span;
+    P.n_tiles = (window + P.tile_rows - 1) / P.tile_rows;
+
+    // LDS layout: shared part (code tables, group table) then kWaves slices
+    size_t sh = 0;
+    for (int s = 0; s < P.n_bp; ++s) {
+        if (has_lut[s]) {
+            P.bp[s].lut_lds_off = (int32_t)sh;
+            sh = align16(sh + (size_t(1) << P.bp[s].w) * 2);
+        }
+    }
+    const size_t table_bytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
+    P.table_lds = table_bytes <= (size_t)kLdsTableBytes ? 1 : 0;
+    if (P.table_lds) {
+        P.table_lds_off = (int32_t)sh;
+        sh = align16(sh + table_bytes);
+    }
+    P.lds_shared_bytes = (int32_t)sh;
+    // wave slice: a 256-byte header (per-column staged counts, first runs and
+    // next-tile cursors), then the staged runs, then row-mode buffers
+    size_t wv = 256;
+    P.off_run_end = (int32_t)wv;
+    wv = align16(wv + 4 * (size_t)P.run_cap);
+    P.off_run_val = (int32_t)wv;
+    wv = align16(wv + 8 * (size_t)P.run_cap);
+    if (P.row_mode) {
+        P.off_rows = (int32_t)wv;
+        wv = align16(wv + 2 * (size_t)kRowTile);
+        for (int s = 0; s < P.n_bp; ++s) {
+            P.bp[s].stage_off = (int32_t)wv;
+            wv = align16(wv + 4 * (size_t)(64 * P.bp[s].w + 2));
+        }
+        P.off_pts = (int32_t)wv;
+        wv = align16(wv + 4 * 64 * (size_t)P.n_idx);
+        P.off_ptpre = (int32_t)wv;
+        wv = align16(wv + 4 * 64 * (size_t)P.n_idx);
+    }
+    P.lds_wave_bytes = (int32_t)wv;
+    P.lds_dyn_bytes = (int32_t)(sh + kWaves * wv);
+    if ((size_t)P.lds_dyn_bytes > t->ctx->lds_per_block)
+        return fail(CCQ_E_UNSUPPORTED, "query needs %d bytes of LDS per workgroup (limit %zu)", P.lds_dyn_bytes,
+                    t->ctx->lds_per_block);
+
+    return CCQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ccq_status ccq_plan_check(const ccq_table* t, const ccq_query_desc* q, int64_t* max_groups,
+                          size_t* workspace_bytes) {
+    Compiled c;
+    if (ccq_status s = compile_plan(t, q, c)) return s;
+    if (max_groups) *max_groups = c.P.n_keys == 0 ? 1 : c.P.n_groups;
+    if (workspace_bytes) *workspace_bytes = workspace_layout(c.P).total;
+    return ok();
+}
+
+ccq_status ccq_plan_create(const ccq_table* t, const ccq_query_desc* q, ccq_plan** out) {
+    if (!out) return fail(CCQ_E_INVALID, "out is NULL");
+    *out = nullptr;
+    Compiled c;
+    if (ccq_status s = compile_plan(t, q, c)) return s;
+    if (t->ctx->device < 0) return fail(CCQ_E_UNSUPPORTED, "host-only context: plans can be checked, not created");
+    DevPlan& P = c.P;
+    hipError_t e = hipSetDevice(t->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void* dblob = nullptr;
+    e = hipMalloc(&dblob, c.blob.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(plan)");
+    for (const auto& f : c.fixes) {
+        const uint64_t addr = (uint64_t)((unsigned char*)dblob + f.second);
+        memcpy((unsigned char*)&P + f.first, &addr, sizeof addr);
+    }
+    memcpy(c.blob.data(), &P, sizeof P);
+    e = hipMemcpy(dblob, c.blob.data(), c.blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dblob);
+        return hip_fail(e, "hipMemcpy(plan)");
+    }
+    ccq_plan* p = new (std::nothrow) ccq_plan;
+    if (!p) {
+        (void)hipFree(dblob);
+        return fail(CCQ_E_NOMEM, "out of host memory");
+    }
+    p->ctx = t->ctx;
+    p->host = P;
+    p->dev = (DevPlan*)dblob;
+    p->blob = dblob;
+    p->grid_fused = fused_grid_limit(P, t->ctx->device);
+    p->max_groups = P.n_keys == 0 ? 1 : P.n_groups;
+    p->ws = workspace_layout(P);
+    *out = p;
+    return ok();
+}
+
+void ccq_plan_destroy(ccq_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipFree(p->blob);
+    delete p;
+}
+
+ccq_status ccq_plan_info(const ccq_plan* p, int64_t* max_groups, size_t* workspace_bytes) {
+    if (!p) return fail(CCQ_E_INVALID, "plan is NULL");
+    if (max_groups) *max_groups = p->max_groups;
+    if (workspace_bytes) *workspace_bytes = p->ws.total;
+    return ok();
+}
+
+ccq_status ccq_execute(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
+                       const ccq_result* r) {
+    if (!p || !r) return fail(CCQ_E_INVALID, "plan or result is NULL");
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(CCQ_E_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < p->ws.total)
+        return fail(CCQ_E_CAPACITY, "workspace of %zu bytes, plan needs %zu", workspace_bytes, p->ws.total);
+    if (r->capacity < p->max_groups)
+        return fail(CCQ_E_CAPACITY, "result capacity %lld < max groups %lld", (long long)r->capacity,
+                    (long long)p->max_groups);
+    if (!r->counts || !r->n_groups || !r->status || (p->host.n_keys && !r->keys) || (p->host.n_aggs && !r->aggs))
+        return fail(CCQ_E_INVALID, "result buffers missing");
+    hipError_t e = hipSetDevice(p->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = launch_query(p->host, p->dev, workspace, (hipStream_t)stream, r->keys, r->counts, r->aggs, r->n_groups,
+                     r->status, p->grid_fused);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return ok();
+}
+
+}  // extern "C"

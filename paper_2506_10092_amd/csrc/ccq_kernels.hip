@@ -1,0 +1,874 @@
+// Kernels for filter / group-by / aggregate on lightweight-encoded columns.
+//
+// One query runs as a short launch sequence on one stream:
+//   k_prepare   clear the group table and the status word;
+//   k_fused     the hot path (every step below), persistent; each wavefront
+//               is an independent worker;
+//   finalize    compact the non-empty groups in key order into the result
+//               (k_fin_single for ungrouped queries, else count/scan/write).
+//
+// k_fused, per wavefront: the wave owns a contiguous slice of the logical
+// row window and walks it tile by tile (2048 rows when bit-packed columns
+// take part, otherwise 64 * span rows with span chosen from run density).
+// Per tile:
+//   stage   the runs of every RLE column that overlap the tile are loaded
+//           64 at a time (coalesced) into the wave's LDS slice; a column
+//           whose runs overflow its share of the slice ends the tile early,
+//           so every tile fits and there is no slow path;
+//   a1      run predicates are evaluated on run values, once per run and
+//           lane (several predicates on one column are folded into one range
+//           or one set on the host, as the paper's composite-predicate rule
+//           does);
+//   a2      each lane owns a span of rows and merges the run ends of all RLE
+//           columns inside it: a boundary of any column starts a new aligned
+//           run (Section 6 alignment; Algorithm 1 restricted to the runs that
+//           survive the predicates, extended to k columns);
+//   a3      run mode: surviving aligned runs are consumed in place;
+//           row mode: surviving rows are compacted with a wavefront scan into
+//           an LDS row list;
+//   a4      row mode: only the bit-packed words under surviving rows are
+//           staged in LDS; each listed row unpacks its code and looks it up in
+//           an LDS code table that folds the column's predicates and its
+//           group-key slot (the RLE x Plain AND of Section 5.1 done per tile);
+//   a5      Index points: in row mode a point bitmap says which listed rows
+//           carry a point (Plain x Index); in run mode each point finds its
+//           runs by binary search over the staged run ends (idx_in_rle,
+//           Algorithm 3);
+//   a6      group id = mixed radix over key slots, first key most
+//           significant, so id order is ascending key order;
+//   a7      COUNT += run length and SUM += value * run length per aligned run
+//           (Section 7, Aggregating Phase), or +1 / +value per row; runs of
+//           one group that follow each other in a lane are added in registers
+//           first; small tables live in LDS per workgroup and are added to the
+//           global table once at the end.
+#include <algorithm>
+
+#include "ccq_plan.h"
+
+namespace ccq {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int64_t ld_val(const void* p, int32_t vtype, int64_t i) {
+    return vtype == 1 ? (int64_t)(((const int32_t*)p)[i]) : ((const int64_t*)p)[i];
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m in the lanes below this one
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ int wave_exclusive_sum(int v, int* total) {
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane_id() >= d) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Cross-lane LDS hand-off inside one wavefront: a wave's LDS operations
+// execute in order, so only compiler reordering has to be prevented.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ bool set_contains(const int64_t* s, int32_t n, int64_t v) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (s[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo < n && s[lo] == v;
+}
+
+__device__ __forceinline__ bool pred_pass(int32_t kind, int64_t lo, int64_t hi, const int64_t* set, int32_t n,
+                                          int64_t v) {
+    if (kind == kPredNone) return true;
+    if (kind == kPredRange) return lo <= v && v < hi;
+    if (kind == kPredSet) return set_contains(set, n, v);
+    return false;
+}
+
+__device__ __forceinline__ void raise_status(int32_t* status, int32_t code) { atomicCAS(status, 0, code); }
+
+// First index i in [0, n) with a[i] > x (n if none); the whole wave takes
+// part and every lane gets the answer.  Each round probes 64 evenly spaced
+// elements and keeps the stretch between the last probe <= x and the first
+// probe > x.
+__device__ int64_t wave_upper_bound(const int64_t* a, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    const int lane = lane_id();
+    while (hi - lo > 64) {
+        const int64_t len = hi - lo;
+        const int64_t p = lo + ((int64_t)(lane + 1) * len) / 64 - 1;
+        const uint64_t m = wave_ballot(a[p] > x);
+        if (m == 0) return hi;
+        const int f = __builtin_ctzll(m);
+        const int64_t nhi = lo + ((int64_t)(f + 1) * len) / 64 - 1;
+        const int64_t nlo = f == 0 ? lo : lo + ((int64_t)f * len) / 64;
+        lo = nlo;
+        hi = nhi;
+    }
+    const int64_t i = lo + lane;
+    const uint64_t m = wave_ballot(i < hi && a[i] > x);
+    return m ? lo + __builtin_ctzll(m) : hi;
+}
+
+// First index i in [0, n) with pos[i] >= x (n if none).
+__device__ int64_t wave_lower_bound_pos(const void* pos, int32_t ptype, int64_t n, int64_t x) {
+    int64_t lo = 0, hi = n;
+    const int lane = lane_id();
+    while (hi - lo > 64) {
+        const int64_t len = hi - lo;
+        const int64_t p = lo + ((int64_t)(lane + 1) * len) / 64 - 1;
+        const uint64_t m = wave_ballot(ld_val(pos, ptype, p) >= x);
+        if (m == 0) return hi;
+        const int f = __builtin_ctzll(m);
+        const int64_t nhi = lo + ((int64_t)(f + 1) * len) / 64 - 1;
+        const int64_t nlo = f == 0 ? lo : lo + ((int64_t)f * len) / 64;
+        lo = nlo;
+        hi = nhi;
+    }
+    const int64_t i = lo + lane;
+    const uint64_t m = wave_ballot(i < hi && ld_val(pos, ptype, i) >= x);
+    return m ? lo + __builtin_ctzll(m) : hi;
+}
+
+// first index j in [0, n) with e[j] > x in an LDS array (n if none)
+__device__ __forceinline__ int lds_upper_bound(const int32_t* e, int n, int32_t x) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (e[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ group table
+
+struct Table {
+    int64_t* g;                 // global: counts[G], then one [G] array per SUM
+    unsigned long long* l;      // per-workgroup LDS copy (same layout) or nullptr
+    int64_t G;
+};
+
+__device__ __forceinline__ void table_add(const Table& t, int which, int64_t gid, int64_t v) {
+    if (t.l) atomicAdd(&t.l[which * t.G + gid], (unsigned long long)v);
+    else atomicAdd((unsigned long long*)&t.g[which * t.G + gid], (unsigned long long)v);
+}
+
+// ------------------------------------------------------------------ prepare
+
+__global__ void k_prepare(int64_t* table, int64_t table_len, int32_t* header) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < table_len; i += nt) table[i] = 0;
+    if (tid == 0) {
+        header[0] = 0;
+        header[1] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ fused kernel
+
+struct WaveLds {
+    unsigned char* base;
+    int32_t* tn;        // [kMaxRle] staged runs of each column in the current tile
+    int64_t* tlo;       // [kMaxRle] run index of each column's first staged run
+    int64_t* cur;       // [kMaxRle] run index holding the next tile's first row
+    int32_t* run_end;   // [run_cap] run end - tile start, capped at 2^30
+    int64_t* run_val;   // [run_cap]
+    uint16_t* rows;     // row mode: surviving rows of the tile, compacted
+    uint32_t* pts;      // row mode: 64-word point bitmap per Index column
+    int32_t* ptpre;     // row mode: exclusive popcount prefix per bitmap word
+    int32_t cap;        // staged runs per column; column c starts at slot c * cap
+};
+
+// Stage the runs of every RLE column that overlap [t0, *t1) into LDS.  A
+// column that would exceed its share shrinks *t1 to the end of its last
+// staged run, so all columns cover the (possibly shorter) tile.
+__device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t* t1) {
+    const int lane = lane_id();
+    for (int c = 0; c < P.k_rle; ++c) {
+        const RleCol& rc = P.rle[c];
+        const int64_t lo = W.cur[c];
+        const int32_t off = c * W.cap;
+        int32_t n = 0;
+        for (;;) {
+            const int64_t i = lo + n + lane;
+            const bool valid = i < rc.n_runs && n + lane < W.cap;
+            const int64_t e = valid ? rc.ends[i] : INT64_MAX;
+            const uint64_t last = wave_ballot(valid && e >= *t1);
+            const uint64_t vmask = wave_ballot(valid);
+            const int cnt = last ? __builtin_ctzll(last) + 1 : __builtin_popcountll(vmask);
+            if (lane < cnt) {
+                const int64_t rel = e - t0;
+                W.run_end[off + n + lane] = (int32_t)(rel < (1 << 30) ? rel : (1 << 30));
+                W.run_val[off + n + lane] = ld_val(rc.vals, rc.vtype, i);
+            }
+            n += cnt;
+            if (last) break;
+            if (n >= W.cap) {
+                const int64_t e_last = __shfl(e, cnt - 1, 64);
+                if (e_last < *t1) *t1 = e_last;
+                break;
+            }
+        }
+        if (lane == 0) {
+            W.tn[c] = n;
+            W.tlo[c] = lo;
+        }
+    }
+    wave_lds_sync();
+}
+
+// A lane's merge over its rows: one cursor per RLE column into the staged
+// runs; the aligned run ends at the nearest cursor end.  Cursors only move
+// at boundaries strictly inside the lane's span, and the staged runs of every
+// column cover the whole tile, so a cursor never runs past its column.
+struct Walk {
+    int32_t j[kMaxRle];
+    int32_t end[kMaxRle];
+    int64_t val[kMaxRle];
+    bool pass[kMaxRle];
+};
+
+__device__ __forceinline__ void walk_load(const DevPlan& P, const WaveLds& W, Walk& w, int c) {
+    const int32_t idx = c * W.cap + w.j[c];
+    w.end[c] = W.run_end[idx];
+    w.val[c] = W.run_val[idx];
+    const RleCol& rc = P.rle[c];
+    w.pass[c] = pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, w.val[c]);
+}
+
+__device__ __forceinline__ void walk_init(const DevPlan& P, const WaveLds& W, Walk& w, int32_t s0) {
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c) {
+        if (c < P.k_rle) {
+            w.j[c] = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], s0);
+            walk_load(P, W, w, c);
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t walk_next(const DevPlan& P, const Walk& w, int32_t s1) {
+    int32_t e = s1;
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c)
+        if (c < P.k_rle) e = min(e, w.end[c]);
+    return e;
+}
+
+__device__ __forceinline__ bool walk_pass(const DevPlan& P, const Walk& w) {
+    bool p = true;
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c)
+        if (c < P.k_rle) p = p && w.pass[c];
+    return p;
+}
+
+__device__ __forceinline__ void walk_advance(const DevPlan& P, const WaveLds& W, Walk& w, int32_t e) {
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c) {
+        if (c < P.k_rle && w.end[c] == e) {
+            w.j[c] += 1;
+            walk_load(P, W, w, c);
+        }
+    }
+}
+
+// Group id part from the RLE keys; false (status raised) if a key is out of
+// its domain.
+__device__ __forceinline__ bool rle_key_part(const DevPlan& P, const int64_t (&vals)[kMaxRle], int64_t* gid,
+                                             int32_t* status) {
+    int64_t g = 0;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c) {
+        if (c < P.k_rle && P.rle[c].key_on) {
+            const int64_t kv = vals[c] >> P.rle[c].key_shift;
+            if (kv < 0 || kv >= P.rle[c].key_card) ok = false;
+            g += kv * P.rle[c].key_stride;
+        }
+    }
+    if (!ok) raise_status(status, -4);
+    *gid = g;
+    return ok;
+}
+
+// consecutive aligned runs of one group, added in registers
+struct RegAcc {
+    int64_t gid;
+    int64_t cnt;
+    int64_t rsum[kMaxRle];   // SUM of each RLE column
+};
+
+__device__ __forceinline__ void regacc_flush(const DevPlan& P, const Table& tb, RegAcc& a) {
+    if (a.gid >= 0 && a.cnt > 0) {
+        table_add(tb, 0, a.gid, a.cnt);
+#pragma unroll
+        for (int c = 0; c < kMaxRle; ++c)
+            if (c < P.k_rle && P.rle[c].sum_slot >= 0 && a.rsum[c] != 0)
+                table_add(tb, 1 + P.rle[c].sum_slot, a.gid, a.rsum[c]);
+    }
+    a.gid = -1;
+    a.cnt = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c) a.rsum[c] = 0;
+}
+
+// Index points of a run-mode tile: each point looks up the runs holding its
+// row in the staged run ends (idx_in_rle) and adds its value.
+__device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L, const Table& tb, int32_t* status,
+                                                int64_t (&pcur)[kMaxIdx]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < kMaxIdx; ++j) {
+        if (j >= P.n_idx) continue;
+        const IdxCol& ic = P.idx[j];
+        int64_t p0 = pcur[j];
+        for (;;) {
+            const int64_t i = p0 + lane;
+            const bool valid = i < ic.n;
+            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
+            const bool in = valid && pos < t0 + L;
+            const uint64_t m = wave_ballot(in);
+            if (in) {
+                const int32_t rel = (int32_t)(pos - t0);
+                bool pass = true;
+                int64_t vals[kMaxRle];
+#pragma unroll
+                for (int c = 0; c < kMaxRle; ++c) {
+                    vals[c] = 0;
+                    if (c < P.k_rle) {
+                        const int32_t jj = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], rel);
+                        vals[c] = W.run_val[c * W.cap + jj];
+                        const RleCol& rc = P.rle[c];
+                        pass = pass && pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, vals[c]);
+                    }
+                }
+                int64_t gid;
+                if (pass && rle_key_part(P, vals, &gid, status) && ic.sum_slot >= 0) {
+                    const int64_t v = ld_val(ic.vals, ic.vtype, i);
+                    if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
+                }
+            }
+            const int c = __builtin_popcountll(m);
+            p0 += c;
+            if (c < 64) break;
+        }
+        pcur[j] = p0;
+    }
+}
+
+// Run mode tile: no bit-packed column; aggregate per aligned run.
+__device__ __forceinline__ void tile_run_mode(const DevPlan& P, const WaveLds& W, int64_t t0,
+                                              int32_t L, const Table& tb, int32_t* status, RegAcc& acc,
+                                              int64_t (&pcur)[kMaxIdx]) {
+    const int32_t s0 = lane_id() * P.span;
+    const int32_t s1 = min(s0 + P.span, L);
+    if (s0 < s1) {
+        Walk w;
+        walk_init(P, W, w, s0);
+        int32_t x = s0;
+        while (x < s1) {
+            const int32_t e = walk_next(P, w, s1);
+            if (walk_pass(P, w)) {
+                int64_t gid;
+                if (rle_key_part(P, w.val, &gid, status)) {
+                    if (gid != acc.gid) {
+                        regacc_flush(P, tb, acc);
+                        acc.gid = gid;
+                    }
+                    const int64_t len = e - x;
+                    acc.cnt += len;
+#pragma unroll
+                    for (int c = 0; c < kMaxRle; ++c)
+                        if (c < P.k_rle && P.rle[c].sum_slot >= 0) acc.rsum[c] += w.val[c] * len;
+                }
+            }
+            if (e < s1) walk_advance(P, W, w, e);
+            x = e;
+        }
+    }
+    if (P.n_idx > 0) run_mode_points(P, W, t0, L, tb, status, pcur);
+}
+
+// Row mode tile (at most 2048 rows, 32 per lane).
+__device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W, int64_t t0,
+                                              int32_t L, const Table& tb, int32_t* status,
+                                              int64_t (&pcur)[kMaxIdx], const uint16_t* const (&luts)[kMaxBp]) {
+    const int lane = lane_id();
+    const int32_t s0 = lane * kRowSpan;
+    const int32_t s1 = min(s0 + kRowSpan, L);
+
+    // a1 + a2: the lane's rows that survive every RLE predicate
+    uint32_t pm = 0;
+    if (s0 < s1) {
+        Walk w;
+        walk_init(P, W, w, s0);
+        int32_t x = s0;
+        while (x < s1) {
+            const int32_t e = walk_next(P, w, s1);
+            if (walk_pass(P, w)) {
+                const uint32_t a = (uint32_t)(x - s0), b = (uint32_t)(e - s0);   // bits [a, b)
+                const uint32_t below_b = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+                pm |= below_b & ~((1u << a) - 1u);
+            }
+            if (e < s1) walk_advance(P, W, w, e);
+            x = e;
+        }
+    }
+
+    // a5: bitmap of the rows that carry an Index point, with prefix counts
+    int64_t pbase[kMaxIdx];
+#pragma unroll
+    for (int j = 0; j < kMaxIdx; ++j) {
+        pbase[j] = 0;
+        if (j >= P.n_idx) continue;
+        const IdxCol& ic = P.idx[j];
+        uint32_t* bm = W.pts + j * 64;
+        bm[lane] = 0;
+        wave_lds_sync();
+        int64_t p0 = pcur[j];
+        pbase[j] = p0;
+        for (;;) {
+            const int64_t i = p0 + lane;
+            const bool valid = i < ic.n;
+            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
+            const bool in = valid && pos < t0 + L;
+            const uint64_t m = wave_ballot(in);
+            if (in) {
+                const int32_t rel = (int32_t)(pos - t0);
+                atomicOr(&bm[rel >> 5], 1u << (rel & 31));
+            }
+            const int c = __builtin_popcountll(m);
+            p0 += c;
+            if (c < 64) break;
+        }
+        pcur[j] = p0;
+        wave_lds_sync();
+        int tot;
+        const int ex = wave_exclusive_sum(__builtin_popcount(bm[lane]), &tot);
+        W.ptpre[j * 64 + lane] = ex;
+        wave_lds_sync();
+    }
+
+    // a3: compact the surviving rows into the wave's row list
+    int total;
+    const int base = wave_exclusive_sum(__builtin_popcount(pm), &total);
+    {
+        uint32_t m = pm;
+        int q = base;
+        while (m) {
+            const int b = __builtin_ctz(m);
+            m &= m - 1;
+            W.rows[q++] = (uint16_t)(s0 + b);
+        }
+    }
+    if (total == 0) {
+        wave_lds_sync();
+        return;
+    }
+
+    // a4: stage only the packed words read by lanes that have surviving rows
+    const uint64_t need_lanes = wave_ballot(pm != 0);
+#pragma unroll
+    for (int j = 0; j < kMaxBp; ++j) {
+        if (j >= P.n_bp) continue;
+        const BpCol& bc = P.bp[j];
+        const int64_t wbase = (t0 * (int64_t)bc.w) >> 5;
+        const int32_t nwords = (int32_t)((((t0 + L) * (int64_t)bc.w - 1) >> 5) + 2 - wbase);
+        const uint32_t magic = ((1u << 20) + (uint32_t)bc.w - 1u) / (uint32_t)bc.w;   // ceil(2^20 / w)
+        uint32_t* st = (uint32_t*)(W.base + bc.stage_off);
+        for (int q = lane; q < nwords; q += 64) {
+            // word q is read by lane floor(q / w) and at most two lanes before it
+            const int f = (int)(((uint32_t)q * magic) >> 20);
+            const int l0 = f >= 2 ? f - 2 : 0;
+            const int l1 = f < 63 ? f : 63;
+            const uint64_t lanes = l1 >= l0 ? (((2ull << (l1 - l0)) - 1ull) << l0) : 0ull;
+            if (need_lanes & lanes) st[q] = bc.packed[wbase + q];
+        }
+    }
+    wave_lds_sync();
+
+    // per surviving row: unpack, bit-packed predicates, group id, aggregates
+    for (int i = lane; i < total; i += 64) {
+        const int32_t r = W.rows[i];
+        bool pass = true;
+        bool dom = false;
+        int64_t gid = 0;
+        int64_t bpv[kMaxBp];
+#pragma unroll
+        for (int j = 0; j < kMaxBp; ++j) {
+            bpv[j] = 0;
+            if (j >= P.n_bp) continue;
+            const BpCol& bc = P.bp[j];
+            const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
+            const int64_t bit = ((t0 * (int64_t)bc.w) & 31) + (int64_t)r * bc.w;
+            const int32_t q = (int32_t)(bit >> 5);
+            const uint32_t sh = (uint32_t)(bit & 31);
+            const uint64_t two = (uint64_t)st[q] | ((uint64_t)st[q + 1] << 32);
+            const uint64_t mask = bc.w == 32 ? 0xFFFFFFFFull : ((1ull << bc.w) - 1ull);
+            const uint32_t code = (uint32_t)((two >> sh) & mask);
+            bpv[j] = bc.base + (int64_t)code;
+            if (luts[j]) {
+                const uint16_t e = luts[j][code];
+                if (e == kLutReject) pass = false;
+                else if (e == kLutDomain) dom = true;
+                else if (bc.key >= 0) gid += (int64_t)e * bc.key_stride;
+            } else {
+                pass = pass && pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, bpv[j]);
+                if (bc.key >= 0) {
+                    const int64_t kv = bpv[j] >> bc.key_shift;
+                    if (kv < 0 || kv >= bc.key_card) dom = true;
+                    else gid += kv * bc.key_stride;
+                }
+            }
+        }
+        if (!pass) continue;
+        int64_t rv[kMaxRle];
+#pragma unroll
+        for (int c = 0; c < kMaxRle; ++c) {
+            rv[c] = 0;
+            if (P.any_rle_row && c < P.k_rle) {
+                const int32_t jj = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], r);
+                rv[c] = W.run_val[c * W.cap + jj];
+            }
+        }
+        if (P.any_rle_row) {
+            int64_t g2;
+            if (!rle_key_part(P, rv, &g2, status)) continue;
+            gid += g2;
+        }
+        if (dom) {
+            raise_status(status, -4);
+            continue;
+        }
+        table_add(tb, 0, gid, 1);
+#pragma unroll
+        for (int c = 0; c < kMaxRle; ++c)
+            if (c < P.k_rle && P.rle[c].sum_slot >= 0) table_add(tb, 1 + P.rle[c].sum_slot, gid, rv[c]);
+#pragma unroll
+        for (int j = 0; j < kMaxBp; ++j)
+            if (j < P.n_bp && P.bp[j].sum_slot >= 0) table_add(tb, 1 + P.bp[j].sum_slot, gid, bpv[j]);
+#pragma unroll
+        for (int j = 0; j < kMaxIdx; ++j) {
+            if (j < P.n_idx && P.idx[j].sum_slot >= 0) {
+                const uint32_t word = W.pts[j * 64 + (r >> 5)];
+                if (word & (1u << (r & 31))) {
+                    const int64_t rank = W.ptpre[j * 64 + (r >> 5)] + __builtin_popcount(word & ((1u << (r & 31)) - 1u));
+                    const int64_t v = ld_val(P.idx[j].vals, P.idx[j].vtype, pbase[j] + rank);
+                    if (v != 0) table_add(tb, 1 + P.idx[j].sum_slot, gid, v);
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
+__global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
+                                                     int32_t* __restrict__ status, int64_t n_waves_total) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const DevPlan& P = *Pg;
+
+    // shared part of dynamic LDS: the code tables, then the group table
+    const uint16_t* luts[kMaxBp];
+#pragma unroll
+    for (int j = 0; j < kMaxBp; ++j) {
+        luts[j] = nullptr;
+        if (j < P.n_bp && P.bp[j].lut) {
+            uint16_t* dst = (uint16_t*)(lds + P.bp[j].lut_lds_off);
+            const uint16_t* src = P.bp[j].lut;
+            const int n = 1 << P.bp[j].w;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+            luts[j] = dst;
+        }
+    }
+    Table tb;
+    tb.g = table;
+    tb.G = P.n_groups;
+    tb.l = nullptr;
+    if (P.table_lds) {
+        tb.l = (unsigned long long*)(lds + P.table_lds_off);
+        const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) tb.l[i] = 0;
+    }
+    __syncthreads();
+
+    // this wave's slice of the window, a whole number of nominal tiles
+    const int wave = threadIdx.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
+    const int64_t w0 = P.row_begin + gw * tiles_per_wave * P.tile_rows;
+    const int64_t w1 = min(P.row_end, w0 + tiles_per_wave * P.tile_rows);
+
+    WaveLds W;
+    W.base = lds + P.lds_shared_bytes + wave * P.lds_wave_bytes;
+    W.tn = (int32_t*)(W.base);            // slice header, 256 bytes (host layout reserves it)
+    W.tlo = (int64_t*)(W.base + 64);
+    W.cur = (int64_t*)(W.base + 128);
+    W.cap = P.k_rle > 0 ? P.run_cap / P.k_rle : 0;
+    W.run_end = (int32_t*)(W.base + P.off_run_end);
+    W.run_val = (int64_t*)(W.base + P.off_run_val);
+    W.rows = (uint16_t*)(W.base + P.off_rows);
+    W.pts = (uint32_t*)(W.base + P.off_pts);
+    W.ptpre = (int32_t*)(W.base + P.off_ptpre);
+
+    RegAcc acc;
+    acc.gid = -1;
+    acc.cnt = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxRle; ++c) acc.rsum[c] = 0;
+
+    if (w0 < w1) {
+        int64_t pcur[kMaxIdx];
+        for (int c = 0; c < P.k_rle; ++c) {
+            const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0);
+            if (lane_id() == 0) W.cur[c] = x;
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxIdx; ++j)
+            pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
+        wave_lds_sync();
+        int64_t t0 = w0;
+        while (t0 < w1) {
+            int64_t t1 = min(t0 + P.tile_rows, w1);
+            stage_runs(P, W, t0, &t1);
+            const int32_t L = (int32_t)(t1 - t0);
+            if (P.row_mode) tile_row_mode(P, W, t0, L, tb, status, pcur, luts);
+            else tile_run_mode(P, W, t0, L, tb, status, acc, pcur);
+            // next tile's first run per column: the first staged run ending after t1
+            for (int c = 0; c < P.k_rle; ++c) {
+                const int64_t x = W.tlo[c] + lds_upper_bound(W.run_end + c * W.cap, W.tn[c], L);
+                if (lane_id() == 0) W.cur[c] = x;
+            }
+            wave_lds_sync();
+            t0 = t1;
+        }
+    }
+    regacc_flush(P, tb, acc);
+
+    if (P.table_lds) {
+        __syncthreads();
+        const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const unsigned long long v = tb.l[i];
+            if (v) atomicAdd((unsigned long long*)&table[i], v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ finalize
+
+// Group id g -> key values (last key varies fastest), count and aggregates.
+__device__ void write_group(const DevPlan& P, int64_t g, int64_t row, const int64_t* table, int64_t G,
+                            int64_t* keys, int64_t* counts, int64_t* aggs) {
+    int64_t rem = g;
+    for (int k = P.n_keys - 1; k >= 0; --k) {
+        const KeyDesc& kd = P.keys[k];
+        const int64_t slot = rem % kd.radix;
+        rem /= kd.radix;
+        keys[row * P.n_keys + k] = kd.via_lut ? kd.slot_keys[slot] : slot;
+    }
+    const int64_t cnt = table[g];
+    counts[row] = cnt;
+    for (int a = 0; a < P.n_aggs; ++a) {
+        const AggDesc& ad = P.aggs[a];
+        aggs[row * P.n_aggs + a] = ad.kind == kAggCount ? cnt : table[(int64_t)(1 + ad.sum_slot) * G + g];
+    }
+}
+
+constexpr int64_t kFinPer = (int64_t)kThreads * 16;   // group ids per finalize block
+
+// phase 1: non-empty groups per block of ids
+__global__ __launch_bounds__(kThreads) void k_fin_count(const int64_t* table, int64_t G, int64_t* block_cnt) {
+    __shared__ int s_part[kWaves];
+    const int64_t b0 = (int64_t)blockIdx.x * kFinPer;
+    const int64_t b1 = min(b0 + kFinPer, G);
+    int c = 0;
+    for (int64_t g = b0 + threadIdx.x; g < b1; g += kThreads) c += table[g] > 0;
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if (lane_id() == 0) s_part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kWaves; ++w) t += s_part[w];
+        block_cnt[blockIdx.x] = t;
+    }
+}
+
+// phase 2 (one workgroup): exclusive scan of the block counts; total -> n_groups
+__global__ __launch_bounds__(kThreads) void k_fin_scan(int64_t* block_cnt, int64_t nb, int64_t* n_groups,
+                                                        const int32_t* status_ws, int32_t* status_out) {
+    __shared__ int64_t s_tot[kThreads];
+    const int64_t per = (nb + kThreads - 1) / kThreads;
+    const int64_t a = (int64_t)threadIdx.x * per, b = min(a + per, nb);
+    int64_t s = 0;
+    for (int64_t i = a; i < b; ++i) s += block_cnt[i];
+    s_tot[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int i = 0; i < kThreads; ++i) {
+            const int64_t v = s_tot[i];
+            s_tot[i] = run;
+            run += v;
+        }
+        *n_groups = run;
+        *status_out = *status_ws;
+    }
+    __syncthreads();
+    int64_t run = s_tot[threadIdx.x];
+    for (int64_t i = a; i < b; ++i) {
+        const int64_t v = block_cnt[i];
+        block_cnt[i] = run;
+        run += v;
+    }
+}
+
+// phase 3: write each block's non-empty groups in id order
+__global__ __launch_bounds__(kThreads) void k_fin_write(const DevPlan* __restrict__ Pg, const int64_t* table,
+                                                         const int64_t* block_off, int64_t* keys, int64_t* counts,
+                                                         int64_t* aggs) {
+    __shared__ int s_wave[kWaves];
+    const DevPlan& P = *Pg;
+    const int64_t G = P.n_groups;
+    const int64_t b0 = (int64_t)blockIdx.x * kFinPer;
+    const int64_t b1 = min(b0 + kFinPer, G);
+    int64_t row = block_off[blockIdx.x];
+    const int wave = threadIdx.x >> 6;
+    for (int64_t base = b0; base < b1; base += kThreads) {
+        const int64_t g = base + threadIdx.x;
+        const bool ne = g < b1 && table[g] > 0;
+        const uint64_t m = wave_ballot(ne);
+        if (lane_id() == 0) s_wave[wave] = __builtin_popcountll(m);
+        __syncthreads();
+        int before = 0, all = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) before += s_wave[w];
+            all += s_wave[w];
+        }
+        if (ne) write_group(P, g, row + before + lanes_below(m), table, G, keys, counts, aggs);
+        row += all;
+        __syncthreads();
+    }
+}
+
+// ungrouped query: exactly one row, also when nothing qualifies
+__global__ void k_fin_single(const DevPlan* __restrict__ Pg, const int64_t* table, int64_t* keys, int64_t* counts,
+                             int64_t* aggs, int64_t* n_groups, const int32_t* status_ws, int32_t* status_out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        write_group(*Pg, 0, 0, table, 1, keys, counts, aggs);
+        *n_groups = 1;
+        *status_out = *status_ws;
+    }
+}
+
+// ------------------------------------------------------------------ validation
+
+__global__ void k_validate_rle(const int64_t* ends, int64_t n, int64_t n_rows, int32_t* flag) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < n; i += nt) {
+        const int64_t prev = i == 0 ? 0 : ends[i - 1];
+        const int64_t e = ends[i];
+        if (e <= prev || (i == n - 1 && e != n_rows)) atomicOr(flag, 1);
+    }
+}
+
+__global__ void k_validate_idx(const void* pos, int32_t ptype, int64_t n, int64_t n_rows, int32_t* flag) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < n; i += nt) {
+        const int64_t p = ld_val(pos, ptype, i);
+        const int64_t prev = i == 0 ? -1 : ld_val(pos, ptype, i - 1);
+        if (p <= prev || p >= n_rows) atomicOr(flag, 1);
+    }
+}
+
+// ------------------------------------------------------------------ host launchers
+
+static int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+WsLayout workspace_layout(const DevPlan& p) {
+    WsLayout L;
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t off = 256;
+    L.table_off = off;
+    off = align(off + sizeof(int64_t) * (size_t)(1 + p.n_sums) * (size_t)p.n_groups);
+    L.scan_off = off;
+    L.scan_blocks = div_up(p.n_groups, kFinPer);
+    off = align(off + sizeof(int64_t) * (size_t)(L.scan_blocks + 1));
+    L.total = off;
+    return L;
+}
+
+int fused_grid_limit(const DevPlan& p, int device) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fused, kThreads, p.lds_dyn_bytes) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    return per_cu * cus;
+}
+
+hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
+                        int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
+                        int grid_fused) {
+    const WsLayout L = workspace_layout(p);
+    unsigned char* base = (unsigned char*)ws;
+    int32_t* header = (int32_t*)base;
+    int64_t* table = (int64_t*)(base + L.table_off);
+    int64_t* scan = (int64_t*)(base + L.scan_off);
+    const int64_t table_len = (int64_t)(1 + p.n_sums) * p.n_groups;
+
+    const int prep_grid = (int)std::min<int64_t>(std::max<int64_t>(div_up(table_len, kThreads), 1), 4096);
+    hipLaunchKernelGGL(k_prepare, dim3(prep_grid), dim3(kThreads), 0, stream, table, table_len, header);
+
+    if (p.n_tiles > 0) {
+        int64_t blocks = std::min<int64_t>(div_up(p.n_tiles, kWaves), grid_fused);
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_fused, dim3((unsigned)blocks), dim3(kThreads), p.lds_dyn_bytes, stream, dp, table,
+                           header, blocks * kWaves);
+    }
+
+    if (p.n_keys == 0) {
+        hipLaunchKernelGGL(k_fin_single, dim3(1), dim3(64), 0, stream, dp, table, out_keys, out_counts, out_aggs,
+                           out_n_groups, header, out_status);
+    } else {
+        hipLaunchKernelGGL(k_fin_count, dim3((unsigned)L.scan_blocks), dim3(kThreads), 0, stream, table,
+                           p.n_groups, scan);
+        hipLaunchKernelGGL(k_fin_scan, dim3(1), dim3(kThreads), 0, stream, scan, L.scan_blocks, out_n_groups,
+                           header, out_status);
+        hipLaunchKernelGGL(k_fin_write, dim3((unsigned)L.scan_blocks), dim3(kThreads), 0, stream, dp, table, scan,
+                           out_keys, out_counts, out_aggs);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_rle(const int64_t* ends, int64_t n, int64_t n_rows, int32_t* flag, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(div_up(n, kThreads), 1), 8192);
+    hipLaunchKernelGGL(k_validate_rle, dim3(grid), dim3(kThreads), 0, s, ends, n, n_rows, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_idx(const void* pos, int32_t ptype, int64_t n, int64_t n_rows, int32_t* flag,
+                               hipStream_t s) {
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(div_up(n, kThreads), 1), 8192);
+    hipLaunchKernelGGL(k_validate_idx, dim3(grid), dim3(kThreads), 0, s, pos, ptype, n, n_rows, flag);
+    return hipGetLastError();
+}
+
+}  // namespace ccq

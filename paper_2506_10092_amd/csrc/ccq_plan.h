@@ -1,0 +1,140 @@
+// Compiled query plan: the device-side descriptor the kernels read, plus the
+// launch entry points implemented in ccq_kernels.hip.  Internal to libccq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccq {
+
+constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
+constexpr int kWaves = kThreads / 64;
+constexpr int kRowSpan = 32;           // rows per lane in row mode (one bitmap word)
+constexpr int kRowTile = 64 * kRowSpan;   // 2048 rows per wavefront tile in row mode
+constexpr int kMaxRle = 8;
+constexpr int kMaxBp = 4;
+constexpr int kMaxIdx = 2;
+constexpr int kMaxKeys = 8;
+constexpr int kMaxAggs = 8;
+constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
+constexpr int64_t kMaxGroups = int64_t(1) << 27;
+constexpr int kLdsTableBytes = 16384;  // group tables up to this size live in LDS
+
+enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3 };
+enum AggKind : int32_t { kAggCount = 0, kAggSumRle = 1, kAggSumBp = 2, kAggSumIdx = 3 };
+enum KeySrc : int32_t { kKeyRle = 0, kKeyBp = 1 };
+
+// code table entries (uint16 per code of a bit-packed column)
+constexpr uint16_t kLutReject = 0xFFFF;    // code fails the column's predicates
+constexpr uint16_t kLutDomain = 0xFFFE;    // code passes but its key is outside [0, card)
+
+struct RleCol {
+    const int64_t* ends;
+    const void* vals;
+    int64_t n_runs;
+    int32_t vtype;          // 1 int32, 2 int64
+    int32_t pred;           // PredKind
+    int64_t lo, hi;         // kPredRange
+    const int64_t* set;     // kPredSet: sorted, unique (device)
+    int32_t set_len;
+    int32_t sum_slot;       // SUM accumulator of this column, or -1
+    int32_t key_on;         // 1 if this column is a group key
+    int32_t key_shift;
+    int64_t key_card;
+    int64_t key_stride;
+};
+
+struct BpCol {
+    const uint32_t* packed;
+    int64_t base;
+    int32_t w;
+    int32_t pred;           // PredKind (used when lut == nullptr)
+    int64_t lo, hi;
+    const int64_t* set;
+    int32_t set_len;
+    int32_t key;            // key index or -1
+    const uint16_t* lut;    // device code table (2^w entries) or nullptr
+    int32_t lut_lds_off;    // byte offset of the code table in dynamic LDS
+    int32_t stage_off;      // byte offset of this column's staged words in a wave slice
+    int32_t sum_slot;       // SUM accumulator of this column, or -1
+    int32_t key_shift;      // key = value >> key_shift when key >= 0 and no code table
+    int64_t key_card;
+    int64_t key_stride;
+};
+
+struct IdxCol {
+    const void* pos;
+    const void* vals;
+    int64_t n;
+    int32_t ptype, vtype;
+    int32_t sum_slot;       // SUM accumulator of this column, or -1
+    int32_t pad_;
+};
+
+struct KeyDesc {
+    int32_t src_kind;       // KeySrc
+    int32_t src;            // column slot within its kind
+    int32_t shift;
+    int32_t via_lut;        // slot comes from the bit-packed code table
+    int64_t card;
+    int64_t radix;          // slots of this key
+    int64_t stride;         // mixed-radix weight
+    const int64_t* slot_keys;   // via_lut: slot -> key value (device), else nullptr
+};
+
+struct AggDesc {
+    int32_t kind;           // AggKind
+    int32_t src;            // column slot within its kind
+    int32_t sum_slot;       // index among SUM accumulators (-1 for COUNT)
+    int32_t pad_;
+};
+
+struct DevPlan {
+    int64_t row_begin, row_end;
+    int64_t tile_rows;      // rows per wavefront tile (64 * span)
+    int64_t n_tiles;        // nominal tiles of the window (tiles may end early)
+    int32_t span;           // rows per lane
+    int32_t row_mode;       // 1 when a bit-packed column is referenced
+    int32_t k_rle, n_bp, n_idx, n_keys, n_aggs, n_sums;
+    int32_t table_lds;      // 1: per-workgroup LDS table, added to the global one at the end
+    int32_t any_rle_row;    // row mode: some key or SUM reads an RLE value per row
+    int64_t n_groups;       // product of key radices (1 when ungrouped)
+    int32_t run_cap;        // staged runs per wave slice, all RLE columns together
+    int32_t lds_dyn_bytes;  // dynamic LDS per workgroup
+    int32_t lds_shared_bytes;   // code tables + group table, before the wave slices
+    int32_t lds_wave_bytes;     // one wave slice
+    int32_t table_lds_off;  // byte offset of the LDS group table
+    int32_t off_run_end, off_run_val, off_rows, off_pts, off_ptpre;   // inside a wave slice
+    RleCol rle[kMaxRle];
+    BpCol bp[kMaxBp];
+    IdxCol idx[kMaxIdx];
+    KeyDesc keys[kMaxKeys];
+    AggDesc aggs[kMaxAggs];
+};
+
+// Workspace layout (device, 256-byte aligned pieces):
+//   [0, 256)   header: int32 status, int32 spare
+//   table      (1 + n_sums) * n_groups int64: counts, then each SUM
+//   scan       finalize block counts
+struct WsLayout {
+    size_t table_off, scan_off, total;
+    int64_t scan_blocks;
+};
+
+WsLayout workspace_layout(const DevPlan& p);
+
+// Launch the whole query on `stream`: prepare (clear), fused
+// filter/align/aggregate, finalize.  `dp` is the device copy of `p`.
+hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
+                        int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
+                        int grid_fused);
+
+// Device validation of one column; writes a nonzero flag on failure.
+hipError_t launch_validate_rle(const int64_t* ends, int64_t n, int64_t n_rows, int32_t* flag, hipStream_t s);
+hipError_t launch_validate_idx(const void* pos, int32_t ptype, int64_t n, int64_t n_rows, int32_t* flag,
+                               hipStream_t s);
+
+// Persistent-grid size for the fused kernel with the plan's LDS use.
+int fused_grid_limit(const DevPlan& p, int device);
+
+}  // namespace ccq

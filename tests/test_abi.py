@@ -1,0 +1,143 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/ccq.h declares, and its host-side validation rejects malformed
+tables and queries with the documented status codes (host-only context)."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_10092_amd import ccq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ccq.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccq_[a-z_]+)\s*\(", text)))
+
+
+def test_header_functions_are_exported():
+    names = header_functions()
+    assert len(names) >= 12
+    out = subprocess.check_output(["nm", "-D", "--defined-only", ccq.LIB_PATH]).decode()
+    exported = set(re.findall(r"\bT (ccq_[a-z_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert sorted(ccq.SIGNATURES) == names          # the binding covers the whole header
+    L = ccq.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+
+
+def test_abi_version():
+    assert ccq.lib().ccq_abi_version() == 1
+
+
+def _host_table(columns, n_rows):
+    ctx = ccq.Context(ccq.HOST_ONLY)
+    return ccq.Table(ctx, n_rows, columns)
+
+
+def _cols(n=1000):
+    t = lambda a, dt: torch.tensor(a, dtype=dt)
+    return {
+        "a": {"enc": "rle", "values": t([1, 2, 3], torch.int32), "run_ends": t([10, 500, n], torch.int64)},
+        "m": {"enc": "rle", "values": t([5], torch.int64), "run_ends": t([n], torch.int64)},
+        "s": {"enc": "index", "positions": t([3, 7], torch.int32), "values": t([1, 2], torch.int64)},
+        "d": {"enc": "bitpacked", "packed": torch.zeros((n * 14 + 31) // 32 + 2, dtype=torch.int32), "w": 14,
+              "base": 0},
+        "p": {"enc": "bitpacked", "packed": torch.zeros((n * 20 + 31) // 32 + 2, dtype=torch.int32), "w": 20,
+              "base": -(1 << 19)},
+    }
+
+
+def test_host_only_context_checks_plans():
+    tb = _host_table(_cols(), 1000)
+    q = {"preds": [("a", "range", 0, 3), ("d", "in", [1, 5, 9])], "keys": [("d", 0, 10000)],
+         "aggs": [("sum", "s"), ("count",)], "window": (0, 1000)}
+    g, ws = ccq.plan_check(tb, q)
+    assert g == 3                       # dense slots over the IN-list
+    assert ws >= 256 + 8 * 2 * 3
+    q2 = dict(q, keys=[("a", 0, 4), ("p", 10, 1024)], preds=[])
+    g, ws = ccq.plan_check(tb, q2)
+    assert g == 4 * 1024
+    with pytest.raises(ccq.CcqError) as e:
+        ccq.Plan(tb, q)
+    assert e.value.status == ccq.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("bad,code", [
+    ({"preds": [("zz", "range", 0, 1)]}, "unknown"),
+    ({"preds": [("s", "range", 0, 1)]}, ccq.E_UNSUPPORTED),
+    ({"keys": [("s", 0, 4)]}, ccq.E_UNSUPPORTED),
+    ({"keys": [("a", 63, 4)]}, ccq.E_INVALID),
+    ({"keys": [("a", 0, 0)]}, ccq.E_INVALID),
+    ({"keys": [("m", 0, 1 << 20), ("a", 0, 1 << 10)]}, ccq.E_UNSUPPORTED),
+    ({"keys": [("a", 0, 4)] * 9}, ccq.E_UNSUPPORTED),
+    ({"aggs": [("count",)] * 9}, ccq.E_UNSUPPORTED),
+    ({"window": (0, 1001)}, ccq.E_INVALID),
+    ({"window": (10, 5)}, ccq.E_INVALID),
+    ({"keys": [("a", 0, 4), ("a", 1, 4)]}, ccq.E_UNSUPPORTED),
+])
+def test_plan_check_rejects(bad, code):
+    tb = _host_table(_cols(), 1000)
+    q = {"preds": [], "keys": [], "aggs": [("count",)], "window": (0, 1000)}
+    q.update(bad)
+    with pytest.raises(ccq.CcqError) as e:
+        ccq.plan_check(tb, q)
+    if code != "unknown":
+        assert e.value.status == code, str(e.value)
+    assert str(e.value)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda c: c["a"].update(values=c["a"]["values"].to(torch.int16)), "int32 or int64"),
+    (lambda c: c["d"].update(w=0), "bit_width"),
+    (lambda c: c["d"].update(w=33), "bit_width"),
+    (lambda c: c.update(x={"enc": "zzz"}), "encoding"),
+])
+def test_table_create_rejects(mutate, msg):
+    cols = _cols()
+    mutate(cols)
+    with pytest.raises(ccq.CcqError, match=msg):
+        _host_table(cols, 1000)
+
+
+def test_table_create_rejects_int32_positions_past_2_31():
+    cols = {"s": {"enc": "index", "positions": torch.tensor([3], dtype=torch.int32),
+                  "values": torch.tensor([1], dtype=torch.int64)}}
+    with pytest.raises(ccq.CcqError, match="int32 positions"):
+        _host_table(cols, 3 * (1 << 31))
+    cols["s"]["positions"] = torch.tensor([3], dtype=torch.int64)
+    _host_table(cols, 3 * (1 << 31))
+
+
+def test_last_error_is_thread_local_and_cleared():
+    L = ccq.lib()
+    h = ccq.ctypes.c_void_p()
+    assert L.ccq_context_create(-7, ccq.ctypes.byref(h)) != 0
+    assert L.ccq_last_error()
+    assert L.ccq_context_create(ccq.HOST_ONLY, ccq.ctypes.byref(h)) == 0
+    assert L.ccq_last_error() == b""
+    L.ccq_context_destroy(h)
+
+
+def test_word_owner_division_is_exact():
+    """The kernel finds which lane reads packed word q as (q * ceil(2^20/w)) >> 20;
+    check it equals q // w for every width and every word a tile can stage."""
+    for w in range(1, 33):
+        magic = ((1 << 20) + w - 1) // w
+        q = np.arange(0, 64 * w + 2, dtype=np.int64)
+        assert np.array_equal((q * magic) >> 20, q // w), w
+
+
+def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(ccq, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ccq, "_lib", None)
+    with pytest.raises(ccq.CcqError, match="not built"):
+        ccq.lib()

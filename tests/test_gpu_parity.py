@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle,
+element by element, on the same seeded inputs.  Integer results must match
+bit for bit."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import oracle
+from tests.cases import tiny_query, tiny_table
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2506_10092_amd import ccq
+    assert torch.cuda.is_available()
+    return ccq.Context(0)
+
+
+def gpu_run(ctx, table, query, repeat=1):
+    from paper_2506_10092_amd import ccq
+    dev = ccq.to_device(table["columns"])
+    t = ccq.Table(ctx, table["n_rows"], dev)
+    p = ccq.Plan(t, query)
+    ws, res = p.new_workspace(), p.new_result()
+    outs = []
+    for _ in range(repeat):
+        p.execute(ws, res)
+        outs.append(res.to_python())
+    for o in outs[1:]:
+        assert o == outs[0], "repeated execution differs"
+    return outs[0]
+
+
+def check(ctx, table, query, n_threads=None, repeat=1):
+    exp = oracle.run(table, query, n_threads=n_threads)
+    got = gpu_run(ctx, table, query, repeat=repeat)
+    assert got["status"] == 0, got["status"]
+    assert got["keys"] == exp["keys"], "keys differ"
+    assert got["counts"] == exp["counts"], "counts differ"
+    assert got["aggs"] == exp["aggs"], "aggregates differ"
+    return got
+
+
+def _np_col(c):
+    c = dict(c)
+    if c["enc"] == "rle":
+        c["values"] = np.array(c["values"], dtype=np.int64)
+        c["run_ends"] = np.array(c["run_ends"], dtype=np.int64)
+    elif c["enc"] == "index":
+        c["positions"] = np.array(c["positions"], dtype=np.int32)
+        c["values"] = np.array(c["values"], dtype=np.int64)
+    return c
+
+
+@pytest.mark.parametrize("name", ["range_intersect.json", "idx_in_rle.json", "alignment.json", "groupby.json"])
+def test_paper_examples(ctx, name):
+    g = json.load(open(os.path.join(GOLDEN, name)))
+    table = {"n_rows": g["n_rows"], "columns": {k: _np_col(v) for k, v in g["columns"].items()}}
+    for q in g["queries"]:
+        query = {"preds": [tuple(p) for p in q["preds"]], "keys": [tuple(k) for k in q["keys"]],
+                 "aggs": [tuple(a) for a in q["aggs"]], "window": (0, g["n_rows"])}
+        got = check(ctx, table, query)
+        assert got["counts"] == q["expect"]["counts"]
+        assert [list(a) for a in got["aggs"]] == q["expect"]["aggs"]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_random_tables(ctx, seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(1, 5000))
+    t, wd = tiny_table(rng, n)
+    for _ in range(3):
+        q = tiny_query(rng, n, wd)
+        say("tiny seed", seed, "n", n, "query", q)
+        check(ctx, t, q)
+
+
+def test_c1_full(ctx):
+    c = datagen.config_c1()
+    say("c1", c["n_rows"])
+    got = check(ctx, c, c["query"], repeat=3)
+    assert got["counts"][0] > 0
+
+
+@pytest.mark.parametrize("window", [None, (0, 2048), (1, 2047), (12_345, 9_876_543), (5_000_000, 5_000_000),
+                                    (19_999_990, 20_000_000), (777, 778)])
+def test_c2_windows(ctx, window):
+    c = datagen.config_c2(n_rows=20_000_003)
+    q = dict(c["query"])
+    if window:
+        q["window"] = window
+    say("c2 2e7 window", q["window"])
+    check(ctx, c, q)
+
+
+def test_c2_more_templates(ctx):
+    c = datagen.config_c2(n_rows=5_000_017, columns=("r0", "r1", "r2", "s", "d", "p"))
+    n = c["n_rows"]
+    in_codes = c["query"]["preds"][2][2]
+    queries = [
+        # RLE-only with sparse SUM (run mode + idx_in_rle probe)
+        {"preds": [("r0", "range", 0, 30000)], "keys": [("r2", 12, 16)], "aggs": [("sum", "s"), ("count",)]},
+        # SUM over RLE and bit-packed in row mode, RLE key with shift
+        {"preds": [("d", "in", in_codes[:7])], "keys": [("r1", 10, 64)], "aggs": [("sum", "r2"), ("sum", "p")]},
+        # range on the 20-bit column (no code table), dict key without IN
+        {"preds": [("p", "range", -100000, 250000)], "keys": [("d", 0, 10000)], "aggs": [("count",), ("sum", "s")]},
+        # three predicates, ungrouped, several sums
+        {"preds": [("r0", "range", 1000, 60000), ("r1", "range", 0, 50000), ("p", "range", 0, 1 << 19)],
+         "keys": [], "aggs": [("sum", "r0"), ("sum", "p"), ("sum", "s"), ("count",)]},
+        # composite predicates on one column (folded), IN on an RLE column
+        {"preds": [("r0", "range", 0, 40000), ("r0", "range", 20000, 60000), ("r1", "in", list(range(0, 65536, 7)))],
+         "keys": [("r0", 8, 256)], "aggs": [("count",)]},
+        # global-table mode: 2 keys, 64k groups
+        {"preds": [], "keys": [("r0", 8, 256), ("r1", 8, 256)], "aggs": [("sum", "r2"), ("count",)]},
+    ]
+    for q in queries:
+        q["window"] = (0, n)
+        say("c2 template", q)
+        check(ctx, c, q)
+
+
+def test_c3_small(ctx):
+    c = datagen.config_c3(n_rows=30_000_001)
+    say("c3 3e7")
+    check(ctx, c, c["query"])
+
+
+def _rle(values, ends, dt=np.int64):
+    return {"enc": "rle", "values": np.asarray(values, dtype=dt), "run_ends": np.asarray(ends, dtype=np.int64)}
+
+
+def test_unit_runs_force_short_tiles(ctx):
+    """Every run one row long in 8 RLE columns: tiles must end early."""
+    n = 300_000
+    rng = np.random.default_rng(7)
+    cols = {"c%d" % i: _rle(rng.integers(0, 4, n), np.arange(1, n + 1), np.int32) for i in range(8)}
+    t = {"n_rows": n, "columns": cols}
+    q = {"preds": [("c0", "range", 1, 4), ("c3", "range", 0, 3)], "keys": [("c1", 0, 4), ("c2", 0, 4)],
+         "aggs": [("sum", "c4"), ("sum", "c7"), ("count",)], "window": (0, n)}
+    check(ctx, t, q)
+    q["window"] = (1234, 250_001)
+    check(ctx, t, q)
+
+
+def test_unit_runs_with_packed_column(ctx):
+    n = 100_003
+    rng = np.random.default_rng(8)
+    codes = rng.integers(0, 1 << 9, n).astype(np.uint32)
+    cols = {"a": _rle(rng.integers(0, 3, n), np.arange(1, n + 1)),
+            "b": _rle(rng.integers(0, 3, n // 3 + 1), np.r_[np.arange(3, n, 3), n]),
+            "d": {"enc": "bitpacked", "packed": datagen.pack_codes(codes, 9), "w": 9, "base": 0}}
+    t = {"n_rows": n, "columns": cols}
+    q = {"preds": [("a", "range", 1, 3), ("d", "range", 100, 400)], "keys": [("d", 5, 16), ("b", 0, 3)],
+         "aggs": [("sum", "a"), ("sum", "d"), ("count",)], "window": (0, n)}
+    check(ctx, t, q)
+
+
+def test_single_long_run_and_empty_filters(ctx):
+    n = 7_000_001
+    t = {"n_rows": n, "columns": {"x": _rle([42], [n]), "y": _rle([1, 2, 3], [10, n - 5, n], np.int32)}}
+    for q in [
+        {"preds": [], "keys": [], "aggs": [("sum", "x"), ("count",)]},
+        {"preds": [("y", "range", 2, 3)], "keys": [("y", 0, 4)], "aggs": [("sum", "x")]},
+        {"preds": [("y", "range", 7, 9)], "keys": [], "aggs": [("sum", "x"), ("count",)]},
+        {"preds": [("y", "range", 7, 9)], "keys": [("y", 0, 4)], "aggs": [("count",)]},
+        {"preds": [("y", "in", [])], "keys": [], "aggs": [("count",)]},
+    ]:
+        q["window"] = (3, n - 2)
+        check(ctx, t, q)
+
+
+@pytest.mark.parametrize("w", [1, 7, 13, 14, 15, 20, 31, 32])
+def test_bit_widths(ctx, w):
+    n = 70_001
+    rng = np.random.default_rng(w)
+    codes = rng.integers(0, 1 << w, n, dtype=np.uint64).astype(np.uint32)
+    base = -(1 << (w - 1))
+    t = {"n_rows": n, "columns": {
+        "p": {"enc": "bitpacked", "packed": datagen.pack_codes(codes, w), "w": w, "base": base},
+        "r": _rle(rng.integers(0, 5, n // 50 + 1), np.r_[np.sort(rng.choice(np.arange(1, n), n // 50, replace=False)), n]),
+        "s": {"enc": "index", "positions": np.sort(rng.choice(n, 700, replace=False)).astype(np.int64),
+              "values": rng.integers(-5, 5, 700).astype(np.int32)}}}
+    lo = base + (1 << w) // 5
+    hi = base + (1 << w) * 4 // 5 + 1
+    shift = max(0, w - 4)
+    qs = [{"preds": [("p", "range", lo, hi)], "keys": [], "aggs": [("sum", "p"), ("sum", "s"), ("count",)]},
+          {"preds": [("p", "range", 0, 1 << 40)], "keys": [("p", shift, 16)], "aggs": [("sum", "s"), ("count",)]},
+          {"preds": [("r", "range", 1, 4)], "keys": [("r", 0, 5)], "aggs": [("sum", "p")]}]
+    for q in qs:
+        q["window"] = (5, n)
+        check(ctx, t, q)
+
+
+def test_key_domain_violation_sets_status(ctx):
+    n = 10_000
+    t = {"n_rows": n, "columns": {"x": _rle([0, 1, 9, 2], [100, 200, 300, n])}}
+    got = gpu_run(ctx, t, {"preds": [], "keys": [("x", 0, 4)], "aggs": [("count",)], "window": (0, n)})
+    assert got["status"] == -4
+    # the violating run filtered out: no error
+    q = {"preds": [("x", "range", 0, 4)], "keys": [("x", 0, 4)], "aggs": [("count",)], "window": (0, n)}
+    check(ctx, t, q)
+    codes = np.array([1, 2, 3, 17] * 25, dtype=np.uint32)
+    t2 = {"n_rows": 100, "columns": {"d": {"enc": "bitpacked", "packed": datagen.pack_codes(codes, 5), "w": 5, "base": 0}}}
+    got = gpu_run(ctx, t2, {"preds": [], "keys": [("d", 0, 8)], "aggs": [("count",)], "window": (0, 100)})
+    assert got["status"] == -4
+
+
+def test_int64_positions_and_int32_values(ctx):
+    n = 3_000_000
+    c = datagen.config_c2(n_rows=n, columns=("r0", "s", "d"))
+    c["columns"]["s"]["positions"] = c["columns"]["s"]["positions"].astype(np.int64)
+    c["columns"]["s"]["values"] = c["columns"]["s"]["values"].astype(np.int32)
+    q = {"preds": [("r0", "range", 0, 40000), ("d", "in", list(range(0, 200, 3)))], "keys": [("d", 0, 10000)],
+         "aggs": [("sum", "s"), ("count",)], "window": (0, n)}
+    check(ctx, c, q)

@@ -12,6 +12,7 @@ import pytest
 import datagen
 from oracle import oracle
 from tests import brute
+from tests.cases import tiny_query as _tiny_query, tiny_table as _tiny_table
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -274,55 +275,6 @@ def test_multi_chunk_group_counts_closed_form():
 
 
 # ------------------------------------------------------------------ brute force and sqlite3
-
-def _tiny_table(rng, n):
-    cols = {}
-    for i in range(3):
-        R = int(rng.integers(1, max(2, n // 2)))
-        cuts = np.sort(rng.choice(np.arange(1, n), size=min(R - 1, n - 1), replace=False)) if n > 1 else []
-        ends = np.r_[cuts, n].astype(np.int64)
-        cols["r%d" % i] = {"enc": "rle", "values": rng.integers(-5, 20, size=len(ends)).astype(np.int64),
-                           "run_ends": ends}
-    nnz = int(rng.integers(0, n + 1))
-    pos = np.sort(rng.choice(n, size=nnz, replace=False)).astype(np.int32)
-    cols["s"] = {"enc": "index", "positions": pos, "values": rng.integers(-100, 100, size=nnz).astype(np.int64)}
-    w = int(rng.integers(1, 9))
-    codes = rng.integers(0, 1 << w, size=n).astype(np.uint32)
-    cols["d"] = {"enc": "bitpacked", "packed": datagen.pack_codes(codes, w), "w": w, "base": 0}
-    wp = int(rng.integers(1, 33))
-    codes = rng.integers(0, 1 << wp, size=n, dtype=np.uint64).astype(np.uint32)
-    cols["p"] = {"enc": "bitpacked", "packed": datagen.pack_codes(codes, wp), "w": wp,
-                 "base": -(1 << (wp - 1))}
-    return {"n_rows": n, "columns": cols}, w
-
-
-def _tiny_query(rng, n, wd):
-    preds = []
-    if rng.random() < 0.7:
-        lo = int(rng.integers(-6, 20))
-        preds.append(("r0", "range", lo, lo + int(rng.integers(1, 20))))
-    if rng.random() < 0.5:
-        lo = int(rng.integers(-6, 20))
-        preds.append(("r1", "range", lo, lo + int(rng.integers(1, 25))))
-    if rng.random() < 0.5:
-        preds.append(("d", "in", sorted(set(int(x) for x in rng.integers(0, 1 << wd, size=int(rng.integers(0, 6)))))))
-    if rng.random() < 0.3:
-        preds.append(("p", "range", int(rng.integers(-1000, 0)), int(rng.integers(0, 1000))))
-    keys = []
-    if rng.random() < 0.5:
-        keys.append(("d", int(rng.integers(0, 2)), 1 << wd))
-    if rng.random() < 0.4:
-        keys.append(("r2", 0, 20))
-        preds.append(("r2", "range", 0, 20))
-    aggs = [("count",)] if rng.random() < 0.5 else []
-    for c in ("r0", "s", "p", "r1"):
-        if rng.random() < 0.4:
-            aggs.append(("sum", c))
-    a = int(rng.integers(0, n))
-    b = int(rng.integers(a, n + 1))
-    win = (a, b) if rng.random() < 0.3 else (0, n)
-    return {"preds": preds, "keys": keys, "aggs": aggs, "window": win}
-
 
 @pytest.mark.parametrize("seed", range(60))
 def test_oracle_matches_brute_force_and_sqlite(seed):
