@@ -188,6 +188,19 @@ ccq_status ccq_plan_info(const ccq_plan* p, int64_t* max_groups, size_t* workspa
 ccq_status ccq_execute(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
                        const ccq_result* result);
 
+/* Options for ccq_execute_ex.  fused_begin / fused_end: hipEvent_t handles
+ * (or NULL) recorded on `stream` immediately before and after the fused
+ * filter / align / aggregate kernel, so a caller can time that kernel alone
+ * with hipEventElapsedTime. */
+typedef struct {
+    void* fused_begin;
+    void* fused_end;
+} ccq_exec_opts;
+
+/* ccq_execute with options (opts may be NULL). */
+ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
+                          const ccq_result* result, const ccq_exec_opts* opts);
+
 #ifdef __cplusplus
 }
 #endif

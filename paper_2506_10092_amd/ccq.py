@@ -71,6 +71,10 @@ class QueryDesc(ctypes.Structure):
                 ("row_begin", ctypes.c_int64), ("row_end", ctypes.c_int64)]
 
 
+class ExecOpts(ctypes.Structure):
+    _fields_ = [("fused_begin", ctypes.c_void_p), ("fused_end", ctypes.c_void_p)]
+
+
 class ResultDesc(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("aggs", ctypes.c_void_p),
                 ("n_groups", ctypes.c_void_p), ("status", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
@@ -91,6 +95,7 @@ SIGNATURES = {
     "ccq_plan_destroy": (None, [_vp]),
     "ccq_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
     "ccq_execute": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc)]),
+    "ccq_execute_ex": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc), ctypes.POINTER(ExecOpts)]),
 }
 
 _lib = None
@@ -189,6 +194,14 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _event_handle(ev, stream):
+    """Raw hipEvent_t of a torch.cuda.Event (created lazily by torch, so
+    record it once first)."""
+    if not ev.cuda_event:
+        ev.record() if stream is None else ev.record(stream)
+    return ctypes.c_void_p(ev.cuda_event)
+
+
 def query_desc(table, query):
     """Marshal a query dict into a QueryDesc; returns (desc, keepalive)."""
     idx = {n: i for i, n in enumerate(table.names)}
@@ -283,10 +296,17 @@ class Plan:
     def new_result(self):
         return Result(self.max_groups, self.n_keys, self.n_aggs, "cuda:%d" % self.table.ctx.device)
 
-    def execute(self, workspace, result, stream=None):
-        """Enqueue the query on `stream` (torch stream, raw handle or None = current)."""
-        _check(lib().ccq_execute(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                                 _stream_ptr(stream), ctypes.byref(result.desc)))
+    def execute(self, workspace, result, stream=None, fused_events=None):
+        """Enqueue the query on `stream` (torch stream, raw handle or None =
+        current).  fused_events: optional (begin, end) torch.cuda.Event pair
+        recorded around the fused kernel on that stream."""
+        if fused_events is None:
+            _check(lib().ccq_execute(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                     _stream_ptr(stream), ctypes.byref(result.desc)))
+            return
+        opts = ExecOpts(_event_handle(fused_events[0], stream), _event_handle(fused_events[1], stream))
+        _check(lib().ccq_execute_ex(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    _stream_ptr(stream), ctypes.byref(result.desc), ctypes.byref(opts)))
 
     def run(self):
         """Execute once and return the result on the host."""

@@ -419,6 +419,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             b.key_stride = P.keys[b.key].stride;
         }
         const bool has_pred = f.is_false || f.has_range || f.has_set;
+        b.n_words = (t->n_rows * (int64_t)c.bit_width + 31) / 32 + 2;
         if (c.bit_width <= kLutMaxBits && (has_pred || b.key >= 0)) {
             const int64_t n = int64_t(1) << c.bit_width;
             std::vector<uint16_t> lut(n);
@@ -433,7 +434,20 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
                 const int64_t kv = v >> kd.shift;
                 lut[code] = (kv < 0 || kv >= kd.card) ? kLutDomain : (uint16_t)rank[kv];
             }
-            fix_ptr(&b.lut, blob_put(lut.data(), lut.size() * 2));
+            // one byte per code when every slot fits below the two marker values
+            const bool u8 = b.key < 0 || P.keys[b.key].radix <= 254;
+            b.lut_u8 = u8 ? 1 : 0;
+            if (u8) {
+                std::vector<uint8_t> l8((n + 3) & ~int64_t(3), 255);
+                for (int64_t code = 0; code < n; ++code)
+                    l8[code] = lut[code] == kLutReject ? 255 : lut[code] == kLutDomain ? 254 : (uint8_t)lut[code];
+                b.lut_bytes = (int32_t)l8.size();
+                fix_ptr(&b.lut, blob_put(l8.data(), l8.size()));
+            } else {
+                if (n % 2) lut.push_back(kLutReject);
+                b.lut_bytes = (int32_t)(lut.size() * 2);
+                fix_ptr(&b.lut, blob_put(lut.data(), lut.size() * 2));
+            }
             has_lut[s] = true;
         } else {
             if (f.is_false) b.pred = kPredFalse;
@@ -480,9 +494,12 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             if (P.aggs[a].kind == kAggSumRle) P.any_rle_row = 1;
     }
     const int64_t window = P.row_end - P.row_begin;
+    P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
+    P.w0 = (P.row_mode && P.n_bp == 1 && !P.any_rle_row && fast_row_width(P.bp[0].w)) ? P.bp[0].w : 0;
     if (P.row_mode) {
+        // a 2048-row tile; each column keeps at least 64 staged runs
         P.span = kRowSpan;
-        P.run_cap = std::max(64 * P.k_rle, 512);
+        P.run_cap = std::max(64 * P.k_rle, 128);
     } else {
         // aim for about a quarter of a column's LDS share per tile, so tiles
         // rarely end early
@@ -500,14 +517,15 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         P.span = (int32_t)span;
     }
     P.tile_rows = (int64_t)64 * P.span;
-    P.n_tiles = (window + P.tile_rows - 1) / P.tile_rows;
+    // nominal tiles: multiples of tile_rows in absolute row numbers that meet the window
+    P.n_tiles = window > 0 ? (P.row_end - 1) / P.tile_rows - P.row_begin / P.tile_rows + 1 : 0;
 
     // LDS layout: shared part (code tables, group table) then kWaves slices
     size_t sh = 0;
     for (int s = 0; s < P.n_bp; ++s) {
         if (has_lut[s]) {
             P.bp[s].lut_lds_off = (int32_t)sh;
-            sh = align16(sh + (size_t(1) << P.bp[s].w) * 2);
+            sh = align16(sh + (size_t)P.bp[s].lut_bytes);
         }
     }
     const size_t table_bytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
@@ -524,13 +542,16 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     wv = align16(wv + 4 * (size_t)P.run_cap);
     P.off_run_val = (int32_t)wv;
     wv = align16(wv + 8 * (size_t)P.run_cap);
-    if (P.row_mode) {
+    if (P.row_mode && P.w0 == 0) {
+        // generic row mode: compacted row list and staged packed words
         P.off_rows = (int32_t)wv;
         wv = align16(wv + 2 * (size_t)kRowTile);
         for (int s = 0; s < P.n_bp; ++s) {
             P.bp[s].stage_off = (int32_t)wv;
             wv = align16(wv + 4 * (size_t)(64 * P.bp[s].w + 2));
         }
+    }
+    if (P.row_mode) {
         P.off_pts = (int32_t)wv;
         wv = align16(wv + 4 * 64 * (size_t)P.n_idx);
         P.off_ptpre = (int32_t)wv;
@@ -612,6 +633,11 @@ ccq_status ccq_plan_info(const ccq_plan* p, int64_t* max_groups, size_t* workspa
 
 ccq_status ccq_execute(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
                        const ccq_result* r) {
+    return ccq_execute_ex(p, workspace, workspace_bytes, stream, r, nullptr);
+}
+
+ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
+                          const ccq_result* r, const ccq_exec_opts* opts) {
     if (!p || !r) return fail(CCQ_E_INVALID, "plan or result is NULL");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(CCQ_E_INVALID, "workspace must be 256-byte aligned");
     if (workspace_bytes < p->ws.total)
@@ -624,7 +650,8 @@ ccq_status ccq_execute(const ccq_plan* p, void* workspace, size_t workspace_byte
     hipError_t e = hipSetDevice(p->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     e = launch_query(p->host, p->dev, workspace, (hipStream_t)stream, r->keys, r->counts, r->aggs, r->n_groups,
-                     r->status, p->grid_fused);
+                     r->status, p->grid_fused, opts ? (hipEvent_t)opts->fused_begin : nullptr,
+                     opts ? (hipEvent_t)opts->fused_end : nullptr);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return ok();
 }

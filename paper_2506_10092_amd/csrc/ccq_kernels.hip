@@ -186,16 +186,18 @@ struct WaveLds {
     int64_t* cur;       // [kMaxRle] run index holding the next tile's first row
     int32_t* run_end;   // [run_cap] run end - tile start, capped at 2^30
     int64_t* run_val;   // [run_cap]
-    uint16_t* rows;     // row mode: surviving rows of the tile, compacted
+    uint16_t* rows;     // generic row mode: surviving rows of the tile, compacted
     uint32_t* pts;      // row mode: 64-word point bitmap per Index column
     int32_t* ptpre;     // row mode: exclusive popcount prefix per bitmap word
     int32_t cap;        // staged runs per column; column c starts at slot c * cap
 };
 
-// Stage the runs of every RLE column that overlap [t0, *t1) into LDS.  A
-// column that would exceed its share shrinks *t1 to the end of its last
-// staged run, so all columns cover the (possibly shorter) tile.
-__device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t* t1) {
+// Stage the runs of every RLE column that overlap [t0, *t1) into LDS, 64 per
+// coalesced batch.  A column that would exceed its share shrinks *t1 to the
+// end of its last staged run (rounded down to `align` rows), so all columns
+// cover the (possibly shorter) tile.
+__device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t* t1,
+                                           int64_t align) {
     const int lane = lane_id();
     for (int c = 0; c < P.k_rle; ++c) {
         const RleCol& rc = P.rle[c];
@@ -205,20 +207,25 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
         for (;;) {
             const int64_t i = lo + n + lane;
             const bool valid = i < rc.n_runs && n + lane < W.cap;
-            const int64_t e = valid ? rc.ends[i] : INT64_MAX;
+            int64_t e = INT64_MAX, v = 0;
+            if (valid) {
+                e = rc.ends[i];
+                v = ld_val(rc.vals, rc.vtype, i);
+            }
             const uint64_t last = wave_ballot(valid && e >= *t1);
             const uint64_t vmask = wave_ballot(valid);
             const int cnt = last ? __builtin_ctzll(last) + 1 : __builtin_popcountll(vmask);
             if (lane < cnt) {
                 const int64_t rel = e - t0;
                 W.run_end[off + n + lane] = (int32_t)(rel < (1 << 30) ? rel : (1 << 30));
-                W.run_val[off + n + lane] = ld_val(rc.vals, rc.vtype, i);
+                W.run_val[off + n + lane] = v;
             }
             n += cnt;
             if (last) break;
             if (n >= W.cap) {
                 const int64_t e_last = __shfl(e, cnt - 1, 64);
-                if (e_last < *t1) *t1 = e_last;
+                const int64_t cut = t0 + ((e_last - t0) / align) * align;
+                if (cut < *t1) *t1 = cut;
                 break;
             }
         }
@@ -232,16 +239,18 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
 
 // A lane's merge over its rows: one cursor per RLE column into the staged
 // runs; the aligned run ends at the nearest cursor end.  Cursors only move
-// at boundaries strictly inside the lane's span, and the staged runs of every
+// at boundaries strictly inside the lane's rows, and the staged runs of every
 // column cover the whole tile, so a cursor never runs past its column.
+template <int KMAX>
 struct Walk {
-    int32_t j[kMaxRle];
-    int32_t end[kMaxRle];
-    int64_t val[kMaxRle];
-    bool pass[kMaxRle];
+    int32_t j[KMAX];
+    int32_t end[KMAX];
+    int64_t val[KMAX];
+    bool pass[KMAX];
 };
 
-__device__ __forceinline__ void walk_load(const DevPlan& P, const WaveLds& W, Walk& w, int c) {
+template <int KMAX>
+__device__ __forceinline__ void walk_load(const DevPlan& P, const WaveLds& W, Walk<KMAX>& w, int c) {
     const int32_t idx = c * W.cap + w.j[c];
     w.end[c] = W.run_end[idx];
     w.val[c] = W.run_val[idx];
@@ -249,9 +258,10 @@ __device__ __forceinline__ void walk_load(const DevPlan& P, const WaveLds& W, Wa
     w.pass[c] = pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, w.val[c]);
 }
 
-__device__ __forceinline__ void walk_init(const DevPlan& P, const WaveLds& W, Walk& w, int32_t s0) {
+template <int KMAX>
+__device__ __forceinline__ void walk_init(const DevPlan& P, const WaveLds& W, Walk<KMAX>& w, int32_t s0) {
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c) {
+    for (int c = 0; c < KMAX; ++c) {
         if (c < P.k_rle) {
             w.j[c] = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], s0);
             walk_load(P, W, w, c);
@@ -259,25 +269,28 @@ __device__ __forceinline__ void walk_init(const DevPlan& P, const WaveLds& W, Wa
     }
 }
 
-__device__ __forceinline__ int32_t walk_next(const DevPlan& P, const Walk& w, int32_t s1) {
+template <int KMAX>
+__device__ __forceinline__ int32_t walk_next(const DevPlan& P, const Walk<KMAX>& w, int32_t s1) {
     int32_t e = s1;
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c)
+    for (int c = 0; c < KMAX; ++c)
         if (c < P.k_rle) e = min(e, w.end[c]);
     return e;
 }
 
-__device__ __forceinline__ bool walk_pass(const DevPlan& P, const Walk& w) {
+template <int KMAX>
+__device__ __forceinline__ bool walk_pass(const DevPlan& P, const Walk<KMAX>& w) {
     bool p = true;
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c)
+    for (int c = 0; c < KMAX; ++c)
         if (c < P.k_rle) p = p && w.pass[c];
     return p;
 }
 
-__device__ __forceinline__ void walk_advance(const DevPlan& P, const WaveLds& W, Walk& w, int32_t e) {
+template <int KMAX>
+__device__ __forceinline__ void walk_advance(const DevPlan& P, const WaveLds& W, Walk<KMAX>& w, int32_t e) {
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c) {
+    for (int c = 0; c < KMAX; ++c) {
         if (c < P.k_rle && w.end[c] == e) {
             w.j[c] += 1;
             walk_load(P, W, w, c);
@@ -287,12 +300,13 @@ __device__ __forceinline__ void walk_advance(const DevPlan& P, const WaveLds& W,
 
 // Group id part from the RLE keys; false (status raised) if a key is out of
 // its domain.
-__device__ __forceinline__ bool rle_key_part(const DevPlan& P, const int64_t (&vals)[kMaxRle], int64_t* gid,
+template <int KMAX>
+__device__ __forceinline__ bool rle_key_part(const DevPlan& P, const int64_t (&vals)[KMAX], int64_t* gid,
                                              int32_t* status) {
     int64_t g = 0;
     bool ok = true;
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c) {
+    for (int c = 0; c < KMAX; ++c) {
         if (c < P.k_rle && P.rle[c].key_on) {
             const int64_t kv = vals[c] >> P.rle[c].key_shift;
             if (kv < 0 || kv >= P.rle[c].key_card) ok = false;
@@ -305,30 +319,33 @@ __device__ __forceinline__ bool rle_key_part(const DevPlan& P, const int64_t (&v
 }
 
 // consecutive aligned runs of one group, added in registers
+template <int KMAX>
 struct RegAcc {
     int64_t gid;
     int64_t cnt;
-    int64_t rsum[kMaxRle];   // SUM of each RLE column
+    int64_t rsum[KMAX];   // SUM of each RLE column
 };
 
-__device__ __forceinline__ void regacc_flush(const DevPlan& P, const Table& tb, RegAcc& a) {
+template <int KMAX>
+__device__ __forceinline__ void regacc_flush(const DevPlan& P, const Table& tb, RegAcc<KMAX>& a) {
     if (a.gid >= 0 && a.cnt > 0) {
         table_add(tb, 0, a.gid, a.cnt);
 #pragma unroll
-        for (int c = 0; c < kMaxRle; ++c)
+        for (int c = 0; c < KMAX; ++c)
             if (c < P.k_rle && P.rle[c].sum_slot >= 0 && a.rsum[c] != 0)
                 table_add(tb, 1 + P.rle[c].sum_slot, a.gid, a.rsum[c]);
     }
     a.gid = -1;
     a.cnt = 0;
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c) a.rsum[c] = 0;
+    for (int c = 0; c < KMAX; ++c) a.rsum[c] = 0;
 }
 
 // Index points of a run-mode tile: each point looks up the runs holding its
 // row in the staged run ends (idx_in_rle) and adds its value.
-__device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L, const Table& tb, int32_t* status,
-                                                int64_t (&pcur)[kMaxIdx]) {
+template <int KMAX>
+__device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
+                                                const Table& tb, int32_t* status, int64_t (&pcur)[kMaxIdx]) {
     const int lane = lane_id();
 #pragma unroll
     for (int j = 0; j < kMaxIdx; ++j) {
@@ -344,9 +361,9 @@ __device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds&
             if (in) {
                 const int32_t rel = (int32_t)(pos - t0);
                 bool pass = true;
-                int64_t vals[kMaxRle];
+                int64_t vals[KMAX];
 #pragma unroll
-                for (int c = 0; c < kMaxRle; ++c) {
+                for (int c = 0; c < KMAX; ++c) {
                     vals[c] = 0;
                     if (c < P.k_rle) {
                         const int32_t jj = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], rel);
@@ -356,7 +373,7 @@ __device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds&
                     }
                 }
                 int64_t gid;
-                if (pass && rle_key_part(P, vals, &gid, status) && ic.sum_slot >= 0) {
+                if (pass && rle_key_part<KMAX>(P, vals, &gid, status) && ic.sum_slot >= 0) {
                     const int64_t v = ld_val(ic.vals, ic.vtype, i);
                     if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
                 }
@@ -370,66 +387,70 @@ __device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds&
 }
 
 // Run mode tile: no bit-packed column; aggregate per aligned run.
-__device__ __forceinline__ void tile_run_mode(const DevPlan& P, const WaveLds& W, int64_t t0,
-                                              int32_t L, const Table& tb, int32_t* status, RegAcc& acc,
+template <int KMAX>
+__device__ __forceinline__ void tile_run_mode(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
+                                              const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
                                               int64_t (&pcur)[kMaxIdx]) {
     const int32_t s0 = lane_id() * P.span;
     const int32_t s1 = min(s0 + P.span, L);
     if (s0 < s1) {
-        Walk w;
-        walk_init(P, W, w, s0);
+        Walk<KMAX> w;
+        walk_init<KMAX>(P, W, w, s0);
         int32_t x = s0;
         while (x < s1) {
-            const int32_t e = walk_next(P, w, s1);
-            if (walk_pass(P, w)) {
+            const int32_t e = walk_next<KMAX>(P, w, s1);
+            if (walk_pass<KMAX>(P, w)) {
                 int64_t gid;
-                if (rle_key_part(P, w.val, &gid, status)) {
+                if (rle_key_part<KMAX>(P, w.val, &gid, status)) {
                     if (gid != acc.gid) {
-                        regacc_flush(P, tb, acc);
+                        regacc_flush<KMAX>(P, tb, acc);
                         acc.gid = gid;
                     }
                     const int64_t len = e - x;
                     acc.cnt += len;
 #pragma unroll
-                    for (int c = 0; c < kMaxRle; ++c)
+                    for (int c = 0; c < KMAX; ++c)
                         if (c < P.k_rle && P.rle[c].sum_slot >= 0) acc.rsum[c] += w.val[c] * len;
                 }
             }
-            if (e < s1) walk_advance(P, W, w, e);
+            if (e < s1) walk_advance<KMAX>(P, W, w, e);
             x = e;
         }
     }
-    if (P.n_idx > 0) run_mode_points(P, W, t0, L, tb, status, pcur);
+    if (P.n_idx > 0) run_mode_points<KMAX>(P, W, t0, L, tb, status, pcur);
 }
 
-// Row mode tile (at most 2048 rows, 32 per lane).
-__device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W, int64_t t0,
-                                              int32_t L, const Table& tb, int32_t* status,
-                                              int64_t (&pcur)[kMaxIdx], const uint16_t* const (&luts)[kMaxBp]) {
-    const int lane = lane_id();
-    const int32_t s0 = lane * kRowSpan;
-    const int32_t s1 = min(s0 + kRowSpan, L);
-
-    // a1 + a2: the lane's rows that survive every RLE predicate
+// The lane's 32 rows [32 lane, 32 lane + 32) of a row-mode tile that survive
+// every RLE predicate, as a bit mask; rows before lo_valid are excluded.
+template <int KMAX>
+__device__ __forceinline__ uint32_t lane_row_mask(const DevPlan& P, const WaveLds& W, int32_t L, int32_t lo_valid) {
+    const int32_t base = lane_id() * kRowSpan;
+    const int32_t s0 = max(base, lo_valid);
+    const int32_t s1 = min(base + kRowSpan, L);
     uint32_t pm = 0;
     if (s0 < s1) {
-        Walk w;
-        walk_init(P, W, w, s0);
+        Walk<KMAX> w;
+        walk_init<KMAX>(P, W, w, s0);
         int32_t x = s0;
         while (x < s1) {
-            const int32_t e = walk_next(P, w, s1);
-            if (walk_pass(P, w)) {
-                const uint32_t a = (uint32_t)(x - s0), b = (uint32_t)(e - s0);   // bits [a, b)
+            const int32_t e = walk_next<KMAX>(P, w, s1);
+            if (walk_pass<KMAX>(P, w)) {
+                const uint32_t a = (uint32_t)(x - base), b = (uint32_t)(e - base);   // bits [a, b)
                 const uint32_t below_b = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
                 pm |= below_b & ~((1u << a) - 1u);
             }
-            if (e < s1) walk_advance(P, W, w, e);
+            if (e < s1) walk_advance<KMAX>(P, W, w, e);
             x = e;
         }
     }
+    return pm;
+}
 
-    // a5: bitmap of the rows that carry an Index point, with prefix counts
-    int64_t pbase[kMaxIdx];
+// Point bitmaps of the tile (one bit per row carrying an Index point) with
+// exclusive prefix counts per word; pbase[j] = index of the tile's first point.
+__device__ __forceinline__ void tile_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
+                                            int64_t (&pcur)[kMaxIdx], int64_t (&pbase)[kMaxIdx]) {
+    const int lane = lane_id();
 #pragma unroll
     for (int j = 0; j < kMaxIdx; ++j) {
         pbase[j] = 0;
@@ -461,13 +482,128 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
         W.ptpre[j * 64 + lane] = ex;
         wave_lds_sync();
     }
+}
+
+// code table lookup: uint8 tables use 254 / 255 for domain / reject
+__device__ __forceinline__ uint32_t lut_get(const void* lut, int32_t u8, uint32_t code) {
+    if (u8) {
+        const uint32_t e = ((const uint8_t*)lut)[code];
+        return e >= 254u ? e + (0xFFFFu - 255u) : e;
+    }
+    return ((const uint16_t*)lut)[code];
+}
+
+// bits [j*W, j*W + W) of the lane's packed words (j and W compile-time)
+template <int W0>
+__device__ __forceinline__ uint32_t extract_code(const uint32_t (&wd)[W0 > 0 ? W0 : 1], int j) {
+    const int b = j * W0, q = b >> 5, sh = b & 31;
+    const uint32_t mask = W0 == 32 ? 0xFFFFFFFFu : ((1u << W0) - 1u);
+    if (sh + W0 <= 32) return (wd[q] >> sh) & mask;
+    return __builtin_amdgcn_alignbit(wd[q + 1], wd[q], sh) & mask;
+}
+
+// Fast row mode: exactly one bit-packed column, of width W0, read from the
+// lane's registers; no RLE value is needed per row.
+template <int KMAX, int W0>
+__device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
+                                              int32_t lo_valid, const Table& tb, int32_t* status,
+                                              int64_t (&pcur)[kMaxIdx], const void* lut0) {
+    const int lane = lane_id();
+    const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
+    int64_t pbase[kMaxIdx];
+    tile_points(P, W, t0, L, pcur, pbase);
+    if (wave_ballot(pm != 0) == 0) return;
+
+    // the lane's 32 rows are W0 whole words of the stream (tiles start at multiples of 32 rows)
+    const BpCol& bc = P.bp[0];
+    uint32_t wd[W0];
+    const int64_t word0 = ((t0 >> 5) + lane) * (int64_t)W0;
+    if (pm && word0 + W0 > bc.n_words) {
+        // the lane's rows reach past the table end: read only the guaranteed words
+#pragma unroll
+        for (int i = 0; i < W0; ++i) wd[i] = word0 + i < bc.n_words ? bc.packed[word0 + i] : 0u;
+    } else if (pm) {
+        const uint32_t* src = bc.packed + word0;
+        if constexpr (W0 % 2 == 0) {
+            const uint2* s2 = (const uint2*)src;
+#pragma unroll
+            for (int i = 0; i < W0 / 2; ++i) {
+                const uint2 v = s2[i];
+                wd[2 * i] = v.x;
+                wd[2 * i + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < W0; ++i) wd[i] = src[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < W0; ++i) wd[i] = 0;
+    }
+    const int32_t u8 = bc.lut_u8;
+    const bool has_lut = lut0 != nullptr;
+    const bool keyed = bc.key >= 0;
+    const int32_t sum_slot = bc.sum_slot;
+#pragma unroll
+    for (int j = 0; j < kRowSpan; ++j) {
+        if (!((pm >> j) & 1u)) continue;
+        const uint32_t code = extract_code<W0>(wd, j);
+        int64_t gid = 0;
+        if (has_lut) {
+            const uint32_t e = lut_get(lut0, u8, code);
+            if (e == kLutReject) continue;
+            if (e == kLutDomain) {
+                raise_status(status, -4);
+                continue;
+            }
+            if (keyed) gid = (int64_t)e * bc.key_stride;
+        } else {
+            const int64_t v = bc.base + (int64_t)code;
+            if (!pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, v)) continue;
+            if (keyed) {
+                const int64_t kv = v >> bc.key_shift;
+                if (kv < 0 || kv >= bc.key_card) {
+                    raise_status(status, -4);
+                    continue;
+                }
+                gid = kv * bc.key_stride;
+            }
+        }
+        table_add(tb, 0, gid, 1);
+        if (sum_slot >= 0) table_add(tb, 1 + sum_slot, gid, bc.base + (int64_t)code);
+#pragma unroll
+        for (int q = 0; q < kMaxIdx; ++q) {
+            if (q < P.n_idx && P.idx[q].sum_slot >= 0) {
+                const uint32_t word = W.pts[q * 64 + lane];
+                if (word & (1u << j)) {
+                    const int64_t rank = W.ptpre[q * 64 + lane] + __builtin_popcount(word & ((1u << j) - 1u));
+                    const int64_t v = ld_val(P.idx[q].vals, P.idx[q].vtype, pbase[q] + rank);
+                    if (v != 0) table_add(tb, 1 + P.idx[q].sum_slot, gid, v);
+                }
+            }
+        }
+    }
+}
+
+// Generic row mode: any number of bit-packed columns of any width, RLE values
+// per row.  Surviving rows are compacted into an LDS list; the packed words
+// they read are staged in LDS.
+template <int KMAX>
+__device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
+                                                 int32_t lo_valid, const Table& tb, int32_t* status,
+                                                 int64_t (&pcur)[kMaxIdx], const void* const (&luts)[kMaxBp]) {
+    const int lane = lane_id();
+    const int32_t s0 = lane * kRowSpan;
+    const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
+    int64_t pbase[kMaxIdx];
+    tile_points(P, W, t0, L, pcur, pbase);
 
     // a3: compact the surviving rows into the wave's row list
     int total;
-    const int base = wave_exclusive_sum(__builtin_popcount(pm), &total);
+    const int first = wave_exclusive_sum(__builtin_popcount(pm), &total);
     {
         uint32_t m = pm;
-        int q = base;
+        int q = first;
         while (m) {
             const int b = __builtin_ctz(m);
             m &= m - 1;
@@ -500,7 +636,6 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
     }
     wave_lds_sync();
 
-    // per surviving row: unpack, bit-packed predicates, group id, aggregates
     for (int i = lane; i < total; i += 64) {
         const int32_t r = W.rows[i];
         bool pass = true;
@@ -521,7 +656,7 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
             const uint32_t code = (uint32_t)((two >> sh) & mask);
             bpv[j] = bc.base + (int64_t)code;
             if (luts[j]) {
-                const uint16_t e = luts[j][code];
+                const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
                 if (e == kLutReject) pass = false;
                 else if (e == kLutDomain) dom = true;
                 else if (bc.key >= 0) gid += (int64_t)e * bc.key_stride;
@@ -535,9 +670,9 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
             }
         }
         if (!pass) continue;
-        int64_t rv[kMaxRle];
+        int64_t rv[KMAX];
 #pragma unroll
-        for (int c = 0; c < kMaxRle; ++c) {
+        for (int c = 0; c < KMAX; ++c) {
             rv[c] = 0;
             if (P.any_rle_row && c < P.k_rle) {
                 const int32_t jj = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], r);
@@ -546,7 +681,7 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
         }
         if (P.any_rle_row) {
             int64_t g2;
-            if (!rle_key_part(P, rv, &g2, status)) continue;
+            if (!rle_key_part<KMAX>(P, rv, &g2, status)) continue;
             gid += g2;
         }
         if (dom) {
@@ -555,7 +690,7 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
         }
         table_add(tb, 0, gid, 1);
 #pragma unroll
-        for (int c = 0; c < kMaxRle; ++c)
+        for (int c = 0; c < KMAX; ++c)
             if (c < P.k_rle && P.rle[c].sum_slot >= 0) table_add(tb, 1 + P.rle[c].sum_slot, gid, rv[c]);
 #pragma unroll
         for (int j = 0; j < kMaxBp; ++j)
@@ -565,7 +700,8 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
             if (j < P.n_idx && P.idx[j].sum_slot >= 0) {
                 const uint32_t word = W.pts[j * 64 + (r >> 5)];
                 if (word & (1u << (r & 31))) {
-                    const int64_t rank = W.ptpre[j * 64 + (r >> 5)] + __builtin_popcount(word & ((1u << (r & 31)) - 1u));
+                    const int64_t rank =
+                        W.ptpre[j * 64 + (r >> 5)] + __builtin_popcount(word & ((1u << (r & 31)) - 1u));
                     const int64_t v = ld_val(P.idx[j].vals, P.idx[j].vtype, pbase[j] + rank);
                     if (v != 0) table_add(tb, 1 + P.idx[j].sum_slot, gid, v);
                 }
@@ -575,20 +711,23 @@ __device__ __forceinline__ void tile_row_mode(const DevPlan& P, const WaveLds& W
     wave_lds_sync();
 }
 
+// KMAX: bound on RLE columns (register arrays); W0: 0 = run mode or generic
+// row mode, else the width of the single bit-packed column of the fast row path.
+template <int KMAX, int W0>
 __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
                                                      int32_t* __restrict__ status, int64_t n_waves_total) {
     extern __shared__ __align__(16) unsigned char lds[];
     const DevPlan& P = *Pg;
 
     // shared part of dynamic LDS: the code tables, then the group table
-    const uint16_t* luts[kMaxBp];
+    const void* luts[kMaxBp];
 #pragma unroll
     for (int j = 0; j < kMaxBp; ++j) {
         luts[j] = nullptr;
         if (j < P.n_bp && P.bp[j].lut) {
-            uint16_t* dst = (uint16_t*)(lds + P.bp[j].lut_lds_off);
-            const uint16_t* src = P.bp[j].lut;
-            const int n = 1 << P.bp[j].w;
+            uint32_t* dst = (uint32_t*)(lds + P.bp[j].lut_lds_off);
+            const uint32_t* src = (const uint32_t*)P.bp[j].lut;
+            const int n = P.bp[j].lut_bytes / 4;
             for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
             luts[j] = dst;
         }
@@ -604,12 +743,14 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     }
     __syncthreads();
 
-    // this wave's slice of the window, a whole number of nominal tiles
+    // this wave's slice of the window: a whole number of nominal tiles,
+    // aligned to multiples of tile_rows in absolute row numbers
     const int wave = threadIdx.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
     const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
-    const int64_t w0 = P.row_begin + gw * tiles_per_wave * P.tile_rows;
-    const int64_t w1 = min(P.row_end, w0 + tiles_per_wave * P.tile_rows);
+    const int64_t first_tile = P.row_begin / P.tile_rows;
+    const int64_t w0 = max(P.row_begin, (first_tile + gw * tiles_per_wave) * P.tile_rows);
+    const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) * P.tile_rows);
 
     WaveLds W;
     W.base = lds + P.lds_shared_bytes + wave * P.lds_wave_bytes;
@@ -623,11 +764,11 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     W.pts = (uint32_t*)(W.base + P.off_pts);
     W.ptpre = (int32_t*)(W.base + P.off_ptpre);
 
-    RegAcc acc;
+    RegAcc<KMAX> acc;
     acc.gid = -1;
     acc.cnt = 0;
 #pragma unroll
-    for (int c = 0; c < kMaxRle; ++c) acc.rsum[c] = 0;
+    for (int c = 0; c < KMAX; ++c) acc.rsum[c] = 0;
 
     if (w0 < w1) {
         int64_t pcur[kMaxIdx];
@@ -639,13 +780,20 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
         for (int j = 0; j < kMaxIdx; ++j)
             pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
         wave_lds_sync();
-        int64_t t0 = w0;
+        // row mode tiles start at multiples of 32 rows (lane words); the first
+        // one may start before the window, whose rows are then masked out
+        int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
         while (t0 < w1) {
-            int64_t t1 = min(t0 + P.tile_rows, w1);
-            stage_runs(P, W, t0, &t1);
+            int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
+            stage_runs(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
             const int32_t L = (int32_t)(t1 - t0);
-            if (P.row_mode) tile_row_mode(P, W, t0, L, tb, status, pcur, luts);
-            else tile_run_mode(P, W, t0, L, tb, status, acc, pcur);
+            const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
+            if (P.row_mode) {
+                if constexpr (W0 > 0) tile_row_fast<KMAX, W0>(P, W, t0, L, lo_valid, tb, status, pcur, luts[0]);
+                else tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
+            } else {
+                tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
+            }
             // next tile's first run per column: the first staged run ending after t1
             for (int c = 0; c < P.k_rle; ++c) {
                 const int64_t x = W.tlo[c] + lds_upper_bound(W.run_end + c * W.cap, W.tn[c], L);
@@ -655,7 +803,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
             t0 = t1;
         }
     }
-    regacc_flush(P, tb, acc);
+    regacc_flush<KMAX>(P, tb, acc);
 
     if (P.table_lds) {
         __syncthreads();
@@ -812,10 +960,31 @@ WsLayout workspace_layout(const DevPlan& p) {
     return L;
 }
 
+// kernel instance for a plan: KMAX bounds the RLE column count, W0 is the
+// bit width of the fast row path (0: run mode or generic row mode)
+typedef void (*FusedFn)(const DevPlan*, int64_t*, int32_t*, int64_t);
+
+static FusedFn fused_kernel(const DevPlan& p) {
+    const int k = p.kmax;
+#define CCQ_PICK(KM)                                       \
+    if (k <= KM) {                                          \
+        if (p.w0 == 14) return &k_fused<KM, 14>;            \
+        if (p.w0 == 20) return &k_fused<KM, 20>;            \
+        return &k_fused<KM, 0>;                             \
+    }
+    CCQ_PICK(2)
+    CCQ_PICK(4)
+    CCQ_PICK(8)
+#undef CCQ_PICK
+    return &k_fused<8, 0>;
+}
+
+bool fast_row_width(int w) { return w == 14 || w == 20; }
+
 int fused_grid_limit(const DevPlan& p, int device) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_fused, kThreads, p.lds_dyn_bytes) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fused_kernel(p), kThreads,
+                                                     p.lds_dyn_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     hipDeviceProp_t prop;
@@ -826,7 +995,7 @@ int fused_grid_limit(const DevPlan& p, int device) {
 
 hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
                         int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
-                        int grid_fused) {
+                        int grid_fused, hipEvent_t ev_begin, hipEvent_t ev_end) {
     const WsLayout L = workspace_layout(p);
     unsigned char* base = (unsigned char*)ws;
     int32_t* header = (int32_t*)base;
@@ -837,11 +1006,19 @@ hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream
     const int prep_grid = (int)std::min<int64_t>(std::max<int64_t>(div_up(table_len, kThreads), 1), 4096);
     hipLaunchKernelGGL(k_prepare, dim3(prep_grid), dim3(kThreads), 0, stream, table, table_len, header);
 
+    if (ev_begin) {
+        hipError_t e = hipEventRecord(ev_begin, stream);
+        if (e != hipSuccess) return e;
+    }
     if (p.n_tiles > 0) {
         int64_t blocks = std::min<int64_t>(div_up(p.n_tiles, kWaves), grid_fused);
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(k_fused, dim3((unsigned)blocks), dim3(kThreads), p.lds_dyn_bytes, stream, dp, table,
-                           header, blocks * kWaves);
+        hipLaunchKernelGGL(fused_kernel(p), dim3((unsigned)blocks), dim3(kThreads), p.lds_dyn_bytes, stream, dp,
+                           table, header, blocks * kWaves);
+    }
+    if (ev_end) {
+        hipError_t e = hipEventRecord(ev_end, stream);
+        if (e != hipSuccess) return e;
     }
 
     if (p.n_keys == 0) {

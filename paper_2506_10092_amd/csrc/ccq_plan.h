@@ -53,7 +53,10 @@ struct BpCol {
     const int64_t* set;
     int32_t set_len;
     int32_t key;            // key index or -1
-    const uint16_t* lut;    // device code table (2^w entries) or nullptr
+    const void* lut;        // device code table (2^w entries of uint8 or uint16) or nullptr
+    int32_t lut_u8;         // entries are uint8 (254 = key out of domain, 255 = reject)
+    int32_t lut_bytes;      // table size, padded to a multiple of 4
+    int64_t n_words;        // words of the stream guaranteed to exist: ceil(rows * w / 32) + 2
     int32_t lut_lds_off;    // byte offset of the code table in dynamic LDS
     int32_t stage_off;      // byte offset of this column's staged words in a wave slice
     int32_t sum_slot;       // SUM accumulator of this column, or -1
@@ -98,6 +101,8 @@ struct DevPlan {
     int32_t k_rle, n_bp, n_idx, n_keys, n_aggs, n_sums;
     int32_t table_lds;      // 1: per-workgroup LDS table, added to the global one at the end
     int32_t any_rle_row;    // row mode: some key or SUM reads an RLE value per row
+    int32_t kmax;           // kernel instance: bound on RLE columns (2, 4 or 8)
+    int32_t w0;             // kernel instance: width of the fast row path's column (0: none)
     int64_t n_groups;       // product of key radices (1 when ungrouped)
     int32_t run_cap;        // staged runs per wave slice, all RLE columns together
     int32_t lds_dyn_bytes;  // dynamic LDS per workgroup
@@ -127,7 +132,7 @@ WsLayout workspace_layout(const DevPlan& p);
 // filter/align/aggregate, finalize.  `dp` is the device copy of `p`.
 hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
                         int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
-                        int grid_fused);
+                        int grid_fused, hipEvent_t ev_begin, hipEvent_t ev_end);
 
 // Device validation of one column; writes a nonzero flag on failure.
 hipError_t launch_validate_rle(const int64_t* ends, int64_t n, int64_t n_rows, int32_t* flag, hipStream_t s);
@@ -136,5 +141,8 @@ hipError_t launch_validate_idx(const void* pos, int32_t ptype, int64_t n, int64_
 
 // Persistent-grid size for the fused kernel with the plan's LDS use.
 int fused_grid_limit(const DevPlan& p, int device);
+
+// Bit widths that have a fast row-mode kernel instance.
+bool fast_row_width(int w);
 
 }  // namespace ccq
