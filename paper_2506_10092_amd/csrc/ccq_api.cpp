@@ -494,8 +494,6 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             if (P.aggs[a].kind == kAggSumRle) P.any_rle_row = 1;
     }
     const int64_t window = P.row_end - P.row_begin;
-    P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
-    P.w0 = (P.row_mode && P.n_bp == 1 && !P.any_rle_row && fast_row_width(P.bp[0].w)) ? P.bp[0].w : 0;
     if (P.row_mode) {
         // a 2048-row tile; each column keeps at least 64 staged runs
         P.span = kRowSpan;
@@ -535,6 +533,36 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         sh = align16(sh + table_bytes);
     }
     P.lds_shared_bytes = (int32_t)sh;
+    P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
+    P.w0 = 0;
+    {
+        // the fast row path: a single bit-packed column of a width with a
+        // kernel instance, no RLE value per row, the group table in LDS, the
+        // column itself the only key, and (without a code table) a range test
+        const size_t tbytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
+        bool fast = P.row_mode && P.n_bp == 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
+                    tbytes <= (size_t)kLdsTableBytes && G <= (int64_t)1 << 20;
+        BpCol& b = P.bp[0];
+        if (fast && b.key < 0 && P.n_keys > 0) fast = false;
+        if (fast && has_lut[0] && (!b.lut_u8 || b.lut_lds_off != 0)) fast = false;
+        if (fast && !has_lut[0]) {
+            if (b.pred == kPredSet) fast = false;
+            const int64_t ncode = int64_t(1) << b.w;
+            int64_t clo = 0, chi = ncode;
+            if (b.pred == kPredFalse) chi = 0;
+            if (b.pred == kPredRange) {
+                // lo <= base + code < hi, in code space, clamped to the codes that exist
+                auto clampc = [&](int64_t x) { return x < 0 ? 0 : x > ncode ? ncode : x; };
+                const bool lo_ok = !__builtin_sub_overflow(b.lo, b.base, &clo);
+                const bool hi_ok = !__builtin_sub_overflow(b.hi, b.base, &chi);
+                clo = lo_ok ? clampc(clo) : (b.lo < 0 ? 0 : ncode);
+                chi = hi_ok ? clampc(chi) : (b.hi < 0 ? 0 : ncode);
+            }
+            b.code_lo = (uint32_t)std::min<int64_t>(clo, ncode - 1);
+            b.code_span = (uint32_t)std::max<int64_t>(0, chi - clo);
+        }
+        if (fast) P.w0 = b.w;
+    }
     // wave slice: a 256-byte header (per-column staged counts, first runs and
     // next-tile cursors), then the staged runs, then row-mode buffers
     size_t wv = 256;
@@ -552,8 +580,9 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
     }
     if (P.row_mode) {
+        // point bitmaps (one per Index column); the fast path keeps the lane masks here
         P.off_pts = (int32_t)wv;
-        wv = align16(wv + 4 * 64 * (size_t)P.n_idx);
+        wv = align16(wv + 4 * 64 * (size_t)std::max(P.n_idx, 1));
         P.off_ptpre = (int32_t)wv;
         wv = align16(wv + 4 * 64 * (size_t)P.n_idx);
     }

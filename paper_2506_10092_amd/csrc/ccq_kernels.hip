@@ -154,15 +154,22 @@ __device__ __forceinline__ int lds_upper_bound(const int32_t* e, int n, int32_t 
 
 // ------------------------------------------------------------------ group table
 
+// Dynamic LDS of the fused kernel.  Everything in it is addressed as this
+// symbol plus an offset (never through a pointer that may be null), so the
+// compiler keeps LDS accesses as ds_* instructions.
+extern __shared__ __align__(16) unsigned char ccq_lds[];
+
 struct Table {
     int64_t* g;                 // global: counts[G], then one [G] array per SUM
-    unsigned long long* l;      // per-workgroup LDS copy (same layout) or nullptr
     int64_t G;
+    int32_t loff;               // byte offset of the per-workgroup LDS copy, or -1
 };
 
 __device__ __forceinline__ void table_add(const Table& t, int which, int64_t gid, int64_t v) {
-    if (t.l) atomicAdd(&t.l[which * t.G + gid], (unsigned long long)v);
-    else atomicAdd((unsigned long long*)&t.g[which * t.G + gid], (unsigned long long)v);
+    if (t.loff >= 0)
+        atomicAdd((unsigned long long*)(ccq_lds + t.loff) + (which * t.G + gid), (unsigned long long)v);
+    else
+        atomicAdd((unsigned long long*)&t.g[which * t.G + gid], (unsigned long long)v);
 }
 
 // ------------------------------------------------------------------ prepare
@@ -192,26 +199,45 @@ struct WaveLds {
     int32_t cap;        // staged runs per column; column c starts at slot c * cap
 };
 
-// Stage the runs of every RLE column that overlap [t0, *t1) into LDS, 64 per
-// coalesced batch.  A column that would exceed its share shrinks *t1 to the
-// end of its last staged run (rounded down to `align` rows), so all columns
-// cover the (possibly shorter) tile.
+// Stage the runs of every RLE column that overlap [t0, *t1) into LDS.  The
+// first 64-run batch of every column is loaded in one round trip; further
+// batches follow only for columns with more runs in the tile.  A column that
+// would exceed its share shrinks *t1 to the end of its last staged run
+// (rounded down to `align` rows), so all columns cover the (possibly
+// shorter) tile.  Also leaves in W.cur the run holding the next tile's first
+// row.
+template <int KMAX>
 __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t* t1,
                                            int64_t align) {
     const int lane = lane_id();
-    for (int c = 0; c < P.k_rle; ++c) {
+    int64_t e0[KMAX], v0[KMAX], lo[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        e0[c] = INT64_MAX;
+        v0[c] = 0;
+        lo[c] = 0;
+        if (c < P.k_rle) {
+            const RleCol& rc = P.rle[c];
+            lo[c] = W.cur[c];
+            const int64_t i = lo[c] + lane;
+            if (i < rc.n_runs) {
+                e0[c] = rc.ends[i];
+                v0[c] = ld_val(rc.vals, rc.vtype, i);
+            }
+        }
+    }
+    bool shrunk = false;
+    int64_t last_e[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        last_e[c] = 0;
+        if (c >= P.k_rle) continue;
         const RleCol& rc = P.rle[c];
-        const int64_t lo = W.cur[c];
         const int32_t off = c * W.cap;
         int32_t n = 0;
+        int64_t e = e0[c], v = v0[c];
         for (;;) {
-            const int64_t i = lo + n + lane;
-            const bool valid = i < rc.n_runs && n + lane < W.cap;
-            int64_t e = INT64_MAX, v = 0;
-            if (valid) {
-                e = rc.ends[i];
-                v = ld_val(rc.vals, rc.vtype, i);
-            }
+            const bool valid = lo[c] + n + lane < rc.n_runs && n + lane < W.cap;
             const uint64_t last = wave_ballot(valid && e >= *t1);
             const uint64_t vmask = wave_ballot(valid);
             const int cnt = last ? __builtin_ctzll(last) + 1 : __builtin_popcountll(vmask);
@@ -220,19 +246,39 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
                 W.run_end[off + n + lane] = (int32_t)(rel < (1 << 30) ? rel : (1 << 30));
                 W.run_val[off + n + lane] = v;
             }
+            last_e[c] = __shfl(e, cnt - 1, 64);
             n += cnt;
             if (last) break;
             if (n >= W.cap) {
-                const int64_t e_last = __shfl(e, cnt - 1, 64);
-                const int64_t cut = t0 + ((e_last - t0) / align) * align;
-                if (cut < *t1) *t1 = cut;
+                const int64_t cut = t0 + ((last_e[c] - t0) / align) * align;
+                if (cut < *t1) {
+                    *t1 = cut;
+                    shrunk = true;
+                }
                 break;
+            }
+            const int64_t i = lo[c] + n + lane;
+            e = INT64_MAX;
+            v = 0;
+            if (i < rc.n_runs && n + lane < W.cap) {
+                e = rc.ends[i];
+                v = ld_val(rc.vals, rc.vtype, i);
             }
         }
         if (lane == 0) {
             W.tn[c] = n;
-            W.tlo[c] = lo;
+            W.tlo[c] = lo[c];
         }
+    }
+    wave_lds_sync();
+    // the run holding row t1: the last staged run unless it ends exactly at t1
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        if (c >= P.k_rle) continue;
+        int64_t nxt;
+        if (!shrunk) nxt = lo[c] + W.tn[c] - (last_e[c] > *t1 ? 1 : 0);
+        else nxt = lo[c] + lds_upper_bound(W.run_end + c * W.cap, W.tn[c], (int32_t)(*t1 - t0));
+        if (lane == 0) W.cur[c] = nxt;
     }
     wave_lds_sync();
 }
@@ -484,13 +530,14 @@ __device__ __forceinline__ void tile_points(const DevPlan& P, const WaveLds& W, 
     }
 }
 
-// code table lookup: uint8 tables use 254 / 255 for domain / reject
-__device__ __forceinline__ uint32_t lut_get(const void* lut, int32_t u8, uint32_t code) {
+// code table lookup (table at LDS byte offset `off`): uint8 tables use
+// 254 / 255 for domain / reject
+__device__ __forceinline__ uint32_t lut_get(int32_t off, int32_t u8, uint32_t code) {
     if (u8) {
-        const uint32_t e = ((const uint8_t*)lut)[code];
+        const uint32_t e = ccq_lds[off + code];
         return e >= 254u ? e + (0xFFFFu - 255u) : e;
     }
-    return ((const uint16_t*)lut)[code];
+    return ((const uint16_t*)(ccq_lds + off))[code];
 }
 
 // bits [j*W, j*W + W) of the lane's packed words (j and W compile-time)
@@ -502,87 +549,136 @@ __device__ __forceinline__ uint32_t extract_code(const uint32_t (&wd)[W0 > 0 ? W
     return __builtin_amdgcn_alignbit(wd[q + 1], wd[q], sh) & mask;
 }
 
-// Fast row mode: exactly one bit-packed column, of width W0, read from the
-// lane's registers; no RLE value is needed per row.
-template <int KMAX, int W0>
+// Fast row mode: one bit-packed column of width W0, read from the lane's
+// registers; no RLE value per row; group table in LDS with at most one key,
+// the bit-packed column itself (so the group id is its slot).  W0 <= 14: the
+// uint8 code table sits at LDS offset 0.  Wider: a code range and
+// key = (base + code) >> shift.  A SUM of the column is accumulated over
+// codes; the flush adds base * count.
+template <int KMAX, int W0, bool SUMBP>
 __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                              int32_t lo_valid, const Table& tb, int32_t* status,
-                                              int64_t (&pcur)[kMaxIdx], const void* lut0) {
+                                              int32_t lo_valid, int32_t* status, int64_t (&pcur)[kMaxIdx]) {
     const int lane = lane_id();
     const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
-    int64_t pbase[kMaxIdx];
-    tile_points(P, W, t0, L, pcur, pbase);
-    if (wave_ballot(pm != 0) == 0) return;
-
-    // the lane's 32 rows are W0 whole words of the stream (tiles start at multiples of 32 rows)
     const BpCol& bc = P.bp[0];
-    uint32_t wd[W0];
-    const int64_t word0 = ((t0 >> 5) + lane) * (int64_t)W0;
-    if (pm && word0 + W0 > bc.n_words) {
-        // the lane's rows reach past the table end: read only the guaranteed words
+    const int32_t G = (int32_t)P.n_groups;
+    unsigned long long* tab = (unsigned long long*)(ccq_lds + P.table_lds_off);
+    const uint64_t any = wave_ballot(pm != 0);
+
+    if (any) {
+        // the lane's 32 rows are W0 whole words of the stream (tiles start at multiples of 32 rows)
+        uint32_t wd[W0];
+        const int64_t word0 = ((t0 >> 5) + lane) * (int64_t)W0;
+        if (pm && word0 + W0 > bc.n_words) {
+            // the lane's rows reach past the table end: read only the guaranteed words
 #pragma unroll
-        for (int i = 0; i < W0; ++i) wd[i] = word0 + i < bc.n_words ? bc.packed[word0 + i] : 0u;
-    } else if (pm) {
-        const uint32_t* src = bc.packed + word0;
-        if constexpr (W0 % 2 == 0) {
-            const uint2* s2 = (const uint2*)src;
+            for (int i = 0; i < W0; ++i) wd[i] = word0 + i < bc.n_words ? bc.packed[word0 + i] : 0u;
+        } else if (pm) {
+            const uint32_t* src = bc.packed + word0;
+            if constexpr (W0 % 2 == 0) {
+                const uint2* s2 = (const uint2*)src;
 #pragma unroll
-            for (int i = 0; i < W0 / 2; ++i) {
-                const uint2 v = s2[i];
-                wd[2 * i] = v.x;
-                wd[2 * i + 1] = v.y;
+                for (int i = 0; i < W0 / 2; ++i) {
+                    const uint2 v = s2[i];
+                    wd[2 * i] = v.x;
+                    wd[2 * i + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < W0; ++i) wd[i] = src[i];
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < W0; ++i) wd[i] = src[i];
+            for (int i = 0; i < W0; ++i) wd[i] = 0;
         }
-    } else {
+        const int32_t sum_off = (1 + bc.sum_slot) * G;
+        bool dom = false;
 #pragma unroll
-        for (int i = 0; i < W0; ++i) wd[i] = 0;
-    }
-    const int32_t u8 = bc.lut_u8;
-    const bool has_lut = lut0 != nullptr;
-    const bool keyed = bc.key >= 0;
-    const int32_t sum_slot = bc.sum_slot;
-#pragma unroll
-    for (int j = 0; j < kRowSpan; ++j) {
-        if (!((pm >> j) & 1u)) continue;
-        const uint32_t code = extract_code<W0>(wd, j);
-        int64_t gid = 0;
-        if (has_lut) {
-            const uint32_t e = lut_get(lut0, u8, code);
-            if (e == kLutReject) continue;
-            if (e == kLutDomain) {
-                raise_status(status, -4);
-                continue;
-            }
-            if (keyed) gid = (int64_t)e * bc.key_stride;
-        } else {
-            const int64_t v = bc.base + (int64_t)code;
-            if (!pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, v)) continue;
-            if (keyed) {
-                const int64_t kv = v >> bc.key_shift;
-                if (kv < 0 || kv >= bc.key_card) {
-                    raise_status(status, -4);
-                    continue;
-                }
-                gid = kv * bc.key_stride;
-            }
-        }
-        table_add(tb, 0, gid, 1);
-        if (sum_slot >= 0) table_add(tb, 1 + sum_slot, gid, bc.base + (int64_t)code);
-#pragma unroll
-        for (int q = 0; q < kMaxIdx; ++q) {
-            if (q < P.n_idx && P.idx[q].sum_slot >= 0) {
-                const uint32_t word = W.pts[q * 64 + lane];
-                if (word & (1u << j)) {
-                    const int64_t rank = W.ptpre[q * 64 + lane] + __builtin_popcount(word & ((1u << j) - 1u));
-                    const int64_t v = ld_val(P.idx[q].vals, P.idx[q].vtype, pbase[q] + rank);
-                    if (v != 0) table_add(tb, 1 + P.idx[q].sum_slot, gid, v);
+        for (int j = 0; j < kRowSpan; ++j) {
+            if (pm & (1u << j)) {
+                const uint32_t code = extract_code<W0>(wd, j);
+                if constexpr (W0 <= kLutMaxBits) {
+                    const uint32_t e = ccq_lds[code];
+                    if (e < 254u) {
+                        atomicAdd(&tab[e], 1ull);
+                        if constexpr (SUMBP) atomicAdd(&tab[sum_off + e], (unsigned long long)code);
+                    } else {
+                        dom = dom || e == 254u;
+                    }
+                } else {
+                    if (code - bc.code_lo < bc.code_span) {
+                        uint32_t slot = 0;
+                        bool ok = true;
+                        if (bc.key >= 0) {
+                            const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
+                            ok = kv >= 0 && kv < bc.key_card;
+                            slot = (uint32_t)kv;
+                        }
+                        if (ok) {
+                            atomicAdd(&tab[slot], 1ull);
+                            if constexpr (SUMBP) atomicAdd(&tab[sum_off + slot], (unsigned long long)code);
+                        } else {
+                            dom = true;
+                        }
+                    }
                 }
             }
         }
+        if (dom) raise_status(status, -4);
     }
+
+    // Index points: each point re-reads its row's code and adds its value
+    // when the row survives (the Plain x Index case of Section 5.1)
+    uint32_t* pmw = W.pts;
+    pmw[lane] = pm;
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < kMaxIdx; ++q) {
+        if (q >= P.n_idx) continue;
+        const IdxCol& ic = P.idx[q];
+        int64_t p0 = pcur[q];
+        for (;;) {
+            const int64_t i = p0 + lane;
+            const bool valid = i < ic.n;
+            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
+            const bool in = valid && pos < t0 + L;
+            const uint64_t m = wave_ballot(in);
+            if (in && any && ic.sum_slot >= 0) {
+                const int32_t rel = (int32_t)(pos - t0);
+                if (pmw[rel >> 5] & (1u << (rel & 31))) {
+                    const int64_t bit = pos * (int64_t)W0;
+                    const int64_t wq = bit >> 5;
+                    const uint32_t sh = (uint32_t)(bit & 31);
+                    const uint32_t lo = bc.packed[wq];
+                    const uint32_t hi = wq + 1 < bc.n_words ? bc.packed[wq + 1] : 0u;
+                    const uint32_t mask = W0 == 32 ? 0xFFFFFFFFu : ((1u << W0) - 1u);
+                    const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & mask;
+                    int64_t slot = -1;
+                    if constexpr (W0 <= kLutMaxBits) {
+                        const uint32_t e = ccq_lds[code];
+                        if (e < 254u) slot = e;
+                    } else {
+                        if (code - bc.code_lo < bc.code_span) {
+                            slot = 0;
+                            if (bc.key >= 0) {
+                                const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
+                                slot = (kv >= 0 && kv < bc.key_card) ? kv : -1;
+                            }
+                        }
+                    }
+                    if (slot >= 0) {
+                        const int64_t v = ld_val(ic.vals, ic.vtype, i);
+                        if (v != 0) atomicAdd(&tab[(int64_t)(1 + ic.sum_slot) * G + slot], (unsigned long long)v);
+                    }
+                }
+            }
+            const int c = __builtin_popcountll(m);
+            p0 += c;
+            if (c < 64) break;
+        }
+        pcur[q] = p0;
+    }
+    wave_lds_sync();
 }
 
 // Generic row mode: any number of bit-packed columns of any width, RLE values
@@ -591,7 +687,7 @@ __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W
 template <int KMAX>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
                                                  int32_t lo_valid, const Table& tb, int32_t* status,
-                                                 int64_t (&pcur)[kMaxIdx], const void* const (&luts)[kMaxBp]) {
+                                                 int64_t (&pcur)[kMaxIdx], const int32_t (&luts)[kMaxBp]) {
     const int lane = lane_id();
     const int32_t s0 = lane * kRowSpan;
     const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
@@ -655,7 +751,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
             const uint64_t mask = bc.w == 32 ? 0xFFFFFFFFull : ((1ull << bc.w) - 1ull);
             const uint32_t code = (uint32_t)((two >> sh) & mask);
             bpv[j] = bc.base + (int64_t)code;
-            if (luts[j]) {
+            if (luts[j] >= 0) {
                 const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
                 if (e == kLutReject) pass = false;
                 else if (e == kLutDomain) dom = true;
@@ -716,30 +812,30 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 template <int KMAX, int W0>
 __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
                                                      int32_t* __restrict__ status, int64_t n_waves_total) {
-    extern __shared__ __align__(16) unsigned char lds[];
     const DevPlan& P = *Pg;
 
     // shared part of dynamic LDS: the code tables, then the group table
-    const void* luts[kMaxBp];
+    int32_t luts[kMaxBp];
 #pragma unroll
     for (int j = 0; j < kMaxBp; ++j) {
-        luts[j] = nullptr;
+        luts[j] = -1;
         if (j < P.n_bp && P.bp[j].lut) {
-            uint32_t* dst = (uint32_t*)(lds + P.bp[j].lut_lds_off);
+            uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].lut_lds_off);
             const uint32_t* src = (const uint32_t*)P.bp[j].lut;
             const int n = P.bp[j].lut_bytes / 4;
             for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-            luts[j] = dst;
+            luts[j] = P.bp[j].lut_lds_off;
         }
     }
     Table tb;
     tb.g = table;
     tb.G = P.n_groups;
-    tb.l = nullptr;
+    tb.loff = -1;
     if (P.table_lds) {
-        tb.l = (unsigned long long*)(lds + P.table_lds_off);
+        tb.loff = P.table_lds_off;
+        unsigned long long* l = (unsigned long long*)(ccq_lds + P.table_lds_off);
         const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) tb.l[i] = 0;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) l[i] = 0;
     }
     __syncthreads();
 
@@ -753,7 +849,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) * P.tile_rows);
 
     WaveLds W;
-    W.base = lds + P.lds_shared_bytes + wave * P.lds_wave_bytes;
+    W.base = ccq_lds + P.lds_shared_bytes + wave * P.lds_wave_bytes;
     W.tn = (int32_t*)(W.base);            // slice header, 256 bytes (host layout reserves it)
     W.tlo = (int64_t*)(W.base + 64);
     W.cur = (int64_t*)(W.base + 128);
@@ -770,6 +866,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) acc.rsum[c] = 0;
 
+    const bool sum_bp = W0 > 0 && P.bp[0].sum_slot >= 0;
     if (w0 < w1) {
         int64_t pcur[kMaxIdx];
         for (int c = 0; c < P.k_rle; ++c) {
@@ -785,21 +882,19 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
         int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
         while (t0 < w1) {
             int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
-            stage_runs(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
+            stage_runs<KMAX>(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
             const int32_t L = (int32_t)(t1 - t0);
             const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
             if (P.row_mode) {
-                if constexpr (W0 > 0) tile_row_fast<KMAX, W0>(P, W, t0, L, lo_valid, tb, status, pcur, luts[0]);
-                else tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
+                if constexpr (W0 > 0) {
+                    if (sum_bp) tile_row_fast<KMAX, W0, true>(P, W, t0, L, lo_valid, status, pcur);
+                    else tile_row_fast<KMAX, W0, false>(P, W, t0, L, lo_valid, status, pcur);
+                } else {
+                    tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
+                }
             } else {
                 tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
             }
-            // next tile's first run per column: the first staged run ending after t1
-            for (int c = 0; c < P.k_rle; ++c) {
-                const int64_t x = W.tlo[c] + lds_upper_bound(W.run_end + c * W.cap, W.tn[c], L);
-                if (lane_id() == 0) W.cur[c] = x;
-            }
-            wave_lds_sync();
             t0 = t1;
         }
     }
@@ -807,9 +902,14 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
 
     if (P.table_lds) {
         __syncthreads();
-        const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
+        const int64_t G = P.n_groups;
+        const unsigned long long* l = (const unsigned long long*)(ccq_lds + P.table_lds_off);
+        const int64_t n = (int64_t)(1 + P.n_sums) * G;
+        const int64_t bp_lo = sum_bp ? (int64_t)(1 + P.bp[0].sum_slot) * G : -1;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const unsigned long long v = tb.l[i];
+            unsigned long long v = l[i];
+            if (i >= bp_lo && i < bp_lo + G && bp_lo >= 0)   // code-space sum -> value sum
+                v += (unsigned long long)P.bp[0].base * l[i - bp_lo];
             if (v) atomicAdd((unsigned long long*)&table[i], v);
         }
     }

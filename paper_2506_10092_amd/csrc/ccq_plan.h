@@ -60,6 +60,7 @@ struct BpCol {
     int32_t lut_lds_off;    // byte offset of the code table in dynamic LDS
     int32_t stage_off;      // byte offset of this column's staged words in a wave slice
     int32_t sum_slot;       // SUM accumulator of this column, or -1
+    uint32_t code_lo, code_span;   // fast path without code table: codes in [code_lo, code_lo + code_span) pass
     int32_t key_shift;      // key = value >> key_shift when key >= 0 and no code table
     int64_t key_card;
     int64_t key_stride;
