@@ -94,6 +94,26 @@ def traffic_from_profile(workload_name):
     return d.get("hbm_bytes_per_launch")
 
 
+def copy_reference(args):
+    """A plain device-to-device copy of known size, timed like a step."""
+    import torch
+    n = args.copy_bytes // 4
+    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record()
+    for _ in range(args.steps):
+        y.copy_(x)
+    e.record()
+    torch.cuda.synchronize()
+    ms = b.elapsed_time(e) / args.steps
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": ms,
+                      "GBps_read_plus_write": 2 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +124,9 @@ def main():
     ap.add_argument("--cpu-sample-rows", type=int, default=1_000_000_000,
                     help="rows of the window the CPU oracle runs over (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the query, time a plain device copy of this many bytes (the "
+                         "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -116,6 +139,10 @@ def main():
     import numpy as np
     import torch
     from paper_2506_10092_amd import ccq
+
+    if args.copy_bytes:
+        copy_reference(args)
+        return
 
     t_gen = time.time()
     wl = make_workload(args.config, args.rows)

@@ -403,7 +403,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         if (P.keys[k].src_kind == kKeyRle) P.rle[P.keys[k].src].key_stride = P.keys[k].stride;
 
     // bit-packed columns: predicates and key slots folded into one code table
-    std::vector<bool> has_lut(P.n_bp, false);
+    // per column (built here, encoded once the kernel path is known)
+    std::vector<std::vector<uint16_t>> lut16(P.n_bp);
     for (int s = 0; s < P.n_bp; ++s) {
         const ccq_column_desc& c = t->cols[bp_cols[s]];
         const Fold& f = fold[bp_cols[s]];
@@ -422,33 +423,19 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         b.n_words = (t->n_rows * (int64_t)c.bit_width + 31) / 32 + 2;
         if (c.bit_width <= kLutMaxBits && (has_pred || b.key >= 0)) {
             const int64_t n = int64_t(1) << c.bit_width;
-            std::vector<uint16_t> lut(n);
+            std::vector<uint16_t>& lut = lut16[s];
+            lut.assign(n, kLutReject);
             std::map<int64_t, int64_t> rank;
             if (b.key >= 0)
                 for (size_t i = 0; i < slot_keys[b.key].size(); ++i) rank[slot_keys[b.key][i]] = (int64_t)i;
             for (int64_t code = 0; code < n; ++code) {
                 const int64_t v = c.base + code;
-                if (!fold_pass(f, v)) { lut[code] = kLutReject; continue; }
+                if (!fold_pass(f, v)) continue;
                 if (b.key < 0) { lut[code] = 0; continue; }
                 const KeyDesc& kd = P.keys[b.key];
                 const int64_t kv = v >> kd.shift;
                 lut[code] = (kv < 0 || kv >= kd.card) ? kLutDomain : (uint16_t)rank[kv];
             }
-            // one byte per code when every slot fits below the two marker values
-            const bool u8 = b.key < 0 || P.keys[b.key].radix <= 254;
-            b.lut_u8 = u8 ? 1 : 0;
-            if (u8) {
-                std::vector<uint8_t> l8((n + 3) & ~int64_t(3), 255);
-                for (int64_t code = 0; code < n; ++code)
-                    l8[code] = lut[code] == kLutReject ? 255 : lut[code] == kLutDomain ? 254 : (uint8_t)lut[code];
-                b.lut_bytes = (int32_t)l8.size();
-                fix_ptr(&b.lut, blob_put(l8.data(), l8.size()));
-            } else {
-                if (n % 2) lut.push_back(kLutReject);
-                b.lut_bytes = (int32_t)(lut.size() * 2);
-                fix_ptr(&b.lut, blob_put(lut.data(), lut.size() * 2));
-            }
-            has_lut[s] = true;
         } else {
             if (f.is_false) b.pred = kPredFalse;
             else if (f.has_set) {
@@ -518,34 +505,22 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     // nominal tiles: multiples of tile_rows in absolute row numbers that meet the window
     P.n_tiles = window > 0 ? (P.row_end - 1) / P.tile_rows - P.row_begin / P.tile_rows + 1 : 0;
 
-    // LDS layout: shared part (code tables, group table) then kWaves slices
-    size_t sh = 0;
-    for (int s = 0; s < P.n_bp; ++s) {
-        if (has_lut[s]) {
-            P.bp[s].lut_lds_off = (int32_t)sh;
-            sh = align16(sh + (size_t)P.bp[s].lut_bytes);
-        }
-    }
-    const size_t table_bytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
-    P.table_lds = table_bytes <= (size_t)kLdsTableBytes ? 1 : 0;
-    if (P.table_lds) {
-        P.table_lds_off = (int32_t)sh;
-        sh = align16(sh + table_bytes);
-    }
-    P.lds_shared_bytes = (int32_t)sh;
+    // kernel path.  The fast row path: a single bit-packed column of a width
+    // with a kernel instance, no RLE value per row, the column itself the only
+    // key (or no key), a code table or a plain range test, and uint32 counts
+    // that cannot overflow within one workgroup.
     P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
     P.w0 = 0;
     {
-        // the fast row path: a single bit-packed column of a width with a
-        // kernel instance, no RLE value per row, the group table in LDS, the
-        // column itself the only key, and (without a code table) a range test
-        const size_t tbytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
         bool fast = P.row_mode && P.n_bp == 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
-                    tbytes <= (size_t)kLdsTableBytes && G <= (int64_t)1 << 20;
+                    (G + 2) * 8 <= kFastCntWords;
         BpCol& b = P.bp[0];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
-        if (fast && has_lut[0] && (!b.lut_u8 || b.lut_lds_off != 0)) fast = false;
-        if (fast && !has_lut[0]) {
+        // workgroups: at least min(tiles / 4, one per CU); rows per workgroup bounded by that
+        const int64_t min_blocks = std::max<int64_t>(1, std::min<int64_t>((P.n_tiles + 3) / 4, t->ctx->cus));
+        const int64_t rows_per_wg = ((P.n_tiles + 4 * min_blocks - 1) / (4 * min_blocks)) * 4 * P.tile_rows;
+        if (fast && rows_per_wg >= (int64_t)1 << 31) fast = false;
+        if (fast && lut16[0].empty()) {
             if (b.pred == kPredSet) fast = false;
             const int64_t ncode = int64_t(1) << b.w;
             int64_t clo = 0, chi = ncode;
@@ -563,6 +538,76 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
         if (fast) P.w0 = b.w;
     }
+
+    // code tables.  Fast path: one byte per code holding the slot, G for a key
+    // out of its domain, G + 1 for rejected codes, plus a reject entry at
+    // index 2^w for rows the RLE predicates removed.  Otherwise uint8 (254 =
+    // domain, 255 = reject) when the slots fit, else uint16.
+    std::vector<bool> has_lut(P.n_bp, false);
+    for (int s = 0; s < P.n_bp; ++s) {
+        if (lut16[s].empty()) continue;
+        BpCol& b = P.bp[s];
+        const std::vector<uint16_t>& lut = lut16[s];
+        const int64_t n = (int64_t)lut.size();
+        has_lut[s] = true;
+        if (P.w0 && s == 0) {
+            std::vector<uint8_t> l8((n + 4 + 3) & ~int64_t(3), (uint8_t)(G + 1));
+            for (int64_t code = 0; code < n; ++code)
+                l8[code] = lut[code] == kLutReject ? (uint8_t)(G + 1) : lut[code] == kLutDomain ? (uint8_t)G
+                                                                                           : (uint8_t)lut[code];
+            b.lut_u8 = 1;
+            b.lut_bytes = (int32_t)l8.size();
+            fix_ptr(&b.lut, blob_put(l8.data(), l8.size()));
+            continue;
+        }
+        const bool u8 = b.key < 0 || P.keys[b.key].radix <= 254;
+        b.lut_u8 = u8 ? 1 : 0;
+        if (u8) {
+            std::vector<uint8_t> l8((n + 3) & ~int64_t(3), 255);
+            for (int64_t code = 0; code < n; ++code)
+                l8[code] = lut[code] == kLutReject ? 255 : lut[code] == kLutDomain ? 254 : (uint8_t)lut[code];
+            b.lut_bytes = (int32_t)l8.size();
+            fix_ptr(&b.lut, blob_put(l8.data(), l8.size()));
+        } else {
+            std::vector<uint16_t> l16 = lut;
+            if (l16.size() % 2) l16.push_back(kLutReject);
+            b.lut_bytes = (int32_t)(l16.size() * 2);
+            fix_ptr(&b.lut, blob_put(l16.data(), l16.size() * 2));
+        }
+    }
+
+    // LDS layout: shared part (code tables, then the group tables) then kWaves slices
+    size_t sh = 0;
+    for (int s = 0; s < P.n_bp; ++s) {
+        if (has_lut[s] && !P.w0) {       // the fast path keeps its table in static LDS
+            P.bp[s].lut_lds_off = (int32_t)sh;
+            sh = align16(sh + (size_t)P.bp[s].lut_bytes);
+        }
+    }
+    if (P.w0) {
+        // lane-replicated uint32 counts in static LDS: 32 replicas (a wave64 LDS
+        // operation runs as two halves of 32 lanes, so no two lanes of a half
+        // share an address), fewer when the slots do not fit
+        const bool sum_bp = P.bp[0].sum_slot >= 0;
+        int rs = 5;
+        while (rs > 3 && ((G + 2) << rs) > kFastCntWords) --rs;
+        P.fast_rep_shift = rs;
+        P.fast_sum_off = (int32_t)sh;
+        if (sum_bp) sh = align16(sh + ((size_t)G * 8 << rs));
+        P.fast_isum_off = (int32_t)sh;
+        sh = align16(sh + (size_t)P.n_idx * G * 8);
+        P.fast_bytes = (int32_t)(sh - P.fast_sum_off);
+        P.table_lds = 0;
+    } else {
+        const size_t table_bytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
+        P.table_lds = table_bytes <= (size_t)kLdsTableBytes ? 1 : 0;
+        if (P.table_lds) {
+            P.table_lds_off = (int32_t)sh;
+            sh = align16(sh + table_bytes);
+        }
+    }
+    P.lds_shared_bytes = (int32_t)sh;
+
     // wave slice: a 256-byte header (per-column staged counts, first runs and
     // next-tile cursors), then the staged runs, then row-mode buffers
     size_t wv = 256;

@@ -550,19 +550,28 @@ __device__ __forceinline__ uint32_t extract_code(const uint32_t (&wd)[W0 > 0 ? W
 }
 
 // Fast row mode: one bit-packed column of width W0, read from the lane's
-// registers; no RLE value per row; group table in LDS with at most one key,
-// the bit-packed column itself (so the group id is its slot).  W0 <= 14: the
-// uint8 code table sits at LDS offset 0.  Wider: a code range and
-// key = (base + code) >> shift.  A SUM of the column is accumulated over
-// codes; the flush adds base * count.
+// registers; no RLE value per row; at most one key, the bit-packed column
+// itself, so a row's group is its slot.  Counts go to a lane-replicated LDS
+// table (slot-major, P.fast_rep replicas, uint32): the lanes of a wave never
+// hit the same address, whatever the skew of the codes.  Slot G counts rows
+// whose key is out of its domain, slot G + 1 rejected rows.  The loop is
+// branch free: each batch of 16 rows first does all its code-table reads,
+// then all its table adds.  W0 <= 14: the uint8 code table sits at LDS
+// offset 0 with the reject entry at index 2^W0.  Wider columns test a code
+// range; key = (base + code) >> shift.  A SUM of the column is accumulated
+// over codes (uint64, same replicas); the flush adds base * count.
 template <int KMAX, int W0, bool SUMBP>
 __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                              int32_t lo_valid, int32_t* status, int64_t (&pcur)[kMaxIdx]) {
+                                              int32_t lo_valid, int64_t (&pcur)[kMaxIdx], const uint8_t* lut,
+                                              uint32_t* cnt) {
     const int lane = lane_id();
     const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
     const BpCol& bc = P.bp[0];
-    const int32_t G = (int32_t)P.n_groups;
-    unsigned long long* tab = (unsigned long long*)(ccq_lds + P.table_lds_off);
+    const uint32_t G = (uint32_t)P.n_groups;
+    const uint32_t rep_sh = (uint32_t)P.fast_rep_shift;             // log2 replicas
+    const uint32_t lane_part = (uint32_t)(lane & ((1 << rep_sh) - 1));
+    const uint32_t lane_bytes = lane_part * 4u, sh_bytes = rep_sh + 2u;
+    unsigned long long* csum = (unsigned long long*)(ccq_lds + P.fast_sum_off);
     const uint64_t any = wave_ballot(pm != 0);
 
     if (any) {
@@ -591,40 +600,36 @@ __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W
 #pragma unroll
             for (int i = 0; i < W0; ++i) wd[i] = 0;
         }
-        const int32_t sum_off = (1 + bc.sum_slot) * G;
-        bool dom = false;
+        const uint32_t reject = G + 1;
 #pragma unroll
-        for (int j = 0; j < kRowSpan; ++j) {
-            if (pm & (1u << j)) {
-                const uint32_t code = extract_code<W0>(wd, j);
+        for (int h = 0; h < kRowSpan; h += 16) {
+            uint32_t slot[16];
+            uint32_t code[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t c = extract_code<W0>(wd, h + j);
+                const bool keep = (pm >> (h + j)) & 1u;
+                code[j] = c;
                 if constexpr (W0 <= kLutMaxBits) {
-                    const uint32_t e = ccq_lds[code];
-                    if (e < 254u) {
-                        atomicAdd(&tab[e], 1ull);
-                        if constexpr (SUMBP) atomicAdd(&tab[sum_off + e], (unsigned long long)code);
-                    } else {
-                        dom = dom || e == 254u;
-                    }
+                    slot[j] = lut[keep ? c : (1u << W0)];
                 } else {
-                    if (code - bc.code_lo < bc.code_span) {
-                        uint32_t slot = 0;
-                        bool ok = true;
-                        if (bc.key >= 0) {
-                            const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
-                            ok = kv >= 0 && kv < bc.key_card;
-                            slot = (uint32_t)kv;
-                        }
-                        if (ok) {
-                            atomicAdd(&tab[slot], 1ull);
-                            if constexpr (SUMBP) atomicAdd(&tab[sum_off + slot], (unsigned long long)code);
-                        } else {
-                            dom = true;
-                        }
+                    uint32_t s = (c - bc.code_lo < bc.code_span) ? 0u : reject;
+                    if (bc.key >= 0 && s == 0u) {
+                        const int64_t kv = (bc.base + (int64_t)c) >> bc.key_shift;
+                        s = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
                     }
+                    slot[j] = keep ? s : reject;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                // byte address in the count table: one shift-add per row
+                atomicAdd((uint32_t*)((unsigned char*)cnt + ((slot[j] << sh_bytes) + lane_bytes)), 1u);
+                if constexpr (SUMBP) {
+                    if (slot[j] < G) atomicAdd(&csum[(slot[j] << rep_sh) + lane_part], (unsigned long long)code[j]);
                 }
             }
         }
-        if (dom) raise_status(status, -4);
     }
 
     // Index points: each point re-reads its row's code and adds its value
@@ -636,6 +641,7 @@ __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W
     for (int q = 0; q < kMaxIdx; ++q) {
         if (q >= P.n_idx) continue;
         const IdxCol& ic = P.idx[q];
+        unsigned long long* isum = (unsigned long long*)(ccq_lds + P.fast_isum_off) + (int64_t)q * G;
         int64_t p0 = pcur[q];
         for (;;) {
             const int64_t i = p0 + lane;
@@ -653,22 +659,19 @@ __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W
                     const uint32_t hi = wq + 1 < bc.n_words ? bc.packed[wq + 1] : 0u;
                     const uint32_t mask = W0 == 32 ? 0xFFFFFFFFu : ((1u << W0) - 1u);
                     const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & mask;
-                    int64_t slot = -1;
+                    uint32_t slot;
                     if constexpr (W0 <= kLutMaxBits) {
-                        const uint32_t e = ccq_lds[code];
-                        if (e < 254u) slot = e;
+                        slot = lut[code];
                     } else {
-                        if (code - bc.code_lo < bc.code_span) {
-                            slot = 0;
-                            if (bc.key >= 0) {
-                                const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
-                                slot = (kv >= 0 && kv < bc.key_card) ? kv : -1;
-                            }
+                        slot = (code - bc.code_lo < bc.code_span) ? 0u : G + 1;
+                        if (bc.key >= 0 && slot == 0u) {
+                            const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
+                            slot = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
                         }
                     }
-                    if (slot >= 0) {
+                    if (slot < G) {
                         const int64_t v = ld_val(ic.vals, ic.vtype, i);
-                        if (v != 0) atomicAdd(&tab[(int64_t)(1 + ic.sum_slot) * G + slot], (unsigned long long)v);
+                        if (v != 0) atomicAdd(&isum[slot], (unsigned long long)v);
                     }
                 }
             }
@@ -679,6 +682,38 @@ __device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W
         pcur[q] = p0;
     }
     wave_lds_sync();
+}
+
+// Flush of the fast path's LDS tables into the global group table: add up
+// the replicas of each slot; the code-space SUM gets base * count; the
+// out-of-domain slot raises the status.
+__device__ __forceinline__ void fast_flush(const DevPlan& P, int64_t* table, int32_t* status, bool sum_bp,
+                                           const uint32_t* cnt) {
+    const int64_t G = P.n_groups;
+    const int R = 1 << P.fast_rep_shift;
+    const unsigned long long* csum = (const unsigned long long*)(ccq_lds + P.fast_sum_off);
+    const unsigned long long* isum = (const unsigned long long*)(ccq_lds + P.fast_isum_off);
+    for (int64_t g = threadIdx.x; g <= G; g += blockDim.x) {
+        unsigned long long c = 0, s = 0;
+        for (int r = 0; r < R; ++r) {
+            c += cnt[g * R + r];
+            if (sum_bp && g < G) s += csum[g * R + r];
+        }
+        if (g == G) {
+            if (c) raise_status(status, -4);
+            continue;
+        }
+        if (c) atomicAdd((unsigned long long*)&table[g], c);
+        if (sum_bp) {
+            const unsigned long long v = s + (unsigned long long)P.bp[0].base * c;
+            if (v) atomicAdd((unsigned long long*)&table[(int64_t)(1 + P.bp[0].sum_slot) * G + g], v);
+        }
+        for (int q = 0; q < P.n_idx; ++q) {
+            const unsigned long long v = isum[q * G + g];
+            if (v && P.idx[q].sum_slot >= 0)
+                atomicAdd((unsigned long long*)&table[(int64_t)(1 + P.idx[q].sum_slot) * G + g], v);
+        }
+    }
 }
 
 // Generic row mode: any number of bit-packed columns of any width, RLE values
@@ -813,13 +848,25 @@ template <int KMAX, int W0>
 __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
                                                      int32_t* __restrict__ status, int64_t n_waves_total) {
     const DevPlan& P = *Pg;
+    // fast row path: code table and lane-replicated counts in static LDS, so
+    // their addresses fold into the ds_* offsets
+    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits) ? (1 << W0) + 16 : 16];
+    __shared__ uint32_t s_cnt[W0 > 0 ? kFastCntWords : 4];
 
     // shared part of dynamic LDS: the code tables, then the group table
     int32_t luts[kMaxBp];
+    if constexpr (W0 > 0 && W0 <= kLutMaxBits) {
+        const uint32_t* src = (const uint32_t*)P.bp[0].lut;
+        uint32_t* dst = (uint32_t*)s_lut;
+        for (int i = threadIdx.x; i < P.bp[0].lut_bytes / 4; i += blockDim.x) dst[i] = src[i];
+    }
+    if constexpr (W0 > 0) {
+        for (int i = threadIdx.x; i < kFastCntWords; i += blockDim.x) s_cnt[i] = 0;
+    }
 #pragma unroll
     for (int j = 0; j < kMaxBp; ++j) {
         luts[j] = -1;
-        if (j < P.n_bp && P.bp[j].lut) {
+        if (W0 == 0 && j < P.n_bp && P.bp[j].lut) {
             uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].lut_lds_off);
             const uint32_t* src = (const uint32_t*)P.bp[j].lut;
             const int n = P.bp[j].lut_bytes / 4;
@@ -836,6 +883,10 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
         unsigned long long* l = (unsigned long long*)(ccq_lds + P.table_lds_off);
         const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) l[i] = 0;
+    }
+    if (W0 > 0) {
+        uint32_t* z = (uint32_t*)(ccq_lds + P.fast_sum_off);
+        for (int i = threadIdx.x; i < P.fast_bytes / 4; i += blockDim.x) z[i] = 0;
     }
     __syncthreads();
 
@@ -887,8 +938,8 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
             const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
             if (P.row_mode) {
                 if constexpr (W0 > 0) {
-                    if (sum_bp) tile_row_fast<KMAX, W0, true>(P, W, t0, L, lo_valid, status, pcur);
-                    else tile_row_fast<KMAX, W0, false>(P, W, t0, L, lo_valid, status, pcur);
+                    if (sum_bp) tile_row_fast<KMAX, W0, true>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
+                    else tile_row_fast<KMAX, W0, false>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
                 } else {
                     tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
                 }
@@ -900,16 +951,15 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     }
     regacc_flush<KMAX>(P, tb, acc);
 
-    if (P.table_lds) {
+    if (W0 > 0) {
         __syncthreads();
-        const int64_t G = P.n_groups;
+        fast_flush(P, table, status, sum_bp, s_cnt);
+    } else if (P.table_lds) {
+        __syncthreads();
         const unsigned long long* l = (const unsigned long long*)(ccq_lds + P.table_lds_off);
-        const int64_t n = (int64_t)(1 + P.n_sums) * G;
-        const int64_t bp_lo = sum_bp ? (int64_t)(1 + P.bp[0].sum_slot) * G : -1;
+        const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            unsigned long long v = l[i];
-            if (i >= bp_lo && i < bp_lo + G && bp_lo >= 0)   // code-space sum -> value sum
-                v += (unsigned long long)P.bp[0].base * l[i - bp_lo];
+            const unsigned long long v = l[i];
             if (v) atomicAdd((unsigned long long*)&table[i], v);
         }
     }

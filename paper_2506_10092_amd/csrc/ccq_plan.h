@@ -19,6 +19,7 @@ constexpr int kMaxAggs = 8;
 constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
 constexpr int64_t kMaxGroups = int64_t(1) << 27;
 constexpr int kLdsTableBytes = 16384;  // group tables up to this size live in LDS
+constexpr int kFastCntWords = 2048;    // fast row path: static LDS counts, (G + 2) * replicas
 
 enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3 };
 enum AggKind : int32_t { kAggCount = 0, kAggSumRle = 1, kAggSumBp = 2, kAggSumIdx = 3 };
@@ -111,6 +112,9 @@ struct DevPlan {
     int32_t lds_wave_bytes;     // one wave slice
     int32_t table_lds_off;  // byte offset of the LDS group table
     int32_t off_run_end, off_run_val, off_rows, off_pts, off_ptpre;   // inside a wave slice
+    // fast row path: uint32 counts [(G + 2) << rep_shift] in static LDS; in
+    // dynamic LDS uint64 code sums [G << rep_shift] and Index sums [n_idx * G]
+    int32_t fast_rep_shift, fast_sum_off, fast_isum_off, fast_bytes;
     RleCol rle[kMaxRle];
     BpCol bp[kMaxBp];
     IdxCol idx[kMaxIdx];
