@@ -78,6 +78,8 @@ def make_workload(name, rows):
         return datagen.config_c2(n_rows=rows or 1_000_000_000)
     if name == "c3":
         return datagen.config_c3(n_rows=rows or 10_000_000_000)
+    if name == "c4":
+        return datagen.config_c4(n_rows=rows or 100_000_000)
     raise SystemExit("unknown --config %s" % name)
 
 
@@ -114,12 +116,96 @@ def copy_reference(args):
                       "GBps_read_plus_write": 2 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def bench_batch(args):
+    """Many queries in one batched launch sequence (autotuned work items,
+    replayed as a hipGraph) against the single-launch path (one ccq_execute
+    per query), over one resident table."""
+    import torch
+    import datagen
+    from paper_2506_10092_amd import ccq
+
+    n_rows = args.rows or 100_000_000
+    t_gen = time.time()
+    t = datagen.config_c2(seed=4, n_rows=n_rows, columns=("r0", "r1", "r2", "s", "d", "p"))
+    qs = datagen.c4_queries(4, n_rows, n_queries=args.queries)
+    log("generated table + %d queries in %.1fs" % (len(qs), time.time() - t_gen))
+    ctx = ccq.Context(0)
+    table = ccq.Table(ctx, n_rows, ccq.to_device(t["columns"]))
+    plans = [ccq.Plan(table, q) for q in qs]
+    log("plans created")
+    rows = sum(q["window"][1] - q["window"][0] for q in qs)
+    alg = sum(algorithmic_bytes(t, q) for q in qs)
+    stream = torch.cuda.Stream()
+
+    # single-launch path: one ccq_execute per query, each with its own buffers
+    wss = [p.new_workspace() for p in plans]
+    res = [p.new_result() for p in plans]
+    with torch.cuda.stream(stream):
+        for p, w, r in zip(plans, wss, res):
+            p.execute(w, r, stream)
+    stream.synchronize()
+    b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        b0.record(stream)
+        for p, w, r in zip(plans, wss, res):
+            p.execute(w, r, stream)
+        b1.record(stream)
+    stream.synchronize()
+    single_ms = b0.elapsed_time(b1)
+    single = [r.to_python() for r in res]
+    log("single-launch path %.3f ms" % single_ms)
+
+    batch = ccq.Batch(ctx, plans, use_graph=True)
+    ws = batch.new_workspace()
+    best, tuned_ms = batch.autotune(ws, candidates=(8, 32, 128, 512), reps=3, stream=stream)
+    log("autotuned tiles_per_item=%d (%.3f ms)" % (best, tuned_ms))
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            batch.execute(ws, stream)
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(args.steps):
+            batch.execute(ws, stream)
+        e1.record(stream)
+    stream.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    if batch.to_python() != single:
+        raise SystemExit("batched results differ from the single-launch path")
+    log("batch %.3f ms per batch of %d queries; results equal the single-launch path" % (ms, len(qs)))
+    out = {
+        "metric": METRIC,
+        "value": rows / (ms * 1e-3),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "c4_batch_%d_over_%g" % (len(qs), n_rows), "rows": rows,
+                   "compressed_bytes": alg, "tiles_per_item": best, "graph": True},
+        "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole batch (clear + persistent launches + finalize)", "kernel_ms": ms},
+        "single_launch": {"ms": single_ms, "rows_per_s": rows / (single_ms * 1e-3),
+                          "speedup_of_batch": single_ms / ms},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--queries", type=int, default=4096, help="c4: queries per batch")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
     ap.add_argument("--cpu-sample-rows", type=int, default=1_000_000_000,
                     help="rows of the window the CPU oracle runs over (bounded sample)")
@@ -142,6 +228,10 @@ def main():
 
     if args.copy_bytes:
         copy_reference(args)
+        return
+
+    if args.config == "c4":
+        bench_batch(args)
         return
 
     t_gen = time.time()

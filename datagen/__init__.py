@@ -207,3 +207,55 @@ def config_c3(seed=3, n_rows=10_000_000_000):
     q = {"preds": [], "keys": [("k%d" % i, 0, c) for i, c in enumerate(cards)],
          "aggs": [("sum", "m"), ("count",)], "window": (0, n_rows)}
     return {"name": "c3_multi_rle_%g" % n_rows, "n_rows": n_rows, "columns": cols, "query": q}
+
+
+def c4_queries(seed, n_rows, n_queries=4096, lo_rows=10_000, hi_rows=100_000_000):
+    """Query templates over a table with config_c2's columns (r0, r1, r2, s,
+    d, p): window length log-uniform in [lo_rows, hi_rows] (clipped to the
+    table) at a uniform offset; 1-3 predicates drawn from {range on r0, r1,
+    r2; IN on d with 1-50 codes; range on p}; 1-2 aggregates from {COUNT(*),
+    SUM(s), SUM(r2), SUM(p)}; GROUP BY none, d, or r_j >> shift (1 to 10k
+    groups)."""
+    rng = np.random.default_rng([int(seed), 4444])
+    pmf = zipf_pmf(1.1, 10000)
+    out = []
+    for _ in range(n_queries):
+        n = int(round(10 ** rng.uniform(np.log10(lo_rows), np.log10(hi_rows))))
+        n = max(1, min(n, n_rows))
+        off = int(rng.integers(0, n_rows - n + 1))
+        kinds = rng.choice(5, size=int(rng.integers(1, 4)), replace=False)
+        preds = []
+        for k in kinds:
+            if k < 3:
+                lo = int(rng.integers(0, 1 << 16))
+                hi = lo + int(rng.integers(1 << 13, 1 << 16))
+                preds.append(("r%d" % k, "range", lo, hi))
+            elif k == 3:
+                m = int(rng.integers(1, 51))
+                codes = rng.choice(10000, size=m, replace=False, p=pmf)
+                preds.append(("d", "in", sorted(int(c) for c in codes)))
+            else:
+                lo = int(rng.integers(-(1 << 19), 1 << 19))
+                preds.append(("p", "range", lo, lo + int(rng.integers(1 << 16, 1 << 20))))
+        aggs = [("count",), ("sum", "s"), ("sum", "r2"), ("sum", "p")]
+        pick = rng.choice(4, size=int(rng.integers(1, 3)), replace=False)
+        aggs = [aggs[i] for i in sorted(pick)]
+        g = int(rng.integers(0, 3))
+        if g == 0:
+            keys = []
+        elif g == 1:
+            keys = [("d", 0, 10000)]
+        else:
+            shift = int(rng.integers(3, 17))
+            keys = [("r%d" % int(rng.integers(0, 3)), shift, 1 << (16 - shift))]
+        out.append({"preds": preds, "keys": keys, "aggs": aggs, "window": (off, off + n)})
+    return out
+
+
+def config_c4(seed=4, n_rows=100_000_000, n_queries=4096):
+    """A table with config_c2's column mix over n_rows rows and n_queries
+    query templates (see c4_queries)."""
+    t = config_c2(seed=seed, n_rows=n_rows, columns=("r0", "r1", "r2", "s", "d", "p"))
+    t["name"] = "c4_batch_%d_over_%g" % (n_queries, n_rows)
+    t["queries"] = c4_queries(seed, n_rows, n_queries)
+    return t

@@ -201,6 +201,89 @@ typedef struct {
 ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
                           const ccq_result* result, const ccq_exec_opts* opts);
 
+/* ---- batched execution: many queries, one launch sequence ----
+ *
+ * A batch runs n compiled plans (over any tables of one device) together:
+ * one clear, one persistent launch per kernel variant in which workgroups
+ * take (query, range of tiles) work items from a device counter, and one
+ * finalize for all queries.  Each query's answer is exactly what
+ * ccq_execute gives for its plan.  Result buffers are fixed at creation;
+ * the workspace is passed per execution (ccq_batch_info gives its size). */
+typedef struct ccq_batch ccq_batch;
+
+typedef struct {
+    int32_t tiles_per_item;    /* tiles per work item (0: default 64); a tuning knob, no effect on results */
+    int32_t use_graph;         /* 1: capture the launch sequence as a hipGraph on the first execution with a
+                                  given (workspace, stream) and replay it afterwards (needs a non-NULL stream) */
+} ccq_batch_opts;
+
+ccq_status ccq_batch_create(ccq_context* ctx, const ccq_plan* const* plans, int32_t n, const ccq_result* results,
+                            const ccq_batch_opts* opts, ccq_batch** out);
+void ccq_batch_destroy(ccq_batch* b);                    /* NULL-safe */
+
+/* Workspace bytes the batch needs and the number of work items. */
+ccq_status ccq_batch_info(const ccq_batch* b, size_t* workspace_bytes, int64_t* n_items);
+
+/* Change the work-item size (rebuilds the item lists; drops a captured graph). */
+ccq_status ccq_batch_set_tiles_per_item(ccq_batch* b, int32_t tiles_per_item);
+
+/* Run every query of the batch on `stream`; asynchronous like ccq_execute. */
+ccq_status ccq_batch_execute(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Time each candidate work-item size (reps executions each, after one warm-up;
+ * synchronises `stream`), keep the fastest by median, report it and its time. */
+ccq_status ccq_batch_autotune(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream,
+                              const int32_t* candidates, int32_t n_candidates, int32_t reps, int32_t* best,
+                              float* best_ms);
+
+/* ---- serving: continuous batching under an HBM budget ----
+ *
+ * A server owns a device arena of hbm_budget_bytes (allocated once, at
+ * creation) from which every admitted query gets its workspace, and a
+ * dispatcher thread.  ccq_server_submit may be called from any host thread;
+ * queries are admitted in arrival order while their workspace fits the
+ * arena and fewer than max_inflight are admitted or running.  Whenever one of
+ * the n_streams launch streams is idle, the dispatcher launches everything
+ * admitted so far on it -- as one batch (batching = 1, as ccq_batch_execute)
+ * or as one ccq_execute per query (batching = 0) -- so queries that arrive
+ * while others run join the next launch and overlap with them on the device.
+ * Each query's answer is exactly what ccq_execute gives.  A query whose
+ * workspace alone exceeds the arena completes with CCQ_E_BUDGET.  The plan
+ * and the result buffers of a submitted query must stay alive until its
+ * completion has been polled. */
+typedef struct ccq_server ccq_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;  /* device arena for workspaces and launch descriptors */
+    int32_t max_inflight;      /* queries admitted or running at once (slots) */
+    int32_t max_batch;         /* queries per launch (0: max_inflight) */
+    int32_t n_streams;         /* launch streams (0: 2) */
+    int32_t batching;          /* 1: one batched launch per dispatch; 0: one ccq_execute per query */
+    int32_t tiles_per_item;    /* batch work-item size (0: 64) */
+    int32_t pad_;
+} ccq_server_config;
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;            /* CCQ_OK, CCQ_E_BUDGET, or CCQ_E_HIP */
+    int32_t pad_;
+    double t_submit;           /* host steady clock, seconds (ccq_now) */
+    double t_start;            /* when its launch was enqueued */
+    double t_done;             /* when the dispatcher saw its launch finish */
+} ccq_completion;
+
+/* Host steady clock in seconds (the clock of ccq_completion). */
+double ccq_now(void);
+
+ccq_status ccq_server_create(ccq_context* ctx, const ccq_server_config* cfg, ccq_server** out);
+ccq_status ccq_server_submit(ccq_server* s, const ccq_plan* p, const ccq_result* r, uint64_t* ticket);
+/* Move up to max completions into out (oldest first); *n = how many. */
+ccq_status ccq_server_poll(ccq_server* s, ccq_completion* out, int32_t max, int32_t* n);
+/* Wait until every submitted query has completed (CCQ_E_BUSY on timeout). */
+ccq_status ccq_server_drain(ccq_server* s, double timeout_s);
+/* Finishes outstanding queries, then stops the dispatcher and frees the arena. */
+void ccq_server_destroy(ccq_server* s);
+
 #ifdef __cplusplus
 }
 #endif

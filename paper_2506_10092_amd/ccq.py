@@ -75,6 +75,21 @@ class ExecOpts(ctypes.Structure):
     _fields_ = [("fused_begin", ctypes.c_void_p), ("fused_end", ctypes.c_void_p)]
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("tiles_per_item", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("batching", ctypes.c_int32),
+                ("tiles_per_item", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class ResultDesc(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("counts", ctypes.c_void_p), ("aggs", ctypes.c_void_p),
                 ("n_groups", ctypes.c_void_p), ("status", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
@@ -96,6 +111,20 @@ SIGNATURES = {
     "ccq_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
     "ccq_execute": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc)]),
     "ccq_execute_ex": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc), ctypes.POINTER(ExecOpts)]),
+    "ccq_batch_create": (_i32, [_vp, ctypes.POINTER(_vp), _i32, ctypes.POINTER(ResultDesc), ctypes.POINTER(BatchOpts),
+                                ctypes.POINTER(_vp)]),
+    "ccq_batch_destroy": (None, [_vp]),
+    "ccq_batch_info": (_i32, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_i64)]),
+    "ccq_batch_set_tiles_per_item": (_i32, [_vp, _i32]),
+    "ccq_batch_execute": (_i32, [_vp, _vp, _sz, _vp]),
+    "ccq_batch_autotune": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(_i32), _i32, _i32, ctypes.POINTER(_i32),
+                                  ctypes.POINTER(ctypes.c_float)]),
+    "ccq_now": (ctypes.c_double, []),
+    "ccq_server_create": (_i32, [_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
+    "ccq_server_submit": (_i32, [_vp, _vp, ctypes.POINTER(ResultDesc), ctypes.POINTER(ctypes.c_uint64)]),
+    "ccq_server_poll": (_i32, [_vp, ctypes.POINTER(Completion), _i32, ctypes.POINTER(_i32)]),
+    "ccq_server_drain": (_i32, [_vp, ctypes.c_double]),
+    "ccq_server_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -318,6 +347,112 @@ class Plan:
         if getattr(self, "h", None) and _lib is not None:
             _lib.ccq_plan_destroy(self.h)
             self.h = None
+
+
+class Batch:
+    """Many plans in one launch sequence (ccq_batch_*); results land in one
+    Result per plan, fixed at creation."""
+
+    def __init__(self, ctx, plans, tiles_per_item=0, use_graph=False):
+        self.ctx = ctx
+        self.plans = list(plans)
+        self.results = [p.new_result() for p in self.plans]
+        n = len(self.plans)
+        parr = (ctypes.c_void_p * max(n, 1))(*[p.h.value for p in self.plans])
+        rarr = (ResultDesc * max(n, 1))()
+        for i, r in enumerate(self.results):
+            rarr[i] = r.desc
+        opts = BatchOpts(int(tiles_per_item), 1 if use_graph else 0)
+        h = ctypes.c_void_p()
+        _check(lib().ccq_batch_create(ctx.h, parr, n, rarr, ctypes.byref(opts), ctypes.byref(h)))
+        self.h = h
+        self._refresh_info()
+
+    def _refresh_info(self):
+        w, n = ctypes.c_size_t(), ctypes.c_int64()
+        _check(lib().ccq_batch_info(self.h, ctypes.byref(w), ctypes.byref(n)))
+        self.workspace_bytes, self.n_items = w.value, n.value
+
+    def new_workspace(self):
+        import torch
+        return torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device="cuda:%d" % self.ctx.device)
+
+    def set_tiles_per_item(self, t):
+        _check(lib().ccq_batch_set_tiles_per_item(self.h, int(t)))
+        self._refresh_info()
+
+    def execute(self, workspace, stream=None):
+        _check(lib().ccq_batch_execute(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                       _stream_ptr(stream)))
+
+    def autotune(self, workspace, candidates=(8, 32, 128, 512), reps=3, stream=None):
+        arr = (ctypes.c_int32 * len(candidates))(*candidates)
+        best, ms = ctypes.c_int32(), ctypes.c_float()
+        _check(lib().ccq_batch_autotune(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                        _stream_ptr(stream), arr, len(candidates), int(reps), ctypes.byref(best),
+                                        ctypes.byref(ms)))
+        self._refresh_info()
+        return best.value, ms.value
+
+    def to_python(self):
+        return [r.to_python() for r in self.results]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ccq_batch_destroy(self.h)
+            self.h = None
+
+
+class Server:
+    """Continuous-batching query server (ccq_server_*).  submit() returns a
+    ticket; the plan and result stay referenced here until the ticket's
+    completion has been polled."""
+
+    def __init__(self, ctx, hbm_budget_bytes, max_inflight=64, max_batch=0, n_streams=2, batching=True,
+                 tiles_per_item=0):
+        self.ctx = ctx
+        cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(max_batch), int(n_streams),
+                           1 if batching else 0, int(tiles_per_item), 0)
+        h = ctypes.c_void_p()
+        _check(lib().ccq_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self._live = {}
+
+    def submit(self, plan, result):
+        t = ctypes.c_uint64()
+        _check(lib().ccq_server_submit(self.h, plan.h, ctypes.byref(result.desc), ctypes.byref(t)))
+        self._live[t.value] = (plan, result)
+        return t.value
+
+    def poll(self, max_n=1024):
+        """Completed queries: list of dicts (ticket, status, t_submit, t_start, t_done)."""
+        arr = (Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().ccq_server_poll(self.h, arr, max_n, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            self._live.pop(c.ticket, None)
+            out.append({"ticket": c.ticket, "status": c.status, "t_submit": c.t_submit, "t_start": c.t_start,
+                        "t_done": c.t_done})
+        return out
+
+    def drain(self, timeout_s=60.0):
+        _check(lib().ccq_server_drain(self.h, float(timeout_s)))
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ccq_server_destroy(self.h)
+            self.h = None
+        self._live = {}
+
+    def __del__(self):
+        self.close()
+
+
+def now():
+    """The host steady clock the server stamps completions with (seconds)."""
+    return lib().ccq_now()
 
 
 def to_device(columns, device="cuda:0"):

@@ -13,14 +13,19 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ccq.h"
-#include "ccq_plan.h"
+#include "ccq_internal.h"
 
 using namespace ccq;
 
-namespace {
+namespace ccq {
+const char* last_error();
+}
 
+namespace ccq {
+
+namespace {
 thread_local std::string g_err;
+}
 
 ccq_status fail(ccq_status code, const char* fmt, ...) {
     char buf[512];
@@ -41,33 +46,13 @@ ccq_status hip_fail(hipError_t e, const char* what) {
     return fail(CCQ_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace
+const char* last_error() { return g_err.c_str(); }
 
-struct ccq_context {
-    int device;
-    int cus;
-    size_t lds_per_block;
-};
-
-struct ccq_table {
-    ccq_context* ctx;
-    int64_t n_rows;
-    std::vector<ccq_column_desc> cols;
-};
-
-struct ccq_plan {
-    ccq_context* ctx;
-    DevPlan host;           // host copy (device pointers inside)
-    DevPlan* dev;           // device copy, inside `blob`
-    void* blob;             // one device allocation: plan, code tables, sets, slot keys
-    int grid_fused;
-    int64_t max_groups;
-    WsLayout ws;
-};
+}  // namespace ccq
 
 extern "C" {
 
-const char* ccq_last_error(void) { return g_err.c_str(); }
+const char* ccq_last_error(void) { return ccq::last_error(); }
 
 int32_t ccq_abi_version(void) { return CCQ_ABI_VERSION; }
 
@@ -684,7 +669,7 @@ ccq_status ccq_plan_create(const ccq_table* t, const ccq_query_desc* q, ccq_plan
     p->host = P;
     p->dev = (DevPlan*)dblob;
     p->blob = dblob;
-    p->grid_fused = fused_grid_limit(P, t->ctx->device);
+    p->grid_fused = fused_grid_limit(P, t->ctx->cus);
     p->max_groups = P.n_keys == 0 ? 1 : P.n_groups;
     p->ws = workspace_layout(P);
     *out = p;

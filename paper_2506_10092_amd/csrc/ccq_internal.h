@@ -1,0 +1,42 @@
+// Host-side handle types and error helpers shared by the C-ABI sources.
+// Internal to libccq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ccq.h"
+#include "ccq_plan.h"
+
+namespace ccq {
+
+// set the thread-local message and return code
+ccq_status fail(ccq_status code, const char* fmt, ...);
+ccq_status ok();
+ccq_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace ccq
+
+struct ccq_context {
+    int device;
+    int cus;
+    size_t lds_per_block;
+};
+
+struct ccq_table {
+    ccq_context* ctx;
+    int64_t n_rows;
+    std::vector<ccq_column_desc> cols;
+};
+
+struct ccq_plan {
+    ccq_context* ctx;
+    ccq::DevPlan host;      // host copy (device pointers inside)
+    ccq::DevPlan* dev;      // device copy, inside `blob`
+    void* blob;             // one device allocation: plan, code tables, sets, slot keys
+    int grid_fused;
+    int64_t max_groups;
+    ccq::WsLayout ws;
+};

@@ -42,6 +42,9 @@
 //           first; small tables live in LDS per workgroup and are added to the
 //           global table once at the end.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "ccq_plan.h"
 
@@ -842,63 +845,45 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
     wave_lds_sync();
 }
 
-// KMAX: bound on RLE columns (register arrays); W0: 0 = run mode or generic
-// row mode, else the width of the single bit-packed column of the fast row path.
-template <int KMAX, int W0>
-__global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
-                                                     int32_t* __restrict__ status, int64_t n_waves_total) {
-    const DevPlan& P = *Pg;
-    // fast row path: code table and lane-replicated counts in static LDS, so
-    // their addresses fold into the ds_* offsets
-    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits) ? (1 << W0) + 16 : 16];
-    __shared__ uint32_t s_cnt[W0 > 0 ? kFastCntWords : 4];
+// ---- workgroup pieces shared by the single-query and the batched kernels
 
-    // shared part of dynamic LDS: the code tables, then the group table
-    int32_t luts[kMaxBp];
-    if constexpr (W0 > 0 && W0 <= kLutMaxBits) {
-        const uint32_t* src = (const uint32_t*)P.bp[0].lut;
-        uint32_t* dst = (uint32_t*)s_lut;
-        for (int i = threadIdx.x; i < P.bp[0].lut_bytes / 4; i += blockDim.x) dst[i] = src[i];
-    }
-    if constexpr (W0 > 0) {
-        for (int i = threadIdx.x; i < kFastCntWords; i += blockDim.x) s_cnt[i] = 0;
-    }
+// Load the plan's code tables and clear its LDS tables (whole workgroup;
+// ends with a barrier).  luts[j]: LDS offset of column j's code table or -1.
+template <int W0>
+__device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint32_t* s_cnt, int32_t (&luts)[kMaxBp],
+                                         bool load_tables) {
+    if (load_tables) {
+        if constexpr (W0 > 0 && W0 <= kLutMaxBits) {
+            const uint32_t* src = (const uint32_t*)P.bp[0].lut;
+            uint32_t* dst = (uint32_t*)s_lut;
+            for (int i = threadIdx.x; i < P.bp[0].lut_bytes / 4; i += blockDim.x) dst[i] = src[i];
+        }
 #pragma unroll
-    for (int j = 0; j < kMaxBp; ++j) {
-        luts[j] = -1;
-        if (W0 == 0 && j < P.n_bp && P.bp[j].lut) {
-            uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].lut_lds_off);
-            const uint32_t* src = (const uint32_t*)P.bp[j].lut;
-            const int n = P.bp[j].lut_bytes / 4;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-            luts[j] = P.bp[j].lut_lds_off;
+        for (int j = 0; j < kMaxBp; ++j) {
+            if (W0 == 0 && j < P.n_bp && P.bp[j].lut) {
+                uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].lut_lds_off);
+                const uint32_t* src = (const uint32_t*)P.bp[j].lut;
+                const int n = P.bp[j].lut_bytes / 4;
+                for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+            }
         }
     }
-    Table tb;
-    tb.g = table;
-    tb.G = P.n_groups;
-    tb.loff = -1;
-    if (P.table_lds) {
-        tb.loff = P.table_lds_off;
+#pragma unroll
+    for (int j = 0; j < kMaxBp; ++j) luts[j] = (W0 == 0 && j < P.n_bp && P.bp[j].lut) ? P.bp[j].lut_lds_off : -1;
+    if constexpr (W0 > 0) {
+        for (int i = threadIdx.x; i < kFastCntWords; i += blockDim.x) s_cnt[i] = 0;
+        uint32_t* z = (uint32_t*)(ccq_lds + P.fast_sum_off);
+        for (int i = threadIdx.x; i < P.fast_bytes / 4; i += blockDim.x) z[i] = 0;
+    } else if (P.table_lds) {
         unsigned long long* l = (unsigned long long*)(ccq_lds + P.table_lds_off);
         const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) l[i] = 0;
     }
-    if (W0 > 0) {
-        uint32_t* z = (uint32_t*)(ccq_lds + P.fast_sum_off);
-        for (int i = threadIdx.x; i < P.fast_bytes / 4; i += blockDim.x) z[i] = 0;
-    }
     __syncthreads();
+}
 
-    // this wave's slice of the window: a whole number of nominal tiles,
-    // aligned to multiples of tile_rows in absolute row numbers
+__device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
     const int wave = threadIdx.x >> 6;
-    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave;
-    const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
-    const int64_t first_tile = P.row_begin / P.tile_rows;
-    const int64_t w0 = max(P.row_begin, (first_tile + gw * tiles_per_wave) * P.tile_rows);
-    const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) * P.tile_rows);
-
     WaveLds W;
     W.base = ccq_lds + P.lds_shared_bytes + wave * P.lds_wave_bytes;
     W.tn = (int32_t*)(W.base);            // slice header, 256 bytes (host layout reserves it)
@@ -910,58 +895,150 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     W.rows = (uint16_t*)(W.base + P.off_rows);
     W.pts = (uint32_t*)(W.base + P.off_pts);
     W.ptpre = (int32_t*)(W.base + P.off_ptpre);
+    return W;
+}
 
-    RegAcc<KMAX> acc;
-    acc.gid = -1;
-    acc.cnt = 0;
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c) acc.rsum[c] = 0;
-
+// One wavefront over rows [w0, w1) of the plan's window.
+template <int KMAX, int W0>
+__device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
+                                           const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
+                                           const int32_t (&luts)[kMaxBp], const uint8_t* s_lut, uint32_t* s_cnt) {
+    if (w0 >= w1) return;
     const bool sum_bp = W0 > 0 && P.bp[0].sum_slot >= 0;
-    if (w0 < w1) {
-        int64_t pcur[kMaxIdx];
-        for (int c = 0; c < P.k_rle; ++c) {
-            const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0);
-            if (lane_id() == 0) W.cur[c] = x;
-        }
-#pragma unroll
-        for (int j = 0; j < kMaxIdx; ++j)
-            pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
-        wave_lds_sync();
-        // row mode tiles start at multiples of 32 rows (lane words); the first
-        // one may start before the window, whose rows are then masked out
-        int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
-        while (t0 < w1) {
-            int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
-            stage_runs<KMAX>(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
-            const int32_t L = (int32_t)(t1 - t0);
-            const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
-            if (P.row_mode) {
-                if constexpr (W0 > 0) {
-                    if (sum_bp) tile_row_fast<KMAX, W0, true>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
-                    else tile_row_fast<KMAX, W0, false>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
-                } else {
-                    tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
-                }
-            } else {
-                tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
-            }
-            t0 = t1;
-        }
+    int64_t pcur[kMaxIdx];
+    for (int c = 0; c < P.k_rle; ++c) {
+        const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0);
+        if (lane_id() == 0) W.cur[c] = x;
     }
-    regacc_flush<KMAX>(P, tb, acc);
+#pragma unroll
+    for (int j = 0; j < kMaxIdx; ++j)
+        pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
+    wave_lds_sync();
+    // row mode tiles start at multiples of 32 rows (lane words); the first
+    // one may start before the window, whose rows are then masked out
+    int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
+    while (t0 < w1) {
+        int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
+        stage_runs<KMAX>(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
+        const int32_t L = (int32_t)(t1 - t0);
+        const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
+        if (P.row_mode) {
+            if constexpr (W0 > 0) {
+                if (sum_bp) tile_row_fast<KMAX, W0, true>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
+                else tile_row_fast<KMAX, W0, false>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
+            } else {
+                tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
+            }
+        } else {
+            tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
+        }
+        t0 = t1;
+    }
+}
 
-    if (W0 > 0) {
-        __syncthreads();
-        fast_flush(P, table, status, sum_bp, s_cnt);
+// Add the workgroup's LDS tables to the plan's global table (whole
+// workgroup; starts with a barrier).
+template <int KMAX, int W0>
+__device__ __forceinline__ void wg_flush(const DevPlan& P, int64_t* table, int32_t* status, const uint32_t* s_cnt) {
+    __syncthreads();
+    if constexpr (W0 > 0) {
+        fast_flush(P, table, status, P.bp[0].sum_slot >= 0, s_cnt);
     } else if (P.table_lds) {
-        __syncthreads();
         const unsigned long long* l = (const unsigned long long*)(ccq_lds + P.table_lds_off);
         const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
             const unsigned long long v = l[i];
             if (v) atomicAdd((unsigned long long*)&table[i], v);
         }
+    }
+}
+
+template <int KMAX>
+__device__ __forceinline__ void regacc_init(RegAcc<KMAX>& acc) {
+    acc.gid = -1;
+    acc.cnt = 0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) acc.rsum[c] = 0;
+}
+
+// KMAX: bound on RLE columns (register arrays); W0: 0 = run mode or generic
+// row mode, else the width of the single bit-packed column of the fast row path.
+// One query: every wavefront takes a contiguous slice of whole nominal tiles.
+template <int KMAX, int W0>
+__global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
+                                                     int32_t* __restrict__ status, int64_t n_waves_total) {
+    const DevPlan& P = *Pg;
+    // fast row path: code table and lane-replicated counts in static LDS, so
+    // their addresses fold into the ds_* offsets
+    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits) ? (1 << W0) + 16 : 16];
+    __shared__ uint32_t s_cnt[W0 > 0 ? kFastCntWords : 4];
+    int32_t luts[kMaxBp];
+    wg_setup<W0>(P, s_lut, s_cnt, luts, true);
+    Table tb;
+    tb.g = table;
+    tb.G = P.n_groups;
+    tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
+
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
+    const int64_t first_tile = P.row_begin / P.tile_rows;
+    const int64_t w0 = max(P.row_begin, (first_tile + gw * tiles_per_wave) * P.tile_rows);
+    const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) * P.tile_rows);
+
+    const WaveLds W = wave_lds(P);
+    RegAcc<KMAX> acc;
+    regacc_init(acc);
+    wave_range<KMAX, W0>(P, W, w0, w1, tb, status, acc, luts, s_lut, s_cnt);
+    regacc_flush<KMAX>(P, tb, acc);
+    wg_flush<KMAX, W0>(P, table, status, s_cnt);
+}
+
+// Many queries: workgroups take work items (a query and a range of its
+// nominal tiles) from a device counter, split the item's tiles across their
+// wavefronts, and add into that query's own table.  Code tables are reloaded
+// only when the query changes.
+template <int KMAX, int W0>
+__global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__ B, int32_t group,
+                                                     unsigned char* __restrict__ ws) {
+    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits) ? (1 << W0) + 16 : 16];
+    __shared__ uint32_t s_cnt[W0 > 0 ? kFastCntWords : 4];
+    __shared__ int32_t s_item;
+    const BatchGroup& grp = B->groups[group];
+    int32_t* counter = B->counters + group;
+    int32_t loaded = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t item = s_item;
+        __syncthreads();
+        if (item >= grp.n_items) break;
+        const BatchItem it = grp.items[item];
+        const DevPlan& P = *B->plans[it.query];
+        int32_t* status = (int32_t*)(ws + B->region[it.query]);
+        int64_t* table = (int64_t*)(ws + B->region[it.query] + 256);
+        int32_t luts[kMaxBp];
+        wg_setup<W0>(P, s_lut, s_cnt, luts, it.query != loaded);
+        loaded = it.query;
+        Table tb;
+        tb.g = table;
+        tb.G = P.n_groups;
+        tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
+
+        // this wave's share of the item's tiles
+        const int wave = threadIdx.x >> 6;
+        const int64_t per = (it.n_tiles + kWaves - 1) / kWaves;
+        const int64_t first_tile = P.row_begin / P.tile_rows;
+        const int64_t a = first_tile + it.first_tile + wave * per;
+        const int64_t b = first_tile + it.first_tile + min((int64_t)it.n_tiles, (wave + 1) * per);
+        const int64_t w0 = max(P.row_begin, a * P.tile_rows);
+        const int64_t w1 = min(P.row_end, b * P.tile_rows);
+
+        const WaveLds W = wave_lds(P);
+        RegAcc<KMAX> acc;
+        regacc_init(acc);
+        wave_range<KMAX, W0>(P, W, w0, w1, tb, status, acc, luts, s_lut, s_cnt);
+        regacc_flush<KMAX>(P, tb, acc);
+        wg_flush<KMAX, W0>(P, table, status, s_cnt);
     }
 }
 
@@ -1071,6 +1148,59 @@ __global__ void k_fin_single(const DevPlan* __restrict__ Pg, const int64_t* tabl
     }
 }
 
+// Clear each query's region of a batch workspace and the item counters.
+__global__ __launch_bounds__(kThreads) void k_batch_clear(const BatchDev* __restrict__ B, unsigned char* ws) {
+    if (blockIdx.x == 0 && threadIdx.x < kMaxInstances) B->counters[threadIdx.x] = 0;
+    for (int32_t q = blockIdx.x; q < B->n; q += gridDim.x) {
+        int64_t* r = (int64_t*)(ws + B->region[q]);
+        const int64_t n = B->region_clear[q] / 8;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = 0;
+    }
+}
+
+// Batched finalize: one workgroup per query; grouped queries with more than
+// kBatchFinMaxGroups ids are finalized by the multi-block kernels instead.
+__global__ __launch_bounds__(kThreads) void k_batch_fin(const BatchDev* __restrict__ B,
+                                                         const unsigned char* __restrict__ ws) {
+    __shared__ int s_wave[kWaves];
+    const int32_t q = blockIdx.x;
+    const DevPlan& P = *B->plans[q];
+    const int32_t* status = (const int32_t*)(ws + B->region[q]);
+    const int64_t* table = (const int64_t*)(ws + B->region[q] + 256);
+    const BatchOut& o = B->outs[q];
+    if (P.n_keys == 0) {
+        if (threadIdx.x == 0) {
+            write_group(P, 0, 0, table, 1, o.keys, o.counts, o.aggs);
+            *o.n_groups = 1;
+            *o.status = *status;
+        }
+        return;
+    }
+    const int64_t G = P.n_groups;
+    if (G > kBatchFinMaxGroups) return;
+    const int wave = threadIdx.x >> 6;
+    int64_t row = 0;
+    for (int64_t base = 0; base < G; base += kThreads) {
+        const int64_t g = base + threadIdx.x;
+        const bool ne = g < G && table[g] > 0;
+        const uint64_t m = wave_ballot(ne);
+        if (lane_id() == 0) s_wave[wave] = __builtin_popcountll(m);
+        __syncthreads();
+        int before = 0, all = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) before += s_wave[w];
+            all += s_wave[w];
+        }
+        if (ne) write_group(P, g, row + before + lanes_below(m), table, G, o.keys, o.counts, o.aggs);
+        row += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *o.n_groups = row;
+        *o.status = *status;
+    }
+}
+
 // ------------------------------------------------------------------ validation
 
 __global__ void k_validate_rle(const int64_t* ends, int64_t n, int64_t n_rows, int32_t* flag) {
@@ -1131,15 +1261,12 @@ static FusedFn fused_kernel(const DevPlan& p) {
 
 bool fast_row_width(int w) { return w == 14 || w == 20; }
 
-int fused_grid_limit(const DevPlan& p, int device) {
+int fused_grid_limit(const DevPlan& p, int cus) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fused_kernel(p), kThreads,
                                                      p.lds_dyn_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    hipDeviceProp_t prop;
-    int cus = 256;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
     return per_cu * cus;
 }
 
@@ -1181,6 +1308,74 @@ hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream
                            header, out_status);
         hipLaunchKernelGGL(k_fin_write, dim3((unsigned)L.scan_blocks), dim3(kThreads), 0, stream, dp, table, scan,
                            out_keys, out_counts, out_aggs);
+    }
+    return hipGetLastError();
+}
+
+typedef void (*BatchFn)(const BatchDev*, int32_t, unsigned char*);
+
+static BatchFn batch_kernel(int kmax, int w0) {
+#define CCQ_PICKB(KM)                                      \
+    if (kmax <= KM) {                                       \
+        if (w0 == 14) return &k_batch<KM, 14>;              \
+        if (w0 == 20) return &k_batch<KM, 20>;              \
+        return &k_batch<KM, 0>;                             \
+    }
+    CCQ_PICKB(2)
+    CCQ_PICKB(4)
+    CCQ_PICKB(8)
+#undef CCQ_PICKB
+    return &k_batch<8, 0>;
+}
+
+int batch_grid_limit(int kmax, int w0, int lds_bytes, int cus) {
+    // occupancy per (instance, LDS bytes), computed once
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, int> cache;
+    const auto key = std::make_tuple(kmax, w0, lds_bytes);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second * cus;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel(kmax, w0), kThreads,
+                                                     lds_bytes) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = per_cu;
+    return per_cu * cus;
+}
+
+hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan* const* plans_host,
+                        const DevPlan* const* plans_dev, const int64_t* region, const BatchOut* outs,
+                        unsigned char* ws, const int* group_grid, const int* group_lds, const int32_t* big,
+                        int32_t n_big, hipStream_t stream) {
+    const int clear_grid = (int)std::min<int64_t>(std::max<int64_t>(host.n, 1), 4096);
+    hipLaunchKernelGGL(k_batch_clear, dim3(clear_grid), dim3(kThreads), 0, stream, dev, ws);
+    for (int g = 0; g < host.n_groups_used; ++g) {
+        const BatchGroup& grp = host.groups[g];
+        if (grp.n_items == 0) continue;
+        const int blocks = std::max(1, std::min(group_grid[g], grp.n_items));
+        hipLaunchKernelGGL(batch_kernel(grp.kmax, grp.w0), dim3(blocks), dim3(kThreads), group_lds[g], stream, dev,
+                           g, ws);
+    }
+    if (host.n > 0) hipLaunchKernelGGL(k_batch_fin, dim3(host.n), dim3(kThreads), 0, stream, dev, ws);
+    for (int i = 0; i < n_big; ++i) {
+        // group tables too large for one workgroup: the multi-block finalize
+        const int32_t q = big[i];
+        const DevPlan& p = *plans_host[q];
+        const WsLayout L = workspace_layout(p);
+        unsigned char* r = ws + region[q];
+        int64_t* table = (int64_t*)(r + L.table_off);
+        int64_t* scan = (int64_t*)(r + L.scan_off);
+        const int64_t nb = L.scan_blocks;
+        hipLaunchKernelGGL(k_fin_count, dim3((unsigned)nb), dim3(kThreads), 0, stream, table, p.n_groups, scan);
+        hipLaunchKernelGGL(k_fin_scan, dim3(1), dim3(kThreads), 0, stream, scan, nb, outs[q].n_groups,
+                           (const int32_t*)r, outs[q].status);
+        hipLaunchKernelGGL(k_fin_write, dim3((unsigned)nb), dim3(kThreads), 0, stream, plans_dev[q], table, scan,
+                           outs[q].keys, outs[q].counts, outs[q].aggs);
     }
     return hipGetLastError();
 }

@@ -122,6 +122,63 @@ struct DevPlan {
     AggDesc aggs[kMaxAggs];
 };
 
+// ---- batched execution (many plans, one launch sequence)
+
+// A work item: one query and a range of its nominal tiles (relative to the
+// query's first tile).
+struct BatchItem {
+    int32_t query;
+    int32_t n_tiles;
+    int64_t first_tile;
+};
+
+// The items of the queries that share one kernel instance.
+struct BatchGroup {
+    const BatchItem* items;
+    int32_t n_items;
+    int32_t kmax, w0;       // kernel instance
+    int32_t pad_;
+};
+
+constexpr int kMaxInstances = 9;     // KMAX in {2, 4, 8} x W0 in {0, 14, 20}
+
+// Where each query's result goes.
+struct BatchOut {
+    int64_t *keys, *counts, *aggs, *n_groups;
+    int32_t* status;
+};
+
+// Each query owns a region of the workspace laid out like a single query's
+// workspace (status header, group table, finalize scan) at byte offset
+// region[q]; the first region_clear[q] bytes are cleared before the launch.
+// counters: one int32 item counter per group (cleared with the regions).
+struct BatchDev {
+    const DevPlan* const* plans;     // [n] device plans
+    const int64_t* region;           // [n] byte offset of query q's region in the workspace
+    const int64_t* region_clear;     // [n] bytes of the region to clear
+    const BatchOut* outs;            // [n]
+    int32_t* counters;               // [kMaxInstances] device item counters
+    BatchGroup groups[kMaxInstances];
+    int32_t n_groups_used;
+    int32_t n;
+};
+
+// Launch a whole batch on `stream`: clear every query's region and the
+// counters, one persistent launch per kernel instance, one finalize
+// workgroup per query, then the multi-block finalize for the queries listed
+// in big (group tables over kBatchFinMaxGroups ids).  Host arrays:
+// plans_host (host copies), plans_dev (device plan pointers), region, outs.
+hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan* const* plans_host,
+                        const DevPlan* const* plans_dev, const int64_t* region, const BatchOut* outs,
+                        unsigned char* ws, const int* group_grid, const int* group_lds, const int32_t* big,
+                        int32_t n_big, hipStream_t stream);
+
+// Persistent-grid size and dynamic LDS of a batch kernel instance.
+int batch_grid_limit(int kmax, int w0, int lds_bytes, int cus);
+
+// Largest group count the single-workgroup batched finalize handles.
+constexpr int64_t kBatchFinMaxGroups = int64_t(1) << 20;
+
 // Workspace layout (device, 256-byte aligned pieces):
 //   [0, 256)   header: int32 status, int32 spare
 //   table      (1 + n_sums) * n_groups int64: counts, then each SUM
@@ -145,7 +202,7 @@ hipError_t launch_validate_idx(const void* pos, int32_t ptype, int64_t n, int64_
                                hipStream_t s);
 
 // Persistent-grid size for the fused kernel with the plan's LDS use.
-int fused_grid_limit(const DevPlan& p, int device);
+int fused_grid_limit(const DevPlan& p, int cus);
 
 // Bit widths that have a fast row-mode kernel instance.
 bool fast_row_width(int w);

@@ -1,0 +1,92 @@
+"""Batched execution: every query of a batch must give exactly what the
+oracle and its own single-launch execution give, whatever the work-item size,
+and a captured hipGraph must give the same answers on every replay."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2506_10092_amd import ccq
+    n = 3_000_017
+    t = datagen.config_c2(seed=44, n_rows=n, columns=("r0", "r1", "r2", "s", "d", "p"))
+    qs = datagen.c4_queries(44, n, n_queries=160, lo_rows=1_000, hi_rows=n)
+    # edge cases: empty window, one row, whole table, a window ending mid-word
+    qs += [dict(qs[0], window=(5, 5)), dict(qs[1], window=(77, 78)), dict(qs[2], window=(0, n)),
+           dict(qs[3], window=(31, n - 3))]
+    ctx = ccq.Context(0)
+    table = ccq.Table(ctx, n, ccq.to_device(t["columns"]))
+    plans = [ccq.Plan(table, q) for q in qs]
+    torch.cuda.synchronize()
+    return {"t": t, "qs": qs, "ctx": ctx, "table": table, "plans": plans}
+
+
+def _single(plans):
+    return [p.run() for p in plans]
+
+
+def test_batch_equals_oracle_and_single_launch(setup):
+    from paper_2506_10092_amd import ccq
+    t, qs, plans = setup["t"], setup["qs"], setup["plans"]
+    single = _single(plans)
+    for tpi in (1, 7, 64, 100000):
+        b = ccq.Batch(setup["ctx"], plans, tiles_per_item=tpi)
+        ws = b.new_workspace()
+        b.execute(ws)
+        got = b.to_python()
+        say("batch tiles_per_item", tpi, "items", b.n_items)
+        assert got == single, "batch differs from single-launch results (tiles_per_item %d)" % tpi
+    for i, q in enumerate(qs):
+        exp = oracle.run(t, q)
+        s = single[i]
+        assert s["status"] == 0
+        assert (s["keys"], s["counts"], s["aggs"]) == (exp["keys"], exp["counts"], exp["aggs"]), (i, q)
+
+
+def test_batch_graph_replays(setup):
+    import torch
+    from paper_2506_10092_amd import ccq
+    plans = setup["plans"]
+    eager = _single(plans)
+    stream = torch.cuda.Stream()
+    b = ccq.Batch(setup["ctx"], plans, tiles_per_item=16, use_graph=True)
+    ws = b.new_workspace()
+    for rep in range(4):
+        with torch.cuda.stream(stream):
+            b.execute(ws, stream)
+        stream.synchronize()
+        got = b.to_python()
+        assert got == eager, "graph replay %d differs" % rep
+        # the program's own eager work between replays
+        x = torch.arange(1 << 20, device="cuda").sum().item()
+        assert x == (1 << 20) * ((1 << 20) - 1) // 2
+        plans[rep].run()
+
+
+def test_batch_autotune_keeps_results(setup):
+    import torch
+    from paper_2506_10092_amd import ccq
+    plans = setup["plans"]
+    eager = _single(plans)
+    stream = torch.cuda.Stream()
+    b = ccq.Batch(setup["ctx"], plans)
+    ws = b.new_workspace()
+    best, ms = b.autotune(ws, candidates=(2, 16, 128), reps=2, stream=stream)
+    say("autotune best", best, "ms", ms)
+    assert best in (2, 16, 128) and ms > 0
+    b.execute(ws, stream)
+    stream.synchronize()
+    assert b.to_python() == eager
