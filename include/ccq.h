@@ -268,7 +268,7 @@ typedef struct {
     int32_t status;            /* CCQ_OK, CCQ_E_BUDGET, or CCQ_E_HIP */
     int32_t pad_;
     double t_submit;           /* host steady clock, seconds (ccq_now) */
-    double t_start;            /* when its launch was enqueued */
+    double t_start;            /* when its launch was enqueued (rejected: when rejected) */
     double t_done;             /* when the dispatcher saw its launch finish */
 } ccq_completion;
 

@@ -293,7 +293,8 @@ void dispatcher(ccq_server* s) {
             if (r.bytes > s->arena.size) {
                 Req dead = r;
                 s->pending.pop_front();
-                complete(s, dead, CCQ_E_BUDGET, now_s());
+                dead.t_start = now_s();   // never launched: start = done = rejection time
+                complete(s, dead, CCQ_E_BUDGET, dead.t_start);
                 continue;
             }
             size_t off;
