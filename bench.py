@@ -199,13 +199,157 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _light_table(t):
+    """What algorithmic_bytes needs of a table (run ends, positions, widths,
+    value types), without the value arrays and packed words."""
+    import numpy as np
+    cols = {}
+    for name, c in t["columns"].items():
+        if c["enc"] == "rle":
+            cols[name] = {"enc": "rle", "run_ends": c["run_ends"], "values": np.empty(0, c["values"].dtype)}
+        elif c["enc"] == "index":
+            cols[name] = {"enc": "index", "positions": c["positions"], "values": np.empty(0, c["values"].dtype)}
+        else:
+            cols[name] = {"enc": c["enc"], "w": c["w"]}
+    return {"n_rows": t["n_rows"], "columns": cols}
+
+
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def bench_serve(args):
+    """Serving: queries of the batched templates arrive as a Poisson process
+    over eight resident tables of the mixed-encoding columns (n_i = scale *
+    1e7 * 10^(3i/7) rows, i = 0..7); a server with continuous batching and a
+    server that launches every query on its own (the single-launch path)
+    answer them under one HBM budget.  Per arrival rate: throughput and
+    p50 / p99 latency from arrival to completion, after a warm-up."""
+    import numpy as np
+    import torch
+    import datagen
+    from paper_2506_10092_amd import ccq
+
+    sizes = [max(1_000_000, int(round(args.serve_scale * 1e7 * 10 ** (3 * i / 7)))) for i in range(8)]
+    cols = ("r0", "r1", "r2", "s", "d", "p")
+    ctx = ccq.Context(0)
+    tables, light = [], []
+    t_gen = time.time()
+    for i, n in enumerate(sizes):
+        t = datagen.config_c2(seed=50 + i, n_rows=n, columns=cols)
+        tables.append(ccq.Table(ctx, n, ccq.to_device(t["columns"])))
+        light.append(_light_table(t))
+        del t
+        log("table %d: %d rows resident (%.1fs)" % (i, n, time.time() - t_gen))
+    torch.cuda.synchronize()
+
+    n_q = args.serve_queries
+    rng = np.random.default_rng([5, 5555])
+    which = rng.integers(0, 8, size=n_q)
+    per = [datagen.c4_queries(500 + i, sizes[i], n_queries=int((which == i).sum())) for i in range(8)]
+    nxt = [0] * 8
+    queries = []
+    for i in which:
+        queries.append((int(i), per[i][nxt[i]]))
+        nxt[i] += 1
+    plans = [ccq.Plan(tables[i], q) for i, q in queries]
+    results = [p.new_result() for p in plans]
+    rows_q = np.array([q["window"][1] - q["window"][0] for _, q in queries], dtype=np.float64)
+    bytes_q = np.array([algorithmic_bytes(light[i], q) for i, q in queries], dtype=np.float64)
+    log("%d plans over %d tables (%.1fs)" % (n_q, len(tables), time.time() - t_gen))
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(args.serve_budget_gb * 1e9, free - 4e9))
+    levels = [float(x) for x in args.qps.split(",")]
+    warm = min(args.serve_warmup, n_q // 2)
+    report = {}
+    answers = {}
+    for batching in (True, False):
+        mode = "batched" if batching else "single_launch"
+        report[mode] = {}
+        for qps in levels:
+            srv = ccq.Server(ctx, budget, max_inflight=args.serve_inflight, n_streams=2, batching=batching,
+                             tiles_per_item=args.serve_tpi)
+            arr = np.cumsum(np.random.default_rng([6, int(qps)]).exponential(1.0 / qps, size=n_q))
+            base = ccq.now() + 0.005
+            sched = {}
+            for k in range(n_q):
+                due = base + arr[k]
+                while ccq.now() < due:
+                    pass
+                sched[srv.submit(plans[k], results[k])] = (k, due)
+            srv.drain(900.0)
+            comps = []
+            while True:
+                got = srv.poll(4096)
+                if not got:
+                    break
+                comps.extend(got)
+            srv.close()
+            if len(comps) != n_q or any(c["status"] != 0 for c in comps):
+                raise SystemExit("server %s at %g QPS: %d completions, statuses %s" %
+                                 (mode, qps, len(comps), sorted({c["status"] for c in comps})))
+            stat = [(sched[c["ticket"]][0], c["t_done"] - sched[c["ticket"]][1], c["t_done"]) for c in comps]
+            stat = [x for x in stat if x[0] >= warm]
+            lat = [x[1] for x in stat]
+            idx = [x[0] for x in stat]
+            t_first = base + arr[warm]
+            dur = max(x[2] for x in stat) - t_first
+            report[mode]["%g" % qps] = {
+                "queries": len(stat), "p50_ms": _pct(lat, 50) * 1e3, "p99_ms": _pct(lat, 99) * 1e3,
+                "queries_per_s": len(stat) / dur, "rows_per_s": float(rows_q[idx].sum()) / dur,
+                "GBps": float(bytes_q[idx].sum()) / dur / 1e9}
+            log("%s %g QPS: p50 %.3f ms p99 %.3f ms, %.0f queries/s" %
+                (mode, qps, report[mode]["%g" % qps]["p50_ms"], report[mode]["%g" % qps]["p99_ms"],
+                 report[mode]["%g" % qps]["queries_per_s"]))
+            if qps == levels[0]:
+                answers[mode] = [r.to_python() for r in results]
+    if answers["batched"] != answers["single_launch"]:
+        raise SystemExit("served results differ between the batched and the single-launch server")
+    top = "%g" % levels[-1]
+    b = report["batched"][top]
+    out = {
+        "metric": METRIC,
+        "value": b["rows_per_s"],
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": n_q,
+        "warmup": warm,
+        "ms_per_step": 1e3 / b["queries_per_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "c5_serve_8_tables_%g_rows" % sum(sizes), "tables": sizes, "queries": n_q,
+                   "qps": levels, "hbm_budget_bytes": budget, "max_inflight": args.serve_inflight,
+                   "tiles_per_item": args.serve_tpi},
+        "serving": report,
+        "p50_ms": b["p50_ms"],
+        "p99_ms": b["p99_ms"],
+        "single_launch_p50_ms": report["single_launch"][top]["p50_ms"],
+        "single_launch_p99_ms": report["single_launch"][top]["p99_ms"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--queries", type=int, default=4096, help="c4: queries per batch")
+    ap.add_argument("--serve-queries", type=int, default=10000, help="c5: queries per arrival rate (after warm-up)")
+    ap.add_argument("--serve-warmup", type=int, default=500, help="c5: leading queries left out of the statistics")
+    ap.add_argument("--serve-scale", type=float, default=1.0, help="c5: scale of the eight table sizes")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0, help="c5: HBM budget of the servers")
+    ap.add_argument("--serve-inflight", type=int, default=512, help="c5: queries admitted or running at once")
+    ap.add_argument("--serve-tpi", type=int, default=64, help="c5: batch work-item size in tiles")
+    ap.add_argument("--qps", default="200,1000,5000", help="c5: Poisson arrival rates")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
     ap.add_argument("--cpu-sample-rows", type=int, default=1_000_000_000,
                     help="rows of the window the CPU oracle runs over (bounded sample)")
@@ -220,7 +364,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the query would shard by row range with one exchange of partial "
-              "group tables; see the design notes). Run with --gpus 1.", file=sys.stderr)
+              "group tables). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -233,6 +377,9 @@ def main():
 
     if args.config == "c4":
         bench_batch(args)
+        return
+    if args.config == "c5":
+        bench_serve(args)
         return
 
     t_gen = time.time()

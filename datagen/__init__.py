@@ -62,6 +62,7 @@ def lib():
         L.dg_sparse_count.restype = i64
         L.dg_sparse_count.argtypes = [u64, u64, dbl, i64]
         L.dg_sparse_fill.argtypes = [u64, u64, dbl, i64, vp, i64]
+        L.dg_sparse_fill64.argtypes = [u64, u64, dbl, i64, vp, i64]
         L.dg_zipf_codes.argtypes = [u64, u64, dbl, i64, vp, i64]
         L.dg_zipf_pmf.argtypes = [dbl, i64, vp]
         L.dg_packed_words.restype = i64
@@ -97,11 +98,16 @@ def rle_column(seed, stream, n_rows, dist, mean, vlo, vhi, vdtype=np.int32, sigm
 
 def sparse_column(seed, stream, n_rows, density, vlo, vhi, vdtype=np.int64):
     """Index column: each row listed independently with probability `density`,
-    values uniform in [vlo, vhi)."""
+    values uniform in [vlo, vhi); int32 positions, int64 past 2^31 rows."""
     L = lib()
     n = L.dg_sparse_count(seed, stream, float(density), int(n_rows))
-    pos = np.empty(n, dtype=np.int32)
-    L.dg_sparse_fill(seed, stream, float(density), int(n_rows), _ptr(pos), n)
+    if n_rows <= (1 << 31) - 1:
+        pos = np.empty(n, dtype=np.int32)
+        L.dg_sparse_fill(seed, stream, float(density), int(n_rows), _ptr(pos), n)
+    else:
+        # positions past 2^31: int64 (the same rows as the int32 form would list)
+        pos = np.empty(n, dtype=np.int64)
+        L.dg_sparse_fill64(seed, stream, float(density), int(n_rows), _ptr(pos), n)
     vals = np.empty(n, dtype=vdtype)
     if vdtype == np.int32:
         L.dg_uniform_i32(seed, stream + 1, int(vlo), int(vhi), _ptr(vals), n)

@@ -150,7 +150,8 @@ void dg_uniform_i64(uint64_t seed, uint64_t stream, int64_t lo, int64_t hi, int6
 /* ------------------------------------------------------------------ */
 #define SP_BLOCK (1 << 20)
 
-static int64_t sparse_block(uint64_t key, int64_t b, double p, int64_t n_rows, int32_t* out) {
+/* out32 / out64: where to write the block's positions (at most one set) */
+static int64_t sparse_block(uint64_t key, int64_t b, double p, int64_t n_rows, int32_t* out32, int64_t* out64) {
     int64_t r0 = b * (int64_t)SP_BLOCK;
     int64_t r1 = r0 + SP_BLOCK < n_rows ? r0 + SP_BLOCK : n_rows;
     uint64_t ctr = (uint64_t)b << 32;
@@ -162,7 +163,8 @@ static int64_t sparse_block(uint64_t key, int64_t b, double p, int64_t n_rows, i
         int64_t gap = 1 + (int64_t)floor(log(u) / lq);
         r += gap;
         if (r >= r1) break;
-        if (out) out[cnt] = (int32_t)r;
+        if (out32) out32[cnt] = (int32_t)r;
+        if (out64) out64[cnt] = r;
         cnt++;
     }
     return cnt;
@@ -174,22 +176,34 @@ int64_t dg_sparse_count(uint64_t seed, uint64_t stream, double p, int64_t n_rows
     int64_t nb = (n_rows + SP_BLOCK - 1) / SP_BLOCK;
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 8) reduction(+ : total)
-    for (int64_t b = 0; b < nb; b++) total += sparse_block(key, b, p, n_rows, NULL);
+    for (int64_t b = 0; b < nb; b++) total += sparse_block(key, b, p, n_rows, NULL, NULL);
     return total;
 }
 
-void dg_sparse_fill(uint64_t seed, uint64_t stream, double p, int64_t n_rows, int32_t* positions, int64_t n) {
+static void sparse_fill(uint64_t seed, uint64_t stream, double p, int64_t n_rows, int32_t* p32, int64_t* p64,
+                        int64_t n) {
     if (n <= 0) return;
     uint64_t key = dg_key(seed, stream);
     int64_t nb = (n_rows + SP_BLOCK - 1) / SP_BLOCK;
     int64_t* offs = (int64_t*)malloc(sizeof(int64_t) * (nb + 1));
 #pragma omp parallel for schedule(dynamic, 8)
-    for (int64_t b = 0; b < nb; b++) offs[b + 1] = sparse_block(key, b, p, n_rows, NULL);
+    for (int64_t b = 0; b < nb; b++) offs[b + 1] = sparse_block(key, b, p, n_rows, NULL, NULL);
     offs[0] = 0;
     for (int64_t b = 0; b < nb; b++) offs[b + 1] += offs[b];
 #pragma omp parallel for schedule(dynamic, 8)
-    for (int64_t b = 0; b < nb; b++) sparse_block(key, b, p, n_rows, positions + offs[b]);
+    for (int64_t b = 0; b < nb; b++)
+        sparse_block(key, b, p, n_rows, p32 ? p32 + offs[b] : NULL, p64 ? p64 + offs[b] : NULL);
     free(offs);
+}
+
+/* int32 positions (tables below 2^31 rows) */
+void dg_sparse_fill(uint64_t seed, uint64_t stream, double p, int64_t n_rows, int32_t* positions, int64_t n) {
+    sparse_fill(seed, stream, p, n_rows, positions, NULL, n);
+}
+
+/* int64 positions (the same rows as dg_sparse_fill) */
+void dg_sparse_fill64(uint64_t seed, uint64_t stream, double p, int64_t n_rows, int64_t* positions, int64_t n) {
+    sparse_fill(seed, stream, p, n_rows, NULL, positions, n);
 }
 
 /* ------------------------------------------------------------------ */
