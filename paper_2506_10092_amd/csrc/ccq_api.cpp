@@ -491,13 +491,13 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.n_tiles = window > 0 ? (P.row_end - 1) / P.tile_rows - P.row_begin / P.tile_rows + 1 : 0;
 
     // kernel path.  The fast row path: a single bit-packed column of a width
-    // with a kernel instance, no RLE value per row, the column itself the only
+    // with a kernel instance, at most one Index column, no RLE value per row, the column itself the only
     // key (or no key), a code table or a plain range test, and uint32 counts
     // that cannot overflow within one workgroup.
     P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
     P.w0 = 0;
     {
-        bool fast = P.row_mode && P.n_bp == 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
+        bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
                     (G + 2) * 8 <= kFastCntWords;
         BpCol& b = P.bp[0];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
@@ -593,9 +593,26 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     }
     P.lds_shared_bytes = (int32_t)sh;
 
-    // wave slice: a 256-byte header (per-column staged counts, first runs and
-    // next-tile cursors), then the staged runs, then row-mode buffers
-    size_t wv = 256;
+    // wave slice.  Fast row path: a 64-word toggle bitmap per RLE column and
+    // two 64-word lane-mask buffers (runs are never staged).  Otherwise a
+    // 256-byte header (per-column staged counts, first runs and next-tile
+    // cursors), then the staged runs, then row-mode buffers.
+    size_t wv = 0;
+    if (P.w0) {
+        P.run_cap = 0;
+        P.off_run_end = P.off_run_val = P.off_rows = P.off_ptpre = 0;
+        P.off_tog = (int32_t)wv;
+        wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
+        P.off_pts = (int32_t)wv;
+        wv = align16(wv + 2 * 256);
+        P.lds_wave_bytes = (int32_t)wv;
+        P.lds_dyn_bytes = (int32_t)(sh + kWaves * wv);
+        if ((size_t)P.lds_dyn_bytes > t->ctx->lds_per_block)
+            return fail(CCQ_E_UNSUPPORTED, "query needs %d bytes of LDS per workgroup (limit %zu)", P.lds_dyn_bytes,
+                        t->ctx->lds_per_block);
+        return CCQ_OK;
+    }
+    wv = 256;
     P.off_run_end = (int32_t)wv;
     wv = align16(wv + 4 * (size_t)P.run_cap);
     P.off_run_val = (int32_t)wv;

@@ -52,11 +52,35 @@ namespace ccq {
 
 // ------------------------------------------------------------------ helpers
 
+// Column data always lives in device global memory: reading it through the
+// global address space gives global_load (counted by vmcnt only) instead of
+// flat_load, whose completion every LDS wait would also have to await.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, int64_t i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+
 __device__ __forceinline__ int64_t ld_val(const void* p, int32_t vtype, int64_t i) {
-    return vtype == 1 ? (int64_t)(((const int32_t*)p)[i]) : ((const int64_t*)p)[i];
+    return vtype == 1 ? (int64_t)gld((const int32_t*)p, i) : gld((const int64_t*)p, i);
+}
+
+// The same without a branch on the type: always two dword loads (the high
+// word of an int32 value reads its low word again), so that every path
+// issues the same loads.
+__device__ __forceinline__ int64_t ld_val_nb(const void* p, int32_t vtype, int64_t i) {
+    const int32_t* q = (const int32_t*)p;
+    const bool wide = vtype != 1;
+    const int64_t k = wide ? 2 * i : i;
+    const uint32_t lo = (uint32_t)gld(q, k);
+    const uint32_t hi = (uint32_t)gld(q, wide ? k + 1 : k);
+    return wide ? (int64_t)(((uint64_t)hi << 32) | lo) : (int64_t)(int32_t)lo;
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// The wavefront's index in its workgroup, known to the compiler as
+// wave-uniform (so everything derived from it stays in scalar registers).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __ballot(p); }
 
@@ -87,9 +111,9 @@ __device__ __forceinline__ bool set_contains(const int64_t* s, int32_t n, int64_
     int32_t lo = 0, hi = n;
     while (lo < hi) {
         int32_t mid = (lo + hi) >> 1;
-        if (s[mid] < v) lo = mid + 1; else hi = mid;
+        if (gld(s, mid) < v) lo = mid + 1; else hi = mid;
     }
-    return lo < n && s[lo] == v;
+    return lo < n && gld(s, lo) == v;
 }
 
 __device__ __forceinline__ bool pred_pass(int32_t kind, int64_t lo, int64_t hi, const int64_t* set, int32_t n,
@@ -112,7 +136,7 @@ __device__ int64_t wave_upper_bound(const int64_t* a, int64_t n, int64_t x) {
     while (hi - lo > 64) {
         const int64_t len = hi - lo;
         const int64_t p = lo + ((int64_t)(lane + 1) * len) / 64 - 1;
-        const uint64_t m = wave_ballot(a[p] > x);
+        const uint64_t m = wave_ballot(gld(a, p) > x);
         if (m == 0) return hi;
         const int f = __builtin_ctzll(m);
         const int64_t nhi = lo + ((int64_t)(f + 1) * len) / 64 - 1;
@@ -121,7 +145,7 @@ __device__ int64_t wave_upper_bound(const int64_t* a, int64_t n, int64_t x) {
         hi = nhi;
     }
     const int64_t i = lo + lane;
-    const uint64_t m = wave_ballot(i < hi && a[i] > x);
+    const uint64_t m = wave_ballot(i < hi && gld(a, i) > x);
     return m ? lo + __builtin_ctzll(m) : hi;
 }
 
@@ -199,6 +223,7 @@ struct WaveLds {
     uint16_t* rows;     // generic row mode: surviving rows of the tile, compacted
     uint32_t* pts;      // row mode: 64-word point bitmap per Index column
     int32_t* ptpre;     // row mode: exclusive popcount prefix per bitmap word
+    uint32_t* tog;      // fast row path: 64-word toggle bitmap per RLE column
     int32_t cap;        // staged runs per column; column c starts at slot c * cap
 };
 
@@ -224,7 +249,7 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             lo[c] = W.cur[c];
             const int64_t i = lo[c] + lane;
             if (i < rc.n_runs) {
-                e0[c] = rc.ends[i];
+                e0[c] = gld(rc.ends, i);
                 v0[c] = ld_val(rc.vals, rc.vtype, i);
             }
         }
@@ -264,7 +289,7 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             e = INT64_MAX;
             v = 0;
             if (i < rc.n_runs && n + lane < W.cap) {
-                e = rc.ends[i];
+                e = gld(rc.ends, i);
                 v = ld_val(rc.vals, rc.vtype, i);
             }
         }
@@ -552,139 +577,382 @@ __device__ __forceinline__ uint32_t extract_code(const uint32_t (&wd)[W0 > 0 ? W
     return __builtin_amdgcn_alignbit(wd[q + 1], wd[q], sh) & mask;
 }
 
-// Fast row mode: one bit-packed column of width W0, read from the lane's
-// registers; no RLE value per row; at most one key, the bit-packed column
-// itself, so a row's group is its slot.  Counts go to a lane-replicated LDS
-// table (slot-major, P.fast_rep replicas, uint32): the lanes of a wave never
-// hit the same address, whatever the skew of the codes.  Slot G counts rows
-// whose key is out of its domain, slot G + 1 rejected rows.  The loop is
-// branch free: each batch of 16 rows first does all its code-table reads,
-// then all its table adds.  W0 <= 14: the uint8 code table sits at LDS
-// offset 0 with the reject entry at index 2^W0.  Wider columns test a code
-// range; key = (base + code) >> shift.  A SUM of the column is accumulated
-// over codes (uint64, same replicas); the flush adds base * count.
-template <int KMAX, int W0, bool SUMBP>
-__device__ __forceinline__ void tile_row_fast(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                              int32_t lo_valid, int64_t (&pcur)[kMaxIdx], const uint8_t* lut,
-                                              uint32_t* cnt) {
+// ---- fast row path
+//
+// One bit-packed column of width W0 (14 or 20); no RLE value per row; at
+// most one key, the bit-packed column itself, so a row's group is its slot.
+// A lane owns 32 consecutive rows of a tile, i.e. W0 whole words of the
+// packed stream (tiles start at multiples of 32 rows), held in registers.
+//
+// RLE predicates never stage runs: each lane takes one run of a 64-run batch
+// read straight from HBM, evaluates the predicate once for it, and marks a
+// toggle at the run's end when the outcome of the next run differs.  The
+// inclusive prefix XOR of the toggles over the tile, started from the
+// outcome of the run holding the tile's first row, is the column's pass
+// mask (Section 6 alignment: the AND over columns of these masks is the
+// merge of their run ends restricted to passing runs).
+//
+// A wave walks its tiles as a software pipeline: while tile i is counted,
+// the packed words of tile i+1 (only for lanes with surviving rows), the run
+// batches of tile i+2 and the Index points of tile i+1 are in flight.
+
+template <int KMAX>
+struct FastRuns {
+    int64_t cur[KMAX];   // wave-uniform: the run held by lane 0 of the batch
+    int64_t e[KMAX];     // this lane's run end (INT64_MAX past the column)
+    int64_t v[KMAX];     // its value
+};
+
+// Prefetches issue the same loads on every path (clamped indices, a word of
+// the plan itself for an absent column), so the compiler's count of loads in
+// flight stays exact and a use waits only for its own loads.
+template <int KMAX>
+__device__ __forceinline__ void fast_runs_fetch(const DevPlan& P, FastRuns<KMAX>& R, int c) {
+    const RleCol& rc = P.rle[c];
+    const bool have = c < P.k_rle && rc.n_runs > 0;
+    const int64_t i = R.cur[c] + lane_id();
+    const bool ok = have && i < rc.n_runs;
+    const int64_t j = ok ? i : 0;
+    const int64_t e = gld(have ? rc.ends : (const int64_t*)&P, j);
+    const int64_t v = ld_val_nb(have ? rc.vals : (const void*)&P, have ? rc.vtype : 2, j);
+    R.e[c] = ok ? e : INT64_MAX;
+    R.v[c] = ok ? v : 0;
+}
+
+// The lane's rows of tile [t0, t1) that pass every RLE predicate.  R holds
+// the batch at the run holding row t0; it is left at the batch holding row
+// t1 with its loads issued.
+template <int KMAX>
+__device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t t1,
+                                                  FastRuns<KMAX>& R) {
     const int lane = lane_id();
-    const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
+    uint32_t first = 0;   // bit c: the run holding row t0 passes column c
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        if (c >= P.k_rle) continue;
+        const RleCol& rc = P.rle[c];
+        uint32_t* tog = W.tog + c * 64;
+        int64_t base = R.cur[c];
+        int64_t e = R.e[c];
+        bool valid = base + lane < rc.n_runs;
+        bool pass = valid && pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, R.v[c]);
+        uint64_t pb = wave_ballot(pass);
+        first |= (uint32_t)(pb & 1u) << c;
+        for (;;) {
+            // the batch is the tile's last when it holds the run of row t1 - 1
+            const bool last = wave_ballot(valid && e >= t1) != 0 || wave_ballot(valid) != ~0ull;
+            int64_t e2 = INT64_MAX;
+            bool valid2 = false, pass2 = false;
+            uint64_t pb2 = 0;
+            if (!last) {
+                const int64_t i = base + 64 + lane;
+                valid2 = i < rc.n_runs;
+                int64_t v2 = 0;
+                if (valid2) {
+                    e2 = gld(rc.ends, i);
+                    v2 = ld_val(rc.vals, rc.vtype, i);
+                }
+                pass2 = valid2 && pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, v2);
+                pb2 = wave_ballot(pass2);
+            }
+            // outcome of the run after this lane's run
+            const bool nxt = lane < 63 ? ((pb >> (lane + 1)) & 1u) != 0 : (last ? pass : (pb2 & 1u) != 0);
+            if (valid && e < t1 && pass != nxt) {
+                const uint32_t rel = (uint32_t)(e - t0);
+                atomicOr(&tog[rel >> 5], 1u << (rel & 31));
+            }
+            if (last) {
+                base += __builtin_popcountll(wave_ballot(valid && e <= t1));
+                break;
+            }
+            base += 64;
+            e = e2;
+            valid = valid2;
+            pass = pass2;
+            pb = pb2;
+        }
+        R.cur[c] = base;
+    }
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) fast_runs_fetch(P, R, c);
+    wave_lds_sync();
+    uint32_t pm = 0xFFFFFFFFu;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        if (c >= P.k_rle) continue;
+        uint32_t* tog = W.tog + c * 64;
+        const uint32_t T = tog[lane];
+        tog[lane] = 0;
+        uint32_t x = T;
+        x ^= x << 1;
+        x ^= x << 2;
+        x ^= x << 4;
+        x ^= x << 8;
+        x ^= x << 16;
+        // toggles in the words below this lane's, plus the starting outcome
+        const uint64_t par = wave_ballot((__builtin_popcount(T) & 1) != 0);
+        const uint32_t flip = ((uint32_t)lanes_below(par) ^ (first >> c)) & 1u;
+        pm &= flip ? ~x : x;
+    }
+    return pm;
+}
+
+// the lane's rows of tile [t0, t1) inside the window (rows >= w0)
+__device__ __forceinline__ uint32_t fast_window_mask(int64_t t0, int64_t t1, int64_t w0) {
+    const int32_t b = lane_id() * kRowSpan;
+    const int32_t lo = (int32_t)(max(t0, w0) - t0) - b;   // first valid bit
+    const int32_t hi = (int32_t)(t1 - t0) - b;            // one past the last
+    uint32_t m = 0xFFFFFFFFu;
+    if (lo > 0) m = lo >= 32 ? 0u : m << lo;
+    if (hi < 32) m &= hi <= 0 ? 0u : ((1u << hi) - 1u);
+    return m;
+}
+
+// The lane's W0 words of the tile at t0; lanes without surviving rows read
+// nothing (an out-of-range buffer offset returns zero without a memory
+// access).
+template <int W0>
+__device__ __forceinline__ void fast_words(const BpCol& bc, int64_t t0, uint32_t pm, uint32_t (&wd)[W0]) {
+    const int lane = lane_id();
+    const int64_t tw = (t0 >> 5) * W0;                 // the tile's first word
+    const int64_t avail = bc.n_words - tw;             // words from there on
+    // the buffer resource lives in scalar registers: the tile is wave-uniform
+    const uint64_t addr = (uint64_t)(bc.packed + tw);
+    const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+    const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+    const int32_t nrec = __builtin_amdgcn_readfirstlane((avail < 64 * W0 ? (int32_t)avail : 64 * W0) * 4);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(((uint64_t)ahi << 32) | alo), (short)0, nrec, 0x00020000);
+    const int32_t lw = lane * W0;
+    constexpr int32_t kNone = 0x40000000;              // beyond any tile's records
+    if (avail >= 64 * W0) {
+        const int32_t off = pm ? lw * 4 : kNone;
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int i = 0; i < W0 / 2; ++i) {
+            const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8 * i, 0, 0);
+            wd[2 * i] = v.x;
+            wd[2 * i + 1] = v.y;
+        }
+    } else {
+        // the stream ends inside this tile: word by word
+        const int32_t rem = pm ? (int32_t)avail - lw : 0;   // the lane's words that exist
+        const int32_t off = lw * 4;
+#pragma unroll
+        for (int i = 0; i < W0; ++i) wd[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, i < rem ? off + 4 * i : kNone, 0, 0);
+    }
+}
+
+// Count the lane's 32 rows into the lane-replicated LDS table (slot-major,
+// 2^rep_shift replicas, uint32): the lanes of a wave never hit the same
+// address, whatever the skew of the codes.  Slot G counts rows whose key is
+// out of its domain, slot G + 1 rejected rows.  Branch free: each batch of
+// kFastBatch rows first does all its code-table reads, then all its table adds.
+// W0 <= 14: the uint8 code table sits at LDS offset 0 with the reject entry
+// at index 2^W0.  Wider columns test a code range; key = (base + code) >>
+// shift.  A SUM of the column is accumulated over codes (uint64, same
+// replicas); the flush adds base * count.
+constexpr int kFastBatch = 8;
+
+template <int W0, bool SUMBP>
+__device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)[W0], uint32_t pm,
+                                          const uint8_t* lut, uint32_t* cnt) {
+    const int lane = lane_id();
     const BpCol& bc = P.bp[0];
     const uint32_t G = (uint32_t)P.n_groups;
-    const uint32_t rep_sh = (uint32_t)P.fast_rep_shift;             // log2 replicas
+    const uint32_t rep_sh = (uint32_t)P.fast_rep_shift;
     const uint32_t lane_part = (uint32_t)(lane & ((1 << rep_sh) - 1));
     const uint32_t lane_bytes = lane_part * 4u, sh_bytes = rep_sh + 2u;
     unsigned long long* csum = (unsigned long long*)(ccq_lds + P.fast_sum_off);
-    const uint64_t any = wave_ballot(pm != 0);
-
-    if (any) {
-        // the lane's 32 rows are W0 whole words of the stream (tiles start at multiples of 32 rows)
-        uint32_t wd[W0];
-        const int64_t word0 = ((t0 >> 5) + lane) * (int64_t)W0;
-        if (pm && word0 + W0 > bc.n_words) {
-            // the lane's rows reach past the table end: read only the guaranteed words
+    const uint32_t reject = G + 1;
 #pragma unroll
-            for (int i = 0; i < W0; ++i) wd[i] = word0 + i < bc.n_words ? bc.packed[word0 + i] : 0u;
-        } else if (pm) {
-            const uint32_t* src = bc.packed + word0;
-            if constexpr (W0 % 2 == 0) {
-                const uint2* s2 = (const uint2*)src;
+    for (int h = 0; h < kRowSpan; h += kFastBatch) {
+        uint32_t slot[kFastBatch];
+        uint32_t code[kFastBatch];
 #pragma unroll
-                for (int i = 0; i < W0 / 2; ++i) {
-                    const uint2 v = s2[i];
-                    wd[2 * i] = v.x;
-                    wd[2 * i + 1] = v.y;
-                }
+        for (int j = 0; j < kFastBatch; ++j) {
+            const uint32_t c = extract_code<W0>(wd, h + j);
+            const bool keep = (pm >> (h + j)) & 1u;
+            code[j] = c;
+            if constexpr (W0 <= kLutMaxBits) {
+                slot[j] = lut[keep ? c : (1u << W0)];
             } else {
-#pragma unroll
-                for (int i = 0; i < W0; ++i) wd[i] = src[i];
+                uint32_t s = (c - bc.code_lo < bc.code_span) ? 0u : reject;
+                if (bc.key >= 0 && s == 0u) {
+                    const int64_t kv = (bc.base + (int64_t)c) >> bc.key_shift;
+                    s = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
+                }
+                slot[j] = keep ? s : reject;
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < W0; ++i) wd[i] = 0;
         }
-        const uint32_t reject = G + 1;
 #pragma unroll
-        for (int h = 0; h < kRowSpan; h += 16) {
-            uint32_t slot[16];
-            uint32_t code[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const uint32_t c = extract_code<W0>(wd, h + j);
-                const bool keep = (pm >> (h + j)) & 1u;
-                code[j] = c;
-                if constexpr (W0 <= kLutMaxBits) {
-                    slot[j] = lut[keep ? c : (1u << W0)];
-                } else {
-                    uint32_t s = (c - bc.code_lo < bc.code_span) ? 0u : reject;
-                    if (bc.key >= 0 && s == 0u) {
-                        const int64_t kv = (bc.base + (int64_t)c) >> bc.key_shift;
-                        s = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
-                    }
-                    slot[j] = keep ? s : reject;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                // byte address in the count table: one shift-add per row
-                atomicAdd((uint32_t*)((unsigned char*)cnt + ((slot[j] << sh_bytes) + lane_bytes)), 1u);
-                if constexpr (SUMBP) {
-                    if (slot[j] < G) atomicAdd(&csum[(slot[j] << rep_sh) + lane_part], (unsigned long long)code[j]);
-                }
+        for (int j = 0; j < kFastBatch; ++j) {
+            atomicAdd((uint32_t*)((unsigned char*)cnt + ((slot[j] << sh_bytes) + lane_bytes)), 1u);
+            if constexpr (SUMBP) {
+                if (slot[j] < G) atomicAdd(&csum[(slot[j] << rep_sh) + lane_part], (unsigned long long)code[j]);
             }
         }
     }
+}
 
-    // Index points: each point re-reads its row's code and adds its value
-    // when the row survives (the Plain x Index case of Section 5.1)
-    uint32_t* pmw = W.pts;
-    pmw[lane] = pm;
-    wave_lds_sync();
-#pragma unroll
-    for (int q = 0; q < kMaxIdx; ++q) {
-        if (q >= P.n_idx) continue;
-        const IdxCol& ic = P.idx[q];
-        unsigned long long* isum = (unsigned long long*)(ccq_lds + P.fast_isum_off) + (int64_t)q * G;
-        int64_t p0 = pcur[q];
-        for (;;) {
-            const int64_t i = p0 + lane;
-            const bool valid = i < ic.n;
-            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
-            const bool in = valid && pos < t0 + L;
-            const uint64_t m = wave_ballot(in);
-            if (in && any && ic.sum_slot >= 0) {
-                const int32_t rel = (int32_t)(pos - t0);
-                if (pmw[rel >> 5] & (1u << (rel & 31))) {
-                    const int64_t bit = pos * (int64_t)W0;
-                    const int64_t wq = bit >> 5;
-                    const uint32_t sh = (uint32_t)(bit & 31);
-                    const uint32_t lo = bc.packed[wq];
-                    const uint32_t hi = wq + 1 < bc.n_words ? bc.packed[wq + 1] : 0u;
-                    const uint32_t mask = W0 == 32 ? 0xFFFFFFFFu : ((1u << W0) - 1u);
-                    const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & mask;
-                    uint32_t slot;
-                    if constexpr (W0 <= kLutMaxBits) {
-                        slot = lut[code];
-                    } else {
-                        slot = (code - bc.code_lo < bc.code_span) ? 0u : G + 1;
-                        if (bc.key >= 0 && slot == 0u) {
-                            const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
-                            slot = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
-                        }
-                    }
-                    if (slot < G) {
-                        const int64_t v = ld_val(ic.vals, ic.vtype, i);
-                        if (v != 0) atomicAdd(&isum[slot], (unsigned long long)v);
-                    }
-                }
-            }
-            const int c = __builtin_popcountll(m);
-            p0 += c;
-            if (c < 64) break;
+// the slot of a code (a row's group, G = key out of domain, G + 1 = rejected)
+template <int W0>
+__device__ __forceinline__ uint32_t fast_slot(const BpCol& bc, uint32_t G, const uint8_t* lut, uint32_t code) {
+    if constexpr (W0 <= kLutMaxBits) {
+        return lut[code];
+    } else {
+        uint32_t slot = (code - bc.code_lo < bc.code_span) ? 0u : G + 1;
+        if (bc.key >= 0 && slot == 0u) {
+            const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
+            slot = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
         }
-        pcur[q] = p0;
+        return slot;
     }
+}
+
+// Index points of the fast path (at most one Index column).  The batch of
+// a tile is fetched one step ahead, the packed words under its points at the
+// start of the tile's own step; a point adds its value to its row's group
+// when the row survives (the Plain x Index case of Section 5.1).
+struct FastPoints {
+    int64_t pc;            // wave-uniform: first point of the batch in pos/val
+    int64_t pos, val;      // this lane's point (INT64_MAX past the column)
+    int64_t npos, nval;    // the batch after it
+};
+
+__device__ __forceinline__ void fast_points_fetch(const DevPlan& P, int64_t pc, int64_t& pos, int64_t& val) {
+    const IdxCol& ic = P.idx[0];
+    const bool have = P.n_idx > 0 && ic.n > 0;
+    const int64_t i = pc + lane_id();
+    const bool ok = have && i < ic.n;
+    const int64_t j = ok ? i : 0;
+    const int64_t p = ld_val_nb(have ? ic.pos : (const void*)&P, have ? ic.ptype : 2, j);
+    const int64_t v = ld_val_nb(have ? ic.vals : (const void*)&P, have ? ic.vtype : 2, j);
+    pos = ok ? p : INT64_MAX;
+    val = ok ? v : 0;
+}
+
+// the two packed words under a point (any word for a lane without one)
+template <int W0>
+__device__ __forceinline__ void fast_point_words(const BpCol& bc, int64_t pos, bool in, uint32_t& lo, uint32_t& hi) {
+    const int64_t wq = in ? (pos * (int64_t)W0) >> 5 : 0;
+    lo = gld(bc.packed, wq);
+    hi = gld(bc.packed, wq + 1 < bc.n_words ? wq + 1 : wq);
+}
+
+template <int W0>
+__device__ __forceinline__ void fast_point_add(const DevPlan& P, const uint32_t* pmw, int64_t t0, int64_t pos,
+                                               int64_t val, uint32_t lo, uint32_t hi, const uint8_t* lut) {
+    const BpCol& bc = P.bp[0];
+    const uint32_t G = (uint32_t)P.n_groups;
+    const int32_t rel = (int32_t)(pos - t0);
+    if (!((pmw[rel >> 5] >> (rel & 31)) & 1u)) return;
+    const uint32_t sh = (uint32_t)((pos * (int64_t)W0) & 31);
+    const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
+    const uint32_t slot = fast_slot<W0>(bc, G, lut, code);
+    if (slot < G && val != 0) {
+        unsigned long long* isum = (unsigned long long*)(ccq_lds + P.fast_isum_off);
+        atomicAdd(&isum[slot], (unsigned long long)val);
+    }
+}
+
+template <int KMAX, int W0>
+struct FastState {
+    FastRuns<KMAX> R;
+    FastPoints Q;
+    int64_t t0, t1, w0, w1;
+    uint32_t pm;
+    int32_t buf;           // which lane-mask buffer holds pm
+};
+
+// One pipeline step: count tile [t0, t1) from `wd` while the next tile's
+// mask is computed and its words are fetched into `wn`.  Returns false after
+// the wave's last tile.
+template <int KMAX, int W0, bool SUMBP>
+__device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, FastState<KMAX, W0>& S,
+                                          const uint32_t (&wd)[W0], uint32_t (&wn)[W0], const uint8_t* lut,
+                                          uint32_t* cnt) {
+    const int lane = lane_id();
+    const BpCol& bc = P.bp[0];
+    const bool sums = P.n_idx > 0 && P.idx[0].sum_slot >= 0;
+    // this tile's points: which lanes hold one; their words; the next batch
+    const bool pin = S.Q.pos < S.t1;
+    const int32_t pk = __builtin_popcountll(wave_ballot(pin));
+    uint32_t plo, phi;
+    fast_point_words<W0>(bc, S.Q.pos, pin, plo, phi);
+    fast_points_fetch(P, S.Q.pc + pk, S.Q.npos, S.Q.nval);
+    // the next tile (empty after the wave's last): its mask, then its words
+    const bool more = S.t1 < S.w1;
+    const int64_t n0 = S.t1;
+    const int64_t n1 = more ? min((n0 / P.tile_rows + 1) * P.tile_rows, S.w1) : n0;
+    const uint32_t pmn = fast_rle_mask<KMAX>(P, W, n0, n1, S.R) & fast_window_mask(n0, n1, S.w0);
+    W.pts[(S.buf ^ 1) * 64 + lane] = pmn;
+    fast_words<W0>(bc, n0, pmn, wn);
+    // this tile's rows
+    if (wave_ballot(S.pm != 0)) fast_rows<W0, SUMBP>(P, wd, S.pm, lut, cnt);
+    // this tile's points
     wave_lds_sync();
+    const uint32_t* pmw = W.pts + S.buf * 64;
+    if (pin && sums) fast_point_add<W0>(P, pmw, S.t0, S.Q.pos, S.Q.val, plo, phi, lut);
+    S.Q.pc += pk;
+    if (pk == 64) {
+        // more than one batch of points in this tile
+        for (;;) {
+            const bool in = S.Q.npos < S.t1;
+            const int32_t k = __builtin_popcountll(wave_ballot(in));
+            if (in && sums) {
+                uint32_t lo, hi;
+                fast_point_words<W0>(bc, S.Q.npos, true, lo, hi);
+                fast_point_add<W0>(P, pmw, S.t0, S.Q.npos, S.Q.nval, lo, hi, lut);
+            }
+            S.Q.pc += k;
+            fast_points_fetch(P, S.Q.pc, S.Q.npos, S.Q.nval);
+            if (k < 64) break;
+        }
+    }
+    S.Q.pos = S.Q.npos;
+    S.Q.val = S.Q.nval;
+    S.t0 = n0;
+    S.t1 = n1;
+    S.pm = pmn;
+    S.buf ^= 1;
+    return more;
+}
+
+// One wavefront over rows [w0, w1) of the plan's window, fast row path.
+template <int KMAX, int W0, bool SUMBP>
+__device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
+                                                const uint8_t* lut, uint32_t* cnt) {
+    if (w0 >= w1) return;
+    const int lane = lane_id();
+    FastState<KMAX, W0> S;
+    S.w0 = w0;
+    S.w1 = w1;
+    S.t0 = w0 & ~(int64_t)31;
+    S.t1 = min((S.t0 / P.tile_rows + 1) * P.tile_rows, w1);
+    S.buf = 0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        S.R.cur[c] = 0;
+        if (c >= P.k_rle) continue;
+        W.tog[c * 64 + lane] = 0;
+        S.R.cur[c] = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, S.t0);
+    }
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) fast_runs_fetch(P, S.R, c);
+    S.Q.pc = P.n_idx > 0 ? wave_lower_bound_pos(P.idx[0].pos, P.idx[0].ptype, P.idx[0].n, w0) : 0;
+    fast_points_fetch(P, S.Q.pc, S.Q.pos, S.Q.val);
+    wave_lds_sync();
+    S.pm = fast_rle_mask<KMAX>(P, W, S.t0, S.t1, S.R) & fast_window_mask(S.t0, S.t1, w0);
+    W.pts[lane] = S.pm;
+    uint32_t wa[W0], wb[W0];
+    fast_words<W0>(P.bp[0], S.t0, S.pm, wa);
+    wave_lds_sync();
+    // two steps per iteration so the word buffers swap without copies
+    for (;;) {
+        if (!fast_step<KMAX, W0, SUMBP>(P, W, S, wa, wb, lut, cnt)) break;
+        if (!fast_step<KMAX, W0, SUMBP>(P, W, S, wb, wa, lut, cnt)) break;
+    }
 }
 
 // Flush of the fast path's LDS tables into the global group table: add up
@@ -765,7 +1033,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
             const int l0 = f >= 2 ? f - 2 : 0;
             const int l1 = f < 63 ? f : 63;
             const uint64_t lanes = l1 >= l0 ? (((2ull << (l1 - l0)) - 1ull) << l0) : 0ull;
-            if (need_lanes & lanes) st[q] = bc.packed[wbase + q];
+            if (need_lanes & lanes) st[q] = gld(bc.packed, wbase + q);
         }
     }
     wave_lds_sync();
@@ -856,7 +1124,7 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
         if constexpr (W0 > 0 && W0 <= kLutMaxBits) {
             const uint32_t* src = (const uint32_t*)P.bp[0].lut;
             uint32_t* dst = (uint32_t*)s_lut;
-            for (int i = threadIdx.x; i < P.bp[0].lut_bytes / 4; i += blockDim.x) dst[i] = src[i];
+            for (int i = threadIdx.x; i < P.bp[0].lut_bytes / 4; i += blockDim.x) dst[i] = gld(src, i);
         }
 #pragma unroll
         for (int j = 0; j < kMaxBp; ++j) {
@@ -864,7 +1132,7 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
                 uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].lut_lds_off);
                 const uint32_t* src = (const uint32_t*)P.bp[j].lut;
                 const int n = P.bp[j].lut_bytes / 4;
-                for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+                for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = gld(src, i);
             }
         }
     }
@@ -883,7 +1151,7 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
 }
 
 __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
     WaveLds W;
     W.base = ccq_lds + P.lds_shared_bytes + wave * P.lds_wave_bytes;
     W.tn = (int32_t*)(W.base);            // slice header, 256 bytes (host layout reserves it)
@@ -895,6 +1163,7 @@ __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
     W.rows = (uint16_t*)(W.base + P.off_rows);
     W.pts = (uint32_t*)(W.base + P.off_pts);
     W.ptpre = (int32_t*)(W.base + P.off_ptpre);
+    W.tog = (uint32_t*)(W.base + P.off_tog);
     return W;
 }
 
@@ -904,35 +1173,31 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
                                            const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
                                            const int32_t (&luts)[kMaxBp], const uint8_t* s_lut, uint32_t* s_cnt) {
     if (w0 >= w1) return;
-    const bool sum_bp = W0 > 0 && P.bp[0].sum_slot >= 0;
-    int64_t pcur[kMaxIdx];
-    for (int c = 0; c < P.k_rle; ++c) {
-        const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0);
-        if (lane_id() == 0) W.cur[c] = x;
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxIdx; ++j)
-        pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
-    wave_lds_sync();
-    // row mode tiles start at multiples of 32 rows (lane words); the first
-    // one may start before the window, whose rows are then masked out
-    int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
-    while (t0 < w1) {
-        int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
-        stage_runs<KMAX>(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
-        const int32_t L = (int32_t)(t1 - t0);
-        const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
-        if (P.row_mode) {
-            if constexpr (W0 > 0) {
-                if (sum_bp) tile_row_fast<KMAX, W0, true>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
-                else tile_row_fast<KMAX, W0, false>(P, W, t0, L, lo_valid, pcur, s_lut, s_cnt);
-            } else {
-                tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
-            }
-        } else {
-            tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
+    if constexpr (W0 > 0) {
+        if (P.bp[0].sum_slot >= 0) wave_range_fast<KMAX, W0, true>(P, W, w0, w1, s_lut, s_cnt);
+        else wave_range_fast<KMAX, W0, false>(P, W, w0, w1, s_lut, s_cnt);
+    } else {
+        int64_t pcur[kMaxIdx];
+        for (int c = 0; c < P.k_rle; ++c) {
+            const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0);
+            if (lane_id() == 0) W.cur[c] = x;
         }
-        t0 = t1;
+#pragma unroll
+        for (int j = 0; j < kMaxIdx; ++j)
+            pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
+        wave_lds_sync();
+        // row mode tiles start at multiples of 32 rows (lane words); the first
+        // one may start before the window, whose rows are then masked out
+        int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
+        while (t0 < w1) {
+            int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
+            stage_runs<KMAX>(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
+            const int32_t L = (int32_t)(t1 - t0);
+            const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
+            if (P.row_mode) tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
+            else tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
+            t0 = t1;
+        }
     }
 }
 
@@ -979,7 +1244,7 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     tb.G = P.n_groups;
     tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
 
-    const int64_t gw = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + wave_id();
     const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
     const int64_t first_tile = P.row_begin / P.tile_rows;
     const int64_t w0 = max(P.row_begin, (first_tile + gw * tiles_per_wave) * P.tile_rows);
@@ -1025,7 +1290,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
 
         // this wave's share of the item's tiles
-        const int wave = threadIdx.x >> 6;
+        const int wave = wave_id();
         const int64_t per = (it.n_tiles + kWaves - 1) / kWaves;
         const int64_t first_tile = P.row_begin / P.tile_rows;
         const int64_t a = first_tile + it.first_tile + wave * per;

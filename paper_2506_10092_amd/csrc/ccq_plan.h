@@ -115,6 +115,9 @@ struct DevPlan {
     // fast row path: uint32 counts [(G + 2) << rep_shift] in static LDS; in
     // dynamic LDS uint64 code sums [G << rep_shift] and Index sums [n_idx * G]
     int32_t fast_rep_shift, fast_sum_off, fast_isum_off, fast_bytes;
+    // fast row path, inside a wave slice: RLE toggle bitmaps (64 words per
+    // column); off_pts holds two 64-word lane-mask buffers
+    int32_t off_tog, pad_fast_;
     RleCol rle[kMaxRle];
     BpCol bp[kMaxBp];
     IdxCol idx[kMaxIdx];
