@@ -466,26 +466,12 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             if (P.aggs[a].kind == kAggSumRle) P.any_rle_row = 1;
     }
     const int64_t window = P.row_end - P.row_begin;
-    if (P.row_mode) {
-        // a 2048-row tile; each column keeps at least 64 staged runs
-        P.span = kRowSpan;
-        P.run_cap = std::max(64 * P.k_rle, 128);
-    } else {
-        // aim for about a quarter of a column's LDS share per tile, so tiles
-        // rarely end early
-        P.run_cap = std::max(64 * P.k_rle, 1024);
-        double dens = 0;
-        for (int s = 0; s < P.k_rle; ++s)
-            dens = std::max(dens, (double)P.rle[s].n_runs / (double)std::max<int64_t>(t->n_rows, 1));
-        const double cap = P.k_rle ? (double)(P.run_cap / P.k_rle) : 0;
-        int64_t span = 1 << 16;
-        if (dens > 0) {
-            double want = cap / 4.0 / dens / 64.0;
-            span = 1;
-            while (span * 2 <= want && span < (1 << 16)) span *= 2;
-        }
-        P.span = (int32_t)span;
-    }
+    // 2048-row tiles, lane l owning rows [32l, 32l + 32) of the tile; each
+    // column keeps at least 64 staged runs (a tile that would overflow ends
+    // early, on a multiple of 32 rows).  Run mode stages more, as its columns
+    // are the only data read.
+    P.span = kRowSpan;
+    P.run_cap = P.row_mode ? std::max(64 * P.k_rle, 128) : std::max(64 * P.k_rle, 1024);
     P.tile_rows = (int64_t)64 * P.span;
     // nominal tiles: multiples of tile_rows in absolute row numbers that meet the window
     P.n_tiles = window > 0 ? (P.row_end - 1) / P.tile_rows - P.row_begin / P.tile_rows + 1 : 0;
@@ -496,32 +482,54 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     // that cannot overflow within one workgroup.
     P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
     P.w0 = 0;
+    P.fast_big = 0;
     {
-        bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
-                    (G + 2) * 8 <= kFastCntWords;
+        bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w);
         BpCol& b = P.bp[0];
+        const Fold& f = fold[bp_cols.empty() ? 0 : bp_cols[0]];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
         // workgroups: at least min(tiles / 4, one per CU); rows per workgroup bounded by that
         const int64_t min_blocks = std::max<int64_t>(1, std::min<int64_t>((P.n_tiles + 3) / 4, t->ctx->cus));
         const int64_t rows_per_wg = ((P.n_tiles + 4 * min_blocks - 1) / (4 * min_blocks)) * 4 * P.tile_rows;
         if (fast && rows_per_wg >= (int64_t)1 << 31) fast = false;
-        if (fast && lut16[0].empty()) {
-            if (b.pred == kPredSet) fast = false;
+        // the replicated static count table holds (G + 2) << 3 words; beyond
+        // that, one uint32 table of G + 2 counts in dynamic LDS, slots
+        // computed from the code (no set predicate, contiguous reachable
+        // keys), no SUM of the column itself
+        bool big = false;
+        if (fast && (G + 2) * 8 > kFastCntWords) {
+            big = (G + 2) * 4 <= kFastBigBytes && b.sum_slot < 0 && !f.has_set;
+            if (big && b.key >= 0 && P.keys[b.key].via_lut) {
+                const std::vector<int64_t>& sk = slot_keys[b.key];
+                big = sk.back() - sk.front() + 1 == (int64_t)sk.size();
+            }
+            if (!big) fast = false;
+        }
+        if (fast && (lut16[0].empty() || big)) {
+            if (!big && b.pred == kPredSet) fast = false;
+            const bool is_false = big ? f.is_false : b.pred == kPredFalse;
+            const bool has_range = big ? f.has_range : b.pred == kPredRange;
+            const int64_t rlo = big ? f.lo : b.lo, rhi = big ? f.hi : b.hi;
             const int64_t ncode = int64_t(1) << b.w;
             int64_t clo = 0, chi = ncode;
-            if (b.pred == kPredFalse) chi = 0;
-            if (b.pred == kPredRange) {
+            if (is_false) chi = 0;
+            if (has_range) {
                 // lo <= base + code < hi, in code space, clamped to the codes that exist
                 auto clampc = [&](int64_t x) { return x < 0 ? 0 : x > ncode ? ncode : x; };
-                const bool lo_ok = !__builtin_sub_overflow(b.lo, b.base, &clo);
-                const bool hi_ok = !__builtin_sub_overflow(b.hi, b.base, &chi);
-                clo = lo_ok ? clampc(clo) : (b.lo < 0 ? 0 : ncode);
-                chi = hi_ok ? clampc(chi) : (b.hi < 0 ? 0 : ncode);
+                const bool lo_ok = !__builtin_sub_overflow(rlo, b.base, &clo);
+                const bool hi_ok = !__builtin_sub_overflow(rhi, b.base, &chi);
+                clo = lo_ok ? clampc(clo) : (rlo < 0 ? 0 : ncode);
+                chi = hi_ok ? clampc(chi) : (rhi < 0 ? 0 : ncode);
             }
             b.code_lo = (uint32_t)std::min<int64_t>(clo, ncode - 1);
             b.code_span = (uint32_t)std::max<int64_t>(0, chi - clo);
+            b.key_lo = (b.key >= 0 && P.keys[b.key].via_lut) ? slot_keys[b.key].front() : 0;
         }
-        if (fast) P.w0 = b.w;
+        if (fast) {
+            P.w0 = b.w;
+            P.fast_big = big ? 1 : 0;
+            if (big) lut16[0].clear();      // no code table
+        }
     }
 
     // code tables.  Fast path: one byte per code holding the slot, G for a key
@@ -569,7 +577,16 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             sh = align16(sh + (size_t)P.bp[s].lut_bytes);
         }
     }
-    if (P.w0) {
+    if (P.w0 && P.fast_big) {
+        // one uint32 count per slot (G, G + 1: out of domain, rejected) in
+        // dynamic LDS; Index sums go to the global table
+        P.fast_rep_shift = 0;
+        P.fast_sum_off = (int32_t)sh;
+        sh = align16(sh + (size_t)(G + 2) * 4);
+        P.fast_isum_off = -1;
+        P.fast_bytes = (int32_t)(sh - P.fast_sum_off);
+        P.table_lds = 0;
+    } else if (P.w0) {
         // lane-replicated uint32 counts in static LDS: 32 replicas (a wave64 LDS
         // operation runs as two halves of 32 lanes, so no two lanes of a half
         // share an address), fewer when the slots do not fit
@@ -617,6 +634,20 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     wv = align16(wv + 4 * (size_t)P.run_cap);
     P.off_run_val = (int32_t)wv;
     wv = align16(wv + 8 * (size_t)P.run_cap);
+    // run-boundary bitmaps, their word prefixes, a toggle scratch bitmap and
+    // the lanes' surviving-row words
+    P.off_bnd = (int32_t)wv;
+    wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
+    P.off_bpre = (int32_t)wv;
+    wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
+    P.off_tog = (int32_t)wv;
+    wv = align16(wv + 256);
+    P.off_pmw = (int32_t)wv;
+    wv = align16(wv + 256);
+    // run mode with a global group table: LDS slots merging group segments
+    P.seg_slots = (!P.row_mode && P.n_keys > 0 && !P.table_lds) ? 1 : 0;
+    P.off_slots = (int32_t)wv;
+    if (P.seg_slots) wv = align16(wv + (size_t)kSegSlots * (2 + P.n_sums) * 8);
     if (P.row_mode && P.w0 == 0) {
         // generic row mode: compacted row list and staged packed words
         P.off_rows = (int32_t)wv;

@@ -30,7 +30,7 @@ struct ccq_batch {
 
     // per kernel instance
     int n_groups_used = 0;
-    int group_of[3][3];              // [kmax index][w0 index] -> group or -1
+    int group_of[3][kVariants];      // [kmax index][variant] -> group or -1
     std::vector<int> group_lds, group_grid;
     std::vector<std::vector<BatchItem>> group_items;
     int64_t n_items = 0;
@@ -53,7 +53,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int kidx(int kmax) { return kmax <= 2 ? 0 : kmax <= 4 ? 1 : 2; }
-int widx(int w0) { return w0 == 14 ? 1 : w0 == 20 ? 2 : 0; }
+int widx(const DevPlan& p) { return variant_of(p.w0, p.fast_big); }
 
 void drop_graph(ccq_batch* b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -78,7 +78,7 @@ ccq_status build_items(ccq_batch* b) {
     b->n_items = 0;
     for (int q : order) {
         const DevPlan& p = b->plans[q]->host;
-        const int g = b->group_of[kidx(p.kmax)][widx(p.w0)];
+        const int g = b->group_of[kidx(p.kmax)][widx(p)];
         for (int64_t t = 0; t < p.n_tiles; t += tpi) {
             BatchItem it;
             it.query = q;
@@ -125,11 +125,12 @@ ccq_status build_items(ccq_batch* b) {
         H.groups[g].n_items = (int32_t)b->group_items[g].size();
     }
     for (int ki = 0; ki < 3; ++ki)
-        for (int wi = 0; wi < 3; ++wi) {
+        for (int wi = 0; wi < kVariants; ++wi) {
             const int g = b->group_of[ki][wi];
             if (g < 0) continue;
             H.groups[g].kmax = ki == 0 ? 2 : ki == 1 ? 4 : 8;
-            H.groups[g].w0 = wi == 0 ? 0 : wi == 1 ? 14 : 20;
+            H.groups[g].w0 = variant_w0(wi);
+            H.groups[g].big = variant_big(wi);
         }
     memcpy(blob.data(), &H, sizeof H);
     memcpy(blob.data() + off_plans, b->plans_dev.data(), sizeof(void*) * n);
@@ -191,7 +192,7 @@ ccq_status ccq_batch_create(ccq_context* ctx, const ccq_plan* const* plans, int3
         const DevPlan& p = plans[i]->host;
         b->region.push_back((int64_t)off);
         off = align256(off + plans[i]->ws.total);
-        int& g = b->group_of[kidx(p.kmax)][widx(p.w0)];
+        int& g = b->group_of[kidx(p.kmax)][widx(p)];
         if (g < 0) {
             g = b->n_groups_used++;
             b->group_lds.push_back(0);
@@ -212,10 +213,10 @@ ccq_status ccq_batch_create(ccq_context* ctx, const ccq_plan* const* plans, int3
     b->ws_total = std::max<size_t>(off, 256);
     b->group_grid.resize(b->n_groups_used);
     for (int ki = 0; ki < 3; ++ki)
-        for (int wi = 0; wi < 3; ++wi) {
+        for (int wi = 0; wi < kVariants; ++wi) {
             const int g = b->group_of[ki][wi];
             if (g < 0) continue;
-            b->group_grid[g] = batch_grid_limit(ki == 0 ? 2 : ki == 1 ? 4 : 8, wi == 0 ? 0 : wi == 1 ? 14 : 20,
+            b->group_grid[g] = batch_grid_limit(ki == 0 ? 2 : ki == 1 ? 4 : 8, variant_w0(wi), variant_big(wi),
                                                 b->group_lds[g], ctx->cus);
         }
     if (ccq_status s = build_items(b)) {

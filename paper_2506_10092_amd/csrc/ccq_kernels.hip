@@ -223,7 +223,10 @@ struct WaveLds {
     uint16_t* rows;     // generic row mode: surviving rows of the tile, compacted
     uint32_t* pts;      // row mode: 64-word point bitmap per Index column
     int32_t* ptpre;     // row mode: exclusive popcount prefix per bitmap word
-    uint32_t* tog;      // fast row path: 64-word toggle bitmap per RLE column
+    uint32_t* tog;      // fast row path: 64-word toggle bitmap per RLE column; else one scratch bitmap
+    uint32_t* bnd;      // staged paths: 64-word run-boundary bitmap per RLE column
+    int32_t* bpre;      // staged paths: exclusive prefix of boundary popcounts per word
+    uint32_t* pmw;      // staged paths: the lanes' surviving-row words
     int32_t cap;        // staged runs per column; column c starts at slot c * cap
 };
 
@@ -494,6 +497,236 @@ __device__ __forceinline__ void tile_run_mode(const DevPlan& P, const WaveLds& W
     if (P.n_idx > 0) run_mode_points<KMAX>(P, W, t0, L, tb, status, pcur);
 }
 
+// ---- staged paths: run boundaries as bitmaps
+//
+// Tiles start at multiples of 32 rows and lane l owns the tile's rows
+// [32l, 32l + 32).  Once the runs of a tile are staged, every RLE column gets
+// a 64-word bitmap with a bit at each row where a new run starts inside the
+// tile, and the exclusive prefix of its popcounts per word: the staged run
+// holding row r is then bpre[r / 32] + popcount(bnd[r / 32] & bits <= r % 32),
+// with no search.  A column with predicates also gets its pass mask: toggles
+// where the outcome changes from one run to the next, prefix XOR, started
+// from the outcome of the tile's first run (Section 6 alignment restricted to
+// passing runs, as in the fast path).
+
+// bits 0..b of a word
+__device__ __forceinline__ uint32_t bits_le(int b) { return 0xFFFFFFFFu >> (31 - b); }
+
+// the lane's rows of [0, L) at or after lo_valid
+__device__ __forceinline__ uint32_t lane_window(int32_t L, int32_t lo_valid) {
+    const int32_t b = lane_id() * kRowSpan;
+    const int32_t lo = lo_valid - b, hi = L - b;
+    uint32_t m = 0xFFFFFFFFu;
+    if (lo > 0) m = lo >= 32 ? 0u : m << lo;
+    if (hi < 32) m &= hi <= 0 ? 0u : ((1u << hi) - 1u);
+    return m;
+}
+
+// Build the boundary bitmaps and prefixes of every RLE column from its
+// staged runs; return the lane's rows that lie in the window and pass every
+// RLE predicate.  The bitmaps are cleared again by tile_bitmaps_clear.
+template <int KMAX>
+__device__ __forceinline__ uint32_t tile_bitmaps(const DevPlan& P, const WaveLds& W, int32_t L, int32_t lo_valid) {
+    const int lane = lane_id();
+    uint32_t pm = lane_window(L, lo_valid);
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        if (c >= P.k_rle) continue;
+        const RleCol& rc = P.rle[c];
+        uint32_t* B = W.bnd + c * 64;
+        const int32_t* re = W.run_end + c * W.cap;
+        const int64_t* rv = W.run_val + c * W.cap;
+        const int n = W.tn[c];
+        const bool haspred = rc.pred != kPredNone;
+        uint32_t first = 0;
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            const int i = i0 + lane;
+            const bool valid = i < n;
+            const int32_t e = valid ? re[i] : 0x7FFFFFFF;
+            const bool pass = valid && (!haspred || pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, rv[i]));
+            const uint64_t pb = wave_ballot(pass);
+            if (i0 == 0) first = (uint32_t)(pb & 1u);
+            if (valid && e < L) {
+                atomicOr(&B[e >> 5], 1u << (e & 31));
+                if (haspred) {
+                    // outcome of the next staged run (it exists: this run ends inside the tile)
+                    const bool nxt = lane < 63 ? ((pb >> (lane + 1)) & 1u) != 0
+                                               : pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, rv[i + 1]);
+                    if (pass != nxt) atomicOr(&W.tog[e >> 5], 1u << (e & 31));
+                }
+            }
+        }
+        wave_lds_sync();
+        int tot;
+        W.bpre[c * 64 + lane] = wave_exclusive_sum(__builtin_popcount(B[lane]), &tot);
+        if (haspred) {
+            const uint32_t T = W.tog[lane];
+            W.tog[lane] = 0;
+            uint32_t x = T;
+            x ^= x << 1;
+            x ^= x << 2;
+            x ^= x << 4;
+            x ^= x << 8;
+            x ^= x << 16;
+            const uint64_t par = wave_ballot((__builtin_popcount(T) & 1) != 0);
+            const uint32_t flip = ((uint32_t)lanes_below(par) ^ first) & 1u;
+            pm &= flip ? ~x : x;
+        }
+        wave_lds_sync();
+    }
+    return pm;
+}
+
+__device__ __forceinline__ void tile_bitmaps_clear(const DevPlan& P, const WaveLds& W) {
+    wave_lds_sync();
+    for (int c = 0; c < P.k_rle; ++c) W.bnd[c * 64 + lane_id()] = 0;
+    wave_lds_sync();
+}
+
+// the staged run of column c holding tile row r
+__device__ __forceinline__ int32_t bm_run(const WaveLds& W, int c, int32_t r) {
+    return W.bpre[c * 64 + (r >> 5)] + __builtin_popcount(W.bnd[c * 64 + (r >> 5)] & bits_le(r & 31));
+}
+
+// Run mode on bitmaps: the lane's word is cut into segments at the run
+// boundaries of the key and SUM columns; a segment's surviving rows are
+// popcount(mask & segment); COUNT += rows and SUM += value * rows per segment
+// (Section 7 aggregating phase), consecutive segments of one group added in
+// registers first.
+template <int KMAX>
+__device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L, uint32_t pm,
+                                              const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
+                                              int64_t (&pcur)[kMaxIdx]) {
+    const int lane = lane_id();
+    uint32_t bw[KMAX];
+    int32_t pre[KMAX];
+    uint32_t U = 0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        bw[c] = 0;
+        pre[c] = 0;
+        if (c >= P.k_rle) continue;
+        bw[c] = W.bnd[c * 64 + lane];
+        pre[c] = W.bpre[c * 64 + lane];
+        if (P.rle[c].key_on || P.rle[c].sum_slot >= 0) U |= bw[c];
+    }
+    // group segments of the tile: cut at the key columns' boundaries; with a
+    // global table their pieces meet in LDS slots first
+    uint32_t K = 0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c)
+        if (c < P.k_rle && P.rle[c].key_on) K |= bw[c];
+    int kpre = 0, ktot = 0;
+    const int stride = 2 + P.n_sums;
+    if (P.seg_slots) kpre = wave_exclusive_sum(__builtin_popcount(K), &ktot);
+    if (pm) {
+        int s = 0;
+        for (;;) {
+            const uint32_t above = U & (0xFFFFFFFEu << s);      // boundaries after row s
+            const int e = above ? __builtin_ctz(above) : 32;
+            const uint32_t seg = (e >= 32 ? 0xFFFFFFFFu : ((1u << e) - 1u)) & (0xFFFFFFFFu << s);
+            const int64_t cnt = __builtin_popcount(pm & seg);
+            if (cnt) {
+                int64_t vals[KMAX];
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) {
+                    vals[c] = 0;
+                    if (c < P.k_rle && (P.rle[c].key_on || P.rle[c].sum_slot >= 0))
+                        vals[c] = W.run_val[c * W.cap + pre[c] + __builtin_popcount(bw[c] & bits_le(s))];
+                }
+                int64_t gid;
+                if (rle_key_part<KMAX>(P, vals, &gid, status)) {
+                    if (P.seg_slots) {
+                        const int sid = kpre + __builtin_popcount(K & bits_le(s));
+                        if (sid < kSegSlots) {
+                            unsigned long long* sl = (unsigned long long*)(W.base + P.off_slots) + sid * stride;
+                            sl[0] = (unsigned long long)gid;
+                            atomicAdd(&sl[1], (unsigned long long)cnt);
+#pragma unroll
+                            for (int c = 0; c < KMAX; ++c)
+                                if (c < P.k_rle && P.rle[c].sum_slot >= 0)
+                                    atomicAdd(&sl[2 + P.rle[c].sum_slot], (unsigned long long)(vals[c] * cnt));
+                        } else {
+                            table_add(tb, 0, gid, cnt);
+#pragma unroll
+                            for (int c = 0; c < KMAX; ++c)
+                                if (c < P.k_rle && P.rle[c].sum_slot >= 0)
+                                    table_add(tb, 1 + P.rle[c].sum_slot, gid, vals[c] * cnt);
+                        }
+                    } else {
+                        if (gid != acc.gid) {
+                            regacc_flush<KMAX>(P, tb, acc);
+                            acc.gid = gid;
+                        }
+                        acc.cnt += cnt;
+#pragma unroll
+                        for (int c = 0; c < KMAX; ++c)
+                            if (c < P.k_rle && P.rle[c].sum_slot >= 0) acc.rsum[c] += vals[c] * cnt;
+                    }
+                }
+            }
+            if (e >= 32) break;
+            s = e;
+        }
+    }
+    if (P.seg_slots) {
+        // one table add per group segment of the tile, then clear the slots
+        wave_lds_sync();
+        unsigned long long* sl = (unsigned long long*)(W.base + P.off_slots);
+        const int nseg = min(ktot + 1, kSegSlots);
+        for (int i = lane; i < nseg; i += 64) {
+            unsigned long long* q = sl + i * stride;
+            const int64_t cnt = (int64_t)q[1];
+            if (cnt) {
+                const int64_t gid = (int64_t)q[0];
+                table_add(tb, 0, gid, cnt);
+                for (int k = 0; k < P.n_sums; ++k)
+                    if (q[2 + k]) table_add(tb, 1 + k, gid, (int64_t)q[2 + k]);
+            }
+            for (int k = 0; k < stride; ++k) q[k] = 0;
+        }
+        wave_lds_sync();
+    }
+    if (P.n_idx > 0) {
+        // Index points: the point's row must survive; its runs come from the bitmaps
+        W.pmw[lane] = pm;
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < kMaxIdx; ++j) {
+            if (j >= P.n_idx) continue;
+            const IdxCol& ic = P.idx[j];
+            int64_t p0 = pcur[j];
+            for (;;) {
+                const int64_t i = p0 + lane;
+                const bool valid = i < ic.n;
+                const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
+                const bool in = valid && pos < t0 + L;
+                const uint64_t m = wave_ballot(in);
+                if (in && ic.sum_slot >= 0) {
+                    const int32_t rel = (int32_t)(pos - t0);
+                    if ((W.pmw[rel >> 5] >> (rel & 31)) & 1u) {
+                        int64_t vals[KMAX];
+#pragma unroll
+                        for (int c = 0; c < KMAX; ++c) {
+                            vals[c] = 0;
+                            if (c < P.k_rle && P.rle[c].key_on) vals[c] = W.run_val[c * W.cap + bm_run(W, c, rel)];
+                        }
+                        int64_t gid;
+                        if (rle_key_part<KMAX>(P, vals, &gid, status)) {
+                            const int64_t v = ld_val(ic.vals, ic.vtype, i);
+                            if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
+                        }
+                    }
+                }
+                const int c = __builtin_popcountll(m);
+                p0 += c;
+                if (c < 64) break;
+            }
+            pcur[j] = p0;
+        }
+    }
+}
+
 // The lane's 32 rows [32 lane, 32 lane + 32) of a row-mode tile that survive
 // every RLE predicate, as a bit mask; rows before lo_valid are excluded.
 template <int KMAX>
@@ -754,7 +987,7 @@ __device__ __forceinline__ void fast_words(const BpCol& bc, int64_t t0, uint32_t
 // replicas); the flush adds base * count.
 constexpr int kFastBatch = 8;
 
-template <int W0, bool SUMBP>
+template <int W0, bool SUMBP, bool BIG>
 __device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)[W0], uint32_t pm,
                                           const uint8_t* lut, uint32_t* cnt) {
     const int lane = lane_id();
@@ -774,13 +1007,13 @@ __device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)
             const uint32_t c = extract_code<W0>(wd, h + j);
             const bool keep = (pm >> (h + j)) & 1u;
             code[j] = c;
-            if constexpr (W0 <= kLutMaxBits) {
+            if constexpr (W0 <= kLutMaxBits && !BIG) {
                 slot[j] = lut[keep ? c : (1u << W0)];
             } else {
                 uint32_t s = (c - bc.code_lo < bc.code_span) ? 0u : reject;
                 if (bc.key >= 0 && s == 0u) {
                     const int64_t kv = (bc.base + (int64_t)c) >> bc.key_shift;
-                    s = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
+                    s = (kv >= 0 && kv < bc.key_card) ? (uint32_t)(kv - bc.key_lo) : G;
                 }
                 slot[j] = keep ? s : reject;
             }
@@ -796,15 +1029,15 @@ __device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)
 }
 
 // the slot of a code (a row's group, G = key out of domain, G + 1 = rejected)
-template <int W0>
+template <int W0, bool BIG>
 __device__ __forceinline__ uint32_t fast_slot(const BpCol& bc, uint32_t G, const uint8_t* lut, uint32_t code) {
-    if constexpr (W0 <= kLutMaxBits) {
+    if constexpr (W0 <= kLutMaxBits && !BIG) {
         return lut[code];
     } else {
         uint32_t slot = (code - bc.code_lo < bc.code_span) ? 0u : G + 1;
         if (bc.key >= 0 && slot == 0u) {
             const int64_t kv = (bc.base + (int64_t)code) >> bc.key_shift;
-            slot = (kv >= 0 && kv < bc.key_card) ? (uint32_t)kv : G;
+            slot = (kv >= 0 && kv < bc.key_card) ? (uint32_t)(kv - bc.key_lo) : G;
         }
         return slot;
     }
@@ -840,19 +1073,25 @@ __device__ __forceinline__ void fast_point_words(const BpCol& bc, int64_t pos, b
     hi = gld(bc.packed, wq + 1 < bc.n_words ? wq + 1 : wq);
 }
 
-template <int W0>
+template <int W0, bool BIG>
 __device__ __forceinline__ void fast_point_add(const DevPlan& P, const uint32_t* pmw, int64_t t0, int64_t pos,
-                                               int64_t val, uint32_t lo, uint32_t hi, const uint8_t* lut) {
+                                               int64_t val, uint32_t lo, uint32_t hi, const uint8_t* lut,
+                                               int64_t* table) {
     const BpCol& bc = P.bp[0];
     const uint32_t G = (uint32_t)P.n_groups;
     const int32_t rel = (int32_t)(pos - t0);
     if (!((pmw[rel >> 5] >> (rel & 31)) & 1u)) return;
     const uint32_t sh = (uint32_t)((pos * (int64_t)W0) & 31);
     const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
-    const uint32_t slot = fast_slot<W0>(bc, G, lut, code);
+    const uint32_t slot = fast_slot<W0, BIG>(bc, G, lut, code);
     if (slot < G && val != 0) {
-        unsigned long long* isum = (unsigned long long*)(ccq_lds + P.fast_isum_off);
-        atomicAdd(&isum[slot], (unsigned long long)val);
+        if constexpr (BIG) {
+            // a large table keeps no Index sums in LDS: points are few
+            atomicAdd((unsigned long long*)&table[(int64_t)(1 + P.idx[0].sum_slot) * G + slot], (unsigned long long)val);
+        } else {
+            unsigned long long* isum = (unsigned long long*)(ccq_lds + P.fast_isum_off);
+            atomicAdd(&isum[slot], (unsigned long long)val);
+        }
     }
 }
 
@@ -868,10 +1107,10 @@ struct FastState {
 // One pipeline step: count tile [t0, t1) from `wd` while the next tile's
 // mask is computed and its words are fetched into `wn`.  Returns false after
 // the wave's last tile.
-template <int KMAX, int W0, bool SUMBP>
+template <int KMAX, int W0, bool SUMBP, bool BIG>
 __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, FastState<KMAX, W0>& S,
                                           const uint32_t (&wd)[W0], uint32_t (&wn)[W0], const uint8_t* lut,
-                                          uint32_t* cnt) {
+                                          uint32_t* cnt, int64_t* table) {
     const int lane = lane_id();
     const BpCol& bc = P.bp[0];
     const bool sums = P.n_idx > 0 && P.idx[0].sum_slot >= 0;
@@ -889,11 +1128,11 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
     W.pts[(S.buf ^ 1) * 64 + lane] = pmn;
     fast_words<W0>(bc, n0, pmn, wn);
     // this tile's rows
-    if (wave_ballot(S.pm != 0)) fast_rows<W0, SUMBP>(P, wd, S.pm, lut, cnt);
+    if (wave_ballot(S.pm != 0)) fast_rows<W0, SUMBP, BIG>(P, wd, S.pm, lut, cnt);
     // this tile's points
     wave_lds_sync();
     const uint32_t* pmw = W.pts + S.buf * 64;
-    if (pin && sums) fast_point_add<W0>(P, pmw, S.t0, S.Q.pos, S.Q.val, plo, phi, lut);
+    if (pin && sums) fast_point_add<W0, BIG>(P, pmw, S.t0, S.Q.pos, S.Q.val, plo, phi, lut, table);
     S.Q.pc += pk;
     if (pk == 64) {
         // more than one batch of points in this tile
@@ -903,7 +1142,7 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
             if (in && sums) {
                 uint32_t lo, hi;
                 fast_point_words<W0>(bc, S.Q.npos, true, lo, hi);
-                fast_point_add<W0>(P, pmw, S.t0, S.Q.npos, S.Q.nval, lo, hi, lut);
+                fast_point_add<W0, BIG>(P, pmw, S.t0, S.Q.npos, S.Q.nval, lo, hi, lut, table);
             }
             S.Q.pc += k;
             fast_points_fetch(P, S.Q.pc, S.Q.npos, S.Q.nval);
@@ -920,9 +1159,9 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
 }
 
 // One wavefront over rows [w0, w1) of the plan's window, fast row path.
-template <int KMAX, int W0, bool SUMBP>
+template <int KMAX, int W0, bool SUMBP, bool BIG>
 __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
-                                                const uint8_t* lut, uint32_t* cnt) {
+                                                const uint8_t* lut, uint32_t* cnt, int64_t* table) {
     if (w0 >= w1) return;
     const int lane = lane_id();
     FastState<KMAX, W0> S;
@@ -950,8 +1189,8 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
     wave_lds_sync();
     // two steps per iteration so the word buffers swap without copies
     for (;;) {
-        if (!fast_step<KMAX, W0, SUMBP>(P, W, S, wa, wb, lut, cnt)) break;
-        if (!fast_step<KMAX, W0, SUMBP>(P, W, S, wb, wa, lut, cnt)) break;
+        if (!fast_step<KMAX, W0, SUMBP, BIG>(P, W, S, wa, wb, lut, cnt, table)) break;
+        if (!fast_step<KMAX, W0, SUMBP, BIG>(P, W, S, wb, wa, lut, cnt, table)) break;
     }
 }
 
@@ -959,7 +1198,7 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
 // the replicas of each slot; the code-space SUM gets base * count; the
 // out-of-domain slot raises the status.
 __device__ __forceinline__ void fast_flush(const DevPlan& P, int64_t* table, int32_t* status, bool sum_bp,
-                                           const uint32_t* cnt) {
+                                           const uint32_t* cnt, bool big) {
     const int64_t G = P.n_groups;
     const int R = 1 << P.fast_rep_shift;
     const unsigned long long* csum = (const unsigned long long*)(ccq_lds + P.fast_sum_off);
@@ -979,7 +1218,7 @@ __device__ __forceinline__ void fast_flush(const DevPlan& P, int64_t* table, int
             const unsigned long long v = s + (unsigned long long)P.bp[0].base * c;
             if (v) atomicAdd((unsigned long long*)&table[(int64_t)(1 + P.bp[0].sum_slot) * G + g], v);
         }
-        for (int q = 0; q < P.n_idx; ++q) {
+        for (int q = 0; q < (big ? 0 : P.n_idx); ++q) {
             const unsigned long long v = isum[q * G + g];
             if (v && P.idx[q].sum_slot >= 0)
                 atomicAdd((unsigned long long*)&table[(int64_t)(1 + P.idx[q].sum_slot) * G + g], v);
@@ -992,11 +1231,10 @@ __device__ __forceinline__ void fast_flush(const DevPlan& P, int64_t* table, int
 // they read are staged in LDS.
 template <int KMAX>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                                 int32_t lo_valid, const Table& tb, int32_t* status,
+                                                 uint32_t pm, const Table& tb, int32_t* status,
                                                  int64_t (&pcur)[kMaxIdx], const int32_t (&luts)[kMaxBp]) {
     const int lane = lane_id();
     const int32_t s0 = lane * kRowSpan;
-    const uint32_t pm = lane_row_mask<KMAX>(P, W, L, lo_valid);
     int64_t pbase[kMaxIdx];
     tile_points(P, W, t0, L, pcur, pbase);
 
@@ -1076,10 +1314,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
             rv[c] = 0;
-            if (P.any_rle_row && c < P.k_rle) {
-                const int32_t jj = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], r);
-                rv[c] = W.run_val[c * W.cap + jj];
-            }
+            if (P.any_rle_row && c < P.k_rle) rv[c] = W.run_val[c * W.cap + bm_run(W, c, r)];
         }
         if (P.any_rle_row) {
             int64_t g2;
@@ -1117,11 +1352,11 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 
 // Load the plan's code tables and clear its LDS tables (whole workgroup;
 // ends with a barrier).  luts[j]: LDS offset of column j's code table or -1.
-template <int W0>
+template <int W0, bool BIG>
 __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint32_t* s_cnt, int32_t (&luts)[kMaxBp],
                                          bool load_tables) {
     if (load_tables) {
-        if constexpr (W0 > 0 && W0 <= kLutMaxBits) {
+        if constexpr (W0 > 0 && W0 <= kLutMaxBits && !BIG) {
             const uint32_t* src = (const uint32_t*)P.bp[0].lut;
             uint32_t* dst = (uint32_t*)s_lut;
             for (int i = threadIdx.x; i < P.bp[0].lut_bytes / 4; i += blockDim.x) dst[i] = gld(src, i);
@@ -1139,7 +1374,8 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
 #pragma unroll
     for (int j = 0; j < kMaxBp; ++j) luts[j] = (W0 == 0 && j < P.n_bp && P.bp[j].lut) ? P.bp[j].lut_lds_off : -1;
     if constexpr (W0 > 0) {
-        for (int i = threadIdx.x; i < kFastCntWords; i += blockDim.x) s_cnt[i] = 0;
+        if constexpr (!BIG)
+            for (int i = threadIdx.x; i < kFastCntWords; i += blockDim.x) s_cnt[i] = 0;
         uint32_t* z = (uint32_t*)(ccq_lds + P.fast_sum_off);
         for (int i = threadIdx.x; i < P.fast_bytes / 4; i += blockDim.x) z[i] = 0;
     } else if (P.table_lds) {
@@ -1164,38 +1400,50 @@ __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
     W.pts = (uint32_t*)(W.base + P.off_pts);
     W.ptpre = (int32_t*)(W.base + P.off_ptpre);
     W.tog = (uint32_t*)(W.base + P.off_tog);
+    W.bnd = (uint32_t*)(W.base + P.off_bnd);
+    W.bpre = (int32_t*)(W.base + P.off_bpre);
+    W.pmw = (uint32_t*)(W.base + P.off_pmw);
     return W;
 }
 
 // One wavefront over rows [w0, w1) of the plan's window.
-template <int KMAX, int W0>
+template <int KMAX, int W0, bool BIG>
 __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
                                            const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
-                                           const int32_t (&luts)[kMaxBp], const uint8_t* s_lut, uint32_t* s_cnt) {
+                                           const int32_t (&luts)[kMaxBp], const uint8_t* s_lut, uint32_t* cnt) {
     if (w0 >= w1) return;
     if constexpr (W0 > 0) {
-        if (P.bp[0].sum_slot >= 0) wave_range_fast<KMAX, W0, true>(P, W, w0, w1, s_lut, s_cnt);
-        else wave_range_fast<KMAX, W0, false>(P, W, w0, w1, s_lut, s_cnt);
+        // a large table takes no SUM of the bit-packed column (host rule)
+        if (!BIG && P.bp[0].sum_slot >= 0) wave_range_fast<KMAX, W0, true, BIG>(P, W, w0, w1, s_lut, cnt, tb.g);
+        else wave_range_fast<KMAX, W0, false, BIG>(P, W, w0, w1, s_lut, cnt, tb.g);
     } else {
         int64_t pcur[kMaxIdx];
         for (int c = 0; c < P.k_rle; ++c) {
-            const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0);
+            const int64_t x = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, w0 & ~(int64_t)31);
             if (lane_id() == 0) W.cur[c] = x;
         }
 #pragma unroll
         for (int j = 0; j < kMaxIdx; ++j)
             pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
         wave_lds_sync();
-        // row mode tiles start at multiples of 32 rows (lane words); the first
-        // one may start before the window, whose rows are then masked out
-        int64_t t0 = P.row_mode ? (w0 & ~(int64_t)31) : w0;
+        for (int c = 0; c < P.k_rle; ++c) W.bnd[c * 64 + lane_id()] = 0;
+        W.tog[lane_id()] = 0;
+        if (P.seg_slots) {
+            unsigned long long* sl = (unsigned long long*)(W.base + P.off_slots);
+            for (int i = lane_id(); i < kSegSlots * (2 + P.n_sums); i += 64) sl[i] = 0;
+        }
+        // tiles start at multiples of 32 rows (lane words); the first one may
+        // start before the window, whose rows are then masked out
+        int64_t t0 = w0 & ~(int64_t)31;
         while (t0 < w1) {
             int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
-            stage_runs<KMAX>(P, W, t0, &t1, P.row_mode ? kRowSpan : 1);
+            stage_runs<KMAX>(P, W, t0, &t1, kRowSpan);
             const int32_t L = (int32_t)(t1 - t0);
             const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
-            if (P.row_mode) tile_row_generic<KMAX>(P, W, t0, L, lo_valid, tb, status, pcur, luts);
-            else tile_run_mode<KMAX>(P, W, t0, L, tb, status, acc, pcur);
+            const uint32_t pm = tile_bitmaps<KMAX>(P, W, L, lo_valid);
+            if (P.row_mode) tile_row_generic<KMAX>(P, W, t0, L, pm, tb, status, pcur, luts);
+            else tile_run_bits<KMAX>(P, W, t0, L, pm, tb, status, acc, pcur);
+            tile_bitmaps_clear(P, W);
             t0 = t1;
         }
     }
@@ -1203,11 +1451,11 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
 
 // Add the workgroup's LDS tables to the plan's global table (whole
 // workgroup; starts with a barrier).
-template <int KMAX, int W0>
-__device__ __forceinline__ void wg_flush(const DevPlan& P, int64_t* table, int32_t* status, const uint32_t* s_cnt) {
+template <int KMAX, int W0, bool BIG>
+__device__ __forceinline__ void wg_flush(const DevPlan& P, int64_t* table, int32_t* status, const uint32_t* cnt) {
     __syncthreads();
     if constexpr (W0 > 0) {
-        fast_flush(P, table, status, P.bp[0].sum_slot >= 0, s_cnt);
+        fast_flush(P, table, status, !BIG && P.bp[0].sum_slot >= 0, cnt, BIG);
     } else if (P.table_lds) {
         const unsigned long long* l = (const unsigned long long*)(ccq_lds + P.table_lds_off);
         const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
@@ -1227,18 +1475,20 @@ __device__ __forceinline__ void regacc_init(RegAcc<KMAX>& acc) {
 }
 
 // KMAX: bound on RLE columns (register arrays); W0: 0 = run mode or generic
-// row mode, else the width of the single bit-packed column of the fast row path.
+// row mode, else the width of the single bit-packed column of the fast row
+// path; BIG: that path with a large table in dynamic LDS.
 // One query: every wavefront takes a contiguous slice of whole nominal tiles.
-template <int KMAX, int W0>
+template <int KMAX, int W0, bool BIG>
 __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
                                                      int32_t* __restrict__ status, int64_t n_waves_total) {
     const DevPlan& P = *Pg;
     // fast row path: code table and lane-replicated counts in static LDS, so
     // their addresses fold into the ds_* offsets
-    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits) ? (1 << W0) + 16 : 16];
-    __shared__ uint32_t s_cnt[W0 > 0 ? kFastCntWords : 4];
+    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits && !BIG) ? (1 << W0) + 16 : 16];
+    __shared__ uint32_t s_cnt[(W0 > 0 && !BIG) ? kFastCntWords : 4];
+    uint32_t* cnt = BIG ? (uint32_t*)(ccq_lds + P.fast_sum_off) : s_cnt;
     int32_t luts[kMaxBp];
-    wg_setup<W0>(P, s_lut, s_cnt, luts, true);
+    wg_setup<W0, BIG>(P, s_lut, s_cnt, luts, true);
     Table tb;
     tb.g = table;
     tb.G = P.n_groups;
@@ -1253,20 +1503,20 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
     const WaveLds W = wave_lds(P);
     RegAcc<KMAX> acc;
     regacc_init(acc);
-    wave_range<KMAX, W0>(P, W, w0, w1, tb, status, acc, luts, s_lut, s_cnt);
+    wave_range<KMAX, W0, BIG>(P, W, w0, w1, tb, status, acc, luts, s_lut, cnt);
     regacc_flush<KMAX>(P, tb, acc);
-    wg_flush<KMAX, W0>(P, table, status, s_cnt);
+    wg_flush<KMAX, W0, BIG>(P, table, status, cnt);
 }
 
 // Many queries: workgroups take work items (a query and a range of its
 // nominal tiles) from a device counter, split the item's tiles across their
 // wavefronts, and add into that query's own table.  Code tables are reloaded
 // only when the query changes.
-template <int KMAX, int W0>
+template <int KMAX, int W0, bool BIG>
 __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__ B, int32_t group,
                                                      unsigned char* __restrict__ ws) {
-    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits) ? (1 << W0) + 16 : 16];
-    __shared__ uint32_t s_cnt[W0 > 0 ? kFastCntWords : 4];
+    __shared__ uint8_t s_lut[(W0 > 0 && W0 <= kLutMaxBits && !BIG) ? (1 << W0) + 16 : 16];
+    __shared__ uint32_t s_cnt[(W0 > 0 && !BIG) ? kFastCntWords : 4];
     __shared__ int32_t s_item;
     const BatchGroup& grp = B->groups[group];
     int32_t* counter = B->counters + group;
@@ -1282,7 +1532,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         int32_t* status = (int32_t*)(ws + B->region[it.query]);
         int64_t* table = (int64_t*)(ws + B->region[it.query] + 256);
         int32_t luts[kMaxBp];
-        wg_setup<W0>(P, s_lut, s_cnt, luts, it.query != loaded);
+        uint32_t* cnt = BIG ? (uint32_t*)(ccq_lds + P.fast_sum_off) : s_cnt;
+        wg_setup<W0, BIG>(P, s_lut, s_cnt, luts, it.query != loaded);
         loaded = it.query;
         Table tb;
         tb.g = table;
@@ -1301,9 +1552,9 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         const WaveLds W = wave_lds(P);
         RegAcc<KMAX> acc;
         regacc_init(acc);
-        wave_range<KMAX, W0>(P, W, w0, w1, tb, status, acc, luts, s_lut, s_cnt);
+        wave_range<KMAX, W0, BIG>(P, W, w0, w1, tb, status, acc, luts, s_lut, cnt);
         regacc_flush<KMAX>(P, tb, acc);
-        wg_flush<KMAX, W0>(P, table, status, s_cnt);
+        wg_flush<KMAX, W0, BIG>(P, table, status, cnt);
     }
 }
 
@@ -1511,17 +1762,18 @@ typedef void (*FusedFn)(const DevPlan*, int64_t*, int32_t*, int64_t);
 
 static FusedFn fused_kernel(const DevPlan& p) {
     const int k = p.kmax;
-#define CCQ_PICK(KM)                                       \
-    if (k <= KM) {                                          \
-        if (p.w0 == 14) return &k_fused<KM, 14>;            \
-        if (p.w0 == 20) return &k_fused<KM, 20>;            \
-        return &k_fused<KM, 0>;                             \
+    const bool big = p.fast_big != 0;
+#define CCQ_PICK(KM)                                                        \
+    if (k <= KM) {                                                           \
+        if (p.w0 == 14) return big ? &k_fused<KM, 14, true> : &k_fused<KM, 14, false>; \
+        if (p.w0 == 20) return big ? &k_fused<KM, 20, true> : &k_fused<KM, 20, false>; \
+        return &k_fused<KM, 0, false>;                                       \
     }
     CCQ_PICK(2)
     CCQ_PICK(4)
     CCQ_PICK(8)
 #undef CCQ_PICK
-    return &k_fused<8, 0>;
+    return &k_fused<8, 0, false>;
 }
 
 bool fast_row_width(int w) { return w == 14 || w == 20; }
@@ -1579,32 +1831,32 @@ hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream
 
 typedef void (*BatchFn)(const BatchDev*, int32_t, unsigned char*);
 
-static BatchFn batch_kernel(int kmax, int w0) {
-#define CCQ_PICKB(KM)                                      \
-    if (kmax <= KM) {                                       \
-        if (w0 == 14) return &k_batch<KM, 14>;              \
-        if (w0 == 20) return &k_batch<KM, 20>;              \
-        return &k_batch<KM, 0>;                             \
+static BatchFn batch_kernel(int kmax, int w0, int big) {
+#define CCQ_PICKB(KM)                                                       \
+    if (kmax <= KM) {                                                        \
+        if (w0 == 14) return big ? &k_batch<KM, 14, true> : &k_batch<KM, 14, false>; \
+        if (w0 == 20) return big ? &k_batch<KM, 20, true> : &k_batch<KM, 20, false>; \
+        return &k_batch<KM, 0, false>;                                       \
     }
     CCQ_PICKB(2)
     CCQ_PICKB(4)
     CCQ_PICKB(8)
 #undef CCQ_PICKB
-    return &k_batch<8, 0>;
+    return &k_batch<8, 0, false>;
 }
 
-int batch_grid_limit(int kmax, int w0, int lds_bytes, int cus) {
+int batch_grid_limit(int kmax, int w0, int big, int lds_bytes, int cus) {
     // occupancy per (instance, LDS bytes), computed once
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int>, int> cache;
-    const auto key = std::make_tuple(kmax, w0, lds_bytes);
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    const auto key = std::make_tuple(kmax, w0, big, lds_bytes);
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = cache.find(key);
         if (it != cache.end()) return it->second * cus;
     }
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel(kmax, w0), kThreads,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel(kmax, w0, big), kThreads,
                                                      lds_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
@@ -1623,7 +1875,7 @@ hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan
         const BatchGroup& grp = host.groups[g];
         if (grp.n_items == 0) continue;
         const int blocks = std::max(1, std::min(group_grid[g], grp.n_items));
-        hipLaunchKernelGGL(batch_kernel(grp.kmax, grp.w0), dim3(blocks), dim3(kThreads), group_lds[g], stream, dev,
+        hipLaunchKernelGGL(batch_kernel(grp.kmax, grp.w0, grp.big), dim3(blocks), dim3(kThreads), group_lds[g], stream, dev,
                            g, ws);
     }
     if (host.n > 0) hipLaunchKernelGGL(k_batch_fin, dim3(host.n), dim3(kThreads), 0, stream, dev, ws);

@@ -19,6 +19,8 @@ constexpr int kMaxAggs = 8;
 constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
 constexpr int64_t kMaxGroups = int64_t(1) << 27;
 constexpr int kLdsTableBytes = 16384;  // group tables up to this size live in LDS
+constexpr int kSegSlots = 128;        // group segments merged per tile in LDS
+constexpr int kFastBigBytes = 65536;   // fast row path: largest uint32 count table in dynamic LDS
 constexpr int kFastCntWords = 2048;    // fast row path: static LDS counts, (G + 2) * replicas
 
 enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3 };
@@ -65,6 +67,7 @@ struct BpCol {
     int32_t key_shift;      // key = value >> key_shift when key >= 0 and no code table
     int64_t key_card;
     int64_t key_stride;
+    int64_t key_lo;         // no code table: slot = key - key_lo (the reachable keys are contiguous)
 };
 
 struct IdxCol {
@@ -117,7 +120,16 @@ struct DevPlan {
     int32_t fast_rep_shift, fast_sum_off, fast_isum_off, fast_bytes;
     // fast row path, inside a wave slice: RLE toggle bitmaps (64 words per
     // column); off_pts holds two 64-word lane-mask buffers
-    int32_t off_tog, pad_fast_;
+    int32_t off_tog;
+    int32_t fast_big;       // fast row path with a large table: uint32 counts [G + 2] in dynamic LDS at
+                            // fast_sum_off, one replica, slots computed without a code table, Index
+                            // sums added to the global table
+    // staged paths, inside a wave slice: run-boundary bitmaps and their word
+    // prefixes (64 words per RLE column), the lanes' surviving-row words
+    int32_t off_bnd, off_bpre, off_pmw, pad_bits_;
+    // run mode with a global group table: per-wave LDS slots that merge the
+    // pieces of one group segment before they reach the table
+    int32_t seg_slots, off_slots;
     RleCol rle[kMaxRle];
     BpCol bp[kMaxBp];
     IdxCol idx[kMaxIdx];
@@ -140,10 +152,16 @@ struct BatchGroup {
     const BatchItem* items;
     int32_t n_items;
     int32_t kmax, w0;       // kernel instance
-    int32_t pad_;
+    int32_t big;            // fast path with a large table
 };
 
-constexpr int kMaxInstances = 9;     // KMAX in {2, 4, 8} x W0 in {0, 14, 20}
+// kernel instance variants besides KMAX: staged paths, fast row path of width
+// 14 or 20, each of those with a large table
+constexpr int kVariants = 5;
+constexpr int kMaxInstances = 3 * kVariants;     // KMAX in {2, 4, 8}
+inline int variant_of(int w0, int big) { return w0 == 0 ? 0 : (w0 == 14 ? 1 : 2) + (big ? 2 : 0); }
+inline int variant_w0(int v) { return v == 0 ? 0 : (v == 1 || v == 3) ? 14 : 20; }
+inline int variant_big(int v) { return v >= 3 ? 1 : 0; }
 
 // Where each query's result goes.
 struct BatchOut {
@@ -177,7 +195,7 @@ hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan
                         int32_t n_big, hipStream_t stream);
 
 // Persistent-grid size and dynamic LDS of a batch kernel instance.
-int batch_grid_limit(int kmax, int w0, int lds_bytes, int cus);
+int batch_grid_limit(int kmax, int w0, int big, int lds_bytes, int cus);
 
 // Largest group count the single-workgroup batched finalize handles.
 constexpr int64_t kBatchFinMaxGroups = int64_t(1) << 20;

@@ -167,19 +167,19 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
         // descriptor: BatchDev | counters | plans | regions | clear sizes | outs | items per group
         const int n = (int)reqs.size();
         const int32_t tpi = s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : 64;
-        int group_of[3][3];
+        int group_of[3][kVariants];
         for (auto& row : group_of)
             for (int& g : row) g = -1;
         int n_groups = 0;
         std::vector<std::vector<BatchItem>> items;
-        std::vector<int> glds, ggrid, gk, gw;
+        std::vector<int> glds, ggrid, gk, gw, gb;
         std::vector<const DevPlan*> plans_host(n), plans_dev(n);
         std::vector<int64_t> region(n), clear(n);
         std::vector<BatchOut> outs(n);
         std::vector<int32_t> big;
         for (int i = 0; i < n; ++i) {
             const DevPlan& p = reqs[i].plan->host;
-            const int ki = p.kmax <= 2 ? 0 : p.kmax <= 4 ? 1 : 2, wi = p.w0 == 14 ? 1 : p.w0 == 20 ? 2 : 0;
+            const int ki = p.kmax <= 2 ? 0 : p.kmax <= 4 ? 1 : 2, wi = variant_of(p.w0, p.fast_big);
             int& g = group_of[ki][wi];
             if (g < 0) {
                 g = n_groups++;
@@ -187,6 +187,7 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
                 glds.push_back(0);
                 gk.push_back(p.kmax);
                 gw.push_back(p.w0);
+                gb.push_back(p.fast_big);
             }
             glds[g] = std::max(glds[g], p.lds_dyn_bytes);
             for (int64_t t0 = 0; t0 < p.n_tiles; t0 += tpi) {
@@ -204,7 +205,7 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
                                reqs[i].result.n_groups, reqs[i].result.status};
             if (p.n_keys > 0 && p.n_groups > kBatchFinMaxGroups) big.push_back(i);
         }
-        for (int g = 0; g < n_groups; ++g) ggrid.push_back(batch_grid_limit(gk[g], gw[g], glds[g], s->ctx->cus));
+        for (int g = 0; g < n_groups; ++g) ggrid.push_back(batch_grid_limit(gk[g], gw[g], gb[g], glds[g], s->ctx->cus));
         size_t off = align256(sizeof(BatchDev));
         const size_t o_cnt = off;
         off = align256(off + sizeof(int32_t) * kMaxInstances);
@@ -238,6 +239,7 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
             H.groups[g].n_items = (int32_t)items[g].size();
             H.groups[g].kmax = gk[g];
             H.groups[g].w0 = gw[g];
+            H.groups[g].big = gb[g];
         }
         memcpy(h, &H, sizeof H);
         memcpy(h + o_plans, plans_dev.data(), sizeof(void*) * n);

@@ -227,3 +227,28 @@ def test_int64_positions_and_int32_values(ctx):
     q = {"preds": [("r0", "range", 0, 40000), ("d", "in", list(range(0, 200, 3)))], "keys": [("d", 0, 10000)],
          "aggs": [("sum", "s"), ("count",)], "window": (0, n)}
     check(ctx, c, q)
+
+
+@pytest.mark.parametrize("q", [
+    # GROUP BY the 14-bit dictionary column without an IN-list: 10,000 slots
+    {"preds": [("r0", "range", 0, 40000)], "keys": [("d", 0, 10000)], "aggs": [("count",), ("sum", "s")]},
+    {"preds": [("d", "range", 100, 9000), ("r1", "range", 5000, 60000)], "keys": [("d", 0, 10000)],
+     "aggs": [("count",)]},
+    # GROUP BY the 20-bit column shifted: 2^20 >> 7 = 8192 slots, window cut mid-word
+    {"preds": [("r0", "range", 10000, 50000)], "keys": [("p", 7, 8192)], "aggs": [("sum", "s"), ("count",)]},
+    # the key's domain excludes part of the column (domain errors are a status, checked elsewhere)
+    {"preds": [("p", "range", -(1 << 19), 0)], "keys": [("p", 6, 16384)], "aggs": [("count",)]},
+])
+def test_large_group_table_fast_path(ctx, q):
+    """Fast row path with a group table too large to replicate: uint32 counts
+    in dynamic LDS, slots computed from the code, Index sums added to the
+    global table."""
+    n = 3_000_017
+    t = datagen.config_c2(seed=61, n_rows=n, columns=("r0", "r1", "s", "d", "p"))
+    for window in ((0, n), (77, n - 5)):
+        qq = dict(q, window=window)
+        if q["keys"][0][0] == "p":
+            # codes of p reach keys below 0 ((base + code) >> shift < 0): restrict to the non-negative half
+            qq["preds"] = [x for x in q["preds"] if x[0] != "p"] + [("p", "range", 0, 1 << 19)]
+        got = check(ctx, t, qq)
+        say("groups", len(got["keys"]))
