@@ -471,7 +471,31 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     // early, on a multiple of 32 rows).  Run mode stages more, as its columns
     // are the only data read.
     P.span = kRowSpan;
-    P.run_cap = P.row_mode ? std::max(64 * P.k_rle, 128) : std::max(64 * P.k_rle, 1024);
+    // staged runs per column: twice the runs a tile holds on average (at
+    // least 64), so tiles rarely end early; run mode stages a little more
+    // (never more than the column's runs, and at most kMaxStagedRuns per
+    // wave in all: a column that needs more ends its tiles early)
+    P.run_cap = 0;
+    {
+        int64_t want[kMaxRle] = {0};
+        int64_t total = 0;
+        for (int s = 0; s < P.k_rle; ++s) {
+            const double per_tile =
+                (double)kRowTile * (double)P.rle[s].n_runs / (double)std::max<int64_t>(t->n_rows, 1);
+            int64_t cap = (int64_t)(2.0 * per_tile) + (P.row_mode ? 16 : 32);
+            cap = std::min<int64_t>(cap, P.rle[s].n_runs + 1);
+            want[s] = std::max<int64_t>(64, (cap + 15) & ~int64_t(15));
+            total += want[s];
+        }
+        for (int s = 0; s < P.k_rle; ++s) {
+            int64_t cap = want[s];
+            if (total > kMaxStagedRuns)
+                cap = std::max<int64_t>(64, (want[s] * kMaxStagedRuns / total) & ~int64_t(15));
+            P.rle[s].stage_base = P.run_cap;
+            P.rle[s].stage_cap = (int32_t)cap;
+            P.run_cap += (int32_t)cap;
+        }
+    }
     P.tile_rows = (int64_t)64 * P.span;
     // nominal tiles: multiples of tile_rows in absolute row numbers that meet the window
     P.n_tiles = window > 0 ? (P.row_end - 1) / P.tile_rows - P.row_begin / P.tile_rows + 1 : 0;

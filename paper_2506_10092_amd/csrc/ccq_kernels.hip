@@ -227,8 +227,11 @@ struct WaveLds {
     uint32_t* bnd;      // staged paths: 64-word run-boundary bitmap per RLE column
     int32_t* bpre;      // staged paths: exclusive prefix of boundary popcounts per word
     uint32_t* pmw;      // staged paths: the lanes' surviving-row words
-    int32_t cap;        // staged runs per column; column c starts at slot c * cap
 };
+
+// first staged-run slot and capacity of RLE column c in a wave slice
+__device__ __forceinline__ int32_t stage_base(const DevPlan& P, int c) { return P.rle[c].stage_base; }
+__device__ __forceinline__ int32_t stage_cap(const DevPlan& P, int c) { return P.rle[c].stage_cap; }
 
 // Stage the runs of every RLE column that overlap [t0, *t1) into LDS.  The
 // first 64-run batch of every column is loaded in one round trip; further
@@ -264,11 +267,12 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
         last_e[c] = 0;
         if (c >= P.k_rle) continue;
         const RleCol& rc = P.rle[c];
-        const int32_t off = c * W.cap;
+        const int32_t off = stage_base(P, c);
+        const int32_t cap = stage_cap(P, c);
         int32_t n = 0;
         int64_t e = e0[c], v = v0[c];
         for (;;) {
-            const bool valid = lo[c] + n + lane < rc.n_runs && n + lane < W.cap;
+            const bool valid = lo[c] + n + lane < rc.n_runs && n + lane < cap;
             const uint64_t last = wave_ballot(valid && e >= *t1);
             const uint64_t vmask = wave_ballot(valid);
             const int cnt = last ? __builtin_ctzll(last) + 1 : __builtin_popcountll(vmask);
@@ -280,7 +284,7 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             last_e[c] = __shfl(e, cnt - 1, 64);
             n += cnt;
             if (last) break;
-            if (n >= W.cap) {
+            if (n >= cap) {
                 const int64_t cut = t0 + ((last_e[c] - t0) / align) * align;
                 if (cut < *t1) {
                     *t1 = cut;
@@ -291,7 +295,7 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             const int64_t i = lo[c] + n + lane;
             e = INT64_MAX;
             v = 0;
-            if (i < rc.n_runs && n + lane < W.cap) {
+            if (i < rc.n_runs && n + lane < cap) {
                 e = gld(rc.ends, i);
                 v = ld_val(rc.vals, rc.vtype, i);
             }
@@ -308,71 +312,10 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
         if (c >= P.k_rle) continue;
         int64_t nxt;
         if (!shrunk) nxt = lo[c] + W.tn[c] - (last_e[c] > *t1 ? 1 : 0);
-        else nxt = lo[c] + lds_upper_bound(W.run_end + c * W.cap, W.tn[c], (int32_t)(*t1 - t0));
+        else nxt = lo[c] + lds_upper_bound(W.run_end + stage_base(P, c), W.tn[c], (int32_t)(*t1 - t0));
         if (lane == 0) W.cur[c] = nxt;
     }
     wave_lds_sync();
-}
-
-// A lane's merge over its rows: one cursor per RLE column into the staged
-// runs; the aligned run ends at the nearest cursor end.  Cursors only move
-// at boundaries strictly inside the lane's rows, and the staged runs of every
-// column cover the whole tile, so a cursor never runs past its column.
-template <int KMAX>
-struct Walk {
-    int32_t j[KMAX];
-    int32_t end[KMAX];
-    int64_t val[KMAX];
-    bool pass[KMAX];
-};
-
-template <int KMAX>
-__device__ __forceinline__ void walk_load(const DevPlan& P, const WaveLds& W, Walk<KMAX>& w, int c) {
-    const int32_t idx = c * W.cap + w.j[c];
-    w.end[c] = W.run_end[idx];
-    w.val[c] = W.run_val[idx];
-    const RleCol& rc = P.rle[c];
-    w.pass[c] = pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, w.val[c]);
-}
-
-template <int KMAX>
-__device__ __forceinline__ void walk_init(const DevPlan& P, const WaveLds& W, Walk<KMAX>& w, int32_t s0) {
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c) {
-        if (c < P.k_rle) {
-            w.j[c] = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], s0);
-            walk_load(P, W, w, c);
-        }
-    }
-}
-
-template <int KMAX>
-__device__ __forceinline__ int32_t walk_next(const DevPlan& P, const Walk<KMAX>& w, int32_t s1) {
-    int32_t e = s1;
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-        if (c < P.k_rle) e = min(e, w.end[c]);
-    return e;
-}
-
-template <int KMAX>
-__device__ __forceinline__ bool walk_pass(const DevPlan& P, const Walk<KMAX>& w) {
-    bool p = true;
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c)
-        if (c < P.k_rle) p = p && w.pass[c];
-    return p;
-}
-
-template <int KMAX>
-__device__ __forceinline__ void walk_advance(const DevPlan& P, const WaveLds& W, Walk<KMAX>& w, int32_t e) {
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c) {
-        if (c < P.k_rle && w.end[c] == e) {
-            w.j[c] += 1;
-            walk_load(P, W, w, c);
-        }
-    }
 }
 
 // Group id part from the RLE keys; false (status raised) if a key is out of
@@ -418,85 +361,6 @@ __device__ __forceinline__ void regacc_flush(const DevPlan& P, const Table& tb, 
     for (int c = 0; c < KMAX; ++c) a.rsum[c] = 0;
 }
 
-// Index points of a run-mode tile: each point looks up the runs holding its
-// row in the staged run ends (idx_in_rle) and adds its value.
-template <int KMAX>
-__device__ __forceinline__ void run_mode_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                                const Table& tb, int32_t* status, int64_t (&pcur)[kMaxIdx]) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int j = 0; j < kMaxIdx; ++j) {
-        if (j >= P.n_idx) continue;
-        const IdxCol& ic = P.idx[j];
-        int64_t p0 = pcur[j];
-        for (;;) {
-            const int64_t i = p0 + lane;
-            const bool valid = i < ic.n;
-            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
-            const bool in = valid && pos < t0 + L;
-            const uint64_t m = wave_ballot(in);
-            if (in) {
-                const int32_t rel = (int32_t)(pos - t0);
-                bool pass = true;
-                int64_t vals[KMAX];
-#pragma unroll
-                for (int c = 0; c < KMAX; ++c) {
-                    vals[c] = 0;
-                    if (c < P.k_rle) {
-                        const int32_t jj = lds_upper_bound(W.run_end + c * W.cap, W.tn[c], rel);
-                        vals[c] = W.run_val[c * W.cap + jj];
-                        const RleCol& rc = P.rle[c];
-                        pass = pass && pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, vals[c]);
-                    }
-                }
-                int64_t gid;
-                if (pass && rle_key_part<KMAX>(P, vals, &gid, status) && ic.sum_slot >= 0) {
-                    const int64_t v = ld_val(ic.vals, ic.vtype, i);
-                    if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
-                }
-            }
-            const int c = __builtin_popcountll(m);
-            p0 += c;
-            if (c < 64) break;
-        }
-        pcur[j] = p0;
-    }
-}
-
-// Run mode tile: no bit-packed column; aggregate per aligned run.
-template <int KMAX>
-__device__ __forceinline__ void tile_run_mode(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                              const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
-                                              int64_t (&pcur)[kMaxIdx]) {
-    const int32_t s0 = lane_id() * P.span;
-    const int32_t s1 = min(s0 + P.span, L);
-    if (s0 < s1) {
-        Walk<KMAX> w;
-        walk_init<KMAX>(P, W, w, s0);
-        int32_t x = s0;
-        while (x < s1) {
-            const int32_t e = walk_next<KMAX>(P, w, s1);
-            if (walk_pass<KMAX>(P, w)) {
-                int64_t gid;
-                if (rle_key_part<KMAX>(P, w.val, &gid, status)) {
-                    if (gid != acc.gid) {
-                        regacc_flush<KMAX>(P, tb, acc);
-                        acc.gid = gid;
-                    }
-                    const int64_t len = e - x;
-                    acc.cnt += len;
-#pragma unroll
-                    for (int c = 0; c < KMAX; ++c)
-                        if (c < P.k_rle && P.rle[c].sum_slot >= 0) acc.rsum[c] += w.val[c] * len;
-                }
-            }
-            if (e < s1) walk_advance<KMAX>(P, W, w, e);
-            x = e;
-        }
-    }
-    if (P.n_idx > 0) run_mode_points<KMAX>(P, W, t0, L, tb, status, pcur);
-}
-
 // ---- staged paths: run boundaries as bitmaps
 //
 // Tiles start at multiples of 32 rows and lane l owns the tile's rows
@@ -534,8 +398,8 @@ __device__ __forceinline__ uint32_t tile_bitmaps(const DevPlan& P, const WaveLds
         if (c >= P.k_rle) continue;
         const RleCol& rc = P.rle[c];
         uint32_t* B = W.bnd + c * 64;
-        const int32_t* re = W.run_end + c * W.cap;
-        const int64_t* rv = W.run_val + c * W.cap;
+        const int32_t* re = W.run_end + stage_base(P, c);
+        const int64_t* rv = W.run_val + stage_base(P, c);
         const int n = W.tn[c];
         const bool haspred = rc.pred != kPredNone;
         uint32_t first = 0;
@@ -632,7 +496,7 @@ __device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W
                 for (int c = 0; c < KMAX; ++c) {
                     vals[c] = 0;
                     if (c < P.k_rle && (P.rle[c].key_on || P.rle[c].sum_slot >= 0))
-                        vals[c] = W.run_val[c * W.cap + pre[c] + __builtin_popcount(bw[c] & bits_le(s))];
+                        vals[c] = W.run_val[stage_base(P, c) + pre[c] + __builtin_popcount(bw[c] & bits_le(s))];
                 }
                 int64_t gid;
                 if (rle_key_part<KMAX>(P, vals, &gid, status)) {
@@ -709,7 +573,7 @@ __device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W
 #pragma unroll
                         for (int c = 0; c < KMAX; ++c) {
                             vals[c] = 0;
-                            if (c < P.k_rle && P.rle[c].key_on) vals[c] = W.run_val[c * W.cap + bm_run(W, c, rel)];
+                            if (c < P.k_rle && P.rle[c].key_on) vals[c] = W.run_val[stage_base(P, c) + bm_run(W, c, rel)];
                         }
                         int64_t gid;
                         if (rle_key_part<KMAX>(P, vals, &gid, status)) {
@@ -725,32 +589,6 @@ __device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W
             pcur[j] = p0;
         }
     }
-}
-
-// The lane's 32 rows [32 lane, 32 lane + 32) of a row-mode tile that survive
-// every RLE predicate, as a bit mask; rows before lo_valid are excluded.
-template <int KMAX>
-__device__ __forceinline__ uint32_t lane_row_mask(const DevPlan& P, const WaveLds& W, int32_t L, int32_t lo_valid) {
-    const int32_t base = lane_id() * kRowSpan;
-    const int32_t s0 = max(base, lo_valid);
-    const int32_t s1 = min(base + kRowSpan, L);
-    uint32_t pm = 0;
-    if (s0 < s1) {
-        Walk<KMAX> w;
-        walk_init<KMAX>(P, W, w, s0);
-        int32_t x = s0;
-        while (x < s1) {
-            const int32_t e = walk_next<KMAX>(P, w, s1);
-            if (walk_pass<KMAX>(P, w)) {
-                const uint32_t a = (uint32_t)(x - base), b = (uint32_t)(e - base);   // bits [a, b)
-                const uint32_t below_b = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
-                pm |= below_b & ~((1u << a) - 1u);
-            }
-            if (e < s1) walk_advance<KMAX>(P, W, w, e);
-            x = e;
-        }
-    }
-    return pm;
 }
 
 // Point bitmaps of the tile (one bit per row carrying an Index point) with
@@ -1123,7 +961,7 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
     // the next tile (empty after the wave's last): its mask, then its words
     const bool more = S.t1 < S.w1;
     const int64_t n0 = S.t1;
-    const int64_t n1 = more ? min((n0 / P.tile_rows + 1) * P.tile_rows, S.w1) : n0;
+    const int64_t n1 = more ? min(((n0 >> kTileShift) + 1) << kTileShift, S.w1) : n0;
     const uint32_t pmn = fast_rle_mask<KMAX>(P, W, n0, n1, S.R) & fast_window_mask(n0, n1, S.w0);
     W.pts[(S.buf ^ 1) * 64 + lane] = pmn;
     fast_words<W0>(bc, n0, pmn, wn);
@@ -1168,7 +1006,7 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
     S.w0 = w0;
     S.w1 = w1;
     S.t0 = w0 & ~(int64_t)31;
-    S.t1 = min((S.t0 / P.tile_rows + 1) * P.tile_rows, w1);
+    S.t1 = min(((S.t0 >> kTileShift) + 1) << kTileShift, w1);
     S.buf = 0;
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
@@ -1314,7 +1152,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
             rv[c] = 0;
-            if (P.any_rle_row && c < P.k_rle) rv[c] = W.run_val[c * W.cap + bm_run(W, c, r)];
+            if (P.any_rle_row && c < P.k_rle) rv[c] = W.run_val[stage_base(P, c) + bm_run(W, c, r)];
         }
         if (P.any_rle_row) {
             int64_t g2;
@@ -1393,7 +1231,6 @@ __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
     W.tn = (int32_t*)(W.base);            // slice header, 256 bytes (host layout reserves it)
     W.tlo = (int64_t*)(W.base + 64);
     W.cur = (int64_t*)(W.base + 128);
-    W.cap = P.k_rle > 0 ? P.run_cap / P.k_rle : 0;
     W.run_end = (int32_t*)(W.base + P.off_run_end);
     W.run_val = (int64_t*)(W.base + P.off_run_val);
     W.rows = (uint16_t*)(W.base + P.off_rows);
@@ -1436,7 +1273,7 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
         // start before the window, whose rows are then masked out
         int64_t t0 = w0 & ~(int64_t)31;
         while (t0 < w1) {
-            int64_t t1 = min((t0 / P.tile_rows + 1) * P.tile_rows, w1);
+            int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
             stage_runs<KMAX>(P, W, t0, &t1, kRowSpan);
             const int32_t L = (int32_t)(t1 - t0);
             const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
@@ -1496,9 +1333,9 @@ __global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ 
 
     const int64_t gw = (int64_t)blockIdx.x * kWaves + wave_id();
     const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
-    const int64_t first_tile = P.row_begin / P.tile_rows;
-    const int64_t w0 = max(P.row_begin, (first_tile + gw * tiles_per_wave) * P.tile_rows);
-    const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) * P.tile_rows);
+    const int64_t first_tile = P.row_begin >> kTileShift;
+    const int64_t w0 = max(P.row_begin, (first_tile + gw * tiles_per_wave) << kTileShift);
+    const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) << kTileShift);
 
     const WaveLds W = wave_lds(P);
     RegAcc<KMAX> acc;
@@ -1543,11 +1380,11 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         // this wave's share of the item's tiles
         const int wave = wave_id();
         const int64_t per = (it.n_tiles + kWaves - 1) / kWaves;
-        const int64_t first_tile = P.row_begin / P.tile_rows;
+        const int64_t first_tile = P.row_begin >> kTileShift;
         const int64_t a = first_tile + it.first_tile + wave * per;
         const int64_t b = first_tile + it.first_tile + min((int64_t)it.n_tiles, (wave + 1) * per);
-        const int64_t w0 = max(P.row_begin, a * P.tile_rows);
-        const int64_t w1 = min(P.row_end, b * P.tile_rows);
+        const int64_t w0 = max(P.row_begin, a << kTileShift);
+        const int64_t w1 = min(P.row_end, b << kTileShift);
 
         const WaveLds W = wave_lds(P);
         RegAcc<KMAX> acc;

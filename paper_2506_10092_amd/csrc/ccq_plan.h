@@ -10,7 +10,8 @@ namespace ccq {
 constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kThreads / 64;
 constexpr int kRowSpan = 32;           // rows per lane in row mode (one bitmap word)
-constexpr int kRowTile = 64 * kRowSpan;   // 2048 rows per wavefront tile in row mode
+constexpr int kRowTile = 64 * kRowSpan;   // 2048 rows per wavefront tile (every path)
+constexpr int kTileShift = 11;            // log2(kRowTile)
 constexpr int kMaxRle = 8;
 constexpr int kMaxBp = 4;
 constexpr int kMaxIdx = 2;
@@ -19,7 +20,8 @@ constexpr int kMaxAggs = 8;
 constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
 constexpr int64_t kMaxGroups = int64_t(1) << 27;
 constexpr int kLdsTableBytes = 16384;  // group tables up to this size live in LDS
-constexpr int kSegSlots = 128;        // group segments merged per tile in LDS
+constexpr int kMaxStagedRuns = 1536;  // staged runs per wave slice, all RLE columns together
+constexpr int kSegSlots = 64;         // group segments merged per tile in LDS
 constexpr int kFastBigBytes = 65536;   // fast row path: largest uint32 count table in dynamic LDS
 constexpr int kFastCntWords = 2048;    // fast row path: static LDS counts, (G + 2) * replicas
 
@@ -45,6 +47,8 @@ struct RleCol {
     int32_t key_shift;
     int64_t key_card;
     int64_t key_stride;
+    int32_t stage_base;     // staged paths: first run slot of this column in a wave slice
+    int32_t stage_cap;      // and its capacity (>= 64)
 };
 
 struct BpCol {
