@@ -1311,12 +1311,19 @@ __device__ __forceinline__ void regacc_init(RegAcc<KMAX>& acc) {
     for (int c = 0; c < KMAX; ++c) acc.rsum[c] = 0;
 }
 
+// Waves per SIMD the single-query fast row path is compiled for: its
+// software pipeline keeps a tile of words in flight per wave, and five waves
+// hide the rest of the HBM latency better than four, even at the price of a
+// few spilled registers (measured); the staged paths and the batched kernel,
+// whose extra state would spill far more, keep the compiler's choice.
+constexpr int kFastWaves(int w0) { return w0 > 0 ? 5 : 1; }
+
 // KMAX: bound on RLE columns (register arrays); W0: 0 = run mode or generic
 // row mode, else the width of the single bit-packed column of the fast row
 // path; BIG: that path with a large table in dynamic LDS.
 // One query: every wavefront takes a contiguous slice of whole nominal tiles.
 template <int KMAX, int W0, bool BIG>
-__global__ __launch_bounds__(kThreads) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
+__global__ __launch_bounds__(kThreads, kFastWaves(W0)) void k_fused(const DevPlan* __restrict__ Pg, int64_t* __restrict__ table,
                                                      int32_t* __restrict__ status, int64_t n_waves_total) {
     const DevPlan& P = *Pg;
     // fast row path: code table and lane-replicated counts in static LDS, so
