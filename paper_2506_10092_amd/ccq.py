@@ -134,6 +134,10 @@ def lib():
     """Load libccq.so; raise if it has not been built."""
     global _lib
     if _lib is None:
+        # torch carries its own HIP runtime; loading it first makes this
+        # library bind to that same runtime, so device pointers and streams
+        # from torch are valid here (one runtime per process)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise CcqError(E_UNSUPPORTED, "libccq.so is not built (run __graft_entry__.build()); "
                                           "there is no CPU fallback")
