@@ -574,6 +574,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
                                                                                            : (uint8_t)lut[code];
             b.lut_u8 = 1;
             b.lut_bytes = (int32_t)l8.size();
+            b.ones_reject = l8[n - 1] == (uint8_t)(G + 1) ? 1 : 0;
             fix_ptr(&b.lut, blob_put(l8.data(), l8.size()));
             continue;
         }

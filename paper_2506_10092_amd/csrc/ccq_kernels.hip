@@ -825,7 +825,7 @@ __device__ __forceinline__ void fast_words(const BpCol& bc, int64_t t0, uint32_t
 // replicas); the flush adds base * count.
 constexpr int kFastBatch = 8;
 
-template <int W0, bool SUMBP, bool BIG>
+template <int W0, bool SUMBP, bool BIG, bool ONES>
 __device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)[W0], uint32_t pm,
                                           const uint8_t* lut, uint32_t* cnt) {
     const int lane = lane_id();
@@ -836,6 +836,7 @@ __device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)
     const uint32_t lane_bytes = lane_part * 4u, sh_bytes = rep_sh + 2u;
     unsigned long long* csum = (unsigned long long*)(ccq_lds + P.fast_sum_off);
     const uint32_t reject = G + 1;
+    const int32_t npm = (int32_t)~pm;
 #pragma unroll
     for (int h = 0; h < kRowSpan; h += kFastBatch) {
         uint32_t slot[kFastBatch];
@@ -845,7 +846,11 @@ __device__ __forceinline__ void fast_rows(const DevPlan& P, const uint32_t (&wd)
             const uint32_t c = extract_code<W0>(wd, h + j);
             const bool keep = (pm >> (h + j)) & 1u;
             code[j] = c;
-            if constexpr (W0 <= kLutMaxBits && !BIG) {
+            if constexpr (W0 <= kLutMaxBits && !BIG && ONES) {
+                // removed rows read the all-ones code, whose entry rejects
+                const uint32_t all = (uint32_t)__builtin_amdgcn_sbfe(npm, h + j, 1);
+                slot[j] = lut[c | (all & ((1u << W0) - 1u))];
+            } else if constexpr (W0 <= kLutMaxBits && !BIG) {
                 slot[j] = lut[keep ? c : (1u << W0)];
             } else {
                 uint32_t s = (c - bc.code_lo < bc.code_span) ? 0u : reject;
@@ -945,7 +950,7 @@ struct FastState {
 // One pipeline step: count tile [t0, t1) from `wd` while the next tile's
 // mask is computed and its words are fetched into `wn`.  Returns false after
 // the wave's last tile.
-template <int KMAX, int W0, bool SUMBP, bool BIG>
+template <int KMAX, int W0, bool SUMBP, bool BIG, bool ONES>
 __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, FastState<KMAX, W0>& S,
                                           const uint32_t (&wd)[W0], uint32_t (&wn)[W0], const uint8_t* lut,
                                           uint32_t* cnt, int64_t* table) {
@@ -966,7 +971,7 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
     W.pts[(S.buf ^ 1) * 64 + lane] = pmn;
     fast_words<W0>(bc, n0, pmn, wn);
     // this tile's rows
-    if (wave_ballot(S.pm != 0)) fast_rows<W0, SUMBP, BIG>(P, wd, S.pm, lut, cnt);
+    if (wave_ballot(S.pm != 0)) fast_rows<W0, SUMBP, BIG, ONES>(P, wd, S.pm, lut, cnt);
     // this tile's points
     wave_lds_sync();
     const uint32_t* pmw = W.pts + S.buf * 64;
@@ -997,7 +1002,7 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
 }
 
 // One wavefront over rows [w0, w1) of the plan's window, fast row path.
-template <int KMAX, int W0, bool SUMBP, bool BIG>
+template <int KMAX, int W0, bool SUMBP, bool BIG, bool ONES>
 __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
                                                 const uint8_t* lut, uint32_t* cnt, int64_t* table) {
     if (w0 >= w1) return;
@@ -1027,8 +1032,8 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
     wave_lds_sync();
     // two steps per iteration so the word buffers swap without copies
     for (;;) {
-        if (!fast_step<KMAX, W0, SUMBP, BIG>(P, W, S, wa, wb, lut, cnt, table)) break;
-        if (!fast_step<KMAX, W0, SUMBP, BIG>(P, W, S, wb, wa, lut, cnt, table)) break;
+        if (!fast_step<KMAX, W0, SUMBP, BIG, ONES>(P, W, S, wa, wb, lut, cnt, table)) break;
+        if (!fast_step<KMAX, W0, SUMBP, BIG, ONES>(P, W, S, wb, wa, lut, cnt, table)) break;
     }
 }
 
@@ -1251,8 +1256,15 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
     if (w0 >= w1) return;
     if constexpr (W0 > 0) {
         // a large table takes no SUM of the bit-packed column (host rule)
-        if (!BIG && P.bp[0].sum_slot >= 0) wave_range_fast<KMAX, W0, true, BIG>(P, W, w0, w1, s_lut, cnt, tb.g);
-        else wave_range_fast<KMAX, W0, false, BIG>(P, W, w0, w1, s_lut, cnt, tb.g);
+        const bool sum = !BIG && P.bp[0].sum_slot >= 0;
+        constexpr bool LUT = W0 <= kLutMaxBits && !BIG;
+        if (LUT && P.bp[0].ones_reject) {
+            if (sum) wave_range_fast<KMAX, W0, true, BIG, LUT>(P, W, w0, w1, s_lut, cnt, tb.g);
+            else wave_range_fast<KMAX, W0, false, BIG, LUT>(P, W, w0, w1, s_lut, cnt, tb.g);
+        } else {
+            if (sum) wave_range_fast<KMAX, W0, true, BIG, false>(P, W, w0, w1, s_lut, cnt, tb.g);
+            else wave_range_fast<KMAX, W0, false, BIG, false>(P, W, w0, w1, s_lut, cnt, tb.g);
+        }
     } else {
         int64_t pcur[kMaxIdx];
         for (int c = 0; c < P.k_rle; ++c) {

@@ -72,6 +72,9 @@ struct BpCol {
     int64_t key_card;
     int64_t key_stride;
     int64_t key_lo;         // no code table: slot = key - key_lo (the reachable keys are contiguous)
+    int32_t ones_reject;    // fast path code table: the all-ones code is rejected, so a row the RLE
+                            // predicates removed can be sent there by OR-ing its code with all ones
+    int32_t pad_ones_;
 };
 
 struct IdxCol {
