@@ -659,16 +659,20 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     wv = align16(wv + 4 * (size_t)P.run_cap);
     P.off_run_val = (int32_t)wv;
     wv = align16(wv + 8 * (size_t)P.run_cap);
-    // run-boundary bitmaps, their word prefixes, a toggle scratch bitmap and
-    // the lanes' surviving-row words
+
+    // run-boundary bitmaps and their word prefixes (one of each per RLE
+    // column), a scratch toggle bitmap (when a column has predicates) and the
+    // lanes' surviving-row words (when Index points are read)
     P.off_bnd = (int32_t)wv;
     wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
     P.off_bpre = (int32_t)wv;
     wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
-    P.off_tog = (int32_t)wv;
-    wv = align16(wv + 256);
+    bool any_pred = false;
+    for (int s = 0; s < P.k_rle; ++s) any_pred = any_pred || P.rle[s].pred != kPredNone;
+    P.off_tog = any_pred ? (int32_t)wv : -1;
+    if (any_pred) wv = align16(wv + 256);
     P.off_pmw = (int32_t)wv;
-    wv = align16(wv + 256);
+    if (P.n_idx > 0) wv = align16(wv + 256);
     // run mode with a global group table: LDS slots merging group segments
     P.seg_slots = (!P.row_mode && P.n_keys > 0 && !P.table_lds) ? 1 : 0;
     P.off_slots = (int32_t)wv;

@@ -100,6 +100,21 @@ __device__ __forceinline__ int wave_exclusive_sum(int v, int* total) {
     return x - v;
 }
 
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS): sums over 4, 8 and 16 lanes within each row of 16,
+// then row 0's total into row 1, row 2's into row 3, and lane 31's into rows
+// 2 and 3.
+__device__ __forceinline__ int wave_inclusive_sum_dpp(int v) {
+    int s = v + __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    s += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);          // row_shr:2
+    s += __builtin_amdgcn_update_dpp(0, v, 0x113, 0xf, 0xf, true);          // row_shr:3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xf, 0xe, false);         // row_shr:4, banks 1-3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xf, 0xc, false);         // row_shr:8, banks 2-3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x142, 0xa, 0xf, false);         // row_bcast:15 into rows 1, 3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x143, 0xc, 0xf, false);         // row_bcast:31 into rows 2, 3
+    return s;
+}
+
 // Cross-lane LDS hand-off inside one wavefront: a wave's LDS operations
 // execute in order, so only compiler reordering has to be prevented.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -219,11 +234,12 @@ struct WaveLds {
     int64_t* tlo;       // [kMaxRle] run index of each column's first staged run
     int64_t* cur;       // [kMaxRle] run index holding the next tile's first row
     int32_t* run_end;   // [run_cap] run end - tile start, capped at 2^30
-    int64_t* run_val;   // [run_cap]
+    int64_t* run_val;   // [run_cap] run value; for a key column that is not summed, its group-id part
+                        // (key value times its radix weight, -1 outside the key's domain)
     uint16_t* rows;     // generic row mode: surviving rows of the tile, compacted
     uint32_t* pts;      // row mode: 64-word point bitmap per Index column
     int32_t* ptpre;     // row mode: exclusive popcount prefix per bitmap word
-    uint32_t* tog;      // fast row path: 64-word toggle bitmap per RLE column; else one scratch bitmap
+    uint32_t* tog;      // 64-word toggle bitmap per RLE column
     uint32_t* bnd;      // staged paths: 64-word run-boundary bitmap per RLE column
     int32_t* bpre;      // staged paths: exclusive prefix of boundary popcounts per word
     uint32_t* pmw;      // staged paths: the lanes' surviving-row words
@@ -233,16 +249,41 @@ struct WaveLds {
 __device__ __forceinline__ int32_t stage_base(const DevPlan& P, int c) { return P.rle[c].stage_base; }
 __device__ __forceinline__ int32_t stage_cap(const DevPlan& P, int c) { return P.rle[c].stage_cap; }
 
-// Stage the runs of every RLE column that overlap [t0, *t1) into LDS.  The
-// first 64-run batch of every column is loaded in one round trip; further
-// batches follow only for columns with more runs in the tile.  A column that
-// would exceed its share shrinks *t1 to the end of its last staged run
-// (rounded down to `align` rows), so all columns cover the (possibly
-// shorter) tile.  Also leaves in W.cur the run holding the next tile's first
-// row.
+// bits 0..b of a word
+__device__ __forceinline__ uint32_t bits_le(int b) { return 0xFFFFFFFFu >> (31 - b); }
+
+// the lane's rows of [0, L) at or after lo_valid
+__device__ __forceinline__ uint32_t lane_window(int32_t L, int32_t lo_valid) {
+    const int32_t b = lane_id() * kRowSpan;
+    const int32_t lo = lo_valid - b, hi = L - b;
+    uint32_t m = 0xFFFFFFFFu;
+    if (lo > 0) m = lo >= 32 ? 0u : m << lo;
+    if (hi < 32) m &= hi <= 0 ? 0u : ((1u << hi) - 1u);
+    return m;
+}
+
+// Stage the runs of every RLE column that overlap [t0, *t1) into LDS and
+// build the tile's bitmaps in the same pass (tiles start at multiples of 32
+// rows; lane l owns rows [32l, 32l + 32)).  The first 64-run batch of every
+// column is loaded in one round trip; further batches follow only for
+// columns with more runs in the tile.  A column that would exceed its share
+// shrinks *t1 to the end of its last staged run, rounded down to 32 rows, so
+// all columns cover the (possibly shorter) tile.  Per column, while a batch
+// is in registers:
+//   - the run's end, value and (key columns) group-id part (key value times
+//     its radix weight, -1 outside the key's domain) go to LDS;
+//   - a bit marks the row where the next run starts (boundary bitmap; its
+//     word prefixes follow with one wavefront scan), so the staged run holding
+//     row r is bpre[r / 32] + popcount(bnd[r / 32] & bits <= r % 32);
+//   - with predicates, a toggle marks the rows where the outcome changes from
+//     one run to the next; the inclusive prefix XOR of the toggles, started
+//     from the outcome of the tile's first run, is the column's pass mask
+//     (Section 6 alignment restricted to passing runs).
+// Returns the lane's rows in the window [w0, ...) that pass every RLE
+// predicate; leaves in W.cur the run holding the next tile's first row.
 template <int KMAX>
-__device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t* t1,
-                                           int64_t align) {
+__device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t* t1,
+                                               int64_t w0) {
     const int lane = lane_id();
     int64_t e0[KMAX], v0[KMAX], lo[KMAX];
 #pragma unroll
@@ -260,6 +301,7 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             }
         }
     }
+    uint32_t pm = 0xFFFFFFFFu;
     bool shrunk = false;
     int64_t last_e[KMAX];
 #pragma unroll
@@ -269,6 +311,12 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
         const RleCol& rc = P.rle[c];
         const int32_t off = stage_base(P, c);
         const int32_t cap = stage_cap(P, c);
+        uint32_t* B = W.bnd + c * 64;
+        uint32_t* T = W.tog;
+        const bool haspred = rc.pred != kPredNone;
+        uint32_t first = 0;
+        bool carry_pass = false;      // the previous batch's last staged run
+        int64_t carry_e = INT64_MAX;
         int32_t n = 0;
         int64_t e = e0[c], v = v0[c];
         for (;;) {
@@ -276,16 +324,39 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             const uint64_t last = wave_ballot(valid && e >= *t1);
             const uint64_t vmask = wave_ballot(valid);
             const int cnt = last ? __builtin_ctzll(last) + 1 : __builtin_popcountll(vmask);
-            if (lane < cnt) {
+            const bool st = lane < cnt;
+            const bool pass = st && (!haspred || pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, v));
+            const uint64_t pb = wave_ballot(pass);
+            if (n == 0) first = (uint32_t)(pb & 1u);
+            else if (haspred && lane == 0 && carry_e < *t1 && carry_pass != ((pb & 1u) != 0)) {
+                const uint32_t r = (uint32_t)(carry_e - t0);
+                atomicOr(&T[r >> 5], 1u << (r & 31));
+            }
+            if (st) {
                 const int64_t rel = e - t0;
                 W.run_end[off + n + lane] = (int32_t)(rel < (1 << 30) ? rel : (1 << 30));
-                W.run_val[off + n + lane] = v;
+                // a key column that is not summed keeps its group-id part instead of its value
+                int64_t keep = v;
+                if (rc.key_on && rc.sum_slot < 0) {
+                    const int64_t kv = v >> rc.key_shift;
+                    keep = (kv >= 0 && kv < rc.key_card) ? kv * rc.key_stride : -1;
+                }
+                W.run_val[off + n + lane] = keep;
+                if (e < *t1) {
+                    const uint32_t r = (uint32_t)rel;
+                    atomicOr(&B[r >> 5], 1u << (r & 31));
+                    // the next run's outcome (within this batch; across batches: below)
+                    if (haspred && lane < cnt - 1 && pass != (((pb >> (lane + 1)) & 1u) != 0))
+                        atomicOr(&T[r >> 5], 1u << (r & 31));
+                }
             }
-            last_e[c] = __shfl(e, cnt - 1, 64);
+            carry_pass = ((pb >> (cnt - 1)) & 1u) != 0;
+            carry_e = __shfl(e, cnt - 1, 64);
+            last_e[c] = carry_e;
             n += cnt;
             if (last) break;
             if (n >= cap) {
-                const int64_t cut = t0 + ((last_e[c] - t0) / align) * align;
+                const int64_t cut = t0 + ((last_e[c] - t0) & ~(int64_t)(kRowSpan - 1));
                 if (cut < *t1) {
                     *t1 = cut;
                     shrunk = true;
@@ -304,6 +375,29 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
             W.tn[c] = n;
             W.tlo[c] = lo[c];
         }
+        if (haspred) {
+            // the column's pass mask from its toggles (one scratch bitmap, cleared for the next column)
+            wave_lds_sync();
+            const uint32_t t = T[lane];
+            T[lane] = 0;
+            uint32_t x = t;
+            x ^= x << 1;
+            x ^= x << 2;
+            x ^= x << 4;
+            x ^= x << 8;
+            x ^= x << 16;
+            const uint64_t par = wave_ballot((__builtin_popcount(t) & 1) != 0);
+            const uint32_t flip = ((uint32_t)lanes_below(par) ^ first) & 1u;
+            pm &= flip ? ~x : x;
+        }
+    }
+    wave_lds_sync();
+    // boundary prefixes per word
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        if (c >= P.k_rle) continue;
+        const int bc = __builtin_popcount(W.bnd[c * 64 + lane]);
+        W.bpre[c * 64 + lane] = wave_inclusive_sum_dpp(bc) - bc;
     }
     wave_lds_sync();
     // the run holding row t1: the last staged run unless it ends exactly at t1
@@ -316,21 +410,28 @@ __device__ __forceinline__ void stage_runs(const DevPlan& P, const WaveLds& W, i
         if (lane == 0) W.cur[c] = nxt;
     }
     wave_lds_sync();
+    return pm & lane_window((int32_t)(*t1 - t0), (int32_t)(max(t0, w0) - t0));
 }
 
-// Group id part from the RLE keys; false (status raised) if a key is out of
-// its domain.
+// Group-id part of the RLE keys from the staged runs' precomputed parts
+// (idx[c]: the staged run of column c); false (status raised) if a key is
+// outside its domain.
 template <int KMAX>
-__device__ __forceinline__ bool rle_key_part(const DevPlan& P, const int64_t (&vals)[KMAX], int64_t* gid,
-                                             int32_t* status) {
+__device__ __forceinline__ bool rle_key_part(const DevPlan& P, const WaveLds& W, const int32_t (&idx)[KMAX],
+                                             int64_t* gid, int32_t* status) {
     int64_t g = 0;
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
         if (c < P.k_rle && P.rle[c].key_on) {
-            const int64_t kv = vals[c] >> P.rle[c].key_shift;
-            if (kv < 0 || kv >= P.rle[c].key_card) ok = false;
-            g += kv * P.rle[c].key_stride;
+            const RleCol& rc = P.rle[c];
+            int64_t part = W.run_val[stage_base(P, c) + idx[c]];   // staged as the part
+            if (rc.sum_slot >= 0) {                                 // staged as the value
+                const int64_t kv = part >> rc.key_shift;
+                part = (kv >= 0 && kv < rc.key_card) ? kv * rc.key_stride : -1;
+            }
+            ok = ok && part >= 0;
+            g += part;
         }
     }
     if (!ok) raise_status(status, -4);
@@ -372,74 +473,6 @@ __device__ __forceinline__ void regacc_flush(const DevPlan& P, const Table& tb, 
 // where the outcome changes from one run to the next, prefix XOR, started
 // from the outcome of the tile's first run (Section 6 alignment restricted to
 // passing runs, as in the fast path).
-
-// bits 0..b of a word
-__device__ __forceinline__ uint32_t bits_le(int b) { return 0xFFFFFFFFu >> (31 - b); }
-
-// the lane's rows of [0, L) at or after lo_valid
-__device__ __forceinline__ uint32_t lane_window(int32_t L, int32_t lo_valid) {
-    const int32_t b = lane_id() * kRowSpan;
-    const int32_t lo = lo_valid - b, hi = L - b;
-    uint32_t m = 0xFFFFFFFFu;
-    if (lo > 0) m = lo >= 32 ? 0u : m << lo;
-    if (hi < 32) m &= hi <= 0 ? 0u : ((1u << hi) - 1u);
-    return m;
-}
-
-// Build the boundary bitmaps and prefixes of every RLE column from its
-// staged runs; return the lane's rows that lie in the window and pass every
-// RLE predicate.  The bitmaps are cleared again by tile_bitmaps_clear.
-template <int KMAX>
-__device__ __forceinline__ uint32_t tile_bitmaps(const DevPlan& P, const WaveLds& W, int32_t L, int32_t lo_valid) {
-    const int lane = lane_id();
-    uint32_t pm = lane_window(L, lo_valid);
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c) {
-        if (c >= P.k_rle) continue;
-        const RleCol& rc = P.rle[c];
-        uint32_t* B = W.bnd + c * 64;
-        const int32_t* re = W.run_end + stage_base(P, c);
-        const int64_t* rv = W.run_val + stage_base(P, c);
-        const int n = W.tn[c];
-        const bool haspred = rc.pred != kPredNone;
-        uint32_t first = 0;
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int i = i0 + lane;
-            const bool valid = i < n;
-            const int32_t e = valid ? re[i] : 0x7FFFFFFF;
-            const bool pass = valid && (!haspred || pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, rv[i]));
-            const uint64_t pb = wave_ballot(pass);
-            if (i0 == 0) first = (uint32_t)(pb & 1u);
-            if (valid && e < L) {
-                atomicOr(&B[e >> 5], 1u << (e & 31));
-                if (haspred) {
-                    // outcome of the next staged run (it exists: this run ends inside the tile)
-                    const bool nxt = lane < 63 ? ((pb >> (lane + 1)) & 1u) != 0
-                                               : pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, rv[i + 1]);
-                    if (pass != nxt) atomicOr(&W.tog[e >> 5], 1u << (e & 31));
-                }
-            }
-        }
-        wave_lds_sync();
-        int tot;
-        W.bpre[c * 64 + lane] = wave_exclusive_sum(__builtin_popcount(B[lane]), &tot);
-        if (haspred) {
-            const uint32_t T = W.tog[lane];
-            W.tog[lane] = 0;
-            uint32_t x = T;
-            x ^= x << 1;
-            x ^= x << 2;
-            x ^= x << 4;
-            x ^= x << 8;
-            x ^= x << 16;
-            const uint64_t par = wave_ballot((__builtin_popcount(T) & 1) != 0);
-            const uint32_t flip = ((uint32_t)lanes_below(par) ^ first) & 1u;
-            pm &= flip ? ~x : x;
-        }
-        wave_lds_sync();
-    }
-    return pm;
-}
 
 __device__ __forceinline__ void tile_bitmaps_clear(const DevPlan& P, const WaveLds& W) {
     wave_lds_sync();
@@ -491,15 +524,19 @@ __device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W
             const uint32_t seg = (e >= 32 ? 0xFFFFFFFFu : ((1u << e) - 1u)) & (0xFFFFFFFFu << s);
             const int64_t cnt = __builtin_popcount(pm & seg);
             if (cnt) {
+                int32_t idx[KMAX];
                 int64_t vals[KMAX];
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c) {
+                    idx[c] = 0;
                     vals[c] = 0;
-                    if (c < P.k_rle && (P.rle[c].key_on || P.rle[c].sum_slot >= 0))
-                        vals[c] = W.run_val[stage_base(P, c) + pre[c] + __builtin_popcount(bw[c] & bits_le(s))];
+                    if (c < P.k_rle && (P.rle[c].key_on || P.rle[c].sum_slot >= 0)) {
+                        idx[c] = pre[c] + __builtin_popcount(bw[c] & bits_le(s));
+                        if (P.rle[c].sum_slot >= 0) vals[c] = W.run_val[stage_base(P, c) + idx[c]];
+                    }
                 }
                 int64_t gid;
-                if (rle_key_part<KMAX>(P, vals, &gid, status)) {
+                if (rle_key_part<KMAX>(P, W, idx, &gid, status)) {
                     if (P.seg_slots) {
                         const int sid = kpre + __builtin_popcount(K & bits_le(s));
                         if (sid < kSegSlots) {
@@ -569,14 +606,14 @@ __device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W
                 if (in && ic.sum_slot >= 0) {
                     const int32_t rel = (int32_t)(pos - t0);
                     if ((W.pmw[rel >> 5] >> (rel & 31)) & 1u) {
-                        int64_t vals[KMAX];
+                        int32_t idx[KMAX];
 #pragma unroll
                         for (int c = 0; c < KMAX; ++c) {
-                            vals[c] = 0;
-                            if (c < P.k_rle && P.rle[c].key_on) vals[c] = W.run_val[stage_base(P, c) + bm_run(W, c, rel)];
+                            idx[c] = 0;
+                            if (c < P.k_rle && P.rle[c].key_on) idx[c] = bm_run(W, c, rel);
                         }
                         int64_t gid;
-                        if (rle_key_part<KMAX>(P, vals, &gid, status)) {
+                        if (rle_key_part<KMAX>(P, W, idx, &gid, status)) {
                             const int64_t v = ld_val(ic.vals, ic.vtype, i);
                             if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
                         }
@@ -1154,14 +1191,19 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
         }
         if (!pass) continue;
         int64_t rv[KMAX];
+        int32_t ridx[KMAX];
 #pragma unroll
         for (int c = 0; c < KMAX; ++c) {
             rv[c] = 0;
-            if (P.any_rle_row && c < P.k_rle) rv[c] = W.run_val[stage_base(P, c) + bm_run(W, c, r)];
+            ridx[c] = 0;
+            if (P.any_rle_row && c < P.k_rle) {
+                ridx[c] = bm_run(W, c, r);
+                if (P.rle[c].sum_slot >= 0) rv[c] = W.run_val[stage_base(P, c) + ridx[c]];
+            }
         }
         if (P.any_rle_row) {
             int64_t g2;
-            if (!rle_key_part<KMAX>(P, rv, &g2, status)) continue;
+            if (!rle_key_part<KMAX>(P, W, ridx, &g2, status)) continue;
             gid += g2;
         }
         if (dom) {
@@ -1276,7 +1318,7 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
             pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
         wave_lds_sync();
         for (int c = 0; c < P.k_rle; ++c) W.bnd[c * 64 + lane_id()] = 0;
-        W.tog[lane_id()] = 0;
+        if (P.off_tog >= 0) W.tog[lane_id()] = 0;
         if (P.seg_slots) {
             unsigned long long* sl = (unsigned long long*)(W.base + P.off_slots);
             for (int i = lane_id(); i < kSegSlots * (2 + P.n_sums); i += 64) sl[i] = 0;
@@ -1286,10 +1328,8 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
         int64_t t0 = w0 & ~(int64_t)31;
         while (t0 < w1) {
             int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
-            stage_runs<KMAX>(P, W, t0, &t1, kRowSpan);
+            const uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
             const int32_t L = (int32_t)(t1 - t0);
-            const int32_t lo_valid = (int32_t)(max(t0, w0) - t0);
-            const uint32_t pm = tile_bitmaps<KMAX>(P, W, L, lo_valid);
             if (P.row_mode) tile_row_generic<KMAX>(P, W, t0, L, pm, tb, status, pcur, luts);
             else tile_run_bits<KMAX>(P, W, t0, L, pm, tb, status, acc, pcur);
             tile_bitmaps_clear(P, W);
