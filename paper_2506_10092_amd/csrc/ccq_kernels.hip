@@ -693,43 +693,120 @@ __device__ __forceinline__ uint32_t extract_code(const uint32_t (&wd)[W0 > 0 ? W
 // packed stream (tiles start at multiples of 32 rows), held in registers.
 //
 // RLE predicates never stage runs: each lane takes one run of a 64-run batch
-// read straight from HBM, evaluates the predicate once for it, and marks a
-// toggle at the run's end when the outcome of the next run differs.  The
-// inclusive prefix XOR of the toggles over the tile, started from the
+// read straight from HBM, the predicate is evaluated once per run, and a
+// toggle is marked at a run's end when the outcome of the next run differs.
+// The inclusive prefix XOR of the toggles over the tile, started from the
 // outcome of the run holding the tile's first row, is the column's pass
 // mask (Section 6 alignment: the AND over columns of these masks is the
-// merge of their run ends restricted to passing runs).
+// merge of their run ends restricted to passing runs).  Outcomes and
+// toggles of a batch are 64-bit lane masks in scalar registers.
 //
 // A wave walks its tiles as a software pipeline: while tile i is counted,
 // the packed words of tile i+1 (only for lanes with surviving rows), the run
-// batches of tile i+2 and the Index points of tile i+1 are in flight.
+// batches of tile i+2 and the Index points of tile i+1 are in flight.  Batch
+// loads address through wave-uniform buffer resources, so their addressing
+// is scalar work only.
 
-template <int KMAX>
-struct FastRuns {
-    int64_t cur[KMAX];   // wave-uniform: the run held by lane 0 of the batch
-    int64_t e[KMAX];     // this lane's run end (INT64_MAX past the column)
-    int64_t v[KMAX];     // its value
-};
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// Prefetches issue the same loads on every path (clamped indices, a word of
-// the plan itself for an absent column), so the compiler's count of loads in
-// flight stays exact and a use waits only for its own loads.
-template <int KMAX>
-__device__ __forceinline__ void fast_runs_fetch(const DevPlan& P, FastRuns<KMAX>& R, int c) {
-    const RleCol& rc = P.rle[c];
-    const bool have = c < P.k_rle && rc.n_runs > 0;
-    const int64_t i = R.cur[c] + lane_id();
-    const bool ok = have && i < rc.n_runs;
-    const int64_t j = ok ? i : 0;
-    const int64_t e = gld(have ? rc.ends : (const int64_t*)&P, j);
-    const int64_t v = ld_val_nb(have ? rc.vals : (const void*)&P, have ? rc.vtype : 2, j);
-    R.e[c] = ok ? e : INT64_MAX;
-    R.v[c] = ok ? v : 0;
+// Wave-uniform buffer resource over the n bytes at p + off, n clamped to
+// [0, cap]; a read past them returns zero without a memory access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uni_rsrc(const void* p, int64_t off, int64_t n, int32_t cap) {
+    const uint64_t a = (uint64_t)p + (uint64_t)off;
+    const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const int32_t nr = __builtin_amdgcn_readfirstlane(n <= 0 ? 0 : (n >= (int64_t)cap ? cap : (int32_t)n));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)ahi << 32) | alo), (short)0, nr, 0x00020000);
 }
 
-// The lane's rows of tile [t0, t1) that pass every RLE predicate.  R holds
-// the batch at the run holding row t0; it is left at the batch holding row
-// t1 with its loads issued.
+// the lanes [0, rem) of a 64-element batch
+__device__ __forceinline__ uint64_t batch_lanes(int64_t rem) {
+    return rem >= 64 ? ~0ull : (rem <= 0 ? 0ull : ((1ull << rem) - 1ull));
+}
+
+// Element i0 + lane of an array of n elements of 4 or 8 bytes (type 1 / 2),
+// as two raw dwords (the second one unused for 4-byte elements); zero past
+// the array.
+struct Raw64 {
+    uint32_t lo, hi;
+};
+
+__device__ __forceinline__ Raw64 batch_load(const void* p, int32_t type, int64_t i0, int64_t n) {
+    const int64_t sz = type == 1 ? 4 : 8;
+    const int64_t rem = n - i0;
+    const __amdgpu_buffer_rsrc_t rs = uni_rsrc(p, i0 * sz, (rem > 64 ? 64 : rem) * sz, 512);
+    const int32_t off = lane_id() * (int32_t)sz;
+    Raw64 r;
+    r.lo = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    r.hi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0);
+    return r;
+}
+
+__device__ __forceinline__ int64_t raw_val(Raw64 r, int32_t type) {
+    return type == 1 ? (int64_t)(int32_t)r.lo : (int64_t)(((uint64_t)r.hi << 32) | r.lo);
+}
+
+// A register copy made by a vector instruction: state carried from one tile
+// to the next is then never the destination of a load still in flight, which
+// would make the compiler wait for every load at each later write of it.
+__device__ __forceinline__ uint32_t vcopy(uint32_t x) {
+    uint32_t y;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+
+// run ends (always int64) of runs i0 + lane
+__device__ __forceinline__ int64_t batch_ends_val(u32x2 r) {
+    return (int64_t)(((uint64_t)vcopy(r.y) << 32) | vcopy(r.x));
+}
+
+__device__ __forceinline__ u32x2 batch_ends(const int64_t* ends, int64_t i0, int64_t n) {
+    const int64_t rem = n - i0;
+    const __amdgpu_buffer_rsrc_t rs = uni_rsrc(ends, i0 * 8, (rem > 64 ? 64 : rem) * 8, 512);
+    return __builtin_amdgcn_raw_buffer_load_b64(rs, lane_id() * 8, 0, 0);
+}
+
+// a lane's bit of a wave-uniform mask, as the execution mask
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// The current batch of a column: runs b .. b + 63, one per lane, with the
+// outcome of each run as a bit of a 64-bit mask.  The next batch is loaded
+// when this one becomes current, so its loads have the whole batch's tiles
+// (two or more for runs longer than 32 rows on average) to arrive.
+template <int KMAX>
+struct FastRuns {
+    int64_t b[KMAX];       // wave-uniform: the batch's first run
+    uint64_t valid[KMAX];  // wave-uniform: lanes holding a run
+    uint64_t pb[KMAX];     // wave-uniform: lanes whose run passes the predicate
+    int64_t e[KMAX];       // this lane's run end
+    u32x2 ne[KMAX];        // raw ends of the next batch
+    Raw64 nv[KMAX];        // raw values of the next batch
+};
+
+// outcome mask of a batch of runs
+__device__ __forceinline__ uint64_t batch_pass(const RleCol& rc, Raw64 v, uint64_t valid) {
+    return wave_ballot(pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, raw_val(v, rc.vtype))) & valid;
+}
+
+__device__ __forceinline__ int64_t rle_runs(const DevPlan& P, int c) { return c < P.k_rle ? P.rle[c].n_runs : 0; }
+
+// make runs b .. b + 63 of column c the current batch (loaded here) and
+// issue the loads of the next one
+template <int KMAX>
+__device__ __forceinline__ void fast_runs_start(const DevPlan& P, FastRuns<KMAX>& R, int c, int64_t b) {
+    const RleCol& rc = P.rle[c];
+    const int64_t n = rle_runs(P, c);
+    R.b[c] = b;
+    R.valid[c] = batch_lanes(n - b);
+    R.e[c] = batch_ends_val(batch_ends(rc.ends, b, n));
+    R.pb[c] = batch_pass(rc, batch_load(rc.vals, rc.vtype, b, n), R.valid[c]);
+    R.ne[c] = batch_ends(rc.ends, b + 64, n);
+    R.nv[c] = batch_load(rc.vals, rc.vtype, b + 64, n);
+}
+
+// The lane's rows of tile [t0, t1) that pass every RLE predicate.  Tiles
+// are visited in increasing order; a column's current batch moves on when
+// its last run ends inside the tile.
 template <int KMAX>
 __device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t t1,
                                                   FastRuns<KMAX>& R) {
@@ -739,50 +816,39 @@ __device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLd
     for (int c = 0; c < KMAX; ++c) {
         if (c >= P.k_rle) continue;
         const RleCol& rc = P.rle[c];
+        const int64_t n = rc.n_runs;
         uint32_t* tog = W.tog + c * 64;
-        int64_t base = R.cur[c];
-        int64_t e = R.e[c];
-        bool valid = base + lane < rc.n_runs;
-        bool pass = valid && pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, R.v[c]);
-        uint64_t pb = wave_ballot(pass);
-        first |= (uint32_t)(pb & 1u) << c;
+        bool found = false;
         for (;;) {
-            // the batch is the tile's last when it holds the run of row t1 - 1
-            const bool last = wave_ballot(valid && e >= t1) != 0 || wave_ballot(valid) != ~0ull;
-            int64_t e2 = INT64_MAX;
-            bool valid2 = false, pass2 = false;
-            uint64_t pb2 = 0;
-            if (!last) {
-                const int64_t i = base + 64 + lane;
-                valid2 = i < rc.n_runs;
-                int64_t v2 = 0;
-                if (valid2) {
-                    e2 = gld(rc.ends, i);
-                    v2 = ld_val(rc.vals, rc.vtype, i);
-                }
-                pass2 = valid2 && pred_pass(rc.pred, rc.lo, rc.hi, rc.set, rc.set_len, v2);
-                pb2 = wave_ballot(pass2);
+            const uint64_t gt = wave_ballot(R.e[c] > t0) & R.valid[c];   // runs ending after t0
+            const uint64_t lt = wave_ballot(R.e[c] < t1) & R.valid[c];   // runs ending before t1
+            if (!found && gt) {
+                // the first run ending after t0 holds row t0
+                first |= (uint32_t)((R.pb[c] >> __builtin_ctzll(gt)) & 1u) << c;
+                found = true;
             }
-            // outcome of the run after this lane's run
-            const bool nxt = lane < 63 ? ((pb >> (lane + 1)) & 1u) != 0 : (last ? pass : (pb2 & 1u) != 0);
-            if (valid && e < t1 && pass != nxt) {
-                const uint32_t rel = (uint32_t)(e - t0);
+            // the outcome changes at the end of run l when run l + 1 differs
+            uint64_t tg = (R.pb[c] ^ (R.pb[c] >> 1)) & 0x7FFFFFFFFFFFFFFFull;
+            const bool next = (lt >> 63) != 0;   // the batch's last run ends before t1
+            uint64_t npb = 0, nvalid = 0;
+            if (next) {
+                nvalid = batch_lanes(n - R.b[c] - 64);
+                npb = batch_pass(rc, R.nv[c], nvalid);
+                tg |= ((R.pb[c] >> 63) ^ (npb & 1u)) << 63;
+            }
+            if (lane_in(gt & lt & tg)) {
+                const uint32_t rel = (uint32_t)R.e[c] - (uint32_t)t0;
                 atomicOr(&tog[rel >> 5], 1u << (rel & 31));
             }
-            if (last) {
-                base += __builtin_popcountll(wave_ballot(valid && e <= t1));
-                break;
-            }
-            base += 64;
-            e = e2;
-            valid = valid2;
-            pass = pass2;
-            pb = pb2;
+            if (!next) break;
+            R.b[c] += 64;
+            R.valid[c] = nvalid;
+            R.pb[c] = npb;
+            R.e[c] = batch_ends_val(R.ne[c]);
+            R.ne[c] = batch_ends(rc.ends, R.b[c] + 64, n);
+            R.nv[c] = batch_load(rc.vals, rc.vtype, R.b[c] + 64, n);
         }
-        R.cur[c] = base;
     }
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c) fast_runs_fetch(P, R, c);
     wave_lds_sync();
     uint32_t pm = 0xFFFFFFFFu;
 #pragma unroll
@@ -807,6 +873,7 @@ __device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLd
 
 // the lane's rows of tile [t0, t1) inside the window (rows >= w0)
 __device__ __forceinline__ uint32_t fast_window_mask(int64_t t0, int64_t t1, int64_t w0) {
+    if (t0 >= w0 && t1 - t0 == kRowTile) return 0xFFFFFFFFu;   // a whole tile inside the window
     const int32_t b = lane_id() * kRowSpan;
     const int32_t lo = (int32_t)(max(t0, w0) - t0) - b;   // first valid bit
     const int32_t hi = (int32_t)(t1 - t0) - b;            // one past the last
@@ -816,29 +883,31 @@ __device__ __forceinline__ uint32_t fast_window_mask(int64_t t0, int64_t t1, int
     return m;
 }
 
+// Buffer resource over the packed words of the tile at t0 and the `extra`
+// words after it (those that exist).
+template <int W0>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_words_rsrc(const BpCol& bc, int64_t t0, int32_t extra,
+                                                                  int64_t* avail) {
+    const int64_t tw = (t0 >> 5) * W0;                 // the tile's first word
+    *avail = bc.n_words - tw;                          // words from there on
+    return uni_rsrc(bc.packed, tw * 4, *avail * 4, (64 * W0 + extra) * 4);
+}
+
 // The lane's W0 words of the tile at t0; lanes without surviving rows read
 // nothing (an out-of-range buffer offset returns zero without a memory
 // access).
 template <int W0>
 __device__ __forceinline__ void fast_words(const BpCol& bc, int64_t t0, uint32_t pm, uint32_t (&wd)[W0]) {
     const int lane = lane_id();
-    const int64_t tw = (t0 >> 5) * W0;                 // the tile's first word
-    const int64_t avail = bc.n_words - tw;             // words from there on
-    // the buffer resource lives in scalar registers: the tile is wave-uniform
-    const uint64_t addr = (uint64_t)(bc.packed + tw);
-    const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
-    const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
-    const int32_t nrec = __builtin_amdgcn_readfirstlane((avail < 64 * W0 ? (int32_t)avail : 64 * W0) * 4);
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)(((uint64_t)ahi << 32) | alo), (short)0, nrec, 0x00020000);
+    int64_t avail;
+    const __amdgpu_buffer_rsrc_t rs = tile_words_rsrc<W0>(bc, t0, 0, &avail);
     const int32_t lw = lane * W0;
     constexpr int32_t kNone = 0x40000000;              // beyond any tile's records
     if (avail >= 64 * W0) {
         const int32_t off = pm ? lw * 4 : kNone;
-        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int i = 0; i < W0 / 2; ++i) {
-            const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8 * i, 0, 0);
+            const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8 * i, 0, 0);
             wd[2 * i] = v.x;
             wd[2 * i + 1] = v.y;
         }
@@ -850,7 +919,6 @@ __device__ __forceinline__ void fast_words(const BpCol& bc, int64_t t0, uint32_t
         for (int i = 0; i < W0; ++i) wd[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, i < rem ? off + 4 * i : kNone, 0, 0);
     }
 }
-
 // Count the lane's 32 rows into the lane-replicated LDS table (slot-major,
 // 2^rep_shift replicas, uint32): the lanes of a wave never hit the same
 // address, whatever the skew of the codes.  Slot G counts rows whose key is
@@ -923,45 +991,51 @@ __device__ __forceinline__ uint32_t fast_slot(const BpCol& bc, uint32_t G, const
     }
 }
 
-// Index points of the fast path (at most one Index column).  The batch of
-// a tile is fetched one step ahead, the packed words under its points at the
-// start of the tile's own step; a point adds its value to its row's group
-// when the row survives (the Plain x Index case of Section 5.1).
+// Index points of the fast path (at most one Index column), in batches of
+// 64 that start at multiples of 64 of the point index.  The current batch is
+// decoded; the next one is loaded when the current one becomes current.  A
+// tile's points lie in the current batch, or at its end and the start of the
+// next one, where (with at most 64 points in the tile) each lane holds at
+// most one of them; denser tiles take a slower batch-by-batch route.  The
+// packed words under a tile's points are read at the start of the tile's
+// step, and a point adds its value to its row's group when the row survives
+// (the Plain x Index case of Section 5.1).
 struct FastPoints {
-    int64_t pc;            // wave-uniform: first point of the batch in pos/val
-    int64_t pos, val;      // this lane's point (INT64_MAX past the column)
-    int64_t npos, nval;    // the batch after it
+    int64_t k;             // wave-uniform: first point of the current batch
+    int64_t pos, val;      // point k + lane (pos INT64_MAX past the column)
+    Raw64 np, nv;          // raw positions and values of the next batch
 };
 
-__device__ __forceinline__ void fast_points_fetch(const DevPlan& P, int64_t pc, int64_t& pos, int64_t& val) {
+__device__ __forceinline__ int64_t idx_points(const DevPlan& P) { return P.n_idx > 0 ? P.idx[0].n : 0; }
+
+__device__ __forceinline__ void fast_points_decode(const IdxCol& ic, int64_t k, int64_t n, Raw64 p, Raw64 v,
+                                                   int64_t& pos, int64_t& val) {
+    const bool ok = k + lane_id() < n;
+    pos = ok ? raw_val(p, ic.ptype) : INT64_MAX;
+    val = ok ? raw_val(v, ic.vtype) : 0;
+}
+
+// make the batch at point k current (loaded here) and issue the next one
+__device__ __forceinline__ void fast_points_start(const DevPlan& P, FastPoints& Q, int64_t k) {
     const IdxCol& ic = P.idx[0];
-    const bool have = P.n_idx > 0 && ic.n > 0;
-    const int64_t i = pc + lane_id();
-    const bool ok = have && i < ic.n;
-    const int64_t j = ok ? i : 0;
-    const int64_t p = ld_val_nb(have ? ic.pos : (const void*)&P, have ? ic.ptype : 2, j);
-    const int64_t v = ld_val_nb(have ? ic.vals : (const void*)&P, have ? ic.vtype : 2, j);
-    pos = ok ? p : INT64_MAX;
-    val = ok ? v : 0;
+    const int64_t n = idx_points(P);
+    Q.k = k;
+    fast_points_decode(ic, k, n, batch_load(ic.pos, ic.ptype, k, n), batch_load(ic.vals, ic.vtype, k, n), Q.pos,
+                       Q.val);
+    Q.np = batch_load(ic.pos, ic.ptype, k + 64, n);
+    Q.nv = batch_load(ic.vals, ic.vtype, k + 64, n);
 }
 
-// the two packed words under a point (any word for a lane without one)
-template <int W0>
-__device__ __forceinline__ void fast_point_words(const BpCol& bc, int64_t pos, bool in, uint32_t& lo, uint32_t& hi) {
-    const int64_t wq = in ? (pos * (int64_t)W0) >> 5 : 0;
-    lo = gld(bc.packed, wq);
-    hi = gld(bc.packed, wq + 1 < bc.n_words ? wq + 1 : wq);
-}
-
+// A point at row offset rel of the tile whose pass mask words are pmw; lo,
+// hi are the two packed words holding its code (bit offset rel * W0 of the
+// tile's stream).
 template <int W0, bool BIG>
-__device__ __forceinline__ void fast_point_add(const DevPlan& P, const uint32_t* pmw, int64_t t0, int64_t pos,
-                                               int64_t val, uint32_t lo, uint32_t hi, const uint8_t* lut,
-                                               int64_t* table) {
+__device__ __forceinline__ void fast_point_add(const DevPlan& P, const uint32_t* pmw, uint32_t rel, int64_t val,
+                                               uint32_t lo, uint32_t hi, const uint8_t* lut, int64_t* table) {
     const BpCol& bc = P.bp[0];
     const uint32_t G = (uint32_t)P.n_groups;
-    const int32_t rel = (int32_t)(pos - t0);
     if (!((pmw[rel >> 5] >> (rel & 31)) & 1u)) return;
-    const uint32_t sh = (uint32_t)((pos * (int64_t)W0) & 31);
+    const uint32_t sh = (rel * (uint32_t)W0) & 31u;
     const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
     const uint32_t slot = fast_slot<W0, BIG>(bc, G, lut, code);
     if (slot < G && val != 0) {
@@ -993,13 +1067,43 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
                                           uint32_t* cnt, int64_t* table) {
     const int lane = lane_id();
     const BpCol& bc = P.bp[0];
-    const bool sums = P.n_idx > 0 && P.idx[0].sum_slot >= 0;
-    // this tile's points: which lanes hold one; their words; the next batch
-    const bool pin = S.Q.pos < S.t1;
-    const int32_t pk = __builtin_popcountll(wave_ballot(pin));
+    const IdxCol& ic = P.idx[0];
+    const bool sums = P.n_idx > 0 && ic.sum_slot >= 0;
+    const int64_t npts = idx_points(P);
+    // this tile's points: which lanes hold one, and the words under them
+    uint64_t pin = wave_ballot(S.Q.pos >= S.t0 && S.Q.pos < S.t1);
+    int64_t ppos = S.Q.pos, pval = S.Q.val;
+    bool pslow = false;
+    int64_t pfirst = 0;
+    if (wave_ballot(S.Q.pos < S.t1) >> 63) {
+        // the current batch ends inside the tile: the next one becomes current
+        pfirst = S.Q.k + __builtin_ctzll(wave_ballot(S.Q.pos >= S.t0));
+        int64_t p2, v2;
+        fast_points_decode(ic, S.Q.k + 64, npts, S.Q.np, S.Q.nv, p2, v2);
+        const uint64_t in2 = wave_ballot(p2 < S.t1);
+        pslow = (in2 & pin) != 0 || (in2 >> 63) != 0;   // more than 64 points in the tile
+        if (lane_in(in2)) {
+            ppos = p2;
+            pval = v2;
+        }
+        pin |= in2;
+        S.Q.k += 64;
+        S.Q.pos = p2;
+        S.Q.val = v2;
+        S.Q.np = batch_load(ic.pos, ic.ptype, S.Q.k + 64, npts);
+        S.Q.nv = batch_load(ic.vals, ic.vtype, S.Q.k + 64, npts);
+    }
+    if (pslow) pin = 0;
+    const uint32_t prel = (uint32_t)ppos - (uint32_t)S.t0;
     uint32_t plo, phi;
-    fast_point_words<W0>(bc, S.Q.pos, pin, plo, phi);
-    fast_points_fetch(P, S.Q.pc + pk, S.Q.npos, S.Q.nval);
+    {
+        int64_t avail;
+        const __amdgpu_buffer_rsrc_t rs = tile_words_rsrc<W0>(bc, S.t0, 2, &avail);
+        constexpr int32_t kNone = 0x40000000;
+        const int32_t off = sums && lane_in(pin) ? (int32_t)((prel * (uint32_t)W0) >> 5) * 4 : kNone;
+        plo = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        phi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0);
+    }
     // the next tile (empty after the wave's last): its mask, then its words
     const bool more = S.t1 < S.w1;
     const int64_t n0 = S.t1;
@@ -1012,30 +1116,42 @@ __device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, Fa
     // this tile's points
     wave_lds_sync();
     const uint32_t* pmw = W.pts + S.buf * 64;
-    if (pin && sums) fast_point_add<W0, BIG>(P, pmw, S.t0, S.Q.pos, S.Q.val, plo, phi, lut, table);
-    S.Q.pc += pk;
-    if (pk == 64) {
-        // more than one batch of points in this tile
+    if (sums && lane_in(pin)) fast_point_add<W0, BIG>(P, pmw, prel, pval, plo, phi, lut, table);
+    if (pslow) {
+        // batch by batch from the tile's first point, then batches again at
+        // the first point after the tile
+        int64_t g = pfirst;
         for (;;) {
-            const bool in = S.Q.npos < S.t1;
-            const int32_t k = __builtin_popcountll(wave_ballot(in));
-            if (in && sums) {
-                uint32_t lo, hi;
-                fast_point_words<W0>(bc, S.Q.npos, true, lo, hi);
-                fast_point_add<W0, BIG>(P, pmw, S.t0, S.Q.npos, S.Q.nval, lo, hi, lut, table);
+            int64_t p3, v3;
+            fast_points_decode(ic, g, npts, batch_load(ic.pos, ic.ptype, g, npts),
+                               batch_load(ic.vals, ic.vtype, g, npts), p3, v3);
+            const uint64_t in3 = wave_ballot(p3 < S.t1);
+            if (sums && lane_in(in3)) {
+                const uint32_t rel = (uint32_t)p3 - (uint32_t)S.t0;
+                const int64_t wq = (S.t0 >> 5) * W0 + ((rel * (uint32_t)W0) >> 5);
+                fast_point_add<W0, BIG>(P, pmw, rel, v3, gld(bc.packed, wq), gld(bc.packed, wq + 1), lut, table);
             }
-            S.Q.pc += k;
-            fast_points_fetch(P, S.Q.pc, S.Q.npos, S.Q.nval);
+            const int32_t k = __builtin_popcountll(in3);
+            g += k;
             if (k < 64) break;
         }
+        fast_points_start(P, S.Q, g & ~(int64_t)63);
     }
-    S.Q.pos = S.Q.npos;
-    S.Q.val = S.Q.nval;
     S.t0 = n0;
     S.t1 = n1;
     S.pm = pmn;
     S.buf ^= 1;
     return more;
+}
+
+// Issue priority from the share of the wave's tiles still ahead: waves that
+// fall behind are picked first, so the waves of a compute unit (whose issue
+// order otherwise favours the oldest) finish their equal slices together.
+__device__ __forceinline__ void balance_priority(int64_t left, int64_t all) {
+    if (left * 2 > all) __builtin_amdgcn_s_setprio(3);
+    else if (left * 4 > all) __builtin_amdgcn_s_setprio(2);
+    else if (left * 8 > all) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
 }
 
 // One wavefront over rows [w0, w1) of the plan's window, fast row path.
@@ -1052,15 +1168,11 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
     S.buf = 0;
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
-        S.R.cur[c] = 0;
-        if (c >= P.k_rle) continue;
-        W.tog[c * 64 + lane] = 0;
-        S.R.cur[c] = wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, S.t0);
+        if (c < P.k_rle) W.tog[c * 64 + lane] = 0;
+        fast_runs_start(P, S.R, c, c < P.k_rle ? wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, S.t0) : 0);
     }
-#pragma unroll
-    for (int c = 0; c < KMAX; ++c) fast_runs_fetch(P, S.R, c);
-    S.Q.pc = P.n_idx > 0 ? wave_lower_bound_pos(P.idx[0].pos, P.idx[0].ptype, P.idx[0].n, w0) : 0;
-    fast_points_fetch(P, S.Q.pc, S.Q.pos, S.Q.val);
+    const int64_t pk = P.n_idx > 0 ? wave_lower_bound_pos(P.idx[0].pos, P.idx[0].ptype, P.idx[0].n, w0) : 0;
+    fast_points_start(P, S.Q, pk & ~(int64_t)63);
     wave_lds_sync();
     S.pm = fast_rle_mask<KMAX>(P, W, S.t0, S.t1, S.R) & fast_window_mask(S.t0, S.t1, w0);
     W.pts[lane] = S.pm;
@@ -1068,10 +1180,15 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
     fast_words<W0>(P.bp[0], S.t0, S.pm, wa);
     wave_lds_sync();
     // two steps per iteration so the word buffers swap without copies
+    const int64_t all = ((w1 - 1) >> kTileShift) - (S.t0 >> kTileShift) + 1;
+    int64_t left = all;
     for (;;) {
+        balance_priority(left--, all);
         if (!fast_step<KMAX, W0, SUMBP, BIG, ONES>(P, W, S, wa, wb, lut, cnt, table)) break;
+        balance_priority(left--, all);
         if (!fast_step<KMAX, W0, SUMBP, BIG, ONES>(P, W, S, wb, wa, lut, cnt, table)) break;
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // Flush of the fast path's LDS tables into the global group table: add up
