@@ -635,8 +635,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     }
     P.lds_shared_bytes = (int32_t)sh;
 
-    // wave slice.  Fast row path: a 64-word toggle bitmap per RLE column and
-    // two 64-word lane-mask buffers (runs are never staged).  Otherwise a
+    // wave slice.  Fast row path: a 128-word toggle bitmap per RLE column (two
+    // tiles are masked together; runs are never staged).  Otherwise a
     // 256-byte header (per-column staged counts, first runs and next-tile
     // cursors), then the staged runs, then row-mode buffers.
     size_t wv = 0;
@@ -644,9 +644,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         P.run_cap = 0;
         P.off_run_end = P.off_run_val = P.off_rows = P.off_ptpre = 0;
         P.off_tog = (int32_t)wv;
-        wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
+        wv = align16(wv + 512 * (size_t)std::max(P.k_rle, 1));
         P.off_pts = (int32_t)wv;
-        wv = align16(wv + 2 * 256);
         P.lds_wave_bytes = (int32_t)wv;
         P.lds_dyn_bytes = (int32_t)(sh + kWaves * wv);
         if ((size_t)P.lds_dyn_bytes > t->ctx->lds_per_block)

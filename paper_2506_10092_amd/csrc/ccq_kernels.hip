@@ -804,12 +804,14 @@ __device__ __forceinline__ void fast_runs_start(const DevPlan& P, FastRuns<KMAX>
     R.nv[c] = batch_load(rc.vals, rc.vtype, b + 64, n);
 }
 
-// The lane's rows of tile [t0, t1) that pass every RLE predicate.  Tiles
-// are visited in increasing order; a column's current batch moves on when
-// its last run ends inside the tile.
+// The lane's rows that pass every RLE predicate in two consecutive tiles,
+// A = [t0, tm) and B = [tm, t1) (B may be empty), with one pass over the
+// runs: toggles of A go to words 0..63 of the column's bitmap, those of B to
+// words 64..127.  Tiles are visited in increasing order; a column's current
+// batch moves on when its last run ends before t1.
 template <int KMAX>
-__device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t t1,
-                                                  FastRuns<KMAX>& R) {
+__device__ __forceinline__ void fast_rle_mask(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t tm, int64_t t1,
+                                              FastRuns<KMAX>& R, uint32_t& pm_a, uint32_t& pm_b) {
     const int lane = lane_id();
     uint32_t first = 0;   // bit c: the run holding row t0 passes column c
 #pragma unroll
@@ -817,7 +819,7 @@ __device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLd
         if (c >= P.k_rle) continue;
         const RleCol& rc = P.rle[c];
         const int64_t n = rc.n_runs;
-        uint32_t* tog = W.tog + c * 64;
+        uint32_t* tog = W.tog + c * 128;
         bool found = false;
         for (;;) {
             const uint64_t gt = wave_ballot(R.e[c] > t0) & R.valid[c];   // runs ending after t0
@@ -837,7 +839,8 @@ __device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLd
                 tg |= ((R.pb[c] >> 63) ^ (npb & 1u)) << 63;
             }
             if (lane_in(gt & lt & tg)) {
-                const uint32_t rel = (uint32_t)R.e[c] - (uint32_t)t0;
+                const int64_t e = R.e[c];
+                const uint32_t rel = e < tm ? (uint32_t)e - (uint32_t)t0 : (uint32_t)e - (uint32_t)tm + (uint32_t)kRowTile;
                 atomicOr(&tog[rel >> 5], 1u << (rel & 31));
             }
             if (!next) break;
@@ -850,25 +853,35 @@ __device__ __forceinline__ uint32_t fast_rle_mask(const DevPlan& P, const WaveLd
         }
     }
     wave_lds_sync();
-    uint32_t pm = 0xFFFFFFFFu;
+    pm_a = 0xFFFFFFFFu;
+    pm_b = 0xFFFFFFFFu;
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
         if (c >= P.k_rle) continue;
-        uint32_t* tog = W.tog + c * 64;
-        const uint32_t T = tog[lane];
+        uint32_t* tog = W.tog + c * 128;
+        const uint32_t Ta = tog[lane], Tb = tog[64 + lane];
         tog[lane] = 0;
-        uint32_t x = T;
-        x ^= x << 1;
-        x ^= x << 2;
-        x ^= x << 4;
-        x ^= x << 8;
-        x ^= x << 16;
-        // toggles in the words below this lane's, plus the starting outcome
-        const uint64_t par = wave_ballot((__builtin_popcount(T) & 1) != 0);
-        const uint32_t flip = ((uint32_t)lanes_below(par) ^ (first >> c)) & 1u;
-        pm &= flip ? ~x : x;
+        tog[64 + lane] = 0;
+        uint32_t xa = Ta, xb = Tb;
+        xa ^= xa << 1;
+        xb ^= xb << 1;
+        xa ^= xa << 2;
+        xb ^= xb << 2;
+        xa ^= xa << 4;
+        xb ^= xb << 4;
+        xa ^= xa << 8;
+        xb ^= xb << 8;
+        xa ^= xa << 16;
+        xb ^= xb << 16;
+        // toggles in the words before this one (B after all of A), plus the
+        // starting outcome
+        const uint64_t para = wave_ballot((__builtin_popcount(Ta) & 1) != 0);
+        const uint64_t parb = wave_ballot((__builtin_popcount(Tb) & 1) != 0);
+        const uint32_t fa = ((uint32_t)lanes_below(para) ^ (first >> c)) & 1u;
+        const uint32_t fb = ((uint32_t)lanes_below(parb) ^ (uint32_t)__builtin_popcountll(para) ^ (first >> c)) & 1u;
+        pm_a &= fa ? ~xa : xa;
+        pm_b &= fb ? ~xb : xb;
     }
-    return pm;
 }
 
 // the lane's rows of tile [t0, t1) inside the window (rows >= w0)
@@ -992,52 +1005,70 @@ __device__ __forceinline__ uint32_t fast_slot(const BpCol& bc, uint32_t G, const
 }
 
 // Index points of the fast path (at most one Index column), in batches of
-// 64 that start at multiples of 64 of the point index.  The current batch is
-// decoded; the next one is loaded when the current one becomes current.  A
-// tile's points lie in the current batch, or at its end and the start of the
-// next one, where (with at most 64 points in the tile) each lane holds at
-// most one of them; denser tiles take a slower batch-by-batch route.  The
-// packed words under a tile's points are read at the start of the tile's
-// step, and a point adds its value to its row's group when the row survives
-// (the Plain x Index case of Section 5.1).
+// 64 that start at multiples of 64 of the point index.  Two batches are
+// decoded, the current one and the next, with the two packed words holding
+// each point's code read when its batch is decoded (a batch spans a few
+// tiles, so the words have that long to arrive); the batch after them is
+// read when the current one is used up.  A tile's points lie in the current
+// batch, or at its end and the start of the next one, where (with at most 64
+// points in the tile) each lane holds at most one of them; denser tiles take
+// a slower batch-by-batch route.  A point whose row survives the RLE
+// predicates adds its value to the row's group (the Plain x Index case of
+// Section 5.1).
+struct PointBatch {
+    int64_t pos, val;      // point k + lane (pos INT64_MAX past the column)
+    uint32_t lo, hi;       // the packed words holding its code
+};
+
 struct FastPoints {
     int64_t k;             // wave-uniform: first point of the current batch
-    int64_t pos, val;      // point k + lane (pos INT64_MAX past the column)
-    Raw64 np, nv;          // raw positions and values of the next batch
+    PointBatch cur, nxt;   // points k + lane and k + 64 + lane
+    Raw64 np, nv;          // raw positions and values of points k + 128 + lane
 };
 
 __device__ __forceinline__ int64_t idx_points(const DevPlan& P) { return P.n_idx > 0 ? P.idx[0].n : 0; }
 
-__device__ __forceinline__ void fast_points_decode(const IdxCol& ic, int64_t k, int64_t n, Raw64 p, Raw64 v,
-                                                   int64_t& pos, int64_t& val) {
+// decode a batch of points starting at k and read the words under them
+template <int W0>
+__device__ __forceinline__ void point_batch(const DevPlan& P, int64_t k, Raw64 p, Raw64 v, PointBatch& B) {
+    const IdxCol& ic = P.idx[0];
+    const BpCol& bc = P.bp[0];
+    const int64_t n = idx_points(P);
     const bool ok = k + lane_id() < n;
-    pos = ok ? raw_val(p, ic.ptype) : INT64_MAX;
-    val = ok ? raw_val(v, ic.vtype) : 0;
+    B.pos = ok ? raw_val(p, ic.ptype) : INT64_MAX;
+    B.val = ok ? raw_val(v, ic.vtype) : 0;
+    const int64_t wq = ok ? (B.pos * W0) >> 5 : 0;
+    B.lo = gld(bc.packed, wq);
+    B.hi = gld(bc.packed, wq + 1 < bc.n_words ? wq + 1 : wq);
 }
 
-// make the batch at point k current (loaded here) and issue the next one
+// make the batch at point k (a multiple of 64) current, read here with the
+// next one; issue the reads of the one after
+template <int W0>
 __device__ __forceinline__ void fast_points_start(const DevPlan& P, FastPoints& Q, int64_t k) {
     const IdxCol& ic = P.idx[0];
     const int64_t n = idx_points(P);
     Q.k = k;
-    fast_points_decode(ic, k, n, batch_load(ic.pos, ic.ptype, k, n), batch_load(ic.vals, ic.vtype, k, n), Q.pos,
-                       Q.val);
-    Q.np = batch_load(ic.pos, ic.ptype, k + 64, n);
-    Q.nv = batch_load(ic.vals, ic.vtype, k + 64, n);
+    point_batch<W0>(P, k, batch_load(ic.pos, ic.ptype, k, n), batch_load(ic.vals, ic.vtype, k, n), Q.cur);
+    point_batch<W0>(P, k + 64, batch_load(ic.pos, ic.ptype, k + 64, n), batch_load(ic.vals, ic.vtype, k + 64, n),
+                    Q.nxt);
+    Q.np = batch_load(ic.pos, ic.ptype, k + 128, n);
+    Q.nv = batch_load(ic.vals, ic.vtype, k + 128, n);
 }
 
-// A point at row offset rel of the tile whose pass mask words are pmw; lo,
-// hi are the two packed words holding its code (bit offset rel * W0 of the
-// tile's stream).
+// the code of a point at row pos from the two packed words holding it
+template <int W0>
+__device__ __forceinline__ uint32_t point_code(int64_t pos, uint32_t lo, uint32_t hi) {
+    const uint32_t sh = (uint32_t)(pos * W0) & 31u;
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
+}
+
+// add a surviving point's value to the group of its code
 template <int W0, bool BIG>
-__device__ __forceinline__ void fast_point_add(const DevPlan& P, const uint32_t* pmw, uint32_t rel, int64_t val,
-                                               uint32_t lo, uint32_t hi, const uint8_t* lut, int64_t* table) {
-    const BpCol& bc = P.bp[0];
+__device__ __forceinline__ void fast_point_add(const DevPlan& P, int64_t val, uint32_t code, const uint8_t* lut,
+                                               int64_t* table) {
     const uint32_t G = (uint32_t)P.n_groups;
-    if (!((pmw[rel >> 5] >> (rel & 31)) & 1u)) return;
-    const uint32_t sh = (rel * (uint32_t)W0) & 31u;
-    const uint32_t code = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
-    const uint32_t slot = fast_slot<W0, BIG>(bc, G, lut, code);
+    const uint32_t slot = fast_slot<W0, BIG>(P.bp[0], G, lut, code);
     if (slot < G && val != 0) {
         if constexpr (BIG) {
             // a large table keeps no Index sums in LDS: points are few
@@ -1049,100 +1080,78 @@ __device__ __forceinline__ void fast_point_add(const DevPlan& P, const uint32_t*
     }
 }
 
-template <int KMAX, int W0>
-struct FastState {
-    FastRuns<KMAX> R;
-    FastPoints Q;
-    int64_t t0, t1, w0, w1;
-    uint32_t pm;
-    int32_t buf;           // which lane-mask buffer holds pm
-};
+// whether the row at offset rel of a tile survives, from the tile's lane
+// masks (every lane takes part: the mask is read across lanes)
+__device__ __forceinline__ bool tile_row_survives(uint32_t pm, uint32_t rel) {
+    const uint32_t owner = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((rel >> 5) << 2), (int)pm);
+    return ((owner >> (rel & 31)) & 1u) != 0;
+}
 
-// One pipeline step: count tile [t0, t1) from `wd` while the next tile's
-// mask is computed and its words are fetched into `wn`.  Returns false after
-// the wave's last tile.
-template <int KMAX, int W0, bool SUMBP, bool BIG, bool ONES>
-__device__ __forceinline__ bool fast_step(const DevPlan& P, const WaveLds& W, FastState<KMAX, W0>& S,
-                                          const uint32_t (&wd)[W0], uint32_t (&wn)[W0], const uint8_t* lut,
-                                          uint32_t* cnt, int64_t* table) {
-    const int lane = lane_id();
-    const BpCol& bc = P.bp[0];
+// The points of tile [a0, a1) whose lane masks are pm.
+template <int W0, bool BIG>
+__device__ __forceinline__ void fast_points_tile(const DevPlan& P, FastPoints& Q, int64_t a0, int64_t a1,
+                                                 uint32_t pm, const uint8_t* lut, int64_t* table) {
     const IdxCol& ic = P.idx[0];
-    const bool sums = P.n_idx > 0 && ic.sum_slot >= 0;
+    const BpCol& bc = P.bp[0];
+    if (!(P.n_idx > 0 && ic.sum_slot >= 0)) return;
     const int64_t npts = idx_points(P);
-    // this tile's points: which lanes hold one, and the words under them
-    uint64_t pin = wave_ballot(S.Q.pos >= S.t0 && S.Q.pos < S.t1);
-    int64_t ppos = S.Q.pos, pval = S.Q.val;
-    bool pslow = false;
-    int64_t pfirst = 0;
-    if (wave_ballot(S.Q.pos < S.t1) >> 63) {
-        // the current batch ends inside the tile: the next one becomes current
-        pfirst = S.Q.k + __builtin_ctzll(wave_ballot(S.Q.pos >= S.t0));
-        int64_t p2, v2;
-        fast_points_decode(ic, S.Q.k + 64, npts, S.Q.np, S.Q.nv, p2, v2);
-        const uint64_t in2 = wave_ballot(p2 < S.t1);
-        pslow = (in2 & pin) != 0 || (in2 >> 63) != 0;   // more than 64 points in the tile
-        if (lane_in(in2)) {
-            ppos = p2;
-            pval = v2;
-        }
-        pin |= in2;
-        S.Q.k += 64;
-        S.Q.pos = p2;
-        S.Q.val = v2;
-        S.Q.np = batch_load(ic.pos, ic.ptype, S.Q.k + 64, npts);
-        S.Q.nv = batch_load(ic.vals, ic.vtype, S.Q.k + 64, npts);
-    }
-    if (pslow) pin = 0;
-    const uint32_t prel = (uint32_t)ppos - (uint32_t)S.t0;
-    uint32_t plo, phi;
-    {
-        int64_t avail;
-        const __amdgpu_buffer_rsrc_t rs = tile_words_rsrc<W0>(bc, S.t0, 2, &avail);
-        constexpr int32_t kNone = 0x40000000;
-        const int32_t off = sums && lane_in(pin) ? (int32_t)((prel * (uint32_t)W0) >> 5) * 4 : kNone;
-        plo = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
-        phi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0);
-    }
-    // the next tile (empty after the wave's last): its mask, then its words
-    const bool more = S.t1 < S.w1;
-    const int64_t n0 = S.t1;
-    const int64_t n1 = more ? min(((n0 >> kTileShift) + 1) << kTileShift, S.w1) : n0;
-    const uint32_t pmn = fast_rle_mask<KMAX>(P, W, n0, n1, S.R) & fast_window_mask(n0, n1, S.w0);
-    W.pts[(S.buf ^ 1) * 64 + lane] = pmn;
-    fast_words<W0>(bc, n0, pmn, wn);
-    // this tile's rows
-    if (wave_ballot(S.pm != 0)) fast_rows<W0, SUMBP, BIG, ONES>(P, wd, S.pm, lut, cnt);
-    // this tile's points
-    wave_lds_sync();
-    const uint32_t* pmw = W.pts + S.buf * 64;
-    if (sums && lane_in(pin)) fast_point_add<W0, BIG>(P, pmw, prel, pval, plo, phi, lut, table);
-    if (pslow) {
-        // batch by batch from the tile's first point, then batches again at
-        // the first point after the tile
-        int64_t g = pfirst;
+    const uint64_t in1 = wave_ballot(Q.cur.pos >= a0 && Q.cur.pos < a1);
+    const bool live1 = tile_row_survives(pm, (uint32_t)Q.cur.pos - (uint32_t)a0) && lane_in(in1);
+    const uint32_t code1 = point_code<W0>(Q.cur.pos, Q.cur.lo, Q.cur.hi);
+    if (live1) fast_point_add<W0, BIG>(P, Q.cur.val, code1, lut, table);
+    if ((wave_ballot(Q.cur.pos < a1) >> 63) == 0) return;
+    // the current batch ends inside the tile: the next one becomes current
+    const int64_t first = Q.k + __builtin_ctzll(wave_ballot(Q.cur.pos >= a0));
+    const uint64_t in2 = wave_ballot(Q.nxt.pos < a1);
+    if ((in2 & in1) != 0 || (in2 >> 63) != 0) {
+        // more than 64 points in the tile: the rest batch by batch, then
+        // batches again at the first point after the tile
+        int64_t g = first + __builtin_popcountll(in1);
         for (;;) {
-            int64_t p3, v3;
-            fast_points_decode(ic, g, npts, batch_load(ic.pos, ic.ptype, g, npts),
-                               batch_load(ic.vals, ic.vtype, g, npts), p3, v3);
-            const uint64_t in3 = wave_ballot(p3 < S.t1);
-            if (sums && lane_in(in3)) {
-                const uint32_t rel = (uint32_t)p3 - (uint32_t)S.t0;
-                const int64_t wq = (S.t0 >> 5) * W0 + ((rel * (uint32_t)W0) >> 5);
-                fast_point_add<W0, BIG>(P, pmw, rel, v3, gld(bc.packed, wq), gld(bc.packed, wq + 1), lut, table);
-            }
+            Raw64 rp = batch_load(ic.pos, ic.ptype, g, npts), rv = batch_load(ic.vals, ic.vtype, g, npts);
+            PointBatch B;
+            point_batch<W0>(P, g, rp, rv, B);
+            const uint64_t in3 = wave_ballot(B.pos < a1);
+            const bool live3 = tile_row_survives(pm, (uint32_t)B.pos - (uint32_t)a0) && lane_in(in3);
+            const uint32_t code3 = point_code<W0>(B.pos, B.lo, B.hi);
+            if (live3) fast_point_add<W0, BIG>(P, B.val, code3, lut, table);
             const int32_t k = __builtin_popcountll(in3);
             g += k;
             if (k < 64) break;
         }
-        fast_points_start(P, S.Q, g & ~(int64_t)63);
+        fast_points_start<W0>(P, Q, g & ~(int64_t)63);
+        return;
     }
-    S.t0 = n0;
-    S.t1 = n1;
-    S.pm = pmn;
-    S.buf ^= 1;
-    return more;
+    const bool live2 = tile_row_survives(pm, (uint32_t)Q.nxt.pos - (uint32_t)a0) && lane_in(in2);
+    const uint32_t code2 = point_code<W0>(Q.nxt.pos, Q.nxt.lo, Q.nxt.hi);
+    if (live2) fast_point_add<W0, BIG>(P, Q.nxt.val, code2, lut, table);
+    Q.k += 64;
+    Q.cur = Q.nxt;
+    point_batch<W0>(P, Q.k + 64, Q.np, Q.nv, Q.nxt);
+    Q.np = batch_load(ic.pos, ic.ptype, Q.k + 128, npts);
+    Q.nv = batch_load(ic.vals, ic.vtype, Q.k + 128, npts);
 }
+
+// The fast path counts rows by lane-words, the 32 rows from a multiple of 32
+// that one lane covers.  A lane-word whose rows all fail the RLE predicates
+// needs no work; the others are gathered from consecutive tiles into batches
+// of 64, one per lane, so the row loop runs only on lane-words with rows that
+// can count.  Tiles are masked in order; a batch's packed words are read when
+// it is complete and counted once the next batch is complete.
+template <int KMAX, int W0>
+struct FastState {
+    FastRuns<KMAX> R;
+    FastPoints Q;
+    int64_t w0, w1;
+    int64_t t0, t1;        // the next tile to mask ([t0, t0) after the last)
+    int64_t lw0;           // the wave's first lane-word
+    int64_t left, all;     // tiles still to mask, of all
+    uint32_t f_pm, f_lw;   // the batch being gathered (lanes below f_n): mask, lane-word - lw0
+    int32_t f_n;
+    bool pend;             // the second of two tiles masked together is still to gather
+    uint32_t pend_pm;
+    int64_t pend_a0;
+};
 
 // Issue priority from the share of the wave's tiles still ahead: waves that
 // fall behind are picked first, so the waves of a compute unit (whose issue
@@ -1154,39 +1163,175 @@ __device__ __forceinline__ void balance_priority(int64_t left, int64_t all) {
     else __builtin_amdgcn_s_setprio(0);
 }
 
+// Mask the next tile, take its points and add its active lane-words to the
+// batch being gathered.  Returns true when that completes a batch of 64,
+// which is then in (r_pm, r_lw).
+template <int KMAX, int W0, bool BIG>
+__device__ __forceinline__ bool fast_tile(const DevPlan& P, const WaveLds& W, FastState<KMAX, W0>& S,
+                                          uint32_t& r_pm, uint32_t& r_lw, const uint8_t* lut, int64_t* table) {
+    const int lane = lane_id();
+    uint32_t pm;
+    int64_t a0;
+    if (S.pend) {
+        // the second tile of the last pair
+        pm = S.pend_pm;
+        a0 = S.pend_a0;
+        S.pend = false;
+    } else {
+        // mask the next two tiles in one pass over the runs
+        a0 = S.t0;
+        const int64_t a1 = S.t1;
+        const int64_t b1 = a1 < S.w1 ? min(((a1 >> kTileShift) + 1) << kTileShift, S.w1) : a1;
+        balance_priority(S.left, S.all);
+        S.left -= 2;
+        uint32_t pmb;
+        fast_rle_mask<KMAX>(P, W, a0, a1, b1, S.R, pm, pmb);
+        pm &= fast_window_mask(a0, a1, S.w0);
+        pmb &= fast_window_mask(a1, b1, S.w0);
+        fast_points_tile<W0, BIG>(P, S.Q, a0, a1, pm, lut, table);
+        if (b1 > a1) {
+            fast_points_tile<W0, BIG>(P, S.Q, a1, b1, pmb, lut, table);
+            S.pend = true;
+            S.pend_pm = pmb;
+            S.pend_a0 = a1;
+        }
+        S.t0 = b1;
+        S.t1 = b1 < S.w1 ? min(((b1 >> kTileShift) + 1) << kTileShift, S.w1) : b1;
+    }
+    // the k-th active lane-word goes to lane f_n + k of the batch, wrapping
+    // into the next batch past 64; the inactive ones fill the other lanes so
+    // the lanes are permuted
+    const uint64_t act = wave_ballot(pm != 0);
+    const int32_t k = __builtin_popcountll(act);
+    const int32_t below = lanes_below(act);
+    const int32_t pos = (S.f_n + (pm != 0 ? below : k + lane - below)) & 63;
+    const uint32_t lw = (uint32_t)((a0 >> 5) - S.lw0) + (uint32_t)lane;
+    const uint32_t v_pm = (uint32_t)__builtin_amdgcn_ds_permute(pos << 2, (int)pm);
+    const uint32_t v_lw = (uint32_t)__builtin_amdgcn_ds_permute(pos << 2, (int)lw);
+    const bool mine = lane >= S.f_n && lane < S.f_n + k;
+    const uint32_t g_pm = mine ? v_pm : S.f_pm;
+    const uint32_t g_lw = mine ? v_lw : S.f_lw;
+    if (S.f_n + k < 64) {
+        S.f_pm = g_pm;
+        S.f_lw = g_lw;
+        S.f_n += k;
+        return false;
+    }
+    r_pm = g_pm;
+    r_lw = g_lw;
+    const int32_t rem = S.f_n + k - 64;
+    S.f_pm = lane < rem ? v_pm : 0u;
+    S.f_lw = lane < rem ? v_lw : 0u;
+    S.f_n = rem;
+    return true;
+}
+
+// The packed words of a batch: lane-word lw0 + lw of each lane with rows
+// (pm != 0); the others read nothing.  Lane-words are in increasing order
+// over the lanes that have rows.
+template <int W0>
+__device__ __forceinline__ void batch_words(const BpCol& bc, int64_t lw0, uint32_t lw, uint32_t pm,
+                                            uint32_t (&wd)[W0]) {
+    constexpr int32_t kNone = 0x40000000;
+    const uint64_t act = wave_ballot(pm != 0);
+    if (act == 0) {
+        for (int i = 0; i < W0; ++i) wd[i] = 0;
+        return;
+    }
+    const uint32_t lw_first = (uint32_t)__builtin_amdgcn_readlane((int)lw, __builtin_ctzll(act));
+    const uint32_t lw_last = (uint32_t)__builtin_amdgcn_readlane((int)lw, 63 - __builtin_clzll(act));
+    const int64_t first_word = (lw0 + lw_first) * W0;
+    const int64_t span = (int64_t)(lw_last - lw_first + 1) * W0;   // words from the first lane-word on
+    const int64_t avail = bc.n_words - first_word;
+    const int64_t rel = (int64_t)(lw - lw_first) * W0;             // this lane's first word from there
+    if (span * 4 <= 0x7FFFFFFFll && avail >= span) {
+        const __amdgpu_buffer_rsrc_t rs = uni_rsrc(bc.packed, first_word * 4, span * 4, 0x7FFFFFFF);
+        const int32_t off = pm ? (int32_t)rel * 4 : kNone;
+#pragma unroll
+        for (int i = 0; i < W0 / 2; ++i) {
+            const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8 * i, 0, 0);
+            wd[2 * i] = v.x;
+            wd[2 * i + 1] = v.y;
+        }
+    } else {
+        // a batch spread over more than 2 GB of the stream, or the stream's
+        // end inside it: word by word from global memory
+#pragma unroll
+        for (int i = 0; i < W0; ++i) {
+            const int64_t q = first_word + rel + i;
+            wd[i] = pm && q < bc.n_words ? gld(bc.packed, q) : 0u;
+        }
+    }
+}
+
 // One wavefront over rows [w0, w1) of the plan's window, fast row path.
 template <int KMAX, int W0, bool SUMBP, bool BIG, bool ONES>
 __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
                                                 const uint8_t* lut, uint32_t* cnt, int64_t* table) {
     if (w0 >= w1) return;
     const int lane = lane_id();
+    const BpCol& bc = P.bp[0];
     FastState<KMAX, W0> S;
     S.w0 = w0;
     S.w1 = w1;
     S.t0 = w0 & ~(int64_t)31;
     S.t1 = min(((S.t0 >> kTileShift) + 1) << kTileShift, w1);
-    S.buf = 0;
+    S.lw0 = S.t0 >> 5;
+    S.all = ((w1 - 1) >> kTileShift) - (S.t0 >> kTileShift) + 1;
+    S.left = S.all;
+    S.f_pm = 0;
+    S.f_lw = 0;
+    S.f_n = 0;
+    S.pend = false;
+    S.pend_pm = 0;
+    S.pend_a0 = 0;
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
-        if (c < P.k_rle) W.tog[c * 64 + lane] = 0;
+        if (c < P.k_rle) {
+            W.tog[c * 128 + lane] = 0;
+            W.tog[c * 128 + 64 + lane] = 0;
+        }
         fast_runs_start(P, S.R, c, c < P.k_rle ? wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, S.t0) : 0);
     }
     const int64_t pk = P.n_idx > 0 ? wave_lower_bound_pos(P.idx[0].pos, P.idx[0].ptype, P.idx[0].n, w0) : 0;
-    fast_points_start(P, S.Q, pk & ~(int64_t)63);
+    fast_points_start<W0>(P, S.Q, pk & ~(int64_t)63);
     wave_lds_sync();
-    S.pm = fast_rle_mask<KMAX>(P, W, S.t0, S.t1, S.R) & fast_window_mask(S.t0, S.t1, w0);
-    W.pts[lane] = S.pm;
+    // batches alternate between two word buffers: a complete batch's words
+    // are read, then the batch before it is counted
     uint32_t wa[W0], wb[W0];
-    fast_words<W0>(P.bp[0], S.t0, S.pm, wa);
-    wave_lds_sync();
-    // two steps per iteration so the word buffers swap without copies
-    const int64_t all = ((w1 - 1) >> kTileShift) - (S.t0 >> kTileShift) + 1;
-    int64_t left = all;
+    uint32_t pa = 0, pb = 0;
+    bool have_b = false;
     for (;;) {
-        balance_priority(left--, all);
-        if (!fast_step<KMAX, W0, SUMBP, BIG, ONES>(P, W, S, wa, wb, lut, cnt, table)) break;
-        balance_priority(left--, all);
-        if (!fast_step<KMAX, W0, SUMBP, BIG, ONES>(P, W, S, wb, wa, lut, cnt, table)) break;
+        uint32_t rp = 0, rl = 0;
+        bool full = false;
+        while ((S.pend || S.t0 < S.t1) && !(full = fast_tile<KMAX, W0, BIG>(P, W, S, rp, rl, lut, table))) {
+        }
+        if (!full) {
+            rp = S.f_pm;
+            rl = S.f_lw;
+        }
+        batch_words<W0>(bc, S.lw0, rl, rp, wa);
+        pa = rp;
+        if (have_b && wave_ballot(pb != 0)) fast_rows<W0, SUMBP, BIG, ONES>(P, wb, pb, lut, cnt);
+        if (!full) {
+            if (wave_ballot(pa != 0)) fast_rows<W0, SUMBP, BIG, ONES>(P, wa, pa, lut, cnt);
+            break;
+        }
+        full = false;
+        while ((S.pend || S.t0 < S.t1) && !(full = fast_tile<KMAX, W0, BIG>(P, W, S, rp, rl, lut, table))) {
+        }
+        if (!full) {
+            rp = S.f_pm;
+            rl = S.f_lw;
+        }
+        batch_words<W0>(bc, S.lw0, rl, rp, wb);
+        pb = rp;
+        if (wave_ballot(pa != 0)) fast_rows<W0, SUMBP, BIG, ONES>(P, wa, pa, lut, cnt);
+        if (!full) {
+            if (wave_ballot(pb != 0)) fast_rows<W0, SUMBP, BIG, ONES>(P, wb, pb, lut, cnt);
+            break;
+        }
+        have_b = true;
     }
     __builtin_amdgcn_s_setprio(0);
 }
@@ -1485,7 +1630,7 @@ __device__ __forceinline__ void regacc_init(RegAcc<KMAX>& acc) {
 // hide the rest of the HBM latency better than four, even at the price of a
 // few spilled registers (measured); the staged paths and the batched kernel,
 // whose extra state would spill far more, keep the compiler's choice.
-constexpr int kFastWaves(int w0) { return w0 > 0 ? 5 : 1; }
+constexpr int kFastWaves(int w0) { return w0 > 0 ? 4 : 1; }
 
 // KMAX: bound on RLE columns (register arrays); W0: 0 = run mode or generic
 // row mode, else the width of the single bit-packed column of the fast row
