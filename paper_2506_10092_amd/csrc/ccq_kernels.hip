@@ -1005,62 +1005,52 @@ __device__ __forceinline__ uint32_t fast_slot(const BpCol& bc, uint32_t G, const
 }
 
 // Index points of the fast path (at most one Index column), in batches of
-// 64 that start at multiples of 64 of the point index.  Two batches are
-// decoded, the current one and the next, with the two packed words holding
-// each point's code read when its batch is decoded (a batch spans a few
-// tiles, so the words have that long to arrive); the batch after them is
-// read when the current one is used up.  A tile's points lie in the current
+// 64 that start at multiples of 64 of the point index: the current batch and
+// the next are decoded, and the raw batch after them is read when the current
+// one is used up.  The points of a pass over two tiles lie in the current
 // batch, or at its end and the start of the next one, where (with at most 64
-// points in the tile) each lane holds at most one of them; denser tiles take
-// a slower batch-by-batch route.  A point whose row survives the RLE
+// points in the pass) each lane holds at most one of them; denser passes
+// take a slower batch-by-batch route.  A point whose row survives the RLE
 // predicates adds its value to the row's group (the Plain x Index case of
-// Section 5.1).
+// Section 5.1).  The packed words holding its code are read when its pass is
+// masked, for surviving points only, and used in the next pass.
 struct PointBatch {
     int64_t pos, val;      // point k + lane (pos INT64_MAX past the column)
-    uint32_t lo, hi;       // the packed words holding its code
 };
 
 struct FastPoints {
     int64_t k;             // wave-uniform: first point of the current batch
     PointBatch cur, nxt;   // points k + lane and k + 64 + lane
     Raw64 np, nv;          // raw positions and values of points k + 128 + lane
+    // the surviving points of the last pass, added in the next one
+    uint64_t d_in;         // wave-uniform: lanes holding one
+    int64_t d_val;
+    uint32_t d_sh, d_lo, d_hi;   // bit offset of its code in the words lo, hi
 };
 
-__device__ __forceinline__ int64_t idx_points(const DevPlan& P) { return P.n_idx > 0 ? P.idx[0].n : 0; }
+__device__ __forceinline__ int64_t idx_points(const DevPlan& P) {
+    return P.n_idx > 0 && P.idx[0].sum_slot >= 0 ? P.idx[0].n : 0;
+}
 
-// decode a batch of points starting at k and read the words under them
-template <int W0>
-__device__ __forceinline__ void point_batch(const DevPlan& P, int64_t k, Raw64 p, Raw64 v, PointBatch& B) {
+// decode points k + lane
+__device__ __forceinline__ void point_decode(const DevPlan& P, int64_t k, Raw64 p, Raw64 v, PointBatch& B) {
     const IdxCol& ic = P.idx[0];
-    const BpCol& bc = P.bp[0];
-    const int64_t n = idx_points(P);
-    const bool ok = k + lane_id() < n;
+    const bool ok = k + lane_id() < idx_points(P);
     B.pos = ok ? raw_val(p, ic.ptype) : INT64_MAX;
     B.val = ok ? raw_val(v, ic.vtype) : 0;
-    const int64_t wq = ok ? (B.pos * W0) >> 5 : 0;
-    B.lo = gld(bc.packed, wq);
-    B.hi = gld(bc.packed, wq + 1 < bc.n_words ? wq + 1 : wq);
 }
 
 // make the batch at point k (a multiple of 64) current, read here with the
 // next one; issue the reads of the one after
-template <int W0>
 __device__ __forceinline__ void fast_points_start(const DevPlan& P, FastPoints& Q, int64_t k) {
     const IdxCol& ic = P.idx[0];
     const int64_t n = idx_points(P);
     Q.k = k;
-    point_batch<W0>(P, k, batch_load(ic.pos, ic.ptype, k, n), batch_load(ic.vals, ic.vtype, k, n), Q.cur);
-    point_batch<W0>(P, k + 64, batch_load(ic.pos, ic.ptype, k + 64, n), batch_load(ic.vals, ic.vtype, k + 64, n),
-                    Q.nxt);
+    point_decode(P, k, batch_load(ic.pos, ic.ptype, k, n), batch_load(ic.vals, ic.vtype, k, n), Q.cur);
+    point_decode(P, k + 64, batch_load(ic.pos, ic.ptype, k + 64, n), batch_load(ic.vals, ic.vtype, k + 64, n), Q.nxt);
     Q.np = batch_load(ic.pos, ic.ptype, k + 128, n);
     Q.nv = batch_load(ic.vals, ic.vtype, k + 128, n);
-}
-
-// the code of a point at row pos from the two packed words holding it
-template <int W0>
-__device__ __forceinline__ uint32_t point_code(int64_t pos, uint32_t lo, uint32_t hi) {
-    const uint32_t sh = (uint32_t)(pos * W0) & 31u;
-    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
+    Q.d_in = 0;
 }
 
 // add a surviving point's value to the group of its code
@@ -1080,56 +1070,92 @@ __device__ __forceinline__ void fast_point_add(const DevPlan& P, int64_t val, ui
     }
 }
 
-// whether the row at offset rel of a tile survives, from the tile's lane
-// masks (every lane takes part: the mask is read across lanes)
-__device__ __forceinline__ bool tile_row_survives(uint32_t pm, uint32_t rel) {
-    const uint32_t owner = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((rel >> 5) << 2), (int)pm);
-    return ((owner >> (rel & 31)) & 1u) != 0;
+// the code at bit offset sh of the two packed words lo, hi
+template <int W0>
+__device__ __forceinline__ uint32_t code_at(uint32_t sh, uint32_t lo, uint32_t hi) {
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) & ((1u << W0) - 1u);
 }
 
-// The points of tile [a0, a1) whose lane masks are pm.
+// the surviving points of the last pass (their words were read a pass ago)
 template <int W0, bool BIG>
-__device__ __forceinline__ void fast_points_tile(const DevPlan& P, FastPoints& Q, int64_t a0, int64_t a1,
-                                                 uint32_t pm, const uint8_t* lut, int64_t* table) {
+__device__ __forceinline__ void fast_points_flush(const DevPlan& P, FastPoints& Q, const uint8_t* lut,
+                                                  int64_t* table) {
+    const uint32_t code = code_at<W0>(Q.d_sh, Q.d_lo, Q.d_hi);
+    if (lane_in(Q.d_in)) fast_point_add<W0, BIG>(P, Q.d_val, code, lut, table);
+    Q.d_in = 0;
+}
+
+// whether the row at pos survives, from the lane masks of tile A = [a0, a1)
+// and B = [a1, ...) (every lane takes part: the masks are read across lanes)
+__device__ __forceinline__ bool pass_row_survives(int64_t pos, int64_t a0, int64_t a1, uint32_t pma, uint32_t pmb) {
+    const uint32_t ra = (uint32_t)pos - (uint32_t)a0, rb = (uint32_t)pos - (uint32_t)a1;
+    const uint32_t oa = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((ra >> 5) << 2), (int)pma);
+    const uint32_t ob = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((rb >> 5) << 2), (int)pmb);
+    return pos < a1 ? ((oa >> (ra & 31)) & 1u) != 0 : ((ob >> (rb & 31)) & 1u) != 0;
+}
+
+// The points of the pass over tile A = [a0, a1) and B = [a1, b1) (masks pma,
+// pmb): add those of the last pass, find these, and read the words under the
+// surviving ones.
+template <int W0, bool BIG>
+__device__ __forceinline__ void fast_points_pass(const DevPlan& P, FastPoints& Q, int64_t a0, int64_t a1, int64_t b1,
+                                                 uint32_t pma, uint32_t pmb, const uint8_t* lut, int64_t* table) {
     const IdxCol& ic = P.idx[0];
     const BpCol& bc = P.bp[0];
-    if (!(P.n_idx > 0 && ic.sum_slot >= 0)) return;
     const int64_t npts = idx_points(P);
-    const uint64_t in1 = wave_ballot(Q.cur.pos >= a0 && Q.cur.pos < a1);
-    const bool live1 = tile_row_survives(pm, (uint32_t)Q.cur.pos - (uint32_t)a0) && lane_in(in1);
-    const uint32_t code1 = point_code<W0>(Q.cur.pos, Q.cur.lo, Q.cur.hi);
-    if (live1) fast_point_add<W0, BIG>(P, Q.cur.val, code1, lut, table);
-    if ((wave_ballot(Q.cur.pos < a1) >> 63) == 0) return;
-    // the current batch ends inside the tile: the next one becomes current
-    const int64_t first = Q.k + __builtin_ctzll(wave_ballot(Q.cur.pos >= a0));
-    const uint64_t in2 = wave_ballot(Q.nxt.pos < a1);
-    if ((in2 & in1) != 0 || (in2 >> 63) != 0) {
-        // more than 64 points in the tile: the rest batch by batch, then
-        // batches again at the first point after the tile
-        int64_t g = first + __builtin_popcountll(in1);
-        for (;;) {
-            Raw64 rp = batch_load(ic.pos, ic.ptype, g, npts), rv = batch_load(ic.vals, ic.vtype, g, npts);
-            PointBatch B;
-            point_batch<W0>(P, g, rp, rv, B);
-            const uint64_t in3 = wave_ballot(B.pos < a1);
-            const bool live3 = tile_row_survives(pm, (uint32_t)B.pos - (uint32_t)a0) && lane_in(in3);
-            const uint32_t code3 = point_code<W0>(B.pos, B.lo, B.hi);
-            if (live3) fast_point_add<W0, BIG>(P, B.val, code3, lut, table);
-            const int32_t k = __builtin_popcountll(in3);
-            g += k;
-            if (k < 64) break;
+    if (npts == 0) return;
+    fast_points_flush<W0, BIG>(P, Q, lut, table);
+    uint64_t in = wave_ballot(Q.cur.pos >= a0 && Q.cur.pos < b1);
+    int64_t pos = Q.cur.pos, val = Q.cur.val;
+    if (wave_ballot(Q.cur.pos < b1) >> 63) {
+        // the current batch ends inside the pass: the next one becomes current
+        const int64_t first = Q.k + __builtin_ctzll(wave_ballot(Q.cur.pos >= a0));
+        const uint64_t in2 = wave_ballot(Q.nxt.pos < b1);
+        if ((in2 & in) != 0 || (in2 >> 63) != 0) {
+            // more than 64 points in the pass: batch by batch with the words
+            // read here, then batches again at the first point after the pass
+            int64_t g = first;
+            for (;;) {
+                PointBatch B;
+                point_decode(P, g, batch_load(ic.pos, ic.ptype, g, npts), batch_load(ic.vals, ic.vtype, g, npts), B);
+                const uint64_t in3 = wave_ballot(B.pos < b1);
+                const bool live3 = pass_row_survives(B.pos, a0, a1, pma, pmb) && lane_in(in3);
+                const int64_t wq = live3 ? (B.pos * W0) >> 5 : 0;
+                uint32_t lo = 0, hi = 0;
+                if (live3) {
+                    lo = gld(bc.packed, wq);
+                    hi = gld(bc.packed, wq + 1);
+                }
+                if (live3) fast_point_add<W0, BIG>(P, B.val, code_at<W0>((uint32_t)(B.pos * W0) & 31u, lo, hi), lut, table);
+                const int32_t k = __builtin_popcountll(in3);
+                g += k;
+                if (k < 64) break;
+            }
+            fast_points_start(P, Q, g & ~(int64_t)63);
+            return;
         }
-        fast_points_start<W0>(P, Q, g & ~(int64_t)63);
-        return;
+        if (lane_in(in2)) {
+            pos = Q.nxt.pos;
+            val = Q.nxt.val;
+        }
+        in |= in2;
+        Q.k += 64;
+        Q.cur = Q.nxt;
+        point_decode(P, Q.k + 64, Q.np, Q.nv, Q.nxt);
+        Q.np = batch_load(ic.pos, ic.ptype, Q.k + 128, npts);
+        Q.nv = batch_load(ic.vals, ic.vtype, Q.k + 128, npts);
     }
-    const bool live2 = tile_row_survives(pm, (uint32_t)Q.nxt.pos - (uint32_t)a0) && lane_in(in2);
-    const uint32_t code2 = point_code<W0>(Q.nxt.pos, Q.nxt.lo, Q.nxt.hi);
-    if (live2) fast_point_add<W0, BIG>(P, Q.nxt.val, code2, lut, table);
-    Q.k += 64;
-    Q.cur = Q.nxt;
-    point_batch<W0>(P, Q.k + 64, Q.np, Q.nv, Q.nxt);
-    Q.np = batch_load(ic.pos, ic.ptype, Q.k + 128, npts);
-    Q.nv = batch_load(ic.vals, ic.vtype, Q.k + 128, npts);
+    const uint64_t live = wave_ballot(pass_row_survives(pos, a0, a1, pma, pmb)) & in;
+    // the words under the surviving points, from the pass's stretch of the stream
+    const int64_t tw = (a0 >> 5) * W0;
+    const __amdgpu_buffer_rsrc_t rs = uni_rsrc(bc.packed, tw * 4, (bc.n_words - tw) * 4, (128 * W0 + 2) * 4);
+    constexpr int32_t kNone = 0x40000000;
+    const int32_t off = lane_in(live) ? (int32_t)((((uint32_t)pos - (uint32_t)a0) * (uint32_t)W0) >> 5) * 4 : kNone;
+    Q.d_lo = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    Q.d_hi = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0);
+    Q.d_in = live;
+    Q.d_val = val;
+    Q.d_sh = (uint32_t)(pos * W0) & 31u;
 }
 
 // The fast path counts rows by lane-words, the 32 rows from a multiple of 32
@@ -1188,9 +1214,8 @@ __device__ __forceinline__ bool fast_tile(const DevPlan& P, const WaveLds& W, Fa
         fast_rle_mask<KMAX>(P, W, a0, a1, b1, S.R, pm, pmb);
         pm &= fast_window_mask(a0, a1, S.w0);
         pmb &= fast_window_mask(a1, b1, S.w0);
-        fast_points_tile<W0, BIG>(P, S.Q, a0, a1, pm, lut, table);
+        fast_points_pass<W0, BIG>(P, S.Q, a0, a1, b1, pm, pmb, lut, table);
         if (b1 > a1) {
-            fast_points_tile<W0, BIG>(P, S.Q, a1, b1, pmb, lut, table);
             S.pend = true;
             S.pend_pm = pmb;
             S.pend_a0 = a1;
@@ -1294,7 +1319,7 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
         fast_runs_start(P, S.R, c, c < P.k_rle ? wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, S.t0) : 0);
     }
     const int64_t pk = P.n_idx > 0 ? wave_lower_bound_pos(P.idx[0].pos, P.idx[0].ptype, P.idx[0].n, w0) : 0;
-    fast_points_start<W0>(P, S.Q, pk & ~(int64_t)63);
+    fast_points_start(P, S.Q, pk & ~(int64_t)63);
     wave_lds_sync();
     // batches alternate between two word buffers: a complete batch's words
     // are read, then the batch before it is counted
@@ -1333,6 +1358,7 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
         }
         have_b = true;
     }
+    if (idx_points(P) > 0) fast_points_flush<W0, BIG>(P, S.Q, lut, table);
     __builtin_amdgcn_s_setprio(0);
 }
 
