@@ -770,9 +770,11 @@ __device__ __forceinline__ u32x2 batch_ends(const int64_t* ends, int64_t i0, int
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
 // The current batch of a column: runs b .. b + 63, one per lane, with the
-// outcome of each run as a bit of a 64-bit mask.  The next batch is loaded
-// when this one becomes current, so its loads have the whole batch's tiles
-// (two or more for runs longer than 32 rows on average) to arrive.
+// outcome of each run as a bit of a 64-bit mask.  The raw next batch is read
+// again after every pass over two tiles, at the same point of the pass, and
+// used in a later pass when the current batch ends; a tile that ends runs of
+// more than two batches (runs shorter than 16 rows on average) reads the
+// further ones directly.
 template <int KMAX>
 struct FastRuns {
     int64_t b[KMAX];       // wave-uniform: the batch's first run
@@ -790,8 +792,7 @@ __device__ __forceinline__ uint64_t batch_pass(const RleCol& rc, Raw64 v, uint64
 
 __device__ __forceinline__ int64_t rle_runs(const DevPlan& P, int c) { return c < P.k_rle ? P.rle[c].n_runs : 0; }
 
-// make runs b .. b + 63 of column c the current batch (loaded here) and
-// issue the loads of the next one
+// make runs b .. b + 63 of column c the current batch (read here)
 template <int KMAX>
 __device__ __forceinline__ void fast_runs_start(const DevPlan& P, FastRuns<KMAX>& R, int c, int64_t b) {
     const RleCol& rc = P.rle[c];
@@ -800,15 +801,41 @@ __device__ __forceinline__ void fast_runs_start(const DevPlan& P, FastRuns<KMAX>
     R.valid[c] = batch_lanes(n - b);
     R.e[c] = batch_ends_val(batch_ends(rc.ends, b, n));
     R.pb[c] = batch_pass(rc, batch_load(rc.vals, rc.vtype, b, n), R.valid[c]);
-    R.ne[c] = batch_ends(rc.ends, b + 64, n);
-    R.nv[c] = batch_load(rc.vals, rc.vtype, b + 64, n);
+}
+
+// read the next batch of every column (again)
+template <int KMAX>
+__device__ __forceinline__ void fast_runs_next(const DevPlan& P, FastRuns<KMAX>& R) {
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        const RleCol& rc = P.rle[c];
+        const int64_t n = rle_runs(P, c);
+        R.ne[c] = batch_ends(rc.ends, R.b[c] + 64, n);
+        R.nv[c] = batch_load(rc.vals, rc.vtype, R.b[c] + 64, n);
+    }
+}
+
+// Toggles at the ends of the runs in m (ends in (t0, t1)): the outcome
+// changes there.  Toggles of tile A = [t0, tm) go to words 0..63 of the
+// column's bitmap, those of B = [tm, t1) to words 64..127.
+__device__ __forceinline__ void run_toggles(uint32_t* tog, int64_t e, uint64_t m, int64_t t0, int64_t tm) {
+    if (lane_in(m)) {
+        const uint32_t rel = e < tm ? (uint32_t)e - (uint32_t)t0 : (uint32_t)e - (uint32_t)tm + (uint32_t)kRowTile;
+        atomicOr(&tog[rel >> 5], 1u << (rel & 31));
+    }
+}
+
+// outcome changes after runs 0..62 of a batch, and after run 63 given the
+// outcome (0 or 1) of the run after it
+__device__ __forceinline__ uint64_t batch_changes(uint64_t pb, uint64_t pb_next) {
+    return pb ^ (pb >> 1) ^ (pb_next << 63);
 }
 
 // The lane's rows that pass every RLE predicate in two consecutive tiles,
 // A = [t0, tm) and B = [tm, t1) (B may be empty), with one pass over the
-// runs: toggles of A go to words 0..63 of the column's bitmap, those of B to
-// words 64..127.  Tiles are visited in increasing order; a column's current
-// batch moves on when its last run ends before t1.
+// runs.  Tiles are visited in increasing order; a column's current batch
+// holds a run ending after t0 and moves on when its last run ends at or
+// before t1.
 template <int KMAX>
 __device__ __forceinline__ void fast_rle_mask(const DevPlan& P, const WaveLds& W, int64_t t0, int64_t tm, int64_t t1,
                                               FastRuns<KMAX>& R, uint32_t& pm_a, uint32_t& pm_b) {
@@ -820,37 +847,42 @@ __device__ __forceinline__ void fast_rle_mask(const DevPlan& P, const WaveLds& W
         const RleCol& rc = P.rle[c];
         const int64_t n = rc.n_runs;
         uint32_t* tog = W.tog + c * 128;
-        bool found = false;
-        for (;;) {
-            const uint64_t gt = wave_ballot(R.e[c] > t0) & R.valid[c];   // runs ending after t0
-            const uint64_t lt = wave_ballot(R.e[c] < t1) & R.valid[c];   // runs ending before t1
-            if (!found && gt) {
-                // the first run ending after t0 holds row t0
-                first |= (uint32_t)((R.pb[c] >> __builtin_ctzll(gt)) & 1u) << c;
-                found = true;
-            }
-            // the outcome changes at the end of run l when run l + 1 differs
-            uint64_t tg = (R.pb[c] ^ (R.pb[c] >> 1)) & 0x7FFFFFFFFFFFFFFFull;
-            const bool next = (lt >> 63) != 0;   // the batch's last run ends before t1
-            uint64_t npb = 0, nvalid = 0;
-            if (next) {
-                nvalid = batch_lanes(n - R.b[c] - 64);
-                npb = batch_pass(rc, R.nv[c], nvalid);
-                tg |= ((R.pb[c] >> 63) ^ (npb & 1u)) << 63;
-            }
-            if (lane_in(gt & lt & tg)) {
-                const int64_t e = R.e[c];
-                const uint32_t rel = e < tm ? (uint32_t)e - (uint32_t)t0 : (uint32_t)e - (uint32_t)tm + (uint32_t)kRowTile;
-                atomicOr(&tog[rel >> 5], 1u << (rel & 31));
-            }
-            if (!next) break;
-            R.b[c] += 64;
-            R.valid[c] = nvalid;
-            R.pb[c] = npb;
-            R.e[c] = batch_ends_val(R.ne[c]);
-            R.ne[c] = batch_ends(rc.ends, R.b[c] + 64, n);
-            R.nv[c] = batch_load(rc.vals, rc.vtype, R.b[c] + 64, n);
+        const uint64_t gt = wave_ballot(R.e[c] > t0) & R.valid[c];   // runs ending after t0
+        const uint64_t lt = wave_ballot(R.e[c] < t1) & R.valid[c];   // runs ending before t1
+        const uint64_t le = wave_ballot(R.e[c] <= t1) & R.valid[c];
+        // the first run ending after t0 holds row t0
+        if (gt) first |= (uint32_t)((R.pb[c] >> __builtin_ctzll(gt)) & 1u) << c;
+        if ((le >> 63) == 0) {
+            run_toggles(tog, R.e[c], gt & lt & batch_changes(R.pb[c], R.pb[c] >> 63), t0, tm);
+            continue;
         }
+        // the batch ends: the next one (read in an earlier pass) is used here
+        // and only here
+        uint64_t valid = batch_lanes(n - R.b[c] - 64);
+        uint64_t pb = batch_pass(rc, R.nv[c], valid);
+        int64_t e = batch_ends_val(R.ne[c]);
+        run_toggles(tog, R.e[c], gt & lt & batch_changes(R.pb[c], pb & 1u), t0, tm);
+        int64_t b = R.b[c] + 64;
+        for (;;) {
+            const uint64_t in = wave_ballot(e > t0 && e < t1) & valid;
+            if (((wave_ballot(e <= t1) & valid) >> 63) == 0) {
+                run_toggles(tog, e, in & batch_changes(pb, pb >> 63), t0, tm);
+                break;
+            }
+            // runs shorter than 16 rows: one more batch inside the tiles
+            const uint64_t valid3 = batch_lanes(n - b - 64);
+            const int64_t e3 = batch_ends_val(batch_ends(rc.ends, b + 64, n));
+            const uint64_t pb3 = batch_pass(rc, batch_load(rc.vals, rc.vtype, b + 64, n), valid3);
+            run_toggles(tog, e, in & batch_changes(pb, pb3 & 1u), t0, tm);
+            b += 64;
+            e = e3;
+            pb = pb3;
+            valid = valid3;
+        }
+        R.b[c] = b;
+        R.valid[c] = valid;
+        R.pb[c] = pb;
+        R.e[c] = e;
     }
     wave_lds_sync();
     pm_a = 0xFFFFFFFFu;
@@ -1215,6 +1247,7 @@ __device__ __forceinline__ bool fast_tile(const DevPlan& P, const WaveLds& W, Fa
         pm &= fast_window_mask(a0, a1, S.w0);
         pmb &= fast_window_mask(a1, b1, S.w0);
         fast_points_pass<W0, BIG>(P, S.Q, a0, a1, b1, pm, pmb, lut, table);
+        fast_runs_next<KMAX>(P, S.R);
         if (b1 > a1) {
             S.pend = true;
             S.pend_pm = pmb;
@@ -1318,6 +1351,7 @@ __device__ __forceinline__ void wave_range_fast(const DevPlan& P, const WaveLds&
         }
         fast_runs_start(P, S.R, c, c < P.k_rle ? wave_upper_bound(P.rle[c].ends, P.rle[c].n_runs, S.t0) : 0);
     }
+    fast_runs_next<KMAX>(P, S.R);
     const int64_t pk = P.n_idx > 0 ? wave_lower_bound_pos(P.idx[0].pos, P.idx[0].ptype, P.idx[0].n, w0) : 0;
     fast_points_start(P, S.Q, pk & ~(int64_t)63);
     wave_lds_sync();
