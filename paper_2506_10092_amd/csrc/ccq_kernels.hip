@@ -928,42 +928,6 @@ __device__ __forceinline__ uint32_t fast_window_mask(int64_t t0, int64_t t1, int
     return m;
 }
 
-// Buffer resource over the packed words of the tile at t0 and the `extra`
-// words after it (those that exist).
-template <int W0>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_words_rsrc(const BpCol& bc, int64_t t0, int32_t extra,
-                                                                  int64_t* avail) {
-    const int64_t tw = (t0 >> 5) * W0;                 // the tile's first word
-    *avail = bc.n_words - tw;                          // words from there on
-    return uni_rsrc(bc.packed, tw * 4, *avail * 4, (64 * W0 + extra) * 4);
-}
-
-// The lane's W0 words of the tile at t0; lanes without surviving rows read
-// nothing (an out-of-range buffer offset returns zero without a memory
-// access).
-template <int W0>
-__device__ __forceinline__ void fast_words(const BpCol& bc, int64_t t0, uint32_t pm, uint32_t (&wd)[W0]) {
-    const int lane = lane_id();
-    int64_t avail;
-    const __amdgpu_buffer_rsrc_t rs = tile_words_rsrc<W0>(bc, t0, 0, &avail);
-    const int32_t lw = lane * W0;
-    constexpr int32_t kNone = 0x40000000;              // beyond any tile's records
-    if (avail >= 64 * W0) {
-        const int32_t off = pm ? lw * 4 : kNone;
-#pragma unroll
-        for (int i = 0; i < W0 / 2; ++i) {
-            const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8 * i, 0, 0);
-            wd[2 * i] = v.x;
-            wd[2 * i + 1] = v.y;
-        }
-    } else {
-        // the stream ends inside this tile: word by word
-        const int32_t rem = pm ? (int32_t)avail - lw : 0;   // the lane's words that exist
-        const int32_t off = lw * 4;
-#pragma unroll
-        for (int i = 0; i < W0; ++i) wd[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, i < rem ? off + 4 * i : kNone, 0, 0);
-    }
-}
 // Count the lane's 32 rows into the lane-replicated LDS table (slot-major,
 // 2^rep_shift replicas, uint32): the lanes of a wave never hit the same
 // address, whatever the skew of the codes.  Slot G counts rows whose key is

@@ -252,3 +252,62 @@ def test_large_group_table_fast_path(ctx, q):
             qq["preds"] = [x for x in q["preds"] if x[0] != "p"] + [("p", "range", 0, 1 << 19)]
         got = check(ctx, t, qq)
         say("groups", len(got["keys"]))
+
+
+def _geometric_runs(rng, n, mean, vlo, vhi, dt=np.int32):
+    """RLE column over n rows with geometric run lengths of the given mean."""
+    lens = rng.geometric(1.0 / mean, size=int(n / mean * 1.3) + 64)
+    ends = np.cumsum(lens)
+    ends = ends[ends < n]
+    ends = np.r_[ends, n]
+    return _rle(rng.integers(vlo, vhi, len(ends)), ends, dt)
+
+
+def _index_col(rng, n, density):
+    keep = rng.random(n) < density
+    pos = np.flatnonzero(keep).astype(np.int32)
+    return {"enc": "index", "positions": pos, "values": rng.integers(1, 1_000_000, len(pos)).astype(np.int64)}
+
+
+@pytest.mark.parametrize("mean_run", [1, 5, 64])
+@pytest.mark.parametrize("density", [0.05, 0.3, 1.0])
+def test_fast_path_short_runs_and_dense_points(ctx, mean_run, density):
+    """The single-packed-column row path with runs shorter than a batch per
+    tile pass (several run batches per pass) and with more than 64 Index
+    points per pass (the batch-by-batch point route); windows cut tiles."""
+    n = 1_000_003
+    rng = np.random.default_rng(1000 + mean_run * 10 + int(density * 10))
+    codes = rng.integers(0, 700, n).astype(np.uint32)
+    cols = {"r0": _geometric_runs(rng, n, mean_run, 0, 4),
+            "r1": _geometric_runs(rng, n, 200, 0, 4),
+            "s": _index_col(rng, n, density),
+            "d": {"enc": "bitpacked", "packed": datagen.pack_codes(codes, 14), "w": 14, "base": 0}}
+    t = {"n_rows": n, "columns": cols}
+    in_codes = [int(x) for x in rng.choice(700, 40, replace=False)]
+    q = {"preds": [("r0", "range", 1, 3), ("r1", "range", 0, 3), ("d", "in", in_codes)],
+         "keys": [("d", 0, 1 << 14)], "aggs": [("sum", "s"), ("count",)], "window": (0, n)}
+    say("fast path mean_run", mean_run, "density", density)
+    check(ctx, t, q)
+    q["window"] = (12_345, n - 777)
+    check(ctx, t, q)
+
+
+@pytest.mark.parametrize("density", [0.01, 0.5])
+def test_fast_path_20bit_code_range(ctx, density):
+    """The 20-bit row path without a code table (a code range and a shifted
+    key), with RLE predicates and an Index SUM."""
+    n = 777_777
+    rng = np.random.default_rng(77 + int(density * 100))
+    codes = rng.integers(0, 1 << 20, n).astype(np.uint32)
+    cols = {"r0": _geometric_runs(rng, n, 30, 0, 8),
+            "s": _index_col(rng, n, density),
+            "p": {"enc": "bitpacked", "packed": datagen.pack_codes(codes, 20), "w": 20, "base": -(1 << 19)}}
+    t = {"n_rows": n, "columns": cols}
+    q = {"preds": [("r0", "range", 2, 7), ("p", "range", -100_000, 300_000)],
+         "keys": [("p", 14, 64)], "aggs": [("sum", "s"), ("count",)], "window": (0, n)}
+    # keys of negative values fall outside [0, card): keep them out with the range
+    q["preds"][1] = ("p", "range", 0, 300_000)
+    say("20-bit fast path density", density)
+    check(ctx, t, q)
+    q["window"] = (31, n - 1)
+    check(ctx, t, q)
