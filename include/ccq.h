@@ -7,7 +7,8 @@
  *   - columns arrive encoded (Section 3.1: Plain, RLE, Index; Section 3.2:
  *     bit-width reduction around a global reference value; dictionary codes
  *     are plain integer codes, Section 2.1);
- *   - a query is a conjunction of selection predicates (Sections 5.1 and 6),
+ *   - a query is a conjunction of selection predicates, each possibly negated
+ *     (Sections 5.1, 5.3 and 6),
  *     a list of group-by keys and SUM / COUNT(*) aggregates (Section 7);
  *   - the answer is the exact aggregate per non-empty group, in ascending key
  *     order (torch.unique order, Section 2.2).  RLE runs contribute
@@ -93,13 +94,18 @@ typedef struct {
     int64_t base;              /* BITPACKED: value = base + code */
 } ccq_column_desc;
 
-/* ---- query (Sections 5-7) ---- */
-enum { CCQ_RANGE = 1, CCQ_IN = 2 };
+/* ---- query (Sections 5-7) ----
+ * CCQ_NOT_RANGE and CCQ_NOT_IN hold where CCQ_RANGE and CCQ_IN fail: the
+ * complement of the predicate's mask (Section 5.3, NOT; Algorithms 7 and 8
+ * complement RLE and Index masks).  Predicates on one column, plain or
+ * negated, fold into one list of value intervals per column. */
+enum { CCQ_RANGE = 1, CCQ_IN = 2, CCQ_NOT_RANGE = 3, CCQ_NOT_IN = 4 };
 typedef struct {
     int32_t col;               /* column index in the table */
-    int32_t op;                /* CCQ_RANGE: lo <= v < hi;  CCQ_IN: v in in_list */
+    int32_t op;                /* CCQ_RANGE: lo <= v < hi;  CCQ_IN: v in in_list;
+                                  CCQ_NOT_RANGE / CCQ_NOT_IN: the negations */
     int64_t lo, hi;
-    const int64_t* in_list;    /* CCQ_IN: HOST array, copied by ccq_plan_create */
+    const int64_t* in_list;    /* CCQ_IN, CCQ_NOT_IN: HOST array, copied by ccq_plan_create */
     int64_t in_len;
 } ccq_pred;
 

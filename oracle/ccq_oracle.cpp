@@ -13,7 +13,8 @@
  *      (value, position); Section 3.2 bit-width reduction with a global
  *      reference value, value = base + code);
  *   2. a row qualifies when every predicate holds on its values (selection,
- *      Section 6);
+ *      Section 6); a negated predicate holds where the plain one fails (NOT,
+ *      Section 5.3);
  *   3. qualifying rows are grouped by their key tuple and COUNT(*) / SUM(col)
  *      are accumulated per group (Section 7, grouping and aggregating phases);
  *   4. groups are emitted in ascending key order (torch.unique returns sorted
@@ -48,7 +49,7 @@ extern "C" {
 
 enum { ORC_RLE = 1, ORC_INDEX = 2, ORC_BITPACKED = 3 };
 enum { ORC_I32 = 1, ORC_I64 = 2 };
-enum { ORC_RANGE = 1, ORC_IN = 2 };
+enum { ORC_RANGE = 1, ORC_IN = 2, ORC_NOT_RANGE = 3, ORC_NOT_IN = 4 };
 enum { ORC_COUNT = 1, ORC_SUM = 2 };
 
 typedef struct {
@@ -69,6 +70,7 @@ typedef struct {
     int32_t op;
     int64_t lo, hi;             /* RANGE: lo <= v < hi */
     const int64_t* in_list;     /* IN */
+                                /* NOT_RANGE, NOT_IN: the negations (Section 5.3) */
     int64_t in_len;
 } orc_pred;
 
@@ -214,8 +216,10 @@ void run_chunks(const Query& q, std::atomic<int64_t>& next_chunk, int64_t n_chun
             bool pass = true;
             for (size_t p = 0; p < q.preds.size() && pass; p++) {
                 int64_t v = x[q.slot[q.preds[p].col]][r];
-                if (q.preds[p].op == ORC_RANGE) pass = q.preds[p].lo <= v && v < q.preds[p].hi;
+                const int32_t op = q.preds[p].op;
+                if (op == ORC_RANGE || op == ORC_NOT_RANGE) pass = q.preds[p].lo <= v && v < q.preds[p].hi;
                 else pass = q.in_sets[p].count(v) != 0;
+                if (op == ORC_NOT_RANGE || op == ORC_NOT_IN) pass = !pass;
             }
             if (!pass) continue;
             for (size_t k = 0; k < q.keys.size(); k++) {
@@ -269,9 +273,9 @@ Result* execute(Query& q, int n_threads) {
     q.in_sets.assign(q.preds.size(), {});
     for (size_t p = 0; p < q.preds.size(); p++) {
         if (!use(q.preds[p].col)) { res->error = "predicate column out of range"; return res; }
-        if (q.preds[p].op == ORC_IN) {
+        if (q.preds[p].op == ORC_IN || q.preds[p].op == ORC_NOT_IN) {
             for (int64_t i = 0; i < q.preds[p].in_len; i++) q.in_sets[p].insert(q.preds[p].in_list[i]);
-        } else if (q.preds[p].op != ORC_RANGE) {
+        } else if (q.preds[p].op != ORC_RANGE && q.preds[p].op != ORC_NOT_RANGE) {
             res->error = "unknown predicate";
             return res;
         }

@@ -24,7 +24,7 @@ _lib = None
 
 RLE, INDEX, BITPACKED = 1, 2, 3
 I32, I64 = 1, 2
-RANGE, IN = 1, 2
+RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
 COUNT, SUM = 1, 2
 
 
@@ -157,12 +157,14 @@ def run(table, query, n_threads=None):
     for i, p in enumerate(query["preds"]):
         op = p[1]
         preds[i].col = col_id(p[0])
-        if op == "range":
-            preds[i].op, preds[i].lo, preds[i].hi = RANGE, int(p[2]), int(p[3])
-        elif op == "in":
+        if op in ("range", "not_range"):
+            preds[i].op = RANGE if op == "range" else NOT_RANGE
+            preds[i].lo, preds[i].hi = int(p[2]), int(p[3])
+        elif op in ("in", "not_in"):
             lst = np.ascontiguousarray(np.array(list(p[2]), dtype=np.int64))
             keep.append(lst)
-            preds[i].op, preds[i].in_list, preds[i].in_len = IN, lst.ctypes.data, len(lst)
+            preds[i].op = IN if op == "in" else NOT_IN
+            preds[i].in_list, preds[i].in_len = lst.ctypes.data, len(lst)
         else:
             raise OracleError("unknown predicate %r" % (op,))
     keys = (OrcKey * max(len(query["keys"]), 1))()
@@ -199,3 +201,29 @@ def run(table, query, n_threads=None):
         "counts": [int(x) for x in cb[:g]],
         "aggs": [tuple(int(x) for x in ab[i * na:(i + 1) * na]) for i in range(g)],
     }
+
+
+# ---- NOT on position-explicit masks (Section 5.3; Appendix, NOT operator)
+#
+# A mask in RLE form lists inclusive row ranges [start_i, end_i] (sorted,
+# disjoint); in Index form it lists single rows.  The complement of an RLE
+# mask is the list of gaps between its ranges (Algorithm 7), that of an
+# Index mask the gaps between its rows, also as ranges (Algorithm 8).  These
+# are the paper's mask forms, kept here to pin the meaning of NOT that the
+# query path evaluates per row.
+
+def not_rle(start, end, total_size):
+    """Gaps of an RLE mask over rows [0, total_size): each candidate gap runs
+    from one range's end + 1 to the next range's start - 1; empty ones drop."""
+    s2 = [e + 1 for e in [-1] + list(end)]
+    e2 = [s - 1 for s in list(start) + [total_size]]
+    keep = [i for i in range(len(s2)) if s2[i] <= e2[i]]
+    return [s2[i] for i in keep], [e2[i] for i in keep]
+
+
+def not_index(pos, total_size):
+    """Gaps of an Index mask over rows [0, total_size), as RLE ranges."""
+    s2 = [p + 1 for p in [-1] + list(pos)]
+    e2 = [p - 1 for p in list(pos) + [total_size]]
+    keep = [i for i in range(len(s2)) if s2[i] <= e2[i] and s2[i] < total_size and e2[i] >= 0]
+    return [s2[i] for i in keep], [e2[i] for i in keep]

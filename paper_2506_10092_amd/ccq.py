@@ -13,7 +13,7 @@ tensors on the GPU::
 
 A query names columns and uses the same dict layout as the generator::
 
-    {"preds": [(col, "range", lo, hi) | (col, "in", [...])],
+    {"preds": [(col, "range" | "not_range", lo, hi) | (col, "in" | "not_in", [...])],
      "keys": [(col, shift, card)], "aggs": [("count",) | ("sum", col)],
      "window": (row_begin, row_end)}
 """
@@ -30,7 +30,7 @@ LIB_PATH = os.path.join(_HERE, "libccq.so")
 OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_KEY_DOMAIN, E_HIP, E_BUDGET, E_BUSY, E_NOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8
 RLE, INDEX, BITPACKED = 1, 2, 3
 I32, I64 = 1, 2
-RANGE, IN = 1, 2
+RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
 COUNT_STAR, SUM = 1, 2
 HOST_ONLY = -1
 
@@ -248,12 +248,14 @@ def query_desc(table, query):
     preds = (Pred * max(len(query["preds"]), 1))()
     for i, p in enumerate(query["preds"]):
         preds[i].col = col(p[0])
-        if p[1] == "range":
-            preds[i].op, preds[i].lo, preds[i].hi = RANGE, int(p[2]), int(p[3])
-        elif p[1] == "in":
+        if p[1] in ("range", "not_range"):
+            preds[i].op = RANGE if p[1] == "range" else NOT_RANGE
+            preds[i].lo, preds[i].hi = int(p[2]), int(p[3])
+        elif p[1] in ("in", "not_in"):
             lst = np.ascontiguousarray(np.array(list(p[2]), dtype=np.int64))
             keep.append(lst)
-            preds[i].op, preds[i].in_list, preds[i].in_len = IN, lst.ctypes.data, len(lst)
+            preds[i].op = IN if p[1] == "in" else NOT_IN
+            preds[i].in_list, preds[i].in_len = lst.ctypes.data, len(lst)
         else:
             raise CcqError(E_INVALID, "unknown predicate %r" % (p[1],))
     keys = (Key * max(len(query["keys"]), 1))()

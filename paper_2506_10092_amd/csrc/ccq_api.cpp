@@ -168,17 +168,65 @@ ccq_status ccq_table_validate(ccq_table* t, void* stream) {
 
 namespace {
 
+// Values as sorted, disjoint inclusive intervals: the conjunction of plain
+// and negated RANGE / IN predicates on one column is one such list.
+typedef std::vector<std::pair<int64_t, int64_t>> Intervals;
+
+Intervals iv_of_range(int64_t lo, int64_t hi) {   // lo <= v < hi
+    if (lo >= hi) return {};
+    return {{lo, hi - 1}};
+}
+
+Intervals iv_of_set(const std::set<int64_t>& s) {
+    Intervals r;
+    for (int64_t v : s) {
+        if (!r.empty() && r.back().second != INT64_MAX && r.back().second + 1 == v) r.back().second = v;
+        else r.push_back({v, v});
+    }
+    return r;
+}
+
+Intervals iv_complement(const Intervals& a) {
+    Intervals r;
+    int64_t next = INT64_MIN;    // lowest value not yet covered
+    bool open = true;            // values from `next` on are still to place
+    for (const auto& x : a) {
+        if (x.first > next) r.push_back({next, x.first - 1});
+        if (x.second == INT64_MAX) {
+            open = false;
+            break;
+        }
+        next = x.second + 1;
+    }
+    if (open) r.push_back({next, INT64_MAX});
+    return r;
+}
+
+Intervals iv_intersect(const Intervals& a, const Intervals& b) {
+    Intervals r;
+    size_t i = 0, j = 0;
+    while (i < a.size() && j < b.size()) {
+        const int64_t lo = std::max(a[i].first, b[j].first), hi = std::min(a[i].second, b[j].second);
+        if (lo <= hi) r.push_back({lo, hi});
+        if (a[i].second < b[j].second) ++i; else ++j;
+    }
+    return r;
+}
+
 struct Fold {               // conjunction of predicates on one column
-    bool has_range = false, has_set = false, is_false = false;
+    bool constrained = false;
+    Intervals iv;             // the passing values, when constrained
+    // the same, in the simplest form the kernels take
+    bool has_range = false, has_set = false, has_iv = false, is_false = false;
     int64_t lo = 0, hi = 0;   // [lo, hi) when has_range
     std::set<int64_t> set;
 };
 
 bool fold_pass(const Fold& f, int64_t v) {
-    if (f.is_false) return false;
-    if (f.has_range && !(f.lo <= v && v < f.hi)) return false;
-    if (f.has_set && !f.set.count(v)) return false;
-    return true;
+    if (!f.constrained) return true;
+    // first interval whose low end is > v
+    auto it = std::upper_bound(f.iv.begin(), f.iv.end(), std::make_pair(v, INT64_MAX));
+    return it != f.iv.begin() && v <= std::prev(it)->second;
 }
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -242,42 +290,39 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         if (t->cols[p.col].encoding == CCQ_INDEX)
             return fail(CCQ_E_UNSUPPORTED, "predicate %d: predicates on INDEX columns are not supported", i);
         Fold& f = fold[p.col];
-        if (p.op == CCQ_RANGE) {
-            if (!f.has_range) {
-                f.has_range = true;
-                f.lo = p.lo;
-                f.hi = p.hi;
-            } else {
-                f.lo = std::max(f.lo, p.lo);
-                f.hi = std::min(f.hi, p.hi);
-            }
-            if (f.lo >= f.hi) f.is_false = true;
-        } else if (p.op == CCQ_IN) {
+        Intervals a;
+        if (p.op == CCQ_RANGE || p.op == CCQ_NOT_RANGE) {
+            a = iv_of_range(p.lo, p.hi);
+        } else if (p.op == CCQ_IN || p.op == CCQ_NOT_IN) {
             if (p.in_len < 0 || (p.in_len > 0 && !p.in_list))
                 return fail(CCQ_E_INVALID, "predicate %d: bad IN list", i);
-            std::set<int64_t> s(p.in_list, p.in_list + p.in_len);
-            if (!f.has_set) {
-                f.has_set = true;
-                f.set = s;
-            } else {
-                std::set<int64_t> both;
-                for (int64_t v : f.set)
-                    if (s.count(v)) both.insert(v);
-                f.set = both;
-            }
+            a = iv_of_set(std::set<int64_t>(p.in_list, p.in_list + p.in_len));
         } else {
             return fail(CCQ_E_INVALID, "predicate %d: unknown op %d", i, p.op);
         }
+        if (p.op == CCQ_NOT_RANGE || p.op == CCQ_NOT_IN) a = iv_complement(a);   // NOT (Section 5.3)
+        f.iv = f.constrained ? iv_intersect(f.iv, a) : a;
+        f.constrained = true;
     }
+    // the simplest form of each column's passing values: nothing, one
+    // half-open range, a set of single values, or a list of intervals
     for (auto& f : fold) {
-        if (f.has_set && f.has_range) {
-            std::set<int64_t> kept;
-            for (int64_t v : f.set)
-                if (f.lo <= v && v < f.hi) kept.insert(v);
-            f.set = kept;
-            f.has_range = false;
+        if (!f.constrained) continue;
+        if (f.iv.empty()) f.is_false = true;
+        else if (f.iv.size() == 1 && f.iv[0].second != INT64_MAX) {
+            f.has_range = true;
+            f.lo = f.iv[0].first;
+            f.hi = f.iv[0].second + 1;
+        } else {
+            bool single = true;
+            for (const auto& x : f.iv) single = single && x.first == x.second;
+            if (single) {
+                f.has_set = true;
+                for (const auto& x : f.iv) f.set.insert(x.first);
+            } else {
+                f.has_iv = true;
+            }
         }
-        if (f.has_set && f.set.empty()) f.is_false = true;
     }
 
     // device blob contents, laid out after the DevPlan
@@ -310,6 +355,15 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             r.pred = kPredSet;
             std::vector<int64_t> v(f.set.begin(), f.set.end());
             r.set_len = (int32_t)v.size();
+            fix_ptr(&r.set, blob_put(v.data(), v.size() * 8));
+        } else if (f.has_iv) {
+            r.pred = kPredIntervals;
+            std::vector<int64_t> v;
+            for (const auto& x : f.iv) {
+                v.push_back(x.first);
+                v.push_back(x.second);
+            }
+            r.set_len = (int32_t)f.iv.size();
             fix_ptr(&r.set, blob_put(v.data(), v.size() * 8));
         } else if (f.has_range) {
             r.pred = kPredRange;
@@ -404,7 +458,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             b.key_card = P.keys[b.key].card;
             b.key_stride = P.keys[b.key].stride;
         }
-        const bool has_pred = f.is_false || f.has_range || f.has_set;
+        const bool has_pred = f.constrained;
         b.n_words = (t->n_rows * (int64_t)c.bit_width + 31) / 32 + 2;
         if (c.bit_width <= kLutMaxBits && (has_pred || b.key >= 0)) {
             const int64_t n = int64_t(1) << c.bit_width;
@@ -427,6 +481,15 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
                 b.pred = kPredSet;
                 std::vector<int64_t> v(f.set.begin(), f.set.end());
                 b.set_len = (int32_t)v.size();
+                fix_ptr(&b.set, blob_put(v.data(), v.size() * 8));
+            } else if (f.has_iv) {
+                b.pred = kPredIntervals;
+                std::vector<int64_t> v;
+                for (const auto& x : f.iv) {
+                    v.push_back(x.first);
+                    v.push_back(x.second);
+                }
+                b.set_len = (int32_t)f.iv.size();
                 fix_ptr(&b.set, blob_put(v.data(), v.size() * 8));
             } else if (f.has_range) {
                 b.pred = kPredRange;
@@ -522,7 +585,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         // keys), no SUM of the column itself
         bool big = false;
         if (fast && (G + 2) * 8 > kFastCntWords) {
-            big = (G + 2) * 4 <= kFastBigBytes && b.sum_slot < 0 && !f.has_set;
+            big = (G + 2) * 4 <= kFastBigBytes && b.sum_slot < 0 && !f.has_set && !f.has_iv;
             if (big && b.key >= 0 && P.keys[b.key].via_lut) {
                 const std::vector<int64_t>& sk = slot_keys[b.key];
                 big = sk.back() - sk.front() + 1 == (int64_t)sk.size();
@@ -530,7 +593,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             if (!big) fast = false;
         }
         if (fast && (lut16[0].empty() || big)) {
-            if (!big && b.pred == kPredSet) fast = false;
+            if (!big && (b.pred == kPredSet || b.pred == kPredIntervals)) fast = false;
             const bool is_false = big ? f.is_false : b.pred == kPredFalse;
             const bool has_range = big ? f.has_range : b.pred == kPredRange;
             const int64_t rlo = big ? f.lo : b.lo, rhi = big ? f.hi : b.hi;

@@ -131,11 +131,22 @@ __device__ __forceinline__ bool set_contains(const int64_t* s, int32_t n, int64_
     return lo < n && gld(s, lo) == v;
 }
 
+// v in one of n sorted, disjoint inclusive intervals (pairs lo, hi)
+__device__ __forceinline__ bool intervals_contain(const int64_t* iv, int32_t n, int64_t v) {
+    int32_t lo = 0, hi = n;   // first interval whose low end is > v
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (gld(iv, 2 * (int64_t)mid) <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo > 0 && v <= gld(iv, 2 * (int64_t)(lo - 1) + 1);
+}
+
 __device__ __forceinline__ bool pred_pass(int32_t kind, int64_t lo, int64_t hi, const int64_t* set, int32_t n,
                                           int64_t v) {
     if (kind == kPredNone) return true;
     if (kind == kPredRange) return lo <= v && v < hi;
     if (kind == kPredSet) return set_contains(set, n, v);
+    if (kind == kPredIntervals) return intervals_contain(set, n, v);
     return false;
 }
 

@@ -25,7 +25,7 @@ constexpr int kSegSlots = 64;         // group segments merged per tile in LDS
 constexpr int kFastBigBytes = 65536;   // fast row path: largest uint32 count table in dynamic LDS
 constexpr int kFastCntWords = 2048;    // fast row path: static LDS counts, (G + 2) * replicas
 
-enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3 };
+enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3, kPredIntervals = 4 };
 enum AggKind : int32_t { kAggCount = 0, kAggSumRle = 1, kAggSumBp = 2, kAggSumIdx = 3 };
 enum KeySrc : int32_t { kKeyRle = 0, kKeyBp = 1 };
 
@@ -40,8 +40,9 @@ struct RleCol {
     int32_t vtype;          // 1 int32, 2 int64
     int32_t pred;           // PredKind
     int64_t lo, hi;         // kPredRange
-    const int64_t* set;     // kPredSet: sorted, unique (device)
-    int32_t set_len;
+    const int64_t* set;     // kPredSet: sorted, unique values; kPredIntervals: sorted,
+                            // disjoint inclusive pairs (lo0, hi0, lo1, hi1, ...) (device)
+    int32_t set_len;        // values, or pairs
     int32_t sum_slot;       // SUM accumulator of this column, or -1
     int32_t key_on;         // 1 if this column is a group key
     int32_t key_shift;

@@ -44,10 +44,12 @@ def run(table, query):
         ok = True
         for p in query["preds"]:
             v = rows[p[0]][r]
-            if p[1] == "range":
+            if p[1] in ("range", "not_range"):
                 ok = p[2] <= v < p[3]
             else:
                 ok = v in set(p[2])
+            if p[1].startswith("not_"):
+                ok = not ok
             if not ok:
                 break
         if not ok:
@@ -83,10 +85,12 @@ def run_sqlite(table, query):
     r0, r1 = query.get("window", (0, n))
     where = ["rid >= %d" % r0, "rid < %d" % r1]
     for p in query["preds"]:
-        if p[1] == "range":
-            where.append('"%s" >= %d AND "%s" < %d' % (p[0], p[2], p[0], p[3]))
+        if p[1] in ("range", "not_range"):
+            cond = '"%s" >= %d AND "%s" < %d' % (p[0], p[2], p[0], p[3])
         else:
-            where.append('"%s" IN (%s)' % (p[0], ", ".join(str(int(x)) for x in p[2]) or "NULL"))
+            # an empty IN list is false (not NULL, which NOT would keep unknown)
+            cond = ('"%s" IN (%s)' % (p[0], ", ".join(str(int(x)) for x in p[2]))) if len(p[2]) else "0"
+        where.append("NOT (%s)" % cond if p[1].startswith("not_") else cond)
     keys = ['("%s" >> %d)' % (c, s) for (c, s, _) in query["keys"]]
     aggs = ["COUNT(*)"] + ["COUNT(*)" if a[0] == "count" else 'COALESCE(SUM("%s"), 0)' % a[1]
                            for a in query["aggs"]]

@@ -52,3 +52,25 @@ def tiny_query(rng, n, wd):
     b = int(rng.integers(a, n + 1))
     win = (a, b) if rng.random() < 0.3 else (0, n)
     return {"preds": preds, "keys": keys, "aggs": aggs, "window": win}
+
+
+def tiny_query_with_not(rng, n, wd):
+    """tiny_query with some predicates negated, plus plain and negated
+    predicates stacked on one column (their conjunction is then a list of
+    value intervals)."""
+    q = tiny_query(rng, n, wd)
+    preds = []
+    for p in q["preds"]:
+        if p[0] != "r2" and rng.random() < 0.5:
+            p = (p[0], "not_" + p[1]) + tuple(p[2:])
+        preds.append(p)
+    if rng.random() < 0.6:
+        lo = int(rng.integers(-3, 12))
+        preds.append(("r0", "not_range", lo, lo + int(rng.integers(0, 6))))
+    if rng.random() < 0.5:
+        preds.append(("d", "not_in", sorted(set(int(x) for x in rng.integers(0, 1 << wd, size=int(rng.integers(1, 8)))))))
+    if rng.random() < 0.4:
+        lo = int(rng.integers(-500, 500))
+        preds.append(("p", "not_range", lo, lo + int(rng.integers(1, 400))))
+    q["preds"] = preds
+    return q

@@ -311,3 +311,44 @@ def test_fast_path_20bit_code_range(ctx, density):
     check(ctx, t, q)
     q["window"] = (31, n - 1)
     check(ctx, t, q)
+
+
+# ---- NOT (Section 5.3): negated predicates, alone and stacked with plain
+# ones on one column, on every kernel path
+
+@pytest.mark.parametrize("seed", range(30))
+def test_tiny_random_tables_with_not(ctx, seed):
+    from tests.cases import tiny_query_with_not
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(1, 5000))
+    t, wd = tiny_table(rng, n)
+    for _ in range(3):
+        q = tiny_query_with_not(rng, n, wd)
+        say("tiny NOT seed", seed, "n", n, "query", q)
+        check(ctx, t, q)
+
+
+def test_not_on_fast_path_and_generic_paths(ctx):
+    """NOT IN on the dictionary column (folded into its code table on the
+    fast path), NOT ranges on RLE columns, and a 20-bit column whose plain
+    and negated ranges leave two intervals (the generic row path)."""
+    n = 2_000_003
+    t = datagen.config_c2(seed=91, n_rows=n, columns=("r0", "r1", "s", "d", "p"))
+    base = t["query"]
+    in_codes = base["preds"][2][2]
+    queries = [
+        {"preds": [("r0", "not_range", 0, 32768), ("r1", "range", 16384, 65536), ("d", "in", in_codes)],
+         "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)]},
+        {"preds": [("r0", "range", 0, 50000), ("r0", "not_range", 10000, 20000), ("d", "not_in", in_codes[:10]),
+                   ("d", "range", 0, 200)],
+         "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)]},
+        {"preds": [("p", "range", -200_000, 400_000), ("p", "not_range", -1000, 5000), ("r1", "not_in", [1, 2, 3])],
+         "keys": [], "aggs": [("sum", "p"), ("sum", "s"), ("count",)]},
+        {"preds": [("r0", "not_in", list(range(0, 65536, 2))), ("r1", "not_range", 0, 100)],
+         "keys": [("r0", 10, 64)], "aggs": [("sum", "r1"), ("count",)]},
+    ]
+    for q in queries:
+        for window in ((0, n), (4097, n - 31)):
+            qq = dict(q, window=window)
+            say("NOT query", qq["preds"], window)
+            check(ctx, t, qq)

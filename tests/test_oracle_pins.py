@@ -342,3 +342,57 @@ def test_empty_results():
     assert r == {"keys": [], "counts": [], "aggs": []}
     r = oracle.run(t, {"preds": [], "keys": [], "aggs": [("count",)], "window": (3, 3)})
     assert r["counts"] == [0]
+
+
+# ---- NOT (Section 5.3): the mask algorithms against the paper's worked
+# examples and against a row-by-row complement; negated predicates in the
+# oracle against brute force and SQL
+
+def test_not_mask_algorithms_paper_examples():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "not_masks.json")))
+    a = g["not_rle"]
+    assert oracle.not_rle(a["start"], a["end"], a["total_size"]) == (a["start_out"], a["end_out"])
+    b = g["not_index"]
+    assert oracle.not_index(b["pos"], b["total_size"]) == (b["start_out"], b["end_out"])
+
+
+def _rows_of_ranges(start, end, n):
+    m = [False] * n
+    for s, e in zip(start, end):
+        for r in range(s, e + 1):
+            m[r] = True
+    return m
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_not_masks_are_row_complements(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 60))
+    rows = sorted(set(int(x) for x in rng.integers(0, n, size=int(rng.integers(0, n + 1)))))
+    # an RLE mask: maximal ranges of the chosen rows
+    start, end = [], []
+    for r in rows:
+        if end and end[-1] == r - 1:
+            end[-1] = r
+        else:
+            start.append(r)
+            end.append(r)
+    want = [not x for x in _rows_of_ranges(start, end, n)]
+    s2, e2 = oracle.not_rle(start, end, n)
+    assert _rows_of_ranges(s2, e2, n) == want
+    assert all(a <= b for a, b in zip(s2, e2)) and all(e2[i] + 1 < s2[i + 1] for i in range(len(s2) - 1))
+    s3, e3 = oracle.not_index(rows, n)
+    assert _rows_of_ranges(s3, e3, n) == want
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_negated_predicates_match_brute_force_and_sqlite(seed):
+    from tests.cases import tiny_query_with_not
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.integers(1, 300))
+    t, wd = _tiny_table(rng, n)
+    for _ in range(4):
+        q = tiny_query_with_not(rng, n, wd)
+        got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
+        assert got == _norm(brute.run(t, q)), q
+        assert got == _norm(brute.run_sqlite(t, q)), q
