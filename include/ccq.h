@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 1
+#define CCQ_ABI_VERSION 2
 
 typedef int32_t ccq_status;
 enum {
@@ -97,8 +97,19 @@ typedef struct {
 /* ---- query (Sections 5-7) ----
  * CCQ_NOT_RANGE and CCQ_NOT_IN hold where CCQ_RANGE and CCQ_IN fail: the
  * complement of the predicate's mask (Section 5.3, NOT; Algorithms 7 and 8
- * complement RLE and Index masks).  Predicates on one column, plain or
- * negated, fold into one list of value intervals per column. */
+ * complement RLE and Index masks).
+ *
+ * The filter is a conjunction of clauses.  A predicate with clause == 0 is a
+ * clause of its own; predicates sharing a clause id k > 0 form one clause,
+ * their OR (Section 5.2, OR of masks: range_union for RLE masks, a merge of
+ * positions for Index masks).  With NOT this expresses any filter over the
+ * predicates (De Morgan; the composite-mask rules of Section 5).  Predicates
+ * on one column fold into one list of value intervals: AND intersects, OR
+ * unites, NOT complements.  An OR clause over several columns must name RLE
+ * columns only (at most 8 RLE column uses per query, counting each column
+ * once for the clause-0 predicates, keys and SUMs and once per clause that
+ * names it); an OR clause over one column takes any encoding that accepts
+ * predicates.  Otherwise CCQ_E_UNSUPPORTED. */
 enum { CCQ_RANGE = 1, CCQ_IN = 2, CCQ_NOT_RANGE = 3, CCQ_NOT_IN = 4 };
 typedef struct {
     int32_t col;               /* column index in the table */
@@ -107,6 +118,9 @@ typedef struct {
     int64_t lo, hi;
     const int64_t* in_list;    /* CCQ_IN, CCQ_NOT_IN: HOST array, copied by ccq_plan_create */
     int64_t in_len;
+    int32_t clause;            /* 0: ANDed on its own; k > 0: ORed with the other predicates of clause k,
+                                  the clause ANDed; must be >= 0 */
+    int32_t pad_;              /* ignored */
 } ccq_pred;
 
 typedef struct {
@@ -122,7 +136,7 @@ typedef struct {
 } ccq_agg;
 
 typedef struct {
-    const ccq_pred* preds;  int32_t n_preds;   /* conjunction */
+    const ccq_pred* preds;  int32_t n_preds;   /* conjunction of clauses (see ccq_pred.clause) */
     const ccq_key* keys;    int32_t n_keys;    /* GROUP BY, first key most significant */
     const ccq_agg* aggs;    int32_t n_aggs;
     int64_t row_begin, row_end;                /* logical window [row_begin, row_end) */

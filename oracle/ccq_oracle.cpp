@@ -12,9 +12,10 @@
  *      row (Section 3.1 "Basic Encodings": RLE runs (value, start, end), Index
  *      (value, position); Section 3.2 bit-width reduction with a global
  *      reference value, value = base + code);
- *   2. a row qualifies when every predicate holds on its values (selection,
- *      Section 6); a negated predicate holds where the plain one fails (NOT,
- *      Section 5.3);
+ *   2. a row qualifies when every clause holds on its values (selection,
+ *      Section 6): a clause is one predicate, or the OR of the predicates
+ *      that share a clause id (OR, Section 5.2); a negated predicate holds
+ *      where the plain one fails (NOT, Section 5.3);
  *   3. qualifying rows are grouped by their key tuple and COUNT(*) / SUM(col)
  *      are accumulated per group (Section 7, grouping and aggregating phases);
  *   4. groups are emitted in ascending key order (torch.unique returns sorted
@@ -72,6 +73,8 @@ typedef struct {
     const int64_t* in_list;     /* IN */
                                 /* NOT_RANGE, NOT_IN: the negations (Section 5.3) */
     int64_t in_len;
+    int32_t clause;             /* 0: a clause of its own; k > 0: ORed with the others of clause k */
+    int32_t pad_;
 } orc_pred;
 
 typedef struct {
@@ -185,6 +188,7 @@ struct Query {
     int64_t n_rows = 0;
     std::vector<orc_pred> preds;
     std::vector<std::set<int64_t>> in_sets;
+    std::vector<std::vector<size_t>> clauses;   /* predicate indices per clause; a row needs one of each */
     std::vector<orc_key> keys;
     std::vector<orc_agg> aggs;
     int64_t row_begin = 0, row_end = 0;
@@ -213,13 +217,19 @@ void run_chunks(const Query& q, std::atomic<int64_t>& next_chunk, int64_t n_chun
             decode(q.cols[q.used[u]], c0, c1, x[u].data());
         }
         for (int64_t r = 0; r < c1 - c0; r++) {
-            bool pass = true;
-            for (size_t p = 0; p < q.preds.size() && pass; p++) {
-                int64_t v = x[q.slot[q.preds[p].col]][r];
+            auto holds = [&](size_t p) {
+                const int64_t v = x[q.slot[q.preds[p].col]][r];
                 const int32_t op = q.preds[p].op;
-                if (op == ORC_RANGE || op == ORC_NOT_RANGE) pass = q.preds[p].lo <= v && v < q.preds[p].hi;
-                else pass = q.in_sets[p].count(v) != 0;
-                if (op == ORC_NOT_RANGE || op == ORC_NOT_IN) pass = !pass;
+                bool h;
+                if (op == ORC_RANGE || op == ORC_NOT_RANGE) h = q.preds[p].lo <= v && v < q.preds[p].hi;
+                else h = q.in_sets[p].count(v) != 0;
+                return (op == ORC_NOT_RANGE || op == ORC_NOT_IN) ? !h : h;
+            };
+            bool pass = true;
+            for (size_t c = 0; c < q.clauses.size() && pass; c++) {
+                bool any = false;
+                for (size_t p : q.clauses[c]) any = any || holds(p);
+                pass = any;
             }
             if (!pass) continue;
             for (size_t k = 0; k < q.keys.size(); k++) {
@@ -271,8 +281,16 @@ Result* execute(Query& q, int n_threads) {
         return true;
     };
     q.in_sets.assign(q.preds.size(), {});
+    std::map<int32_t, size_t> clause_at;
     for (size_t p = 0; p < q.preds.size(); p++) {
         if (!use(q.preds[p].col)) { res->error = "predicate column out of range"; return res; }
+        const int32_t k = q.preds[p].clause;
+        if (k < 0) { res->error = "negative clause id"; return res; }
+        if (k == 0 || !clause_at.count(k)) {
+            if (k != 0) clause_at[k] = q.clauses.size();
+            q.clauses.push_back({});
+        }
+        q.clauses[k == 0 ? q.clauses.size() - 1 : clause_at[k]].push_back(p);
         if (q.preds[p].op == ORC_IN || q.preds[p].op == ORC_NOT_IN) {
             for (int64_t i = 0; i < q.preds[p].in_len; i++) q.in_sets[p].insert(q.preds[p].in_list[i]);
         } else if (q.preds[p].op != ORC_RANGE && q.preds[p].op != ORC_NOT_RANGE) {

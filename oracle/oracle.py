@@ -37,7 +37,8 @@ class OrcColumn(ctypes.Structure):
 
 class OrcPred(ctypes.Structure):
     _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
-                ("in_list", ctypes.c_void_p), ("in_len", ctypes.c_int64)]
+                ("in_list", ctypes.c_void_p), ("in_len", ctypes.c_int64), ("clause", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class OrcKey(ctypes.Structure):
@@ -153,10 +154,18 @@ def run(table, query, n_threads=None):
             raise OracleError("unknown column %r" % (name,))
         return idx[name]
 
-    preds = (OrcPred * max(len(query["preds"]), 1))()
-    for i, p in enumerate(query["preds"]):
+    # the filter: every entry of "preds" AND every clause of "or", a clause
+    # being the OR of its predicates (Section 5.2)
+    flat = [(p, 0) for p in query["preds"]]
+    for k, clause in enumerate(query.get("or", ())):
+        if not clause:
+            raise OracleError("empty OR clause")
+        flat += [(p, k + 1) for p in clause]
+    preds = (OrcPred * max(len(flat), 1))()
+    for i, (p, clause) in enumerate(flat):
         op = p[1]
         preds[i].col = col_id(p[0])
+        preds[i].clause = clause
         if op in ("range", "not_range"):
             preds[i].op = RANGE if op == "range" else NOT_RANGE
             preds[i].lo, preds[i].hi = int(p[2]), int(p[3])
@@ -182,7 +191,7 @@ def run(table, query, n_threads=None):
     if n_threads is None:
         n_threads = os.cpu_count() or 1
     L = lib()
-    h = L.orc_query(cols, len(names), n_rows, preds, len(query["preds"]), keys, len(query["keys"]), aggs,
+    h = L.orc_query(cols, len(names), n_rows, preds, len(flat), keys, len(query["keys"]), aggs,
                     len(query["aggs"]), int(rb), int(re_), int(n_threads))
     try:
         err = L.orc_error(h)
@@ -227,3 +236,49 @@ def not_index(pos, total_size):
     e2 = [p - 1 for p in list(pos) + [total_size]]
     keep = [i for i in range(len(s2)) if s2[i] <= e2[i] and s2[i] < total_size and e2[i] >= 0]
     return [s2[i] for i in keep], [e2[i] for i in keep]
+
+
+# ---- OR on position-explicit masks (Section 5.2; Tables 4 and 5)
+#
+# The OR of two Plain masks is the element-wise OR; that of two RLE masks is
+# the union of their row ranges, as maximal ranges of consecutive passing
+# rows; that of two Index masks is the sorted union of their rows.  The query
+# path evaluates OR per row; these pin what that means on the paper's masks.
+
+def or_plain(m1, m2):
+    """Element-wise OR of two boolean masks of one length."""
+    if len(m1) != len(m2):
+        raise OracleError("masks of different lengths")
+    return [bool(a) or bool(b) for a, b in zip(m1, m2)]
+
+
+def range_union(start1, end1, start2, end2):
+    """Union of two RLE masks (sorted, disjoint inclusive ranges each): the
+    ranges of both, taken by start, with each range that overlaps or touches
+    the one before folded into it."""
+    ranges = sorted(zip(list(start1) + list(start2), list(end1) + list(end2)))
+    s_out, e_out = [], []
+    for s, e in ranges:
+        if e_out and s <= e_out[-1] + 1:
+            e_out[-1] = max(e_out[-1], e)
+        else:
+            s_out.append(s)
+            e_out.append(e)
+    return s_out, e_out
+
+
+def merge_sorted_idx(pos1, pos2):
+    """Union of two Index masks (sorted, unique rows each), sorted, each row
+    once: a two-way merge."""
+    out = []
+    i = j = 0
+    while i < len(pos1) or j < len(pos2):
+        if j == len(pos2) or (i < len(pos1) and pos1[i] <= pos2[j]):
+            x = pos1[i]
+            i += 1
+        else:
+            x = pos2[j]
+            j += 1
+        if not out or out[-1] != x:
+            out.append(x)
+    return out

@@ -14,8 +14,12 @@ tensors on the GPU::
 A query names columns and uses the same dict layout as the generator::
 
     {"preds": [(col, "range" | "not_range", lo, hi) | (col, "in" | "not_in", [...])],
+     "or": [[pred, pred, ...], ...],
      "keys": [(col, shift, card)], "aggs": [("count",) | ("sum", col)],
      "window": (row_begin, row_end)}
+
+The filter is every entry of "preds" ANDed with every clause of "or" (optional),
+a clause being the OR of its predicates.
 """
 from __future__ import annotations
 
@@ -53,7 +57,8 @@ class ColumnDesc(ctypes.Structure):
 
 class Pred(ctypes.Structure):
     _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("lo", ctypes.c_int64), ("hi", ctypes.c_int64),
-                ("in_list", ctypes.c_void_p), ("in_len", ctypes.c_int64)]
+                ("in_list", ctypes.c_void_p), ("in_len", ctypes.c_int64), ("clause", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class Key(ctypes.Structure):
@@ -245,9 +250,15 @@ def query_desc(table, query):
         return idx[name]
 
     keep = []
-    preds = (Pred * max(len(query["preds"]), 1))()
-    for i, p in enumerate(query["preds"]):
+    flat = [(p, 0) for p in query["preds"]]
+    for k, clause in enumerate(query.get("or", ())):
+        if not clause:
+            raise CcqError(E_INVALID, "OR clause %d is empty" % k)
+        flat += [(p, k + 1) for p in clause]
+    preds = (Pred * max(len(flat), 1))()
+    for i, (p, clause) in enumerate(flat):
         preds[i].col = col(p[0])
+        preds[i].clause = clause
         if p[1] in ("range", "not_range"):
             preds[i].op = RANGE if p[1] == "range" else NOT_RANGE
             preds[i].lo, preds[i].hi = int(p[2]), int(p[3])
@@ -270,7 +281,7 @@ def query_desc(table, query):
         else:
             raise CcqError(E_INVALID, "unknown aggregate %r" % (a[0],))
     rb, re_ = query.get("window", (0, table.n_rows))
-    d = QueryDesc(preds, len(query["preds"]), keys, len(query["keys"]), aggs, len(query["aggs"]), int(rb), int(re_))
+    d = QueryDesc(preds, len(flat), keys, len(query["keys"]), aggs, len(query["aggs"]), int(rb), int(re_))
     keep += [preds, keys, aggs]
     return d, keep
 

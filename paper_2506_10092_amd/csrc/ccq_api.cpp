@@ -213,6 +213,28 @@ Intervals iv_intersect(const Intervals& a, const Intervals& b) {
     return r;
 }
 
+Intervals iv_union(const Intervals& a, const Intervals& b) {
+    return iv_complement(iv_intersect(iv_complement(a), iv_complement(b)));
+}
+
+bool iv_all(const Intervals& a) {
+    return a.size() == 1 && a[0].first == INT64_MIN && a[0].second == INT64_MAX;
+}
+
+// the values a predicate passes
+ccq_status pred_intervals(const ccq_pred& p, int i, Intervals& a) {
+    if (p.op == CCQ_RANGE || p.op == CCQ_NOT_RANGE) {
+        a = iv_of_range(p.lo, p.hi);
+    } else if (p.op == CCQ_IN || p.op == CCQ_NOT_IN) {
+        if (p.in_len < 0 || (p.in_len > 0 && !p.in_list)) return fail(CCQ_E_INVALID, "predicate %d: bad IN list", i);
+        a = iv_of_set(std::set<int64_t>(p.in_list, p.in_list + p.in_len));
+    } else {
+        return fail(CCQ_E_INVALID, "predicate %d: unknown op %d", i, p.op);
+    }
+    if (p.op == CCQ_NOT_RANGE || p.op == CCQ_NOT_IN) a = iv_complement(a);   // NOT (Section 5.3)
+    return CCQ_OK;
+}
+
 struct Fold {               // conjunction of predicates on one column
     bool constrained = false;
     Intervals iv;             // the passing values, when constrained
@@ -221,6 +243,29 @@ struct Fold {               // conjunction of predicates on one column
     int64_t lo = 0, hi = 0;   // [lo, hi) when has_range
     std::set<int64_t> set;
 };
+
+// the simplest form of a column's passing values: nothing, one half-open
+// range, a set of single values, or a list of intervals
+void fold_classify(Fold& f) {
+    if (f.constrained && iv_all(f.iv)) f.constrained = false;
+    if (!f.constrained) return;
+    if (f.iv.empty()) {
+        f.is_false = true;
+    } else if (f.iv.size() == 1 && f.iv[0].second != INT64_MAX) {
+        f.has_range = true;
+        f.lo = f.iv[0].first;
+        f.hi = f.iv[0].second + 1;
+    } else {
+        bool single = true;
+        for (const auto& x : f.iv) single = single && x.first == x.second;
+        if (single) {
+            f.has_set = true;
+            for (const auto& x : f.iv) f.set.insert(x.first);
+        } else {
+            f.has_iv = true;
+        }
+    }
+}
 
 bool fold_pass(const Fold& f, int64_t v) {
     if (!f.constrained) return true;
@@ -266,8 +311,17 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         v.push_back(c);
         return CCQ_OK;
     };
+    for (int i = 0; i < q->n_preds; ++i) {
+        const ccq_pred& p = q->preds[i];
+        if (p.col < 0 || p.col >= ncol) return fail(CCQ_E_INVALID, "predicate %d: column %d out of range", i, p.col);
+        if (p.clause < 0) return fail(CCQ_E_INVALID, "predicate %d: clause must be >= 0", i);
+        if (t->cols[p.col].encoding == CCQ_INDEX)
+            return fail(CCQ_E_UNSUPPORTED, "predicate %d: predicates on INDEX columns are not supported", i);
+    }
+    // clause-0 predicates, keys and SUMs use the columns' own slots
     for (int i = 0; i < q->n_preds; ++i)
-        if (ccq_status s = use(q->preds[i].col)) return s;
+        if (q->preds[i].clause == 0)
+            if (ccq_status s = use(q->preds[i].col)) return s;
     for (int i = 0; i < q->n_keys; ++i)
         if (ccq_status s = use(q->keys[i].col)) return s;
     for (int i = 0; i < q->n_aggs; ++i) {
@@ -277,53 +331,98 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             return fail(CCQ_E_INVALID, "aggregate %d: unknown function %d", i, q->aggs[i].func);
         }
     }
-    if ((int)rle_cols.size() > kMaxRle) return fail(CCQ_E_UNSUPPORTED, "at most %d RLE columns per query", kMaxRle);
-    if ((int)bp_cols.size() > kMaxBp)
-        return fail(CCQ_E_UNSUPPORTED, "at most %d bit-packed columns per query", kMaxBp);
-    if ((int)idx_cols.size() > kMaxIdx) return fail(CCQ_E_UNSUPPORTED, "at most %d Index columns per query", kMaxIdx);
 
-    // fold the conjunction per column (composite predicates on one column
-    // become one range or one set)
+    // fold the clause-0 predicates per column (AND: composite predicates on
+    // one column become one list of intervals)
     std::vector<Fold> fold(ncol);
     for (int i = 0; i < q->n_preds; ++i) {
         const ccq_pred& p = q->preds[i];
-        if (t->cols[p.col].encoding == CCQ_INDEX)
-            return fail(CCQ_E_UNSUPPORTED, "predicate %d: predicates on INDEX columns are not supported", i);
-        Fold& f = fold[p.col];
+        if (p.clause != 0) continue;
         Intervals a;
-        if (p.op == CCQ_RANGE || p.op == CCQ_NOT_RANGE) {
-            a = iv_of_range(p.lo, p.hi);
-        } else if (p.op == CCQ_IN || p.op == CCQ_NOT_IN) {
-            if (p.in_len < 0 || (p.in_len > 0 && !p.in_list))
-                return fail(CCQ_E_INVALID, "predicate %d: bad IN list", i);
-            a = iv_of_set(std::set<int64_t>(p.in_list, p.in_list + p.in_len));
-        } else {
-            return fail(CCQ_E_INVALID, "predicate %d: unknown op %d", i, p.op);
-        }
-        if (p.op == CCQ_NOT_RANGE || p.op == CCQ_NOT_IN) a = iv_complement(a);   // NOT (Section 5.3)
+        if (ccq_status s = pred_intervals(p, i, a)) return s;
+        Fold& f = fold[p.col];
         f.iv = f.constrained ? iv_intersect(f.iv, a) : a;
         f.constrained = true;
     }
-    // the simplest form of each column's passing values: nothing, one
-    // half-open range, a set of single values, or a list of intervals
-    for (auto& f : fold) {
-        if (!f.constrained) continue;
-        if (f.iv.empty()) f.is_false = true;
-        else if (f.iv.size() == 1 && f.iv[0].second != INT64_MAX) {
-            f.has_range = true;
-            f.lo = f.iv[0].first;
-            f.hi = f.iv[0].second + 1;
+    // OR clauses (Section 5.2): per clause and column, the union of the
+    // predicates' intervals.  A clause over one column is one more AND on
+    // that column; a clause over several RLE columns gets a slot per column,
+    // consecutive, whose pass masks the kernels OR
+    struct Clause {
+        int32_t id;
+        std::vector<int> cols;
+        std::vector<Intervals> iv;
+    };
+    std::vector<Clause> clauses;
+    for (int i = 0; i < q->n_preds; ++i) {
+        const ccq_pred& p = q->preds[i];
+        if (p.clause == 0) continue;
+        Intervals a;
+        if (ccq_status s = pred_intervals(p, i, a)) return s;
+        size_t k = 0;
+        while (k < clauses.size() && clauses[k].id != p.clause) ++k;
+        if (k == clauses.size()) clauses.push_back({p.clause, {}, {}});
+        Clause& cl = clauses[k];
+        size_t j = 0;
+        while (j < cl.cols.size() && cl.cols[j] != p.col) ++j;
+        if (j == cl.cols.size()) {
+            cl.cols.push_back(p.col);
+            cl.iv.push_back(a);
         } else {
-            bool single = true;
-            for (const auto& x : f.iv) single = single && x.first == x.second;
-            if (single) {
-                f.has_set = true;
-                for (const auto& x : f.iv) f.set.insert(x.first);
-            } else {
-                f.has_iv = true;
-            }
+            cl.iv[j] = iv_union(cl.iv[j], a);
         }
     }
+    struct OrSlot {
+        int col;
+        Fold f;
+        bool or_next;
+    };
+    std::vector<OrSlot> or_slots;
+    int false_col = -1;    // a clause no row can pass: the query is false
+    for (const Clause& cl : clauses) {
+        std::vector<size_t> live;
+        bool always = false;
+        for (size_t j = 0; j < cl.cols.size(); ++j) {
+            if (iv_all(cl.iv[j])) always = true;
+            else if (!cl.iv[j].empty()) live.push_back(j);
+        }
+        if (always) continue;
+        if (live.empty()) {
+            if (false_col < 0) false_col = cl.cols[0];
+            continue;
+        }
+        if (live.size() == 1) {
+            const int c = cl.cols[live[0]];
+            Fold& f = fold[c];
+            f.iv = f.constrained ? iv_intersect(f.iv, cl.iv[live[0]]) : cl.iv[live[0]];
+            f.constrained = true;
+            if (ccq_status s = use(c)) return s;
+            continue;
+        }
+        for (size_t j : live)
+            if (t->cols[cl.cols[j]].encoding != CCQ_RLE)
+                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes RLE columns only", cl.id);
+        for (size_t n = 0; n < live.size(); ++n) {
+            OrSlot o;
+            o.col = cl.cols[live[n]];
+            o.f.constrained = true;
+            o.f.iv = cl.iv[live[n]];
+            fold_classify(o.f);
+            o.or_next = n + 1 < live.size();
+            or_slots.push_back(o);
+        }
+    }
+    if (false_col >= 0) {
+        if (ccq_status s = use(false_col)) return s;
+        fold[false_col].constrained = true;
+        fold[false_col].iv.clear();
+    }
+    if ((int)(rle_cols.size() + or_slots.size()) > kMaxRle)
+        return fail(CCQ_E_UNSUPPORTED, "at most %d RLE column uses per query (one per column, plus one per OR clause naming it)", kMaxRle);
+    if ((int)bp_cols.size() > kMaxBp)
+        return fail(CCQ_E_UNSUPPORTED, "at most %d bit-packed columns per query", kMaxBp);
+    if ((int)idx_cols.size() > kMaxIdx) return fail(CCQ_E_UNSUPPORTED, "at most %d Index columns per query", kMaxIdx);
+    for (auto& f : fold) fold_classify(f);
 
     // device blob contents, laid out after the DevPlan
     std::vector<unsigned char>& blob = out.blob;
@@ -338,13 +437,16 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         out.fixes.push_back({(size_t)((const unsigned char*)field - (const unsigned char*)&P), data_off});
     };
 
-    P.k_rle = (int)rle_cols.size();
+    P.k_rle = (int)(rle_cols.size() + or_slots.size());
     P.n_bp = (int)bp_cols.size();
     P.n_idx = (int)idx_cols.size();
     for (int s = 0; s < P.k_rle; ++s) {
-        const ccq_column_desc& c = t->cols[rle_cols[s]];
-        const Fold& f = fold[rle_cols[s]];
+        const bool own = s < (int)rle_cols.size();
+        const OrSlot* o = own ? nullptr : &or_slots[s - rle_cols.size()];
+        const ccq_column_desc& c = t->cols[own ? rle_cols[s] : o->col];
+        const Fold& f = own ? fold[rle_cols[s]] : o->f;
         RleCol& r = P.rle[s];
+        r.or_next = (o && o->or_next) ? 1 : 0;
         r.sum_slot = -1;
         r.ends = c.run_ends;
         r.vals = c.values;

@@ -313,6 +313,7 @@ __device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& 
         }
     }
     uint32_t pm = 0xFFFFFFFFu;
+    uint32_t any = 0;             // the open OR clause's rows
     bool shrunk = false;
     int64_t last_e[KMAX];
 #pragma unroll
@@ -399,7 +400,11 @@ __device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& 
             x ^= x << 16;
             const uint64_t par = wave_ballot((__builtin_popcount(t) & 1) != 0);
             const uint32_t flip = ((uint32_t)lanes_below(par) ^ first) & 1u;
-            pm &= flip ? ~x : x;
+            any |= flip ? ~x : x;
+            if (!rc.or_next) {
+                pm &= any;
+                any = 0;
+            }
         }
     }
     wave_lds_sync();
@@ -898,6 +903,7 @@ __device__ __forceinline__ void fast_rle_mask(const DevPlan& P, const WaveLds& W
     wave_lds_sync();
     pm_a = 0xFFFFFFFFu;
     pm_b = 0xFFFFFFFFu;
+    uint32_t any_a = 0, any_b = 0;   // the open OR clause's rows
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) {
         if (c >= P.k_rle) continue;
@@ -922,8 +928,14 @@ __device__ __forceinline__ void fast_rle_mask(const DevPlan& P, const WaveLds& W
         const uint64_t parb = wave_ballot((__builtin_popcount(Tb) & 1) != 0);
         const uint32_t fa = ((uint32_t)lanes_below(para) ^ (first >> c)) & 1u;
         const uint32_t fb = ((uint32_t)lanes_below(parb) ^ (uint32_t)__builtin_popcountll(para) ^ (first >> c)) & 1u;
-        pm_a &= fa ? ~xa : xa;
-        pm_b &= fb ? ~xb : xb;
+        any_a |= fa ? ~xa : xa;
+        any_b |= fb ? ~xb : xb;
+        if (!P.rle[c].or_next) {
+            pm_a &= any_a;
+            pm_b &= any_b;
+            any_a = 0;
+            any_b = 0;
+        }
     }
 }
 

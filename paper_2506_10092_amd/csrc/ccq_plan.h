@@ -50,6 +50,9 @@ struct RleCol {
     int64_t key_stride;
     int32_t stage_base;     // staged paths: first run slot of this column in a wave slice
     int32_t stage_cap;      // and its capacity (>= 64)
+    int32_t or_next;        // 1: this column's pass mask is ORed with the next column's (one OR
+                            // clause spans consecutive columns); 0: the clause ends here and is ANDed
+    int32_t pad_;
 };
 
 struct BpCol {

@@ -40,18 +40,18 @@ def run(table, query):
     rows = {name: decode_rows(c, n) for name, c in table["columns"].items()}
     r0, r1 = query.get("window", (0, n))
     groups = {}
+
+    def holds(p, r):
+        v = rows[p[0]][r]
+        if p[1] in ("range", "not_range"):
+            ok = p[2] <= v < p[3]
+        else:
+            ok = v in set(p[2])
+        return not ok if p[1].startswith("not_") else ok
+
     for r in range(r0, r1):
-        ok = True
-        for p in query["preds"]:
-            v = rows[p[0]][r]
-            if p[1] in ("range", "not_range"):
-                ok = p[2] <= v < p[3]
-            else:
-                ok = v in set(p[2])
-            if p[1].startswith("not_"):
-                ok = not ok
-            if not ok:
-                break
+        ok = all(holds(p, r) for p in query["preds"])
+        ok = ok and all(any(holds(p, r) for p in clause) for clause in query.get("or", ()))
         if not ok:
             continue
         key = []
@@ -84,13 +84,17 @@ def run_sqlite(table, query):
                    [(r,) + tuple(rows[c][r] for c in names) for r in range(n)])
     r0, r1 = query.get("window", (0, n))
     where = ["rid >= %d" % r0, "rid < %d" % r1]
-    for p in query["preds"]:
+
+    def sql_pred(p):
         if p[1] in ("range", "not_range"):
             cond = '"%s" >= %d AND "%s" < %d' % (p[0], p[2], p[0], p[3])
         else:
             # an empty IN list is false (not NULL, which NOT would keep unknown)
             cond = ('"%s" IN (%s)' % (p[0], ", ".join(str(int(x)) for x in p[2]))) if len(p[2]) else "0"
-        where.append("NOT (%s)" % cond if p[1].startswith("not_") else cond)
+        return "NOT (%s)" % cond if p[1].startswith("not_") else "(%s)" % cond
+
+    where += [sql_pred(p) for p in query["preds"]]
+    where += ["(%s)" % " OR ".join(sql_pred(p) for p in clause) for clause in query.get("or", ())]
     keys = ['("%s" >> %d)' % (c, s) for (c, s, _) in query["keys"]]
     aggs = ["COUNT(*)"] + ["COUNT(*)" if a[0] == "count" else 'COALESCE(SUM("%s"), 0)' % a[1]
                            for a in query["aggs"]]

@@ -74,3 +74,30 @@ def tiny_query_with_not(rng, n, wd):
         preds.append(("p", "not_range", lo, lo + int(rng.integers(1, 400))))
     q["preds"] = preds
     return q
+
+
+def _rle_literal(rng, col):
+    op = ["range", "in", "not_range", "not_in"][int(rng.integers(0, 4))]
+    if op.endswith("range"):
+        lo = int(rng.integers(-6, 20))
+        return (col, op, lo, lo + int(rng.integers(0, 12)))
+    return (col, op, sorted(set(int(x) for x in rng.integers(-5, 20, size=int(rng.integers(0, 5))))))
+
+
+def tiny_query_with_or(rng, n, wd):
+    """tiny_query_with_not plus OR clauses: one or two over the RLE columns
+    (two or three predicates, a column possibly named twice), and at times
+    one over the dictionary column alone or the wide column alone."""
+    q = tiny_query_with_not(rng, n, wd)
+    clauses = []
+    for _ in range(int(rng.integers(1, 3))):
+        cols = ["r%d" % int(rng.integers(0, 3)) for _ in range(int(rng.integers(2, 4)))]
+        clauses.append([_rle_literal(rng, c) for c in cols])
+    if rng.random() < 0.4:
+        clauses.append([("d", "in", sorted(set(int(x) for x in rng.integers(0, 1 << wd, size=3)))),
+                        ("d", "range", int(rng.integers(0, 1 << wd)), int(rng.integers(0, 1 << wd)) + 1)])
+    if rng.random() < 0.3:
+        lo = int(rng.integers(-1000, 0))
+        clauses.append([("p", "range", lo, lo + 300), ("p", "not_range", -2000, 2000)])
+    q["or"] = clauses
+    return q

@@ -35,7 +35,7 @@ def test_header_functions_are_exported():
 
 
 def test_abi_version():
-    assert ccq.lib().ccq_abi_version() == 1
+    assert ccq.lib().ccq_abi_version() == 2
 
 
 def _host_table(columns, n_rows):
@@ -83,6 +83,12 @@ def test_host_only_context_checks_plans():
     ({"window": (0, 1001)}, ccq.E_INVALID),
     ({"window": (10, 5)}, ccq.E_INVALID),
     ({"keys": [("a", 0, 4), ("a", 1, 4)]}, ccq.E_UNSUPPORTED),
+    # OR across an RLE and a bit-packed column; OR on an Index column
+    ({"or": [[("a", "range", 0, 2), ("d", "in", [1])]]}, ccq.E_UNSUPPORTED),
+    ({"or": [[("s", "range", 0, 2), ("a", "in", [1])]]}, ccq.E_UNSUPPORTED),
+    # five two-column OR clauses need ten RLE column uses (at most eight)
+    ({"or": [[("a", "range", 0, 2 + i), ("m", "range", 0, 5)] for i in range(5)]}, ccq.E_UNSUPPORTED),
+    ({"or": [[]]}, ccq.E_INVALID),
 ])
 def test_plan_check_rejects(bad, code):
     tb = _host_table(_cols(), 1000)
@@ -93,6 +99,23 @@ def test_plan_check_rejects(bad, code):
     if code != "unknown":
         assert e.value.status == code, str(e.value)
     assert str(e.value)
+
+
+def test_or_clauses_fold_or_take_rle_slots():
+    """An OR clause over one column folds into that column (any encoding);
+    clauses that always hold drop; clauses over RLE columns are accepted up
+    to eight RLE column uses."""
+    tb = _host_table(_cols(), 1000)
+    base = {"preds": [], "keys": [("d", 0, 1 << 14)], "aggs": [("count",)], "window": (0, 1000)}
+    ok = [
+        [[("d", "in", [1, 2]), ("d", "range", 100, 200)]],
+        [[("p", "range", 0, 5), ("p", "not_range", -9, 9)]],
+        [[("a", "range", 0, 2), ("m", "in", [5])]] * 3 + [[("m", "range", 0, 9), ("m", "in", [7])]],
+        [[("a", "not_in", []), ("d", "in", [3])]],        # holds for every row: dropped
+        [[("a", "in", []), ("d", "in", [3])]],            # one live predicate: folds into d
+    ]
+    for clauses in ok:
+        ccq.plan_check(tb, dict(base, preds=[("a", "range", 1, 3)], **{"or": clauses}))
 
 
 @pytest.mark.parametrize("mutate,msg", [

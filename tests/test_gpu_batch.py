@@ -27,6 +27,10 @@ def setup():
     # edge cases: empty window, one row, whole table, a window ending mid-word
     qs += [dict(qs[0], window=(5, 5)), dict(qs[1], window=(77, 78)), dict(qs[2], window=(0, n)),
            dict(qs[3], window=(31, n - 3))]
+    # OR clauses over RLE columns (one column in two clauses)
+    qs += [dict(qs[4], **{"or": [[("r0", "range", 0, 20000), ("r1", "range", 50000, 65536)]]}),
+           dict(qs[5], **{"or": [[("r2", "not_range", 0, 100), ("r0", "in", [1, 2, 3])],
+                                 [("r0", "range", 0, 30000), ("r1", "range", 0, 10000)]]})]
     ctx = ccq.Context(0)
     table = ccq.Table(ctx, n, ccq.to_device(t["columns"]))
     plans = [ccq.Plan(table, q) for q in qs]

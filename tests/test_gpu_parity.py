@@ -328,6 +328,50 @@ def test_tiny_random_tables_with_not(ctx, seed):
         check(ctx, t, q)
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_tiny_random_tables_with_or(ctx, seed):
+    from tests.cases import tiny_query_with_or
+    rng = np.random.default_rng(7500 + seed)
+    n = int(rng.integers(1, 5000))
+    t, wd = tiny_table(rng, n)
+    for _ in range(3):
+        q = tiny_query_with_or(rng, n, wd)
+        say("tiny OR seed", seed, "n", n, "query", q)
+        check(ctx, t, q)
+
+
+def test_or_on_fast_path_run_mode_and_generic_paths(ctx):
+    """OR clauses over the RLE columns (Section 5.2, range_union): on the
+    fast path (dictionary column), in run mode (no bit-packed column) and on
+    the generic row path (20-bit column); a column named in the clause-0
+    predicates and in two OR clauses (three slots); clauses with a false
+    predicate, an always-true predicate, and a clause no row passes."""
+    n = 2_000_003
+    t = datagen.config_c2(seed=93, n_rows=n, columns=("r0", "r1", "s", "d", "p"))
+    in_codes = t["query"]["preds"][2][2]
+    fast = {"keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)]}
+    queries = [
+        dict(fast, preds=[("d", "in", in_codes)], **{"or": [[("r0", "range", 0, 20000), ("r1", "range", 50000, 65536)]]}),
+        dict(fast, preds=[("r0", "range", 0, 40000), ("d", "in", in_codes)],
+             **{"or": [[("r0", "not_range", 5000, 30000), ("r1", "in", list(range(0, 65536, 3)))]]}),
+        dict(fast, preds=[("d", "not_in", in_codes[:5])],
+             **{"or": [[("r0", "range", 0, 10000), ("r1", "range", 60000, 65536)],
+                       [("r0", "range", 30000, 65536), ("r1", "not_range", 20000, 65536)]]}),
+        {"preds": [], "keys": [("r0", 10, 64)], "aggs": [("sum", "r1"), ("count",)],
+         "or": [[("r0", "range", 0, 8000), ("r1", "range", 30000, 40000), ("r0", "in", [60000, 60001])]]},
+        {"preds": [("p", "range", -200_000, 400_000)], "keys": [], "aggs": [("sum", "p"), ("sum", "s"), ("count",)],
+         "or": [[("r1", "range", 0, 16384), ("r0", "not_range", 0, 60000)]]},
+        dict(fast, preds=[("d", "in", in_codes)],
+             **{"or": [[("r0", "in", []), ("r1", "range", 0, 30000)], [("r1", "not_in", []), ("r0", "range", 0, 10)]]}),
+        dict(fast, preds=[("d", "in", in_codes)], **{"or": [[("r0", "in", []), ("r1", "range", 5, 5)]]}),
+    ]
+    for q in queries:
+        for window in ((0, n), (4097, n - 31)):
+            qq = dict(q, window=window)
+            say("OR query", qq["preds"], qq["or"], window)
+            check(ctx, t, qq)
+
+
 def test_not_on_fast_path_and_generic_paths(ctx):
     """NOT IN on the dictionary column (folded into its code table on the
     fast path), NOT ranges on RLE columns, and a 20-bit column whose plain

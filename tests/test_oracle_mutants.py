@@ -11,10 +11,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "ccq_oracle.cpp")
 
 MUTANTS = {
-    "range_upper_inclusive": ("pass = q.preds[p].lo <= v && v < q.preds[p].hi",
-                              "pass = q.preds[p].lo <= v && v <= q.preds[p].hi"),
-    "range_lower_exclusive": ("pass = q.preds[p].lo <= v && v < q.preds[p].hi",
-                              "pass = q.preds[p].lo < v && v < q.preds[p].hi"),
+    "range_upper_inclusive": ("h = q.preds[p].lo <= v && v < q.preds[p].hi",
+                              "h = q.preds[p].lo <= v && v <= q.preds[p].hi"),
+    "range_lower_exclusive": ("h = q.preds[p].lo <= v && v < q.preds[p].hi",
+                              "h = q.preds[p].lo < v && v < q.preds[p].hi"),
+    "not_ignored": ("return (op == ORC_NOT_RANGE || op == ORC_NOT_IN) ? !h : h;", "return h;"),
+    "or_clause_as_and": ("bool any = false;\n                for (size_t p : q.clauses[c]) any = any || holds(p);",
+                         "bool any = true;\n                for (size_t p : q.clauses[c]) any = any && holds(p);"),
+    "or_clause_first_only": ("for (size_t p : q.clauses[c]) any = any || holds(p);",
+                             "any = holds(q.clauses[c][0]);"),
     "rle_run_one_row_long": ("int64_t stop = std::min(c.run_ends[i], r1);",
                              "int64_t stop = std::min(c.run_ends[i] + 1, r1);"),
     "rle_value_of_next_run": ("int64_t v = value_at(c, i);",

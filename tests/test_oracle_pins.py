@@ -396,3 +396,87 @@ def test_negated_predicates_match_brute_force_and_sqlite(seed):
         got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
         assert got == _norm(brute.run(t, q)), q
         assert got == _norm(brute.run_sqlite(t, q)), q
+
+
+# ---- OR (Section 5.2): mask forms against the paper's example and against
+# row sets; OR clauses in the oracle against brute force and SQL
+
+def _ranges_of_rows(rows):
+    start, end = [], []
+    for r in rows:
+        if end and end[-1] == r - 1:
+            end[-1] = r
+        else:
+            start.append(r)
+            end.append(r)
+    return start, end
+
+
+def test_or_plain_paper_example():
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "or_masks.json")))["or_plain"]
+    assert oracle.or_plain(g["m1"], g["m2"]) == g["out"]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_or_masks_are_row_unions(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 60))
+    a = sorted(set(int(x) for x in rng.integers(0, n, size=int(rng.integers(0, n + 1)))))
+    b = sorted(set(int(x) for x in rng.integers(0, n, size=int(rng.integers(0, n + 1)))))
+    want = sorted(set(a) | set(b))
+    # RLE masks: arbitrary (not necessarily maximal) cuts of the row sets
+    sa, ea = _ranges_of_rows(a)
+    sb, eb = _ranges_of_rows(b)
+    s, e = oracle.range_union(sa, ea, sb, eb)
+    assert _rows_of_ranges(s, e, n) == [r in set(want) for r in range(n)]
+    # the output is maximal: disjoint, sorted, no two ranges touch
+    assert all(x <= y for x, y in zip(s, e)) and all(e[i] + 1 < s[i + 1] for i in range(len(s) - 1))
+    assert (s, e) == _ranges_of_rows(want)
+    # De Morgan with the paper's NOT: a OR b = NOT(NOT a AND NOT b)
+    na = set(r for r in range(n) if _rows_of_ranges(*oracle.not_rle(sa, ea, n), n)[r])
+    nb = set(r for r in range(n) if _rows_of_ranges(*oracle.not_rle(sb, eb, n), n)[r])
+    ns, ne = oracle.not_rle(*_ranges_of_rows(sorted(na & nb)), n)
+    assert (ns, ne) == (s, e)
+    assert oracle.merge_sorted_idx(a, b) == want
+    ma = [r in set(a) for r in range(n)]
+    mb = [r in set(b) for r in range(n)]
+    assert oracle.or_plain(ma, mb) == [r in set(want) for r in range(n)]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_or_clause_rows_are_the_union_of_the_column_masks(seed):
+    # COUNT(*) under (p1 on r0 OR p2 on r1) equals the rows of range_union
+    # of the two columns' RLE masks (the runs whose values pass, as ranges)
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(1, 400))
+    t, wd = _tiny_table(rng, n)
+
+    def mask(col, lo, hi):
+        c = t["columns"][col]
+        ends = [int(x) for x in c["run_ends"]]
+        starts = [0] + ends[:-1]
+        rows = []
+        for s0, e0, v in zip(starts, ends, c["values"]):
+            if lo <= int(v) < hi:
+                rows += list(range(s0, e0))
+        return _ranges_of_rows(rows)
+
+    l0, l1 = int(rng.integers(-6, 20)), int(rng.integers(-6, 20))
+    h0, h1 = l0 + int(rng.integers(0, 10)), l1 + int(rng.integers(0, 10))
+    s, e = oracle.range_union(*mask("r0", l0, h0), *mask("r1", l1, h1))
+    q = {"preds": [], "or": [[("r0", "range", l0, h0), ("r1", "range", l1, h1)]], "keys": [], "aggs": [("count",)]}
+    got = oracle.run(t, q, n_threads=1)
+    assert got["counts"] == [sum(y - x + 1 for x, y in zip(s, e))]
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_or_clauses_match_brute_force_and_sqlite(seed):
+    from tests.cases import tiny_query_with_or
+    rng = np.random.default_rng(9500 + seed)
+    n = int(rng.integers(1, 300))
+    t, wd = _tiny_table(rng, n)
+    for _ in range(4):
+        q = tiny_query_with_or(rng, n, wd)
+        got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
+        assert got == _norm(brute.run(t, q)), q
+        assert got == _norm(brute.run_sqlite(t, q)), q
