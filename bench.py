@@ -51,7 +51,7 @@ def algorithmic_bytes(table, query):
     import numpy as np
     n0, n1 = query["window"]
     used = {p[0] for p in query["preds"]} | {k[0] for k in query["keys"]} | \
-           {a[1] for a in query["aggs"] if a[0] == "sum"}
+           {a[1] for a in query["aggs"] if a[0] == "sum"} | {p[0] for cl in query.get("or", ()) for p in cl}
     total = 0
     for name in sorted(used):
         c = table["columns"][name]
@@ -351,6 +351,9 @@ def main():
     ap.add_argument("--serve-tpi", type=int, default=64, help="c5: batch work-item size in tiles")
     ap.add_argument("--qps", default="200,1000,5000", help="c5: Poisson arrival rates")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
+    ap.add_argument("--filter", default="and", choices=["and", "not", "or"],
+                    help="c2: the workload's filter (and), or the same table under a filter with NOT "
+                         "(r0 outside a middle range: two value intervals) or an OR of the two RLE ranges")
     ap.add_argument("--cpu-sample-rows", type=int, default=1_000_000_000,
                     help="rows of the window the CPU oracle runs over (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,6 +388,14 @@ def main():
     t_gen = time.time()
     wl = make_workload(args.config, args.rows)
     query = wl["query"]
+    if args.filter != "and":
+        if args.config != "c2":
+            raise SystemExit("--filter applies to --config c2")
+        r0, r1, din = query["preds"]
+        if args.filter == "not":
+            query = dict(query, preds=[("r0", "not_range", 16384, 49152), r1, din])
+        else:
+            query = dict(query, preds=[din], **{"or": [[r0, r1]]})
     n0, n1 = query["window"]
     log("generated %s in %.1fs" % (wl["name"], time.time() - t_gen))
 
@@ -426,7 +437,7 @@ def main():
     rows = n1 - n0
     alg = algorithmic_bytes(wl, query)
     achieved = alg / (fused_avg * 1e-3) / 1e9
-    traffic = traffic_from_profile(wl["name"])
+    traffic = traffic_from_profile(wl["name"]) if args.filter == "and" else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -470,7 +481,9 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": wl["name"], "rows": rows, "groups": len(gpu_result["keys"]),
-                   "compressed_bytes": alg, "query": "single-launch path, one query per ccq_execute"},
+                   "compressed_bytes": alg, "query": "single-launch path, one query per ccq_execute",
+                   "filter": {"and": "r0 range AND r1 range AND d IN", "not": "NOT r0 range AND r1 range AND d IN",
+                              "or": "(r0 range OR r1 range) AND d IN"}[args.filter]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "ccq::k_fused", "kernel_ms": fused_avg},
