@@ -282,3 +282,17 @@ def merge_sorted_idx(pos1, pos2):
         if not out or out[-1] != x:
             out.append(x)
     return out
+
+
+# ---- AND of two Index masks (Algorithm 4, idx_in_idx)
+
+def idx_in_idx(pos1, pos2):
+    """Rows of Index mask pos1 also in Index mask pos2 (both sorted, unique):
+    for each row of pos1, the last row of pos2 at or before it (an upper-bound
+    bucketize, minus one) must be that row itself."""
+    pos1 = np.asarray(pos1, dtype=np.int64)
+    pos2 = np.asarray(pos2, dtype=np.int64)
+    b = np.searchsorted(pos2, pos1, side="right") - 1
+    ok = b >= 0
+    ok[ok] = pos2[b[ok]] == pos1[ok]
+    return [int(x) for x in pos1[ok]]

@@ -315,8 +315,6 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         const ccq_pred& p = q->preds[i];
         if (p.col < 0 || p.col >= ncol) return fail(CCQ_E_INVALID, "predicate %d: column %d out of range", i, p.col);
         if (p.clause < 0) return fail(CCQ_E_INVALID, "predicate %d: clause must be >= 0", i);
-        if (t->cols[p.col].encoding == CCQ_INDEX)
-            return fail(CCQ_E_UNSUPPORTED, "predicate %d: predicates on INDEX columns are not supported", i);
     }
     // clause-0 predicates, keys and SUMs use the columns' own slots
     for (int i = 0; i < q->n_preds; ++i)
@@ -440,6 +438,30 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.k_rle = (int)(rle_cols.size() + or_slots.size());
     P.n_bp = (int)bp_cols.size();
     P.n_idx = (int)idx_cols.size();
+    // a column's folded predicate in the form the kernels test
+    auto put_pred = [&](const Fold& f, int32_t& pred, int64_t& lo, int64_t& hi, const int64_t*& set,
+                        int32_t& set_len) {
+        if (f.is_false) pred = kPredFalse;
+        else if (f.has_set) {
+            pred = kPredSet;
+            std::vector<int64_t> v(f.set.begin(), f.set.end());
+            set_len = (int32_t)v.size();
+            fix_ptr(&set, blob_put(v.data(), v.size() * 8));
+        } else if (f.has_iv) {
+            pred = kPredIntervals;
+            std::vector<int64_t> v;
+            for (const auto& x : f.iv) {
+                v.push_back(x.first);
+                v.push_back(x.second);
+            }
+            set_len = (int32_t)f.iv.size();
+            fix_ptr(&set, blob_put(v.data(), v.size() * 8));
+        } else if (f.has_range) {
+            pred = kPredRange;
+            lo = f.lo;
+            hi = f.hi;
+        } else pred = kPredNone;
+    };
     for (int s = 0; s < P.k_rle; ++s) {
         const bool own = s < (int)rle_cols.size();
         const OrSlot* o = own ? nullptr : &or_slots[s - rle_cols.size()];
@@ -452,27 +474,9 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         r.vals = c.values;
         r.n_runs = c.n_entries;
         r.vtype = c.value_type;
-        if (f.is_false) r.pred = kPredFalse;
-        else if (f.has_set) {
-            r.pred = kPredSet;
-            std::vector<int64_t> v(f.set.begin(), f.set.end());
-            r.set_len = (int32_t)v.size();
-            fix_ptr(&r.set, blob_put(v.data(), v.size() * 8));
-        } else if (f.has_iv) {
-            r.pred = kPredIntervals;
-            std::vector<int64_t> v;
-            for (const auto& x : f.iv) {
-                v.push_back(x.first);
-                v.push_back(x.second);
-            }
-            r.set_len = (int32_t)f.iv.size();
-            fix_ptr(&r.set, blob_put(v.data(), v.size() * 8));
-        } else if (f.has_range) {
-            r.pred = kPredRange;
-            r.lo = f.lo;
-            r.hi = f.hi;
-        } else r.pred = kPredNone;
+        put_pred(f, r.pred, r.lo, r.hi, r.set, r.set_len);
     }
+    bool idx_pred = false;
     for (int s = 0; s < P.n_idx; ++s) {
         const ccq_column_desc& c = t->cols[idx_cols[s]];
         IdxCol& x = P.idx[s];
@@ -482,6 +486,11 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         x.ptype = c.position_type;
         x.vtype = c.value_type;
         x.sum_slot = -1;
+        // an Index column's value is 0 at the rows it does not list
+        const Fold& f = fold[idx_cols[s]];
+        put_pred(f, x.pred, x.lo, x.hi, x.set, x.set_len);
+        x.zero_pass = fold_pass(f, 0) ? 1 : 0;
+        idx_pred = idx_pred || x.pred != kPredNone;
     }
 
     // keys: mixed radix; bit-packed keys up to kLutMaxBits bits get dense
@@ -666,14 +675,15 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.n_tiles = window > 0 ? (P.row_end - 1) / P.tile_rows - P.row_begin / P.tile_rows + 1 : 0;
 
     // kernel path.  The fast row path: a single bit-packed column of a width
-    // with a kernel instance, at most one Index column, no RLE value per row, the column itself the only
+    // with a kernel instance, at most one Index column and no predicate on it, no RLE value per row, the column itself the only
     // key (or no key), a code table or a plain range test, and uint32 counts
     // that cannot overflow within one workgroup.
     P.kmax = P.k_rle <= 2 ? 2 : P.k_rle <= 4 ? 4 : 8;
     P.w0 = 0;
     P.fast_big = 0;
     {
-        bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w);
+        bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
+                    !idx_pred;
         BpCol& b = P.bp[0];
         const Fold& f = fold[bp_cols.empty() ? 0 : bp_cols[0]];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
@@ -833,6 +843,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     wv = align16(wv + 256 * (size_t)std::max(P.k_rle, 1));
     bool any_pred = false;
     for (int s = 0; s < P.k_rle; ++s) any_pred = any_pred || P.rle[s].pred != kPredNone;
+    any_pred = any_pred || idx_pred;     // Index predicates use the same scratch bitmap
     P.off_tog = any_pred ? (int32_t)wv : -1;
     if (any_pred) wv = align16(wv + 256);
     P.off_pmw = (int32_t)wv;

@@ -644,6 +644,48 @@ __device__ __forceinline__ void tile_run_bits(const DevPlan& P, const WaveLds& W
     }
 }
 
+// Predicates on Index columns (Table 2: RLE x Index and Index x Index AND,
+// idx_in_rle / idx_in_idx, here on 32-row words).  A column's value is 0 at
+// the rows it does not list, so only its points can differ from the outcome
+// of 0: those points go into a scratch bitmap, and the column's pass mask is
+// that bitmap, or its complement (NOT, Section 5.3) when 0 passes.  The
+// tile's points start at pcur (not advanced here).
+__device__ __forceinline__ uint32_t idx_pred_mask(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
+                                                  const int64_t (&pcur)[kMaxIdx], uint32_t pm) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < kMaxIdx; ++j) {
+        if (j >= P.n_idx) continue;
+        const IdxCol& ic = P.idx[j];
+        if (ic.pred == kPredNone) continue;
+        uint32_t* T = W.tog;
+        int64_t p0 = pcur[j];
+        for (;;) {
+            const int64_t i = p0 + lane;
+            const bool valid = i < ic.n;
+            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
+            const bool in = valid && pos < t0 + L;
+            const uint64_t m = wave_ballot(in);
+            if (in) {
+                const bool pass = pred_pass(ic.pred, ic.lo, ic.hi, ic.set, ic.set_len, ld_val(ic.vals, ic.vtype, i));
+                if (pass != (ic.zero_pass != 0)) {
+                    const int32_t rel = (int32_t)(pos - t0);
+                    atomicOr(&T[rel >> 5], 1u << (rel & 31));
+                }
+            }
+            const int c = __builtin_popcountll(m);
+            p0 += c;
+            if (c < 64) break;
+        }
+        wave_lds_sync();
+        const uint32_t x = T[lane];
+        T[lane] = 0;
+        wave_lds_sync();
+        pm &= ic.zero_pass ? ~x : x;
+    }
+    return pm;
+}
+
 // Point bitmaps of the tile (one bit per row carrying an Index point) with
 // exclusive prefix counts per word; pbase[j] = index of the tile's first point.
 __device__ __forceinline__ void tile_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
@@ -1637,8 +1679,9 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
         int64_t t0 = w0 & ~(int64_t)31;
         while (t0 < w1) {
             int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
-            const uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
+            uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
             const int32_t L = (int32_t)(t1 - t0);
+            pm = idx_pred_mask(P, W, t0, L, pcur, pm);
             if (P.row_mode) tile_row_generic<KMAX>(P, W, t0, L, pm, tb, status, pcur, luts);
             else tile_run_bits<KMAX>(P, W, t0, L, pm, tb, status, acc, pcur);
             tile_bitmaps_clear(P, W);

@@ -87,7 +87,11 @@ struct IdxCol {
     int64_t n;
     int32_t ptype, vtype;
     int32_t sum_slot;       // SUM accumulator of this column, or -1
-    int32_t pad_;
+    int32_t pred;           // PredKind on the row's value (0 at rows the column does not list)
+    int64_t lo, hi;         // kPredRange
+    const int64_t* set;     // kPredSet / kPredIntervals, as for RLE columns (device)
+    int32_t set_len;
+    int32_t zero_pass;      // 1 when the value 0 passes the predicate
 };
 
 struct KeyDesc {

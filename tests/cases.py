@@ -101,3 +101,26 @@ def tiny_query_with_or(rng, n, wd):
         clauses.append([("p", "range", lo, lo + 300), ("p", "not_range", -2000, 2000)])
     q["or"] = clauses
     return q
+
+
+def tiny_query_with_index_pred(rng, n, wd):
+    """tiny_query_with_not plus one or two predicates on the Index column s
+    (unlisted rows hold 0): ranges and IN-lists with and without 0, plain or
+    negated, at times inside a one-column OR clause."""
+    q = tiny_query_with_not(rng, n, wd)
+    preds = []
+    for _ in range(int(rng.integers(1, 3))):
+        op = ["range", "in", "not_range", "not_in"][int(rng.integers(0, 4))]
+        if op.endswith("range"):
+            lo = int(rng.integers(-120, 60))
+            preds.append(("s", op, lo, lo + int(rng.integers(0, 150))))
+        else:
+            vals = set(int(x) for x in rng.integers(-100, 100, size=int(rng.integers(0, 6))))
+            if rng.random() < 0.4:
+                vals.add(0)
+            preds.append(("s", op, sorted(vals)))
+    if rng.random() < 0.3:
+        q["or"] = [preds]
+    else:
+        q["preds"] = q["preds"] + preds
+    return q

@@ -73,7 +73,6 @@ def test_host_only_context_checks_plans():
 
 @pytest.mark.parametrize("bad,code", [
     ({"preds": [("zz", "range", 0, 1)]}, "unknown"),
-    ({"preds": [("s", "range", 0, 1)]}, ccq.E_UNSUPPORTED),
     ({"keys": [("s", 0, 4)]}, ccq.E_UNSUPPORTED),
     ({"keys": [("a", 63, 4)]}, ccq.E_INVALID),
     ({"keys": [("a", 0, 0)]}, ccq.E_INVALID),

@@ -372,6 +372,43 @@ def test_or_on_fast_path_run_mode_and_generic_paths(ctx):
             check(ctx, t, qq)
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_tiny_random_tables_with_index_predicates(ctx, seed):
+    from tests.cases import tiny_query_with_index_pred
+    rng = np.random.default_rng(7800 + seed)
+    n = int(rng.integers(1, 5000))
+    t, wd = tiny_table(rng, n)
+    for _ in range(3):
+        q = tiny_query_with_index_pred(rng, n, wd)
+        say("tiny Index-predicate seed", seed, "n", n, "query", q)
+        check(ctx, t, q)
+
+
+def test_index_predicates_run_mode_and_row_mode(ctx):
+    """Predicates on the Index column (1% of rows listed, values >= 1, 0
+    elsewhere): one that 0 fails (only listed rows can qualify: idx_in_rle),
+    one that 0 passes (every unlisted row qualifies: the complement of the
+    failing points), with and without the dictionary column, in a window."""
+    n = 2_000_003
+    t = datagen.config_c2(seed=95, n_rows=n, columns=("r0", "r1", "s", "d", "p"))
+    in_codes = t["query"]["preds"][2][2]
+    queries = [
+        {"preds": [("s", "range", 1, 500_000), ("r0", "range", 0, 32768)], "keys": [("r1", 12, 16)],
+         "aggs": [("sum", "s"), ("count",)]},
+        {"preds": [("s", "not_range", 1, 300_000), ("r1", "range", 16384, 65536)], "keys": [],
+         "aggs": [("sum", "s"), ("sum", "r0"), ("count",)]},
+        {"preds": [("s", "range", 250_000, 750_000), ("d", "in", in_codes)], "keys": [("d", 0, 10000)],
+         "aggs": [("sum", "s"), ("count",)]},
+        {"preds": [("s", "not_in", [1, 2, 3]), ("p", "range", -100_000, 300_000)], "keys": [],
+         "aggs": [("sum", "p"), ("count",)], "or": [[("s", "range", 0, 1), ("s", "range", 900_000, 10**6)]]},
+    ]
+    for q in queries:
+        for window in ((0, n), (4097, n - 31)):
+            qq = dict(q, window=window)
+            say("Index-predicate query", qq["preds"], qq.get("or"), window)
+            check(ctx, t, qq)
+
+
 def test_not_on_fast_path_and_generic_paths(ctx):
     """NOT IN on the dictionary column (folded into its code table on the
     fast path), NOT ranges on RLE columns, and a 20-bit column whose plain

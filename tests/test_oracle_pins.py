@@ -480,3 +480,48 @@ def test_or_clauses_match_brute_force_and_sqlite(seed):
         got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
         assert got == _norm(brute.run(t, q)), q
         assert got == _norm(brute.run_sqlite(t, q)), q
+
+
+
+# ---- predicates on Index columns: Algorithm 4 (idx_in_idx) against row
+# sets; the oracle's per-row Index predicates against brute force and SQL
+
+@pytest.mark.parametrize("seed", range(30))
+def test_idx_in_idx_is_the_row_intersection(seed):
+    rng = np.random.default_rng(1100 + seed)
+    n = int(rng.integers(1, 80))
+    a = sorted(set(int(x) for x in rng.integers(0, n, size=int(rng.integers(0, n + 1)))))
+    b = sorted(set(int(x) for x in rng.integers(0, n, size=int(rng.integers(0, n + 1)))))
+    assert oracle.idx_in_idx(a, b) == sorted(set(a) & set(b))
+    assert oracle.idx_in_idx(b, a) == sorted(set(a) & set(b))
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_and_of_two_index_predicates_counts_idx_in_idx(seed):
+    # two Index columns, predicates that 0 fails: the qualifying rows are
+    # idx_in_idx of the two columns' Index masks (their passing points)
+    rng = np.random.default_rng(1200 + seed)
+    n = int(rng.integers(1, 300))
+    cols = {}
+    masks = []
+    for name in ("s1", "s2"):
+        pos = np.sort(rng.choice(n, size=int(rng.integers(0, n + 1)), replace=False)).astype(np.int64)
+        val = rng.integers(-20, 20, size=len(pos)).astype(np.int64)
+        cols[name] = {"enc": "index", "positions": pos, "values": val}
+        masks.append([int(p) for p, v in zip(pos, val) if 3 <= v < 15])
+    t = {"n_rows": n, "columns": cols}
+    q = {"preds": [("s1", "range", 3, 15), ("s2", "range", 3, 15)], "keys": [], "aggs": [("count",)]}
+    assert oracle.run(t, q, n_threads=1)["counts"] == [len(oracle.idx_in_idx(masks[0], masks[1]))]
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_index_predicates_match_brute_force_and_sqlite(seed):
+    from tests.cases import tiny_query_with_index_pred
+    rng = np.random.default_rng(9800 + seed)
+    n = int(rng.integers(1, 300))
+    t, wd = _tiny_table(rng, n)
+    for _ in range(4):
+        q = tiny_query_with_index_pred(rng, n, wd)
+        got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
+        assert got == _norm(brute.run(t, q)), q
+        assert got == _norm(brute.run_sqlite(t, q)), q
