@@ -284,6 +284,12 @@ def merge_sorted_idx(pos1, pos2):
     return out
 
 
+def concat_sort(pos1, pos2):
+    """Union of two Index masks for small inputs: both lists joined, sorted,
+    repeated rows dropped."""
+    return sorted(set(int(x) for x in list(pos1) + list(pos2)))
+
+
 # ---- AND of two Index masks (Algorithm 4, idx_in_idx)
 
 def idx_in_idx(pos1, pos2):

@@ -240,6 +240,7 @@ struct Fold {               // conjunction of predicates on one column
     Intervals iv;             // the passing values, when constrained
     // the same, in the simplest form the kernels take
     bool has_range = false, has_set = false, has_iv = false, is_false = false;
+    bool has_not_range = false;   // every value outside [lo, hi)
     int64_t lo = 0, hi = 0;   // [lo, hi) when has_range
     std::set<int64_t> set;
 };
@@ -255,6 +256,14 @@ void fold_classify(Fold& f) {
         f.has_range = true;
         f.lo = f.iv[0].first;
         f.hi = f.iv[0].second + 1;
+    } else if (f.iv.size() == 1) {               // [lo, INT64_MAX]: outside [INT64_MIN, lo)
+        f.has_not_range = true;
+        f.lo = INT64_MIN;
+        f.hi = f.iv[0].first;
+    } else if (f.iv.size() == 2 && f.iv[0].first == INT64_MIN && f.iv[1].second == INT64_MAX) {
+        f.has_not_range = true;                  // the complement of one range (NOT, Section 5.3)
+        f.lo = f.iv[0].second + 1;
+        f.hi = f.iv[1].first;
     } else {
         bool single = true;
         for (const auto& x : f.iv) single = single && x.first == x.second;
@@ -460,6 +469,10 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             pred = kPredRange;
             lo = f.lo;
             hi = f.hi;
+        } else if (f.has_not_range) {
+            pred = kPredNotRange;
+            lo = f.lo;
+            hi = f.hi;
         } else pred = kPredNone;
     };
     for (int s = 0; s < P.k_rle; ++s) {
@@ -587,26 +600,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
                 lut[code] = (kv < 0 || kv >= kd.card) ? kLutDomain : (uint16_t)rank[kv];
             }
         } else {
-            if (f.is_false) b.pred = kPredFalse;
-            else if (f.has_set) {
-                b.pred = kPredSet;
-                std::vector<int64_t> v(f.set.begin(), f.set.end());
-                b.set_len = (int32_t)v.size();
-                fix_ptr(&b.set, blob_put(v.data(), v.size() * 8));
-            } else if (f.has_iv) {
-                b.pred = kPredIntervals;
-                std::vector<int64_t> v;
-                for (const auto& x : f.iv) {
-                    v.push_back(x.first);
-                    v.push_back(x.second);
-                }
-                b.set_len = (int32_t)f.iv.size();
-                fix_ptr(&b.set, blob_put(v.data(), v.size() * 8));
-            } else if (f.has_range) {
-                b.pred = kPredRange;
-                b.lo = f.lo;
-                b.hi = f.hi;
-            } else b.pred = kPredNone;
+            put_pred(f, b.pred, b.lo, b.hi, b.set, b.set_len);
         }
     }
 
@@ -697,7 +691,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         // keys), no SUM of the column itself
         bool big = false;
         if (fast && (G + 2) * 8 > kFastCntWords) {
-            big = (G + 2) * 4 <= kFastBigBytes && b.sum_slot < 0 && !f.has_set && !f.has_iv;
+            big = (G + 2) * 4 <= kFastBigBytes && b.sum_slot < 0 && !f.has_set && !f.has_iv && !f.has_not_range;
             if (big && b.key >= 0 && P.keys[b.key].via_lut) {
                 const std::vector<int64_t>& sk = slot_keys[b.key];
                 big = sk.back() - sk.front() + 1 == (int64_t)sk.size();
@@ -705,7 +699,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             if (!big) fast = false;
         }
         if (fast && (lut16[0].empty() || big)) {
-            if (!big && (b.pred == kPredSet || b.pred == kPredIntervals)) fast = false;
+            if (!big && (b.pred == kPredSet || b.pred == kPredIntervals || b.pred == kPredNotRange)) fast = false;
             const bool is_false = big ? f.is_false : b.pred == kPredFalse;
             const bool has_range = big ? f.has_range : b.pred == kPredRange;
             const int64_t rlo = big ? f.lo : b.lo, rhi = big ? f.hi : b.hi;

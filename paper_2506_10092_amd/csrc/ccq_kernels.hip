@@ -145,6 +145,7 @@ __device__ __forceinline__ bool pred_pass(int32_t kind, int64_t lo, int64_t hi, 
                                           int64_t v) {
     if (kind == kPredNone) return true;
     if (kind == kPredRange) return lo <= v && v < hi;
+    if (kind == kPredNotRange) return v < lo || v >= hi;
     if (kind == kPredSet) return set_contains(set, n, v);
     if (kind == kPredIntervals) return intervals_contain(set, n, v);
     return false;

@@ -25,7 +25,8 @@ constexpr int kSegSlots = 64;         // group segments merged per tile in LDS
 constexpr int kFastBigBytes = 65536;   // fast row path: largest uint32 count table in dynamic LDS
 constexpr int kFastCntWords = 2048;    // fast row path: static LDS counts, (G + 2) * replicas
 
-enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3, kPredIntervals = 4 };
+enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3, kPredIntervals = 4,
+                          kPredNotRange = 5 };   // kPredNotRange: v < lo or v >= hi
 enum AggKind : int32_t { kAggCount = 0, kAggSumRle = 1, kAggSumBp = 2, kAggSumIdx = 3 };
 enum KeySrc : int32_t { kKeyRle = 0, kKeyBp = 1 };
 

@@ -427,6 +427,11 @@ def test_not_on_fast_path_and_generic_paths(ctx):
          "keys": [], "aggs": [("sum", "p"), ("sum", "s"), ("count",)]},
         {"preds": [("r0", "not_in", list(range(0, 65536, 2))), ("r1", "not_range", 0, 100)],
          "keys": [("r0", 10, 64)], "aggs": [("sum", "r1"), ("count",)]},
+        # NOT of a range open to the left: every value from 1000 up
+        {"preds": [("r1", "not_range", -(1 << 63), 1000), ("d", "in", in_codes)],
+         "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)]},
+        {"preds": [("p", "not_range", -(1 << 63), -1000), ("p", "not_range", 2000, 1 << 62)],
+         "keys": [], "aggs": [("sum", "p"), ("count",)]},
     ]
     for q in queries:
         for window in ((0, n), (4097, n - 31)):

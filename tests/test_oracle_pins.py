@@ -438,6 +438,7 @@ def test_or_masks_are_row_unions(seed):
     ns, ne = oracle.not_rle(*_ranges_of_rows(sorted(na & nb)), n)
     assert (ns, ne) == (s, e)
     assert oracle.merge_sorted_idx(a, b) == want
+    assert oracle.concat_sort(a, b) == want
     ma = [r in set(a) for r in range(n)]
     mb = [r in set(b) for r in range(n)]
     assert oracle.or_plain(ma, mb) == [r in set(want) for r in range(n)]
