@@ -49,6 +49,28 @@ def test_c2_full_1e9():
     assert len(got["keys"]) == 50
 
 
+@pytest.mark.timeout(600)
+def test_c2_full_1e9_not_or_and_index_filters():
+    """The same table under NOT, OR and Index-column filters (the filters
+    bench.py --filter times, plus an Index predicate), over all 1e9 rows."""
+    c = datagen.config_c2()
+    r0, r1, din = c["query"]["preds"]
+    base = dict(c["query"])
+    queries = [
+        dict(base, preds=[("r0", "not_range", 16384, 49152), r1, din]),
+        dict(base, preds=[din], **{"or": [[r0, r1]]}),
+        dict(base, preds=[r0, ("s", "range", 1, 500_000)], keys=[("r1", 12, 16)]),
+    ]
+    from paper_2506_10092_amd import ccq
+    ctx = ccq.Context(0)
+    t = ccq.Table(ctx, c["n_rows"], ccq.to_device(c["columns"]))
+    for q in queries:
+        say("query", q["preds"], q.get("or"))
+        got = ccq.Plan(t, q).run()
+        exp = oracle.run(c, q, n_threads=os.cpu_count())
+        _compare(got, exp)
+
+
 @pytest.mark.timeout(900)
 def test_c3_full_1e10():
     t0 = time.time()
