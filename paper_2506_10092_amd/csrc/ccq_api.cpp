@@ -305,6 +305,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
 
     DevPlan& P = out.P;
     memset(&P, 0, sizeof P);
+    P.off_rcl = -1;       // no row clause unless the layout below places one
     P.row_begin = q->row_begin;
     P.row_end = q->row_end;
 
@@ -383,8 +384,14 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         int col;
         Fold f;
         bool or_next;
+        bool row_clause;
     };
     std::vector<OrSlot> or_slots;
+    // at most one clause over RLE and bit-packed columns (RLE mask OR Plain
+    // mask, Table 4): its RLE part is a mask of its own, and each row of it
+    // is tested against the bit-packed part
+    bool row_clause = false;
+    std::vector<std::pair<int, Intervals>> bp_or;
     int false_col = -1;    // a clause no row can pass: the query is false
     for (const Clause& cl : clauses) {
         std::vector<size_t> live;
@@ -406,16 +413,35 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             if (ccq_status s = use(c)) return s;
             continue;
         }
-        for (size_t j : live)
-            if (t->cols[cl.cols[j]].encoding != CCQ_RLE)
-                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes RLE columns only", cl.id);
-        for (size_t n = 0; n < live.size(); ++n) {
+        bool mixed = false;
+        for (size_t j : live) {
+            if (t->cols[cl.cols[j]].encoding == CCQ_INDEX)
+                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes no INDEX column", cl.id);
+            mixed = mixed || t->cols[cl.cols[j]].encoding == CCQ_BITPACKED;
+        }
+        if (mixed) {
+            if (row_clause)
+                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: at most one OR clause may span RLE and bit-packed columns",
+                            cl.id);
+            row_clause = true;
+        }
+        std::vector<size_t> rle_live;
+        for (size_t j : live) {
+            if (t->cols[cl.cols[j]].encoding == CCQ_RLE) {
+                rle_live.push_back(j);
+            } else {
+                bp_or.push_back({cl.cols[j], cl.iv[j]});
+                if (ccq_status s = use(cl.cols[j])) return s;
+            }
+        }
+        for (size_t n = 0; n < rle_live.size(); ++n) {
             OrSlot o;
-            o.col = cl.cols[live[n]];
+            o.col = cl.cols[rle_live[n]];
             o.f.constrained = true;
-            o.f.iv = cl.iv[live[n]];
+            o.f.iv = cl.iv[rle_live[n]];
             fold_classify(o.f);
-            o.or_next = n + 1 < live.size();
+            o.or_next = n + 1 < rle_live.size();
+            o.row_clause = mixed;
             or_slots.push_back(o);
         }
     }
@@ -482,6 +508,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         const Fold& f = own ? fold[rle_cols[s]] : o->f;
         RleCol& r = P.rle[s];
         r.or_next = (o && o->or_next) ? 1 : 0;
+        r.row_clause = (o && o->row_clause) ? 1 : 0;
         r.sum_slot = -1;
         r.ends = c.run_ends;
         r.vals = c.values;
@@ -604,6 +631,20 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
     }
 
+    // the bit-packed part of the row clause, per column
+    for (int s = 0; s < P.n_bp; ++s) {
+        BpCol& b = P.bp[s];
+        b.or_pred = kPredNone;
+        for (const auto& m : bp_or) {
+            if (m.first != bp_cols[s]) continue;
+            Fold f;
+            f.constrained = true;
+            f.iv = m.second;
+            fold_classify(f);
+            put_pred(f, b.or_pred, b.or_lo, b.or_hi, b.or_set, b.or_set_len);
+        }
+    }
+
     // aggregates
     P.n_aggs = q->n_aggs;
     for (int a = 0; a < q->n_aggs; ++a) {
@@ -677,7 +718,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.fast_big = 0;
     {
         bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
-                    !idx_pred;
+                    !idx_pred && !row_clause;
         BpCol& b = P.bp[0];
         const Fold& f = fold[bp_cols.empty() ? 0 : bp_cols[0]];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
@@ -842,6 +883,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     if (any_pred) wv = align16(wv + 256);
     P.off_pmw = (int32_t)wv;
     if (P.n_idx > 0) wv = align16(wv + 256);
+    P.off_rcl = row_clause ? (int32_t)wv : -1;
+    if (row_clause) wv = align16(wv + 256);
     // run mode with a global group table: LDS slots merging group segments
     P.seg_slots = (!P.row_mode && P.n_keys > 0 && !P.table_lds) ? 1 : 0;
     P.off_slots = (int32_t)wv;

@@ -255,6 +255,7 @@ struct WaveLds {
     uint32_t* bnd;      // staged paths: 64-word run-boundary bitmap per RLE column
     int32_t* bpre;      // staged paths: exclusive prefix of boundary popcounts per word
     uint32_t* pmw;      // staged paths: the lanes' surviving-row words
+    uint32_t* rcl;      // staged row mode: the row clause's RLE rows, one word per lane
 };
 
 // first staged-run slot and capacity of RLE column c in a wave slice
@@ -315,6 +316,7 @@ __device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& 
     }
     uint32_t pm = 0xFFFFFFFFu;
     uint32_t any = 0;             // the open OR clause's rows
+    uint32_t rcl = 0;             // the row clause's RLE rows
     bool shrunk = false;
     int64_t last_e[KMAX];
 #pragma unroll
@@ -403,7 +405,8 @@ __device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& 
             const uint32_t flip = ((uint32_t)lanes_below(par) ^ first) & 1u;
             any |= flip ? ~x : x;
             if (!rc.or_next) {
-                pm &= any;
+                if (rc.row_clause) rcl = any;
+                else pm &= any;
                 any = 0;
             }
         }
@@ -426,6 +429,7 @@ __device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& 
         else nxt = lo[c] + lds_upper_bound(W.run_end + stage_base(P, c), W.tn[c], (int32_t)(*t1 - t0));
         if (lane == 0) W.cur[c] = nxt;
     }
+    if (W.rcl) W.rcl[lane] = rcl;
     wave_lds_sync();
     return pm & lane_window((int32_t)(*t1 - t0), (int32_t)(max(t0, w0) - t0));
 }
@@ -1542,6 +1546,17 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
             }
         }
         if (!pass) continue;
+        if (W.rcl) {
+            // the row clause (Section 5.2, RLE mask OR Plain mask): its RLE
+            // rows, or a bit-packed part holding on this row's value
+            bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
+#pragma unroll
+            for (int j = 0; j < kMaxBp; ++j)
+                if (j < P.n_bp && P.bp[j].or_pred != kPredNone)
+                    in = in || pred_pass(P.bp[j].or_pred, P.bp[j].or_lo, P.bp[j].or_hi, P.bp[j].or_set,
+                                         P.bp[j].or_set_len, bpv[j]);
+            if (!in) continue;
+        }
         int64_t rv[KMAX];
         int32_t ridx[KMAX];
 #pragma unroll
@@ -1639,6 +1654,7 @@ __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
     W.bnd = (uint32_t*)(W.base + P.off_bnd);
     W.bpre = (int32_t*)(W.base + P.off_bpre);
     W.pmw = (uint32_t*)(W.base + P.off_pmw);
+    W.rcl = P.off_rcl >= 0 ? (uint32_t*)(W.base + P.off_rcl) : nullptr;
     return W;
 }
 

@@ -53,7 +53,7 @@ struct RleCol {
     int32_t stage_cap;      // and its capacity (>= 64)
     int32_t or_next;        // 1: this column's pass mask is ORed with the next column's (one OR
                             // clause spans consecutive columns); 0: the clause ends here and is ANDed
-    int32_t pad_;
+    int32_t row_clause;     // 1: the clause is the row clause (its mask goes to the row test instead)
 };
 
 struct BpCol {
@@ -80,6 +80,12 @@ struct BpCol {
     int32_t ones_reject;    // fast path code table: the all-ones code is rejected, so a row the RLE
                             // predicates removed can be sent there by OR-ing its code with all ones
     int32_t pad_ones_;
+    // the row clause (an OR over RLE and bit-packed columns): this column's
+    // part of it, tested per row on the value (kPredNone: not in it)
+    int32_t or_pred;
+    int32_t or_set_len;
+    int64_t or_lo, or_hi;
+    const int64_t* or_set;
 };
 
 struct IdxCol {
@@ -142,7 +148,9 @@ struct DevPlan {
                             // sums added to the global table
     // staged paths, inside a wave slice: run-boundary bitmaps and their word
     // prefixes (64 words per RLE column), the lanes' surviving-row words
-    int32_t off_bnd, off_bpre, off_pmw, pad_bits_;
+    int32_t off_bnd, off_bpre, off_pmw;
+    int32_t off_rcl;        // staged row mode with a row clause: the RLE part of that clause, one
+                            // word per lane (LDS offset in a wave slice), else -1
     // run mode with a global group table: per-wave LDS slots that merge the
     // pieces of one group segment before they reach the table
     int32_t seg_slots, off_slots;

@@ -86,8 +86,9 @@ def _rle_literal(rng, col):
 
 def tiny_query_with_or(rng, n, wd):
     """tiny_query_with_not plus OR clauses: one or two over the RLE columns
-    (two or three predicates, a column possibly named twice), and at times
-    one over the dictionary column alone or the wide column alone."""
+    (two or three predicates, a column possibly named twice), at times one
+    over the dictionary column alone or the wide column alone, and at times
+    one over RLE and bit-packed columns."""
     q = tiny_query_with_not(rng, n, wd)
     clauses = []
     for _ in range(int(rng.integers(1, 3))):
@@ -99,6 +100,18 @@ def tiny_query_with_or(rng, n, wd):
     if rng.random() < 0.3:
         lo = int(rng.integers(-1000, 0))
         clauses.append([("p", "range", lo, lo + 300), ("p", "not_range", -2000, 2000)])
+    if rng.random() < 0.5:
+        # one clause over RLE and bit-packed columns (RLE mask OR Plain mask)
+        d_lit = ("d", "in", sorted(set(int(x) for x in rng.integers(0, 1 << wd, size=3))))
+        lo = int(rng.integers(-1000, 500))
+        p_lit = ("p", ["range", "not_range"][int(rng.integers(0, 2))], lo, lo + int(rng.integers(1, 800)))
+        pick = int(rng.integers(0, 3))
+        if pick == 0:
+            clauses.append([_rle_literal(rng, "r%d" % int(rng.integers(0, 3))), d_lit])
+        elif pick == 1:
+            clauses.append([_rle_literal(rng, "r0"), _rle_literal(rng, "r1"), p_lit])
+        else:
+            clauses.append([d_lit, p_lit])
     q["or"] = clauses
     return q
 

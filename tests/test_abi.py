@@ -82,8 +82,9 @@ def test_host_only_context_checks_plans():
     ({"window": (0, 1001)}, ccq.E_INVALID),
     ({"window": (10, 5)}, ccq.E_INVALID),
     ({"keys": [("a", 0, 4), ("a", 1, 4)]}, ccq.E_UNSUPPORTED),
-    # OR across an RLE and a bit-packed column; OR on an Index column
-    ({"or": [[("a", "range", 0, 2), ("d", "in", [1])]]}, ccq.E_UNSUPPORTED),
+    # two OR clauses spanning RLE and bit-packed columns; OR across an Index column
+    ({"or": [[("a", "range", 0, 2), ("d", "in", [1])], [("m", "range", 0, 2), ("p", "range", 0, 5)]]},
+     ccq.E_UNSUPPORTED),
     ({"or": [[("s", "range", 0, 2), ("a", "in", [1])]]}, ccq.E_UNSUPPORTED),
     # five two-column OR clauses need ten RLE column uses (at most eight)
     ({"or": [[("a", "range", 0, 2 + i), ("m", "range", 0, 5)] for i in range(5)]}, ccq.E_UNSUPPORTED),
@@ -112,6 +113,8 @@ def test_or_clauses_fold_or_take_rle_slots():
         [[("a", "range", 0, 2), ("m", "in", [5])]] * 3 + [[("m", "range", 0, 9), ("m", "in", [7])]],
         [[("a", "not_in", []), ("d", "in", [3])]],        # holds for every row: dropped
         [[("a", "in", []), ("d", "in", [3])]],            # one live predicate: folds into d
+        [[("a", "range", 0, 2), ("d", "in", [3])]],       # RLE OR bit-packed: the row clause
+        [[("d", "in", [3]), ("p", "range", 0, 9)], [("a", "range", 0, 2), ("m", "in", [5])]],
     ]
     for clauses in ok:
         ccq.plan_check(tb, dict(base, preds=[("a", "range", 1, 3)], **{"or": clauses}))

@@ -384,6 +384,29 @@ def test_tiny_random_tables_with_index_predicates(ctx, seed):
         check(ctx, t, q)
 
 
+def test_or_across_rle_and_bitpacked_columns(ctx):
+    """One OR clause over RLE and bit-packed columns (Table 4, RLE mask OR
+    Plain mask): its RLE part is a mask of its own and each row is tested on
+    its codes; with other clauses, a key on the dictionary column, windows."""
+    n = 2_000_003
+    t = datagen.config_c2(seed=97, n_rows=n, columns=("r0", "r1", "s", "d", "p"))
+    in_codes = t["query"]["preds"][2][2]
+    queries = [
+        {"preds": [], "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)],
+         "or": [[("r0", "range", 0, 4000), ("d", "in", in_codes[:20])]]},
+        {"preds": [("d", "in", in_codes)], "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)],
+         "or": [[("r1", "range", 60000, 65536), ("r0", "in", [5, 6, 7]), ("p", "range", -1000, 20_000)],
+                [("r0", "range", 0, 40000), ("r1", "range", 0, 30000)]]},
+        {"preds": [("r1", "range", 0, 50000)], "keys": [], "aggs": [("sum", "p"), ("sum", "r0"), ("count",)],
+         "or": [[("d", "not_in", in_codes), ("p", "not_range", -400_000, 400_000)]]},
+    ]
+    for q in queries:
+        for window in ((0, n), (4097, n - 31)):
+            qq = dict(q, window=window)
+            say("mixed OR query", qq["preds"], qq["or"], window)
+            check(ctx, t, qq)
+
+
 def test_index_predicates_run_mode_and_row_mode(ctx):
     """Predicates on the Index column (1% of rows listed, values >= 1, 0
     elsewhere): one that 0 fails (only listed rows can qualify: idx_in_rle),
