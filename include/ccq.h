@@ -21,7 +21,7 @@
  *     run i covers rows [run_ends[i-1], run_ends[i]) (run_ends[-1] = 0), i.e.
  *     the paper's inclusive end plus one; base columns have no gaps;
  *   - an Index column lists (position, value) pairs; rows it does not list
- *     hold the value 0;
+ *     hold the value 0 (for SUM and for predicates on the column);
  *   - a bit-packed column stores row r's code in bits [r*w, r*w + w) of an
  *     LSB-first stream of little-endian uint32 words; value = base + code;
  *   - RANGE predicates are half open, lo <= v < hi; IN has set semantics;
@@ -105,11 +105,13 @@ typedef struct {
  * positions for Index masks).  With NOT this expresses any filter over the
  * predicates (De Morgan; the composite-mask rules of Section 5).  Predicates
  * on one column fold into one list of value intervals: AND intersects, OR
- * unites, NOT complements.  An OR clause over several columns must name RLE
- * columns only (at most 8 RLE column uses per query, counting each column
- * once for the clause-0 predicates, keys and SUMs and once per clause that
- * names it); an OR clause over one column takes any encoding that accepts
- * predicates.  Otherwise CCQ_E_UNSUPPORTED. */
+ * unites, NOT complements.  An OR clause over one column takes any
+ * encoding.  An OR clause over several columns names RLE columns, except
+ * that one clause per query may also name bit-packed columns (Table 4, RLE
+ * mask OR Plain mask); no Index column.  At most 8 RLE column uses per
+ * query, counting each column once for the clause-0 predicates, keys and
+ * SUMs and once per clause over several columns that names it.  Otherwise
+ * CCQ_E_UNSUPPORTED. */
 enum { CCQ_RANGE = 1, CCQ_IN = 2, CCQ_NOT_RANGE = 3, CCQ_NOT_IN = 4 };
 typedef struct {
     int32_t col;               /* column index in the table */
@@ -187,8 +189,9 @@ ccq_status ccq_table_validate(ccq_table* t, void* stream);
 /* Compile a query against a table: validates the query, folds predicates
  * per column, builds code lookup tables, chooses tiles and allocates the
  * plan's device descriptor.  CCQ_E_UNSUPPORTED for query shapes the kernels
- * do not implement (predicates or keys on INDEX columns, more than 8 RLE or
- * 4 bit-packed columns, more than 2^27 key combinations). */
+ * do not implement (keys on INDEX columns, OR clauses outside the forms
+ * above, more than 8 RLE column uses or 4 bit-packed columns, more than 2^27
+ * key combinations). */
 ccq_status ccq_plan_create(const ccq_table* t, const ccq_query_desc* q, ccq_plan** out);
 void ccq_plan_destroy(ccq_plan* p);                      /* NULL-safe */
 
