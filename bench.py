@@ -351,9 +351,10 @@ def main():
     ap.add_argument("--serve-tpi", type=int, default=64, help="c5: batch work-item size in tiles")
     ap.add_argument("--qps", default="200,1000,5000", help="c5: Poisson arrival rates")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
-    ap.add_argument("--filter", default="and", choices=["and", "not", "or"],
+    ap.add_argument("--filter", default="and", choices=["and", "not", "or", "or_dict"],
                     help="c2: the workload's filter (and), or the same table under a filter with NOT "
-                         "(r0 outside a middle range: two value intervals) or an OR of the two RLE ranges")
+                         "(r0 outside a middle range), an OR of the two RLE ranges (or), or an OR of the "
+                         "r0 range and the dictionary IN-list (or_dict)")
     ap.add_argument("--cpu-sample-rows", type=int, default=1_000_000_000,
                     help="rows of the window the CPU oracle runs over (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -394,8 +395,10 @@ def main():
         r0, r1, din = query["preds"]
         if args.filter == "not":
             query = dict(query, preds=[("r0", "not_range", 16384, 49152), r1, din])
-        else:
+        elif args.filter == "or":
             query = dict(query, preds=[din], **{"or": [[r0, r1]]})
+        else:
+            query = dict(query, preds=[r1], **{"or": [[r0, din]]})
     n0, n1 = query["window"]
     log("generated %s in %.1fs" % (wl["name"], time.time() - t_gen))
 
@@ -483,7 +486,8 @@ def main():
         "config": {"workload": wl["name"], "rows": rows, "groups": len(gpu_result["keys"]),
                    "compressed_bytes": alg, "query": "single-launch path, one query per ccq_execute",
                    "filter": {"and": "r0 range AND r1 range AND d IN", "not": "NOT r0 range AND r1 range AND d IN",
-                              "or": "(r0 range OR r1 range) AND d IN"}[args.filter]},
+                              "or": "(r0 range OR r1 range) AND d IN",
+                              "or_dict": "r1 range AND (r0 range OR d IN)"}[args.filter]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "ccq::k_fused", "kernel_ms": fused_avg},

@@ -30,7 +30,10 @@ def setup():
     # OR clauses over RLE columns (one column in two clauses)
     qs += [dict(qs[4], **{"or": [[("r0", "range", 0, 20000), ("r1", "range", 50000, 65536)]]}),
            dict(qs[5], **{"or": [[("r2", "not_range", 0, 100), ("r0", "in", [1, 2, 3])],
-                                 [("r0", "range", 0, 30000), ("r1", "range", 0, 10000)]]})]
+                                 [("r0", "range", 0, 30000), ("r1", "range", 0, 10000)]]}),
+           # an OR clause over RLE and bit-packed columns; a predicate on the Index column
+           dict(qs[6], **{"or": [[("r1", "range", 0, 20000), ("d", "in", [1, 2, 3, 4, 5])]]}),
+           dict(qs[7], preds=qs[7]["preds"] + [("s", "not_range", 1, 500_000)])]
     ctx = ccq.Context(0)
     table = ccq.Table(ctx, n, ccq.to_device(t["columns"]))
     plans = [ccq.Plan(table, q) for q in qs]
