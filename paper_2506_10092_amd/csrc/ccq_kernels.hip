@@ -1465,6 +1465,15 @@ __device__ __forceinline__ void fast_flush(const DevPlan& P, int64_t* table, int
 // Generic row mode: any number of bit-packed columns of any width, RLE values
 // per row.  Surviving rows are compacted into an LDS list; the packed words
 // they read are staged in LDS.
+// sum of a 64-bit value over the wave (every lane gets it)
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+constexpr int kPeelRounds = 8;
+
 template <int KMAX>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
                                                  uint32_t pm, const Table& tb, int32_t* status,
@@ -1512,89 +1521,124 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
     }
     wave_lds_sync();
 
-    for (int i = lane; i < total; i += 64) {
-        const int32_t r = W.rows[i];
-        bool pass = true;
-        bool dom = false;
+    for (int i0 = 0; i0 < total; i0 += 64) {
+        // a8 per row: the row's group and its SUM terms (add[slot])
+        const int i = i0 + lane;
+        bool ok = i < total;
+        const int32_t r = ok ? W.rows[i] : 0;
         int64_t gid = 0;
-        int64_t bpv[kMaxBp];
+        int64_t add[kMaxAggs];
 #pragma unroll
-        for (int j = 0; j < kMaxBp; ++j) {
-            bpv[j] = 0;
-            if (j >= P.n_bp) continue;
-            const BpCol& bc = P.bp[j];
-            const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
-            const int64_t bit = ((t0 * (int64_t)bc.w) & 31) + (int64_t)r * bc.w;
-            const int32_t q = (int32_t)(bit >> 5);
-            const uint32_t sh = (uint32_t)(bit & 31);
-            const uint64_t two = (uint64_t)st[q] | ((uint64_t)st[q + 1] << 32);
-            const uint64_t mask = bc.w == 32 ? 0xFFFFFFFFull : ((1ull << bc.w) - 1ull);
-            const uint32_t code = (uint32_t)((two >> sh) & mask);
-            bpv[j] = bc.base + (int64_t)code;
-            if (luts[j] >= 0) {
-                const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
-                if (e == kLutReject) pass = false;
-                else if (e == kLutDomain) dom = true;
-                else if (bc.key >= 0) gid += (int64_t)e * bc.key_stride;
+        for (int k = 0; k < kMaxAggs; ++k) add[k] = 0;
+        if (ok) {
+            bool pass = true;
+            bool dom = false;
+            int64_t bpv[kMaxBp];
+#pragma unroll
+            for (int j = 0; j < kMaxBp; ++j) {
+                bpv[j] = 0;
+                if (j >= P.n_bp) continue;
+                const BpCol& bc = P.bp[j];
+                const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
+                const int64_t bit = ((t0 * (int64_t)bc.w) & 31) + (int64_t)r * bc.w;
+                const int32_t q = (int32_t)(bit >> 5);
+                const uint32_t sh = (uint32_t)(bit & 31);
+                const uint64_t two = (uint64_t)st[q] | ((uint64_t)st[q + 1] << 32);
+                const uint64_t mask = bc.w == 32 ? 0xFFFFFFFFull : ((1ull << bc.w) - 1ull);
+                const uint32_t code = (uint32_t)((two >> sh) & mask);
+                bpv[j] = bc.base + (int64_t)code;
+                if (luts[j] >= 0) {
+                    const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
+                    if (e == kLutReject) pass = false;
+                    else if (e == kLutDomain) dom = true;
+                    else if (bc.key >= 0) gid += (int64_t)e * bc.key_stride;
+                } else {
+                    pass = pass && pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, bpv[j]);
+                    if (bc.key >= 0) {
+                        const int64_t kv = bpv[j] >> bc.key_shift;
+                        if (kv < 0 || kv >= bc.key_card) dom = true;
+                        else gid += kv * bc.key_stride;
+                    }
+                }
+            }
+            if (pass && W.rcl) {
+                // the row clause (Section 5.2, RLE mask OR Plain mask): its RLE
+                // rows, or a bit-packed part holding on this row's value
+                bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
+#pragma unroll
+                for (int j = 0; j < kMaxBp; ++j)
+                    if (j < P.n_bp && P.bp[j].or_pred != kPredNone)
+                        in = in || pred_pass(P.bp[j].or_pred, P.bp[j].or_lo, P.bp[j].or_hi, P.bp[j].or_set,
+                                             P.bp[j].or_set_len, bpv[j]);
+                pass = in;
+            }
+            int64_t rv[KMAX];
+            int32_t ridx[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                rv[c] = 0;
+                ridx[c] = 0;
+                if (pass && P.any_rle_row && c < P.k_rle) {
+                    ridx[c] = bm_run(W, c, r);
+                    if (P.rle[c].sum_slot >= 0) rv[c] = W.run_val[stage_base(P, c) + ridx[c]];
+                }
+            }
+            if (pass && P.any_rle_row) {
+                int64_t g2;
+                if (rle_key_part<KMAX>(P, W, ridx, &g2, status)) gid += g2;
+                else pass = false;
+            }
+            if (pass && dom) {
+                raise_status(status, -4);
+                pass = false;
+            }
+            ok = pass;
+            if (ok) {
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c)
+                    if (c < P.k_rle && P.rle[c].sum_slot >= 0) add[P.rle[c].sum_slot] = rv[c];
+#pragma unroll
+                for (int j = 0; j < kMaxBp; ++j)
+                    if (j < P.n_bp && P.bp[j].sum_slot >= 0) add[P.bp[j].sum_slot] = bpv[j];
+#pragma unroll
+                for (int j = 0; j < kMaxIdx; ++j) {
+                    if (j < P.n_idx && P.idx[j].sum_slot >= 0) {
+                        const uint32_t word = W.pts[j * 64 + (r >> 5)];
+                        if (word & (1u << (r & 31))) {
+                            const int64_t rank =
+                                W.ptpre[j * 64 + (r >> 5)] + __builtin_popcount(word & ((1u << (r & 31)) - 1u));
+                            add[P.idx[j].sum_slot] = ld_val(P.idx[j].vals, P.idx[j].vtype, pbase[j] + rank);
+                        }
+                    }
+                }
+            }
+        }
+        // Groups holding two or more of these 64 rows (Zipf-hot keys) are
+        // summed across the wave and added once, by the lowest lane holding
+        // them, in at most kPeelRounds rounds; every other row adds itself.
+        // This keeps hot groups from serialising the table's atomics.
+        uint64_t todo = wave_ballot(ok);
+        for (int round = 0; round < kPeelRounds && todo; ++round) {
+            const int leader = __builtin_ctzll(todo);
+            const int64_t g0 = __shfl(gid, leader, 64);
+            const bool mine = ((todo >> lane) & 1ull) && gid == g0;
+            const uint64_t same = wave_ballot(mine);
+            if (__builtin_popcountll(same) >= 2) {
+                if (lane == leader) table_add(tb, 0, g0, __builtin_popcountll(same));
+                for (int k = 0; k < P.n_sums; ++k) {
+                    const int64_t tot = wave_sum64(mine ? add[k] : 0);
+                    if (lane == leader && tot != 0) table_add(tb, 1 + k, g0, tot);
+                }
+                if (mine) ok = false;
+                todo &= ~same;
             } else {
-                pass = pass && pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, bpv[j]);
-                if (bc.key >= 0) {
-                    const int64_t kv = bpv[j] >> bc.key_shift;
-                    if (kv < 0 || kv >= bc.key_card) dom = true;
-                    else gid += kv * bc.key_stride;
-                }
+                todo &= todo - 1;     // the leader's group has this row only: it adds itself
             }
         }
-        if (!pass) continue;
-        if (W.rcl) {
-            // the row clause (Section 5.2, RLE mask OR Plain mask): its RLE
-            // rows, or a bit-packed part holding on this row's value
-            bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
-#pragma unroll
-            for (int j = 0; j < kMaxBp; ++j)
-                if (j < P.n_bp && P.bp[j].or_pred != kPredNone)
-                    in = in || pred_pass(P.bp[j].or_pred, P.bp[j].or_lo, P.bp[j].or_hi, P.bp[j].or_set,
-                                         P.bp[j].or_set_len, bpv[j]);
-            if (!in) continue;
-        }
-        int64_t rv[KMAX];
-        int32_t ridx[KMAX];
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            rv[c] = 0;
-            ridx[c] = 0;
-            if (P.any_rle_row && c < P.k_rle) {
-                ridx[c] = bm_run(W, c, r);
-                if (P.rle[c].sum_slot >= 0) rv[c] = W.run_val[stage_base(P, c) + ridx[c]];
-            }
-        }
-        if (P.any_rle_row) {
-            int64_t g2;
-            if (!rle_key_part<KMAX>(P, W, ridx, &g2, status)) continue;
-            gid += g2;
-        }
-        if (dom) {
-            raise_status(status, -4);
-            continue;
-        }
-        table_add(tb, 0, gid, 1);
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c)
-            if (c < P.k_rle && P.rle[c].sum_slot >= 0) table_add(tb, 1 + P.rle[c].sum_slot, gid, rv[c]);
-#pragma unroll
-        for (int j = 0; j < kMaxBp; ++j)
-            if (j < P.n_bp && P.bp[j].sum_slot >= 0) table_add(tb, 1 + P.bp[j].sum_slot, gid, bpv[j]);
-#pragma unroll
-        for (int j = 0; j < kMaxIdx; ++j) {
-            if (j < P.n_idx && P.idx[j].sum_slot >= 0) {
-                const uint32_t word = W.pts[j * 64 + (r >> 5)];
-                if (word & (1u << (r & 31))) {
-                    const int64_t rank =
-                        W.ptpre[j * 64 + (r >> 5)] + __builtin_popcount(word & ((1u << (r & 31)) - 1u));
-                    const int64_t v = ld_val(P.idx[j].vals, P.idx[j].vtype, pbase[j] + rank);
-                    if (v != 0) table_add(tb, 1 + P.idx[j].sum_slot, gid, v);
-                }
-            }
+        if (ok) {
+            table_add(tb, 0, gid, 1);
+            for (int k = 0; k < P.n_sums; ++k)
+                if (add[k] != 0) table_add(tb, 1 + k, gid, add[k]);
         }
     }
     wave_lds_sync();
