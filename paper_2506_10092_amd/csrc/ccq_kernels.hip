@@ -1472,7 +1472,7 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
     return v;
 }
 
-constexpr int kPeelRounds = 8;
+constexpr int kPeelRounds = 16;
 
 template <int KMAX>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
