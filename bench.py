@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark: one filter / group-by / aggregate query over lightweight-encoded
-columns, resident in HBM, per step.
+"""Benchmark: filter / group-by / aggregate queries over lightweight-encoded
+columns resident in HBM.
 
-Default workload (mixed encodings, 1e9 logical rows): RLE int32 columns r0,
-r1 (lognormal runs, means 64 / 200, values uniform in [0, 2^16)), an
+Default workload (the batched form against the plain path): one table of
+1e8 logical rows with the mixed-encoding columns -- RLE int32 r0, r1, r2
+(lognormal runs, means 64 / 200 / 1000, values uniform in [0, 2^16)), an
 index-encoded int64 column s (1% of rows), dictionary codes d (Zipf s=1.1
-over 10k entries) packed to 14 bits;
-    SELECT d, SUM(s), COUNT(*) WHERE r0 IN [0,32768) AND r1 IN [16384,65536)
-    AND d IN (50 codes) GROUP BY d.
-A step is one ccq_execute (clear, fused kernel, finalize) on one stream.
+over 10k entries, 14 bits) and a 20-bit plain column p -- and 4096 seeded
+query templates (windows log-uniform in [1e4, 1e8] rows; 1-3 predicates,
+1-2 aggregates, GROUP BY none, d or an RLE value >> shift).  A step is one
+execution of the whole batch (work-item size autotuned, replayed as a
+hipGraph); the same 4096 queries as 4096 single launches are timed beside
+it.  Every answer is checked against the CPU oracle, which is timed on the
+host's cores as the CPU baseline.
 
-Prints one JSON line: logical rows/s; the fused kernel's achieved
+--config c2 | c3 | c1: one query per step (single-launch path), the
+1e9-row mixed-encoding GROUP BY d query, the 1e10-row four-key RLE GROUP
+BY, or the 1e6-row two-column query.  --config c5: the serving loop.
+
+Prints one JSON line: logical rows/s; the persistent kernels' achieved
 compressed-bytes bandwidth against the 8 TB/s HBM peak (bytes = the encoded
-bytes of the referenced columns inside the window); the CPU oracle timed on
-the host's cores on a bounded sample, whose answer must equal the GPU's.
+bytes each query references inside its window); the CPU oracle's rate.
 """
 import argparse
 import hashlib
@@ -29,7 +36,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "logical rows/s + HBM GB/s (% of peak); batched p50/p99 latency vs plain path"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2506_10092_amd", "csrc", f)
-                  for f in ("ccq_kernels.hip", "ccq_plan.h", "ccq_api.cpp")]
+                  for f in ("ccq_device.h", "ccq_inst.hip", "ccq_kernels.hip", "ccq_plan.h", "ccq_api.cpp")]
 
 
 def log(*a):
@@ -83,10 +90,11 @@ def make_workload(name, rows):
     raise SystemExit("unknown --config %s" % name)
 
 
-def traffic_from_profile(workload_name):
-    """HBM bytes per fused-kernel launch from the committed rocprofv3 counter
-    summary, or None when it is missing or was taken on other kernel code."""
-    path = os.path.join(ROOT, "profiles", "k_fused_%s_traffic.json" % workload_name)
+def traffic_from_profile(kernel, workload_name):
+    """HBM bytes per launch of `kernel` on a workload from the committed
+    rocprofv3 counter summary, or None when it is missing or was taken on
+    other kernel code."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload_name))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -94,6 +102,30 @@ def traffic_from_profile(workload_name):
     if d.get("kernel_sha") != kernel_hash():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def cpu_threads():
+    """Host threads the CPU oracle may use: this process's CPU share (at
+    most 16, a one-GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def oracle_check(table, queries, answers, what):
+    """Every answer against the CPU oracle (exits on the first mismatch);
+    returns (rows, seconds, threads) of the oracle work."""
+    from oracle import oracle
+    threads = cpu_threads()
+    rows, t0 = 0, time.time()
+    for i, (q, got) in enumerate(zip(queries, answers)):
+        exp = oracle.run(table, q, n_threads=threads)
+        if got["status"] != 0 or any(got[k] != exp[k] for k in ("keys", "counts", "aggs")):
+            raise SystemExit("%s: query %d differs from the CPU oracle (status %d): %r" % (what, i, got["status"], q))
+        rows += q["window"][1] - q["window"][0]
+    return rows, time.time() - t0, threads
 
 
 def copy_reference(args):
@@ -119,14 +151,15 @@ def copy_reference(args):
 def bench_batch(args):
     """Many queries in one batched launch sequence (autotuned work items,
     replayed as a hipGraph) against the single-launch path (one ccq_execute
-    per query), over one resident table."""
+    per query), over one resident table; every answer is checked against
+    the CPU oracle."""
     import torch
     import datagen
     from paper_2506_10092_amd import ccq
 
     n_rows = args.rows or 100_000_000
     t_gen = time.time()
-    t = datagen.config_c2(seed=4, n_rows=n_rows, columns=("r0", "r1", "r2", "s", "d", "p"))
+    t = datagen.config_c2(seed=4, n_rows=n_rows, columns=datagen.C2_COLS)
     qs = datagen.c4_queries(4, n_rows, n_queries=args.queries)
     log("generated table + %d queries in %.1fs" % (len(qs), time.time() - t_gen))
     ctx = ccq.Context(0)
@@ -137,7 +170,8 @@ def bench_batch(args):
     alg = sum(algorithmic_bytes(t, q) for q in qs)
     stream = torch.cuda.Stream()
 
-    # single-launch path: one ccq_execute per query, each with its own buffers
+    # single-launch path: one ccq_execute per query, each with its own
+    # buffers; one untimed pass, then one timed pass
     wss = [p.new_workspace() for p in plans]
     res = [p.new_result() for p in plans]
     with torch.cuda.stream(stream):
@@ -163,17 +197,49 @@ def bench_batch(args):
         for _ in range(args.warmup):
             batch.execute(ws, stream)
     stream.synchronize()
+    # the step: whole-batch graph replays
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         e0.record(stream)
         for _ in range(args.steps):
             batch.execute(ws, stream)
         e1.record(stream)
     stream.synchronize()
+    torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    if batch.to_python() != single:
+    got = batch.to_python()
+    if got != single:
         raise SystemExit("batched results differ from the single-launch path")
-    log("batch %.3f ms per batch of %d queries; results equal the single-launch path" % (ms, len(qs)))
+    # the persistent launches alone (the dominant kernels), timed with events
+    # recorded on the launch stream around them
+    K = args.steps
+    fb = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    fe = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for e in fb + fe:
+        e.record(stream)
+    stream.synchronize()
+    with torch.cuda.stream(stream):
+        for i in range(K):
+            batch.execute(ws, stream, fused_events=(fb[i], fe[i]))
+    stream.synchronize()
+    kernel_ms = sum(fb[i].elapsed_time(fe[i]) for i in range(K)) / K
+    if batch.to_python() != single:
+        raise SystemExit("batched results (direct launches) differ from the single-launch path")
+    log("batch %.3f ms per batch of %d queries (persistent launches %.3f ms); equal to the single-launch path"
+        % (ms, len(qs), kernel_ms))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        o_rows, o_s, threads = oracle_check(t, qs, got, "c4 batch")
+        cpu = {"value": o_rows / o_s, "unit": "rows/s", "cores": threads, "kind": "oracle",
+               "sample": "all %d queries of the batch (%d logical rows), %.1f s wall; every batched answer "
+                         "equal to the oracle's bit for bit" % (len(qs), o_rows, o_s)}
+        log("cpu oracle: %d queries in %.1f s, all equal" % (len(qs), o_s))
+
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    wl_name = "c4_batch_%d_over_%g" % (len(qs), n_rows)
+    traffic = traffic_from_profile("k_batch", wl_name)
     out = {
         "metric": METRIC,
         "value": rows / (ms * 1e-3),
@@ -187,14 +253,17 @@ def bench_batch(args):
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": "c4_batch_%d_over_%g" % (len(qs), n_rows), "rows": rows,
-                   "compressed_bytes": alg, "tiles_per_item": best, "graph": True},
-        "roofline": {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "whole batch (clear + persistent launches + finalize)", "kernel_ms": ms},
+        "config": {"workload": wl_name, "queries": len(qs), "table_rows": n_rows, "rows": rows,
+                   "compressed_bytes": alg, "tiles_per_item": best, "graph": True,
+                   "step": "one batched execution of all queries (hipGraph replay)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_frac": (traffic / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "kernel": "ccq::k_batch (the batch's persistent launches, timed together)",
+                     "kernel_ms": kernel_ms},
         "single_launch": {"ms": single_ms, "rows_per_s": rows / (single_ms * 1e-3),
-                          "speedup_of_batch": single_ms / ms},
-        "cpu_baseline": None,
+                          "GBps": alg / (single_ms * 1e-3) / 1e9, "speedup_of_batch": single_ms / ms},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -234,12 +303,13 @@ def bench_serve(args):
     sizes = [max(1_000_000, int(round(args.serve_scale * 1e7 * 10 ** (3 * i / 7)))) for i in range(8)]
     cols = ("r0", "r1", "r2", "s", "d", "p")
     ctx = ccq.Context(0)
-    tables, light = [], []
+    tables, light, host = [], [], []
     t_gen = time.time()
     for i, n in enumerate(sizes):
         t = datagen.config_c2(seed=50 + i, n_rows=n, columns=cols)
         tables.append(ccq.Table(ctx, n, ccq.to_device(t["columns"])))
         light.append(_light_table(t))
+        host.append(t if not args.no_cpu_baseline else None)   # kept for the oracle check
         del t
         log("table %d: %d rows resident (%.1fs)" % (i, n, time.time() - t_gen))
     torch.cuda.synchronize()
@@ -307,6 +377,21 @@ def bench_serve(args):
                 answers[mode] = [r.to_python() for r in results]
     if answers["batched"] != answers["single_launch"]:
         raise SystemExit("served results differ between the batched and the single-launch server")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # a seeded sample of the served answers against the CPU oracle
+        pick = sorted(np.random.default_rng([7, 7777]).choice(n_q, size=min(args.serve_check, n_q), replace=False))
+        o_rows, o_s, threads = 0, 0.0, 1
+        for k in pick:
+            i, q = queries[k]
+            r, s_, threads = oracle_check(host[i], [q], [answers["batched"][k]], "c5 served query %d" % k)
+            o_rows += r
+            o_s += s_
+        cpu = {"value": o_rows / o_s, "unit": "rows/s", "cores": threads, "kind": "oracle",
+               "sample": "%d served queries drawn at random (seeded) from the %d of the first arrival rate, "
+                         "%d logical rows, %.1f s wall; every sampled answer equal to the oracle's bit for bit"
+                         % (len(pick), n_q, o_rows, o_s)}
+        log("cpu oracle: %d sampled served answers equal (%.1f s)" % (len(pick), o_s))
     top = "%g" % levels[-1]
     b = report["batched"][top]
     out = {
@@ -330,10 +415,23 @@ def bench_serve(args):
         "p99_ms": b["p99_ms"],
         "single_launch_p50_ms": report["single_launch"][top]["p50_ms"],
         "single_launch_p99_ms": report["single_launch"][top]["p99_ms"],
-        "roofline": None,
-        "cpu_baseline": None,
+        "roofline": {"bound": "hbm", "achieved": b["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": b["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole served load at the top arrival rate (encoded bytes of the completed "
+                               "queries / wall time)"},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def describe_query(wl, query, flt):
+    """A short text of a single-launch workload's filter and grouping."""
+    if wl["name"].startswith("c2"):
+        return {"and": "r0 range AND r1 range AND d IN", "not": "NOT r0 range AND r1 range AND d IN",
+                "or": "(r0 range OR r1 range) AND d IN", "or_dict": "r1 range AND (r0 range OR d IN)"}[flt]
+    if wl["name"].startswith("c3"):
+        return "no filter; GROUP BY k0, k1, k2, k3 -> SUM(m), COUNT(*)"
+    return "a < 500 -> SUM(b), COUNT(*)"
 
 
 def main():
@@ -341,7 +439,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--queries", type=int, default=4096, help="c4: queries per batch")
     ap.add_argument("--serve-queries", type=int, default=10000, help="c5: queries per arrival rate (after warm-up)")
     ap.add_argument("--serve-warmup", type=int, default=500, help="c5: leading queries left out of the statistics")
@@ -350,6 +448,7 @@ def main():
     ap.add_argument("--serve-inflight", type=int, default=512, help="c5: queries admitted or running at once")
     ap.add_argument("--serve-tpi", type=int, default=64, help="c5: batch work-item size in tiles")
     ap.add_argument("--qps", default="200,1000,5000", help="c5: Poisson arrival rates")
+    ap.add_argument("--serve-check", type=int, default=1000, help="c5: served answers checked against the oracle")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
     ap.add_argument("--filter", default="and", choices=["and", "not", "or", "or_dict"],
                     help="c2: the workload's filter (and), or the same table under a filter with NOT "
@@ -440,7 +539,7 @@ def main():
     rows = n1 - n0
     alg = algorithmic_bytes(wl, query)
     achieved = alg / (fused_avg * 1e-3) / 1e9
-    traffic = traffic_from_profile(wl["name"]) if args.filter == "and" else None
+    traffic = traffic_from_profile("k_fused", wl["name"]) if args.filter == "and" else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -485,11 +584,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "rows": rows, "groups": len(gpu_result["keys"]),
                    "compressed_bytes": alg, "query": "single-launch path, one query per ccq_execute",
-                   "filter": {"and": "r0 range AND r1 range AND d IN", "not": "NOT r0 range AND r1 range AND d IN",
-                              "or": "(r0 range OR r1 range) AND d IN",
-                              "or_dict": "r1 range AND (r0 range OR d IN)"}[args.filter]},
+                   "filter": describe_query(wl, query, args.filter)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_frac": (traffic / (fused_avg * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
                      "kernel": "ccq::k_fused", "kernel_ms": fused_avg},
         "cpu_baseline": cpu,
     }

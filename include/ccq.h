@@ -183,7 +183,13 @@ void ccq_table_destroy(ccq_table* t);                    /* NULL-safe; plans kee
 
 /* Check on the device that run ends are strictly increasing with the last
  * equal to n_rows and that positions are strictly increasing in range.
- * Synchronises `stream`; returns CCQ_OK or CCQ_E_INVALID. */
+ * Synchronises `stream`; returns CCQ_OK or CCQ_E_INVALID (naming the first
+ * bad column).  It only reads inside each column's arrays.
+ * Precondition of every execution: the kernels trust run ends and positions
+ * (they index LDS tiles and packed words by them), so running a plan on a
+ * table whose columns break these rules is undefined behaviour (wrong
+ * results or faulting accesses).  Callers that did not build the columns
+ * themselves should validate the table once, before its first execution. */
 ccq_status ccq_table_validate(ccq_table* t, void* stream);
 
 /* Compile a query against a table: validates the query, folds predicates
@@ -252,6 +258,14 @@ ccq_status ccq_batch_set_tiles_per_item(ccq_batch* b, int32_t tiles_per_item);
 
 /* Run every query of the batch on `stream`; asynchronous like ccq_execute. */
 ccq_status ccq_batch_execute(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ccq_batch_execute with options (opts may be NULL).  With events set, the
+ * fused_begin / fused_end events of ccq_exec_opts are recorded on `stream`
+ * right before the first and after the last persistent launch of the batch,
+ * so those launches can be timed together; such an execution is launched
+ * directly, never replayed from the captured graph. */
+ccq_status ccq_batch_execute_ex(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream,
+                                const ccq_exec_opts* opts);
 
 /* Time each candidate work-item size (reps executions each, after one warm-up;
  * synchronises `stream`), keep the fastest by median, report it and its time. */

@@ -122,6 +122,7 @@ SIGNATURES = {
     "ccq_batch_info": (_i32, [_vp, ctypes.POINTER(_sz), ctypes.POINTER(_i64)]),
     "ccq_batch_set_tiles_per_item": (_i32, [_vp, _i32]),
     "ccq_batch_execute": (_i32, [_vp, _vp, _sz, _vp]),
+    "ccq_batch_execute_ex": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ExecOpts)]),
     "ccq_batch_autotune": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(_i32), _i32, _i32, ctypes.POINTER(_i32),
                                   ctypes.POINTER(ctypes.c_float)]),
     "ccq_now": (ctypes.c_double, []),
@@ -398,9 +399,17 @@ class Batch:
         _check(lib().ccq_batch_set_tiles_per_item(self.h, int(t)))
         self._refresh_info()
 
-    def execute(self, workspace, stream=None):
-        _check(lib().ccq_batch_execute(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                                       _stream_ptr(stream)))
+    def execute(self, workspace, stream=None, fused_events=None):
+        """Enqueue the batch on `stream`.  fused_events: optional (begin, end)
+        torch.cuda.Event pair recorded around the batch's persistent launches
+        (such an execution is launched directly, not replayed from a graph)."""
+        if fused_events is None:
+            _check(lib().ccq_batch_execute(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                           _stream_ptr(stream)))
+            return
+        opts = ExecOpts(_event_handle(fused_events[0], stream), _event_handle(fused_events[1], stream))
+        _check(lib().ccq_batch_execute_ex(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                          _stream_ptr(stream), ctypes.byref(opts)))
 
     def autotune(self, workspace, candidates=(8, 32, 128, 512), reps=3, stream=None):
         arr = (ctypes.c_int32 * len(candidates))(*candidates)

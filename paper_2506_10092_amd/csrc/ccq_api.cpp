@@ -142,23 +142,24 @@ ccq_status ccq_table_validate(ccq_table* t, void* stream) {
     hipError_t e = hipSetDevice(t->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    int32_t* flag = nullptr;
-    e = hipMalloc(&flag, sizeof(int32_t) * 64);
+    const size_t nc = std::max<size_t>(t->cols.size(), 1);
+    int32_t* flag = nullptr;                    // one flag per column
+    e = hipMalloc(&flag, sizeof(int32_t) * nc);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
-    int32_t host[64] = {0};
-    e = hipMemcpyAsync(flag, host, sizeof host, hipMemcpyHostToDevice, s);
+    std::vector<int32_t> host(nc, 0);
+    e = hipMemcpyAsync(flag, host.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s);
     for (size_t i = 0; i < t->cols.size() && e == hipSuccess; ++i) {
         const ccq_column_desc& c = t->cols[i];
-        if (c.encoding == CCQ_RLE && c.n_entries > 0) e = launch_validate_rle(c.run_ends, c.n_entries, t->n_rows, flag + (i % 64), s);
+        if (c.encoding == CCQ_RLE && c.n_entries > 0) e = launch_validate_rle(c.run_ends, c.n_entries, t->n_rows, flag + i, s);
         if (c.encoding == CCQ_INDEX && c.n_entries > 0)
-            e = launch_validate_idx(c.positions, c.position_type, c.n_entries, t->n_rows, flag + (i % 64), s);
+            e = launch_validate_idx(c.positions, c.position_type, c.n_entries, t->n_rows, flag + i, s);
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(host, flag, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), flag, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(flag);
     if (e != hipSuccess) return hip_fail(e, "table validation");
     for (size_t i = 0; i < t->cols.size(); ++i)
-        if (host[i % 64]) return fail(CCQ_E_INVALID, "column %zu: run ends or positions are not valid", i);
+        if (host[i]) return fail(CCQ_E_INVALID, "column %zu: run ends or positions are not valid", i);
     return ok();
 }
 

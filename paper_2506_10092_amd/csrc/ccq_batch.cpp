@@ -147,10 +147,11 @@ ccq_status build_items(ccq_batch* b) {
     return CCQ_OK;
 }
 
-ccq_status launch(ccq_batch* b, unsigned char* ws, hipStream_t s) {
+ccq_status launch(ccq_batch* b, unsigned char* ws, hipStream_t s, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr) {
     hipError_t e = launch_batch(b->host, (const BatchDev*)b->dblob, b->plans_host.data(), b->plans_dev.data(),
                                 b->region.data(), b->outs.data(), ws, b->group_grid.data(), b->group_lds.data(),
-                                b->big.data(), (int32_t)b->big.size(), s);
+                                b->big.data(), (int32_t)b->big.size(), s, ev0, ev1);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return CCQ_OK;
 }
@@ -163,6 +164,8 @@ ccq_status ccq_batch_create(ccq_context* ctx, const ccq_plan* const* plans, int3
                             const ccq_batch_opts* opts, ccq_batch** out) {
     if (!out) return fail(CCQ_E_INVALID, "out is NULL");
     *out = nullptr;
+    if (opts && (opts->tiles_per_item < 0 || opts->tiles_per_item > kMaxTilesPerItem))
+        return fail(CCQ_E_INVALID, "tiles_per_item must be in 0..%d", (int)kMaxTilesPerItem);
     if (!ctx || ctx->device < 0) return fail(CCQ_E_INVALID, "batch needs a device context");
     if (n < 0 || (n > 0 && (!plans || !results))) return fail(CCQ_E_INVALID, "bad plan / result arrays");
     for (int i = 0; i < n; ++i) {
@@ -244,7 +247,8 @@ ccq_status ccq_batch_info(const ccq_batch* b, size_t* workspace_bytes, int64_t* 
 
 ccq_status ccq_batch_set_tiles_per_item(ccq_batch* b, int32_t tiles_per_item) {
     if (!b) return fail(CCQ_E_INVALID, "batch is NULL");
-    if (tiles_per_item < 1) return fail(CCQ_E_INVALID, "tiles_per_item must be >= 1");
+    if (tiles_per_item < 1 || tiles_per_item > kMaxTilesPerItem)
+        return fail(CCQ_E_INVALID, "tiles_per_item must be in 1..%d", (int)kMaxTilesPerItem);
     hipError_t e = hipSetDevice(b->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     b->tiles_per_item = tiles_per_item;
@@ -253,6 +257,11 @@ ccq_status ccq_batch_set_tiles_per_item(ccq_batch* b, int32_t tiles_per_item) {
 }
 
 ccq_status ccq_batch_execute(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream) {
+    return ccq_batch_execute_ex(b, workspace, workspace_bytes, stream, nullptr);
+}
+
+ccq_status ccq_batch_execute_ex(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream,
+                                const ccq_exec_opts* opts) {
     if (!b) return fail(CCQ_E_INVALID, "batch is NULL");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(CCQ_E_INVALID, "workspace must be 256-byte aligned");
     if (workspace_bytes < b->ws_total)
@@ -261,8 +270,11 @@ ccq_status ccq_batch_execute(ccq_batch* b, void* workspace, size_t workspace_byt
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     unsigned char* ws = (unsigned char*)workspace;
-    if (!b->use_graph || s == nullptr) {
-        if (ccq_status st = launch(b, ws, s)) return st;
+    const bool timed = opts && (opts->fused_begin || opts->fused_end);
+    if (!b->use_graph || s == nullptr || timed) {
+        if (ccq_status st = launch(b, ws, s, opts ? (hipEvent_t)opts->fused_begin : nullptr,
+                                   opts ? (hipEvent_t)opts->fused_end : nullptr))
+            return st;
         return ok();
     }
     if (!b->gexec || b->g_ws != workspace || b->g_stream != s) {

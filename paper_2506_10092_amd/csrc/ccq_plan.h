@@ -213,13 +213,20 @@ struct BatchDev {
 // workgroup per query, then the multi-block finalize for the queries listed
 // in big (group tables over kBatchFinMaxGroups ids).  Host arrays:
 // plans_host (host copies), plans_dev (device plan pointers), region, outs.
+// ev_begin / ev_end (or null): recorded right before the first and after
+// the last persistent launch.
 hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan* const* plans_host,
                         const DevPlan* const* plans_dev, const int64_t* region, const BatchOut* outs,
                         unsigned char* ws, const int* group_grid, const int* group_lds, const int32_t* big,
-                        int32_t n_big, hipStream_t stream);
+                        int32_t n_big, hipStream_t stream, hipEvent_t ev_begin = nullptr,
+                        hipEvent_t ev_end = nullptr);
 
 // Persistent-grid size and dynamic LDS of a batch kernel instance.
 int batch_grid_limit(int kmax, int w0, int big, int lds_bytes, int cus);
+
+// Largest work item, in 2048-row tiles: one workgroup counts an item's rows
+// in uint32 LDS counters, so an item stays below 2^31 rows.
+constexpr int32_t kMaxTilesPerItem = int32_t(1) << 19;
 
 // Largest group count the single-workgroup batched finalize handles.
 constexpr int64_t kBatchFinMaxGroups = int64_t(1) << 20;
@@ -240,6 +247,18 @@ WsLayout workspace_layout(const DevPlan& p);
 hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
                         int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
                         int grid_fused, hipEvent_t ev_begin, hipEvent_t ev_end);
+
+// Kernel instances (ccq_inst.hip, one object per RLE-column bound 2 / 4 / 8):
+// w0 = 0 for the staged paths, 14 or 20 for the fast row path; big = that
+// path with a large table.
+typedef void (*FusedFn)(const DevPlan*, int64_t*, int32_t*, int64_t);
+typedef void (*BatchFn)(const BatchDev*, int32_t, unsigned char*);
+FusedFn fused_kernel_k2(int w0, bool big);
+FusedFn fused_kernel_k4(int w0, bool big);
+FusedFn fused_kernel_k8(int w0, bool big);
+BatchFn batch_kernel_k2(int w0, bool big);
+BatchFn batch_kernel_k4(int w0, bool big);
+BatchFn batch_kernel_k8(int w0, bool big);
 
 // Device validation of one column; writes a nonzero flag on failure.
 hipError_t launch_validate_rle(const int64_t* ends, int64_t n, int64_t n_rows, int32_t* flag, hipStream_t s);

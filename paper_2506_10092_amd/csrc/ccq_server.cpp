@@ -345,9 +345,11 @@ double ccq_now(void) { return now_s(); }
 ccq_status ccq_server_create(ccq_context* ctx, const ccq_server_config* cfg, ccq_server** out) {
     if (!out) return fail(CCQ_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (!ctx || ctx->device < 0) return fail(CCQ_E_INVALID, "server needs a device context");
     if (!cfg || cfg->hbm_budget_bytes < 4096 || cfg->max_inflight < 1)
         return fail(CCQ_E_INVALID, "config needs hbm_budget_bytes >= 4096 and max_inflight >= 1");
+    if (cfg->tiles_per_item < 0 || cfg->tiles_per_item > kMaxTilesPerItem)
+        return fail(CCQ_E_INVALID, "tiles_per_item must be in 0..%d", (int)kMaxTilesPerItem);
+    if (!ctx || ctx->device < 0) return fail(CCQ_E_INVALID, "server needs a device context");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     ccq_server* s = new (std::nothrow) ccq_server;

@@ -166,3 +166,21 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(ccq, "_lib", None)
     with pytest.raises(ccq.CcqError, match="not built"):
         ccq.lib()
+
+
+def test_work_item_size_is_capped():
+    """A work item is counted by one workgroup in uint32 LDS counters, so the
+    batch and the server reject items of 2^19 tiles (2^30 rows) or more
+    before anything else (the check needs no device)."""
+    L = ccq.lib()
+    ctx = ccq.Context(ccq.HOST_ONLY)
+    h = ccq.ctypes.c_void_p()
+    opts = ccq.BatchOpts(1 << 20, 0)
+    assert L.ccq_batch_create(ctx.h, None, 0, None, ccq.ctypes.byref(opts), ccq.ctypes.byref(h)) == ccq.E_INVALID
+    assert b"tiles_per_item" in L.ccq_last_error()
+    opts = ccq.BatchOpts(1 << 19, 0)      # the largest item size passes this check
+    assert L.ccq_batch_create(ctx.h, None, 0, None, ccq.ctypes.byref(opts), ccq.ctypes.byref(h)) == ccq.E_INVALID
+    assert b"device context" in L.ccq_last_error()
+    cfg = ccq.ServerConfig(1 << 30, 8, 0, 1, 1, (1 << 19) + 1, 0)
+    assert L.ccq_server_create(ctx.h, ccq.ctypes.byref(cfg), ccq.ctypes.byref(h)) == ccq.E_INVALID
+    assert b"tiles_per_item" in L.ccq_last_error()

@@ -461,3 +461,32 @@ def test_not_on_fast_path_and_generic_paths(ctx):
             qq = dict(q, window=window)
             say("NOT query", qq["preds"], window)
             check(ctx, t, qq)
+
+
+def test_table_validate_rejects_malformed_columns(ctx):
+    """ccq_table_validate: well-formed columns pass; run ends that do not
+    increase, a last run end other than the row count and a position out of
+    range are rejected, naming the column (also past the 64th)."""
+    import torch
+    from paper_2506_10092_amd import ccq
+    n = 1000
+    t = lambda a, dt: torch.tensor(a, dtype=dt, device="cuda")
+
+    def table(bad_col=None, bad=None):
+        cols = {}
+        for i in range(70):
+            cols["c%d" % i] = {"enc": "rle", "values": t([1, 2, 3], torch.int32), "run_ends": t([10, 500, n], torch.int64)}
+        cols["s"] = {"enc": "index", "positions": t([3, 7, 999], torch.int32), "values": t([1, 2, 3], torch.int64)}
+        if bad_col is not None:
+            cols[bad_col] = bad
+        return ccq.Table(ctx, n, cols)
+
+    table().validate()
+    cases = [("c3", {"enc": "rle", "values": t([1, 2, 3], torch.int32), "run_ends": t([10, 10, n], torch.int64)}, 3),
+             ("c68", {"enc": "rle", "values": t([1, 2], torch.int32), "run_ends": t([10, n - 1], torch.int64)}, 68),
+             ("s", {"enc": "index", "positions": t([3, 7, n], torch.int32), "values": t([1, 2, 3], torch.int64)}, 70),
+             ("s", {"enc": "index", "positions": t([3, 3, 9], torch.int32), "values": t([1, 2, 3], torch.int64)}, 70)]
+    for name, bad, idx in cases:
+        with pytest.raises(ccq.CcqError, match="column %d:" % idx):
+            table(name, bad).validate()
+    say("table validation: good table passes, %d malformed columns rejected" % len(cases))

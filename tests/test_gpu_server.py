@@ -1,14 +1,16 @@
 """Serving loop (ccq_server_*): every query answered through the server --
 batched or one launch per query, submitted from one thread or several, with
-the HBM budget forcing admission to wait -- must give exactly what its own
-ccq_execute gives; a query whose workspace exceeds the budget completes with
-CCQ_E_BUDGET and does not disturb the others."""
+the HBM budget forcing admission to wait -- must give exactly the CPU
+oracle's answer (and so what its own ccq_execute gives, alone); a query whose
+workspace exceeds the budget completes with CCQ_E_BUDGET and does not
+disturb the others."""
 import sys
 import threading
 
 import pytest
 
 import datagen
+from oracle import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +32,14 @@ def setup():
     plans = [ccq.Plan(table, q) for q in qs]
     single = [p.run() for p in plans]
     torch.cuda.synchronize()
-    return {"ctx": ctx, "table": table, "plans": plans, "single": single}
+    # the expected answers come from the CPU oracle; each query alone
+    # (ccq_execute) must give them too
+    expect = []
+    for q in qs:
+        e = oracle.run(t, q)
+        expect.append({"keys": e["keys"], "counts": e["counts"], "aggs": e["aggs"], "status": 0})
+    assert single == expect, "a query alone differs from the CPU oracle"
+    return {"ctx": ctx, "table": table, "plans": plans, "single": single, "expect": expect}
 
 
 def _serve(setup, server, plans, threads=1):
@@ -64,8 +73,8 @@ def test_server_matches_single_launch(setup, batching):
     comps, got = _serve(setup, s, setup["plans"])
     s.close()
     assert all(c["status"] == 0 for c in comps)
-    assert got == setup["single"]
-    say("server batching=%s: %d queries match" % (batching, len(got)))
+    assert got == setup["expect"], "a served answer differs from the CPU oracle"
+    say("server batching=%s: %d served answers equal the oracle's" % (batching, len(got)))
 
 
 def test_server_tight_budget_and_threads(setup):
@@ -76,7 +85,7 @@ def test_server_tight_budget_and_threads(setup):
     comps, got = _serve(setup, s, setup["plans"], threads=4)
     s.close()
     assert all(c["status"] == 0 for c in comps)
-    assert got == setup["single"]
+    assert got == setup["expect"]
 
 
 def test_server_budget_rejection(setup):
@@ -91,7 +100,7 @@ def test_server_budget_rejection(setup):
     comps, got = _serve(setup, s, plans)
     s.close()
     assert [c["status"] for c in comps] == [0, ccq.E_BUDGET, 0]
-    assert got[0] == setup["single"][0] and got[2] == setup["single"][1]
+    assert got[0] == setup["expect"][0] and got[2] == setup["expect"][1]
 
 
 def test_server_rejects_bad_config(setup):
