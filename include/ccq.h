@@ -230,6 +230,22 @@ typedef struct {
 ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
                           const ccq_result* result, const ccq_exec_opts* opts);
 
+/* ccq_execute without a caller workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The query's workspace is a fixed device array of
+ * CCQ_NOALLOC_WORKSPACE_BYTES that the library holds on every device it runs
+ * on until the process ends (its address is looked up when the context is
+ * created).  Nothing is allocated or freed: no hipMalloc / hipFree, no
+ * allocating library call.  The launch sequence clears what must start at
+ * zero (status header, group table) itself.  Every call on one device shares
+ * that array, so calls whose execution overlaps on one device (other streams,
+ * other threads, other contexts of the device) race and give wrong results;
+ * serialise them.  Returns CCQ_E_CAPACITY when the plan's workspace
+ * (ccq_plan_info) exceeds CCQ_NOALLOC_WORKSPACE_BYTES, and otherwise the
+ * codes of ccq_execute; results are identical to ccq_execute's. */
+#define CCQ_NOALLOC_WORKSPACE_BYTES ((size_t)32 << 20)
+ccq_status ccq_execute_noalloc(const ccq_plan* p, void* stream, const ccq_result* result);
+
 /* ---- batched execution: many queries, one launch sequence ----
  *
  * A batch runs n compiled plans (over any tables of one device) together:

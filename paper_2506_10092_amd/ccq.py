@@ -37,6 +37,8 @@ I32, I64 = 1, 2
 RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
 COUNT_STAR, SUM = 1, 2
 HOST_ONLY = -1
+# size of the fixed device scratch ccq_execute_noalloc uses as the workspace (include/ccq.h)
+NOALLOC_WORKSPACE_BYTES = 32 << 20
 
 _STATUS_NAMES = {0: "CCQ_OK", -1: "CCQ_E_INVALID", -2: "CCQ_E_UNSUPPORTED", -3: "CCQ_E_CAPACITY",
                  -4: "CCQ_E_KEY_DOMAIN", -5: "CCQ_E_HIP", -6: "CCQ_E_BUDGET", -7: "CCQ_E_BUSY", -8: "CCQ_E_NOMEM"}
@@ -116,6 +118,7 @@ SIGNATURES = {
     "ccq_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_sz)]),
     "ccq_execute": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc)]),
     "ccq_execute_ex": (_i32, [_vp, _vp, _sz, _vp, ctypes.POINTER(ResultDesc), ctypes.POINTER(ExecOpts)]),
+    "ccq_execute_noalloc": (_i32, [_vp, _vp, ctypes.POINTER(ResultDesc)]),
     "ccq_batch_create": (_i32, [_vp, ctypes.POINTER(_vp), _i32, ctypes.POINTER(ResultDesc), ctypes.POINTER(BatchOpts),
                                 ctypes.POINTER(_vp)]),
     "ccq_batch_destroy": (None, [_vp]),
@@ -354,6 +357,11 @@ class Plan:
         opts = ExecOpts(_event_handle(fused_events[0], stream), _event_handle(fused_events[1], stream))
         _check(lib().ccq_execute_ex(self.h, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                     _stream_ptr(stream), ctypes.byref(result.desc), ctypes.byref(opts)))
+
+    def execute_noalloc(self, result, stream=None):
+        """Enqueue the query on `stream` with the library's fixed device
+        scratch as its workspace (ccq_execute_noalloc)."""
+        _check(lib().ccq_execute_noalloc(self.h, _stream_ptr(stream), ctypes.byref(result.desc)))
 
     def run(self):
         """Execute once and return the result on the host."""

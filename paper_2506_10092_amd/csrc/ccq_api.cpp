@@ -65,6 +65,7 @@ ccq_status ccq_context_create(int32_t device, ccq_context** out) {
         c->device = -1;
         c->cus = 256;
         c->lds_per_block = 160 * 1024;
+        c->scratch = nullptr;
         *out = c;
         return ok();
     }
@@ -77,11 +78,18 @@ ccq_status ccq_context_create(int32_t device, ccq_context** out) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
         return fail(CCQ_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+    // the fixed scratch's address on this device (each device holds its own copy)
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void* scratch = nullptr;
+    e = scratch_address(&scratch);
+    if (e != hipSuccess || !scratch) return hip_fail(e, "hipGetSymbolAddress(scratch)");
     ccq_context* c = new (std::nothrow) ccq_context;
     if (!c) return fail(CCQ_E_NOMEM, "out of host memory");
     c->device = device;
     c->cus = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
+    c->scratch = scratch;
     *out = c;
     return ok();
 }
@@ -985,17 +993,27 @@ ccq_status ccq_execute(const ccq_plan* p, void* workspace, size_t workspace_byte
     return ccq_execute_ex(p, workspace, workspace_bytes, stream, r, nullptr);
 }
 
+namespace {
+
+// checks shared by the execute entry points (workspace checked by the caller)
+ccq_status check_result(const ccq_plan* p, const ccq_result* r) {
+    if (r->capacity < p->max_groups)
+        return fail(CCQ_E_CAPACITY, "result capacity %lld < max groups %lld", (long long)r->capacity,
+                    (long long)p->max_groups);
+    if (!r->counts || !r->n_groups || !r->status || (p->host.n_keys && !r->keys) || (p->host.n_aggs && !r->aggs))
+        return fail(CCQ_E_INVALID, "result buffers missing");
+    return CCQ_OK;
+}
+
+}  // namespace
+
 ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_bytes, void* stream,
                           const ccq_result* r, const ccq_exec_opts* opts) {
     if (!p || !r) return fail(CCQ_E_INVALID, "plan or result is NULL");
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(CCQ_E_INVALID, "workspace must be 256-byte aligned");
     if (workspace_bytes < p->ws.total)
         return fail(CCQ_E_CAPACITY, "workspace of %zu bytes, plan needs %zu", workspace_bytes, p->ws.total);
-    if (r->capacity < p->max_groups)
-        return fail(CCQ_E_CAPACITY, "result capacity %lld < max groups %lld", (long long)r->capacity,
-                    (long long)p->max_groups);
-    if (!r->counts || !r->n_groups || !r->status || (p->host.n_keys && !r->keys) || (p->host.n_aggs && !r->aggs))
-        return fail(CCQ_E_INVALID, "result buffers missing");
+    if (ccq_status s = check_result(p, r)) return s;
     hipError_t e = hipSetDevice(p->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     e = launch_query(p->host, p->dev, workspace, (hipStream_t)stream, r->keys, r->counts, r->aggs, r->n_groups,
@@ -1005,4 +1023,22 @@ ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_b
     return ok();
 }
 
+ccq_status ccq_execute_noalloc(const ccq_plan* p, void* stream, const ccq_result* r) {
+    if (!p || !r) return fail(CCQ_E_INVALID, "plan or result is NULL");
+    if (p->ws.total > kScratchBytes)
+        return fail(CCQ_E_CAPACITY, "plan needs a %zu-byte workspace; the fixed scratch holds %zu", p->ws.total,
+                    kScratchBytes);
+    if (!p->ctx->scratch) return fail(CCQ_E_INVALID, "context has no device scratch");
+    if (ccq_status s = check_result(p, r)) return s;
+    hipError_t e = hipSetDevice(p->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    // the launch sequence clears the status header and the group table itself
+    e = launch_query(p->host, p->dev, p->ctx->scratch, (hipStream_t)stream, r->keys, r->counts, r->aggs,
+                     r->n_groups, r->status, p->grid_fused, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return ok();
+}
+
 }  // extern "C"
+
+static_assert(ccq::kScratchBytes == CCQ_NOALLOC_WORKSPACE_BYTES, "fixed scratch size differs from the header's");

@@ -23,6 +23,7 @@ struct ccq_context {
     int device;
     int cus;
     size_t lds_per_block;
+    void* scratch;          // device address of the fixed scratch on this device (null: host only)
 };
 
 struct ccq_table {

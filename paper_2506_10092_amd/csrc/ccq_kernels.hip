@@ -240,6 +240,14 @@ int fused_grid_limit(const DevPlan& p, int cus) {
     return per_cu * cus;
 }
 
+// Fixed device scratch for callers that cannot allocate: one query's
+// workspace (status header, group table, finalize scan), shared by every
+// call on the device.  Host code never uses the array's name as an address:
+// scratch_address() looks the address up once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
+
 hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
                         int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
                         int grid_fused, hipEvent_t ev_begin, hipEvent_t ev_end) {

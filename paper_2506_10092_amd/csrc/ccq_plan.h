@@ -248,6 +248,11 @@ hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream
                         int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
                         int grid_fused, hipEvent_t ev_begin, hipEvent_t ev_end);
 
+// Size of the fixed device scratch that ccq_execute_noalloc uses as the
+// workspace, and the lookup of its address on the current device.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+hipError_t scratch_address(void** out);
+
 // Kernel instances (ccq_inst.hip, one object per RLE-column bound 2 / 4 / 8):
 // w0 = 0 for the staged paths, 14 or 20 for the fast row path; big = that
 // path with a large table.
