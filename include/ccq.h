@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 2
+#define CCQ_ABI_VERSION 3
 
 typedef int32_t ccq_status;
 enum {
@@ -92,6 +92,13 @@ typedef struct {
     int32_t bit_width;         /* BITPACKED: 1..32 */
     int32_t position_type;     /* INDEX: CCQ_I32 or CCQ_I64 */
     int64_t base;              /* BITPACKED: value = base + code */
+    const int64_t* dict_values;  /* BITPACKED, optional (NULL: none): device int64[dict_size], the
+                                  dictionary of a dictionary-encoded column (Section 2.1).  Predicates,
+                                  keys and the row order see the code value (base + code); a group key on
+                                  this column reports dict_values[key] in the result instead of the key.
+                                  Such a key needs shift 0 and card <= dict_size; SUM over the column is
+                                  CCQ_E_UNSUPPORTED.  Borrowed like the other column buffers. */
+    int64_t dict_size;         /* entries of dict_values (>= 1 when dict_values is set, else 0) */
 } ccq_column_desc;
 
 /* ---- query (Sections 5-7) ----

@@ -177,8 +177,18 @@ def run(table, query, n_threads=None):
         else:
             raise OracleError("unknown predicate %r" % (op,))
     keys = (OrcKey * max(len(query["keys"]), 1))()
+    dicts = []
     for i, k in enumerate(query["keys"]):
         keys[i].col, keys[i].shift, keys[i].card = col_id(k[0]), int(k[1]), int(k[2])
+        d = table["columns"][k[0]].get("dict")
+        if d is not None:
+            d = np.asarray(d, dtype=np.int64)
+            if int(k[1]) != 0 or int(k[2]) > len(d):
+                raise OracleError("a key on a dictionary column needs shift 0 and card <= the dictionary size")
+        dicts.append(d)
+    for a in query["aggs"]:
+        if a[0] == "sum" and table["columns"].get(a[1], {}).get("dict") is not None:
+            raise OracleError("SUM over a dictionary-encoded column")
     aggs = (OrcAgg * max(len(query["aggs"]), 1))()
     for i, a in enumerate(query["aggs"]):
         if a[0] == "count":
@@ -205,8 +215,15 @@ def run(table, query, n_threads=None):
         L.orc_copy(h, kb.ctypes.data, cb.ctypes.data, ab.ctypes.data)
     finally:
         L.orc_free(h)
+    # Dictionary encoding (Section 2.1) stores a code per row and the
+    # distinct values once: a key on such a column is a code, and the result
+    # reports the value the code stands for, dict[code].  Groups keep the
+    # order of their codes.
+    def decode(j, x):
+        return int(x) if dicts[j] is None else int(dicts[j][int(x)])
+
     return {
-        "keys": [tuple(int(x) for x in kb[i * nk:(i + 1) * nk]) for i in range(g)],
+        "keys": [tuple(decode(j, x) for j, x in enumerate(kb[i * nk:(i + 1) * nk])) for i in range(g)],
         "counts": [int(x) for x in cb[:g]],
         "aggs": [tuple(int(x) for x in ab[i * na:(i + 1) * na]) for i in range(g)],
     }

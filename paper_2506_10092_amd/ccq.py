@@ -54,7 +54,7 @@ class ColumnDesc(ctypes.Structure):
     _fields_ = [("encoding", ctypes.c_int32), ("value_type", ctypes.c_int32), ("n_entries", ctypes.c_int64),
                 ("values", ctypes.c_void_p), ("run_ends", ctypes.c_void_p), ("positions", ctypes.c_void_p),
                 ("packed", ctypes.c_void_p), ("bit_width", ctypes.c_int32), ("position_type", ctypes.c_int32),
-                ("base", ctypes.c_int64)]
+                ("base", ctypes.c_int64), ("dict_values", ctypes.c_void_p), ("dict_size", ctypes.c_int64)]
 
 
 class Pred(ctypes.Structure):
@@ -198,6 +198,8 @@ def _column_desc(c, n_rows):
     elif c["enc"] == "bitpacked":
         d.encoding, d.n_entries, d.bit_width, d.base = BITPACKED, n_rows, int(c["w"]), int(c.get("base", 0))
         d.packed = c["packed"].data_ptr()
+        if c.get("dict") is not None:      # int64 dictionary tensor (device)
+            d.dict_values, d.dict_size = c["dict"].data_ptr(), c["dict"].numel()
     else:
         raise CcqError(E_INVALID, "unknown encoding %r" % (c["enc"],))
     return d

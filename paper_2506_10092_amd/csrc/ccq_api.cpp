@@ -132,6 +132,10 @@ ccq_status ccq_table_create(ccq_context* ctx, int64_t n_rows, const ccq_column_d
         } else {
             return fail(CCQ_E_INVALID, "column %d: unknown encoding %d", i, c.encoding);
         }
+        if (c.dict_values ? (c.encoding != CCQ_BITPACKED || c.dict_size < 1) : c.dict_size != 0)
+            return fail(CCQ_E_INVALID,
+                        "column %d: a dictionary needs a BITPACKED column and dict_size >= 1 (dict_size 0 without one)",
+                        i);
     }
     ccq_table* t = new (std::nothrow) ccq_table;
     if (!t) return fail(CCQ_E_NOMEM, "out of host memory");
@@ -566,6 +570,13 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             r.key_card = key.card;
         } else if (c.encoding == CCQ_BITPACKED) {
             kd.src_kind = kKeyBp;
+            if (c.dict_values) {
+                if (key.shift != 0 || key.card > c.dict_size)
+                    return fail(CCQ_E_INVALID,
+                                "key %d: a key on a dictionary column needs shift 0 and card <= dict_size (%lld)", k,
+                                (long long)c.dict_size);
+                kd.dict = c.dict_values;
+            }
             if (bp_key[kd.src] >= 0)
                 return fail(CCQ_E_UNSUPPORTED, "key %d: a bit-packed column may be one group key only", k);
             bp_key[kd.src] = k;
@@ -665,6 +676,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
         const int col = q->aggs[a].col;
         const int enc = t->cols[col].encoding;
+        if (t->cols[col].dict_values)
+            return fail(CCQ_E_UNSUPPORTED, "aggregate %d: SUM over a dictionary-encoded column", a);
         ad.kind = enc == CCQ_RLE ? kAggSumRle : enc == CCQ_BITPACKED ? kAggSumBp : kAggSumIdx;
         ad.src = kind_slot[col];
         // one accumulator per column: repeated SUMs of a column share it

@@ -32,7 +32,9 @@ __device__ void write_group(const DevPlan& P, int64_t g, int64_t row, const int6
         const KeyDesc& kd = P.keys[k];
         const int64_t slot = rem % kd.radix;
         rem /= kd.radix;
-        keys[row * P.n_keys + k] = kd.via_lut ? kd.slot_keys[slot] : slot;
+        const int64_t key = kd.via_lut ? kd.slot_keys[slot] : slot;
+        // a dictionary column reports the dictionary entry (the plan checked card <= dict_size)
+        keys[row * P.n_keys + k] = kd.dict ? kd.dict[key] : key;
     }
     const int64_t cnt = table[g];
     counts[row] = cnt;

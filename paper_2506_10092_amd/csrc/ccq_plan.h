@@ -110,6 +110,7 @@ struct KeyDesc {
     int64_t radix;          // slots of this key
     int64_t stride;         // mixed-radix weight
     const int64_t* slot_keys;   // via_lut: slot -> key value (device), else nullptr
+    const int64_t* dict;        // the key column's dictionary (device): the result reports dict[key]
 };
 
 struct AggDesc {

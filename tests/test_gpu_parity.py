@@ -490,3 +490,51 @@ def test_table_validate_rejects_malformed_columns(ctx):
         with pytest.raises(ccq.CcqError, match="column %d:" % idx):
             table(name, bad).validate()
     say("table validation: good table passes, %d malformed columns rejected" % len(cases))
+
+
+@pytest.mark.parametrize("shape", ["fast_in", "fast_big", "generic", "batch"])
+def test_dictionary_keys_decode(ctx, shape):
+    """GROUP BY a dictionary-encoded column: every kernel path reports
+    dict[code] (values unlike the codes, permuted, negative and 64-bit
+    wide), equal to the oracle."""
+    from paper_2506_10092_amd import ccq
+    n = 1_500_007
+    t = datagen.config_c2(seed=12, n_rows=n, columns=datagen.C2_COLS)
+    rng = np.random.default_rng(77)
+    t["columns"]["d"]["dict"] = rng.permutation(
+        rng.integers(-(1 << 62), 1 << 62, size=10_000, dtype=np.int64))
+    base = t["query"]
+    q = {"fast_in": base,
+         "fast_big": dict(base, preds=base["preds"][:2], aggs=[("count",)]),
+         "generic": dict(base, aggs=[("sum", "p"), ("sum", "s"), ("count",)]),
+         "batch": base}[shape]
+    say("dictionary case:", shape)
+    if shape == "batch":
+        tb = ccq.Table(ctx, n, ccq.to_device(t["columns"]))
+        qs = [q, dict(q, window=(1000, 700_000)), dict(q, aggs=[("sum", "p"), ("count",)])]
+        b = ccq.Batch(ctx, [ccq.Plan(tb, x) for x in qs])
+        ws = b.new_workspace()
+        b.execute(ws)
+        got = b.to_python()
+        for x, g in zip(qs, got):
+            exp = oracle.run(t, x)
+            assert g["status"] == 0
+            for k in ("keys", "counts", "aggs"):
+                assert g[k] == exp[k], k
+        return
+    got = check(ctx, t, q)
+    assert len(got["keys"]) > 0
+    assert all(k[0] in set(int(v) for v in t["columns"]["d"]["dict"]) for k in got["keys"][:20])
+
+
+def test_dictionary_plan_rules(ctx):
+    from paper_2506_10092_amd import ccq
+    t = datagen.config_c2(seed=12, n_rows=100_003, columns=("r0", "d"))
+    t["columns"]["d"]["dict"] = np.arange(10_000, dtype=np.int64) * 3
+    tb = ccq.Table(ctx, t["n_rows"], ccq.to_device(t["columns"]))
+    base = {"preds": [], "aggs": [("count",)], "window": (0, t["n_rows"])}
+    for bad, status in ((dict(base, keys=[("d", 1, 5000)]), -1), (dict(base, keys=[("d", 0, 10_001)]), -1),
+                        (dict(base, keys=[], aggs=[("sum", "d")]), -2)):
+        with pytest.raises(ccq.CcqError) as e:
+            ccq.Plan(tb, bad)
+        assert e.value.status == status

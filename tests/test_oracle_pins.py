@@ -526,3 +526,64 @@ def test_index_predicates_match_brute_force_and_sqlite(seed):
         got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
         assert got == _norm(brute.run(t, q)), q
         assert got == _norm(brute.run_sqlite(t, q)), q
+
+
+# ---- dictionary decoding of key columns (Section 2.1, dictionary encoding)
+
+def _dict_table(rng, n, values, order):
+    """A column of arbitrary int64 values, dictionary-encoded: a dictionary
+    of its distinct values (sorted, or permuted when order == 'shuffled')
+    and one bit-packed code per row, plus an RLE column to sum."""
+    uniq = np.unique(values)
+    dic = uniq.copy() if order == "sorted" else rng.permutation(uniq)
+    pos = {int(v): i for i, v in enumerate(dic)}
+    codes = np.array([pos[int(v)] for v in values], dtype=np.int64)
+    w = max(1, int(len(dic) - 1).bit_length())
+    ends = np.cumsum(rng.integers(1, 40, size=n)).astype(np.int64)
+    ends = ends[ends < n]
+    ends = np.append(ends, n)
+    cols = {"v": {"enc": "bitpacked", "packed": datagen.pack_codes(codes, w), "w": w, "base": 0, "dict": dic},
+            "m": {"enc": "rle", "values": rng.integers(-1000, 1000, size=len(ends)).astype(np.int64),
+                  "run_ends": ends}}
+    return {"n_rows": n, "columns": cols}, dic, codes
+
+
+@pytest.mark.parametrize("order", ["sorted", "shuffled"])
+@pytest.mark.parametrize("seed", range(6))
+def test_dictionary_keys_round_trip(seed, order):
+    """GROUP BY a dictionary-encoded column reports the original values:
+    with a sorted dictionary the result is np.unique of the decoded column
+    (values and counts); with a permuted one the groups come in code order
+    and each reports dict[code].  Per-group SUMs of another column are the
+    row-level sums over the rows holding that value."""
+    rng = np.random.default_rng([seed, 31])
+    n = int(rng.integers(1, 5000))
+    pool = rng.integers(-(1 << 62), 1 << 62, size=int(rng.integers(1, 300)), dtype=np.int64)
+    values = pool[rng.integers(0, len(pool), size=n)]
+    t, dic, codes = _dict_table(rng, n, values, order)
+    q = {"preds": [], "keys": [("v", 0, len(dic))], "aggs": [("count",), ("sum", "m")], "window": (0, n)}
+    got = oracle.run(t, q, n_threads=3)
+    m_rows = np.repeat(t["columns"]["m"]["values"],
+                       np.diff(np.concatenate([[0], t["columns"]["m"]["run_ends"]])))
+    if order == "sorted":
+        u, cnt = np.unique(values, return_counts=True)
+        assert got["keys"] == [(int(x),) for x in u]
+        assert got["counts"] == [int(x) for x in cnt]
+    else:
+        present = sorted(set(int(c) for c in codes))
+        assert got["keys"] == [(int(dic[c]),) for c in present]
+        assert got["counts"] == [int((codes == c).sum()) for c in present]
+    sums = [int(m_rows[values == k[0]].sum()) for k in got["keys"]]
+    assert [a[1] for a in got["aggs"]] == sums
+
+
+def test_dictionary_rules():
+    rng = np.random.default_rng(5)
+    t, dic, _ = _dict_table(rng, 100, rng.integers(0, 9, size=100), "sorted")
+    base = {"preds": [], "aggs": [("count",)], "window": (0, 100)}
+    with pytest.raises(oracle.OracleError):
+        oracle.run(t, dict(base, keys=[("v", 1, 4)]))                  # shifted dictionary key
+    with pytest.raises(oracle.OracleError):
+        oracle.run(t, dict(base, keys=[("v", 0, len(dic) + 1)]))       # domain beyond the dictionary
+    with pytest.raises(oracle.OracleError):
+        oracle.run(t, dict(base, keys=[], aggs=[("sum", "v")]))        # SUM over dictionary codes
