@@ -788,6 +788,26 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
     }
 
+    // The generic row path tests a range (or no predicate) in registers, and
+    // a key whose reachable values are contiguous is slot = key - key_lo, so
+    // such columns drop their code table (up to 32 KB of LDS per workgroup,
+    // which goes to the group table instead).
+    if (!P.w0) {
+        for (int s = 0; s < P.n_bp; ++s) {
+            if (lut16[s].empty()) continue;
+            BpCol& b = P.bp[s];
+            const Fold& f = fold[bp_cols[s]];
+            if (f.has_set || f.has_iv) continue;
+            if (b.key >= 0) {
+                const std::vector<int64_t>& sk = slot_keys[b.key];
+                if (sk.back() - sk.front() + 1 != (int64_t)sk.size()) continue;
+                b.key_lo = sk.front();
+            }
+            put_pred(f, b.pred, b.lo, b.hi, b.set, b.set_len);
+            lut16[s].clear();
+        }
+    }
+
     // code tables.  Fast path: one byte per code holding the slot, G for a key
     // out of its domain, G + 1 for rejected codes, plus a reject entry at
     // index 2^w for rows the RLE predicates removed.  Otherwise uint8 (254 =
@@ -857,13 +877,18 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         sh = align16(sh + (size_t)P.n_idx * G * 8);
         P.fast_bytes = (int32_t)(sh - P.fast_sum_off);
         P.table_lds = 0;
-    } else {
+    } else if (!P.row_mode) {
+        // run mode adds once per group segment: int64 cells in LDS up to
+        // kLdsTableBytes, else the global table
         const size_t table_bytes = sizeof(int64_t) * (size_t)(1 + P.n_sums) * (size_t)G;
-        P.table_lds = table_bytes <= (size_t)kLdsTableBytes ? 1 : 0;
-        if (P.table_lds) {
+        if (table_bytes <= (size_t)kLdsTableBytes) {
+            P.table_lds = 1;
+            P.table_lds_groups = G;
             P.table_lds_off = (int32_t)sh;
             sh = align16(sh + table_bytes);
         }
+    } else {
+        P.table_lds = 0;      // generic row path: placed below, once the wave slice is known
     }
     P.lds_shared_bytes = (int32_t)sh;
 
@@ -874,13 +899,13 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     size_t wv = 0;
     if (P.w0) {
         P.run_cap = 0;
-        P.off_run_end = P.off_run_val = P.off_rows = P.off_ptpre = 0;
+        P.off_run_end = P.off_run_val = 0;
         P.off_tog = (int32_t)wv;
         wv = align16(wv + 512 * (size_t)std::max(P.k_rle, 1));
         P.off_pts = (int32_t)wv;
         P.lds_wave_bytes = (int32_t)wv;
         P.lds_dyn_bytes = (int32_t)(sh + kWaves * wv);
-        if ((size_t)P.lds_dyn_bytes > t->ctx->lds_per_block)
+        if ((size_t)P.lds_dyn_bytes + kernel_static_lds(P.w0, P.fast_big) > t->ctx->lds_per_block)
             return fail(CCQ_E_UNSUPPORTED, "query needs %d bytes of LDS per workgroup (limit %zu)", P.lds_dyn_bytes,
                         t->ctx->lds_per_block);
         return CCQ_OK;
@@ -911,25 +936,50 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.seg_slots = (!P.row_mode && P.n_keys > 0 && !P.table_lds) ? 1 : 0;
     P.off_slots = (int32_t)wv;
     if (P.seg_slots) wv = align16(wv + (size_t)kSegSlots * (2 + P.n_sums) * 8);
-    if (P.row_mode && P.w0 == 0) {
-        // generic row mode: compacted row list and staged packed words
-        P.off_rows = (int32_t)wv;
-        wv = align16(wv + 2 * (size_t)kRowTile);
+    if (P.row_mode) {
+        // generic row mode: the staged packed words of the tile
         for (int s = 0; s < P.n_bp; ++s) {
             P.bp[s].stage_off = (int32_t)wv;
             wv = align16(wv + 4 * (size_t)(64 * P.bp[s].w + 2));
         }
     }
-    if (P.row_mode) {
-        // point bitmaps (one per Index column); the fast path keeps the lane masks here
-        P.off_pts = (int32_t)wv;
-        wv = align16(wv + 4 * 64 * (size_t)std::max(P.n_idx, 1));
-        P.off_ptpre = (int32_t)wv;
-        wv = align16(wv + 4 * 64 * (size_t)P.n_idx);
-    }
+    P.off_pts = 0;
     P.lds_wave_bytes = (int32_t)wv;
+
+    // The generic row path's group table, per workgroup in LDS, added to
+    // the global table once at the end.  A bit-packed key changes from row
+    // to row, so the table takes compact 32-bit cells, as many groups as the
+    // workgroup's LDS allows, while a workgroup counts fewer than 2^31 rows
+    // (the counts are uint32).
+    if (P.row_mode) {
+        // Groups [0, table_lds_groups) get LDS cells, the rest add to the
+        // global table.  With a bit-packed key the group changes from row to
+        // row, so the table takes what LDS is left; with RLE keys only, rows
+        // reach the table about once per run, and a table beyond
+        // kLdsTableBytes stays global (keeping occupancy).
+        bool bp_keyed = false;
+        for (int k = 0; k < P.n_keys; ++k) bp_keyed = bp_keyed || P.keys[k].src_kind == kKeyBp;
+        const size_t cell_row = sizeof(uint32_t) * (size_t)(1 + P.n_sums);
+        const int64_t min_blocks = std::max<int64_t>(1, std::min<int64_t>((P.n_tiles + 3) / 4, t->ctx->cus));
+        const int64_t rows_per_wg = ((P.n_tiles + 4 * min_blocks - 1) / (4 * min_blocks)) * 4 * P.tile_rows;
+        // dynamic LDS left: the workgroup's LDS minus the kernel's static LDS
+        const size_t avail = t->ctx->lds_per_block - (size_t)kernel_static_lds(0, 0);
+        const size_t used = align16(sh) + kWaves * wv;
+        int64_t lg = 0;
+        if (used < avail) lg = (int64_t)((avail - used) / cell_row) & ~int64_t(3);
+        lg = std::min<int64_t>(lg, G);
+        if (!bp_keyed && (size_t)G * cell_row > (size_t)kLdsTableBytes) lg = 0;
+        if (lg > 0 && rows_per_wg < ((int64_t)1 << 31)) {
+            P.table_lds = 1;
+            P.table_c32 = 1;
+            P.table_lds_groups = lg;
+            P.table_lds_off = (int32_t)sh;
+            sh = align16(sh + (size_t)lg * cell_row);
+        }
+    }
+    P.lds_shared_bytes = (int32_t)sh;
     P.lds_dyn_bytes = (int32_t)(sh + kWaves * wv);
-    if ((size_t)P.lds_dyn_bytes > t->ctx->lds_per_block)
+    if ((size_t)P.lds_dyn_bytes + kernel_static_lds(P.w0, P.fast_big) > t->ctx->lds_per_block)
         return fail(CCQ_E_UNSUPPORTED, "query needs %d bytes of LDS per workgroup (limit %zu)", P.lds_dyn_bytes,
                     t->ctx->lds_per_block);
 

@@ -218,13 +218,37 @@ struct Table {
     int64_t* g;                 // global: counts[G], then one [G] array per SUM
     int64_t G;
     int32_t loff;               // byte offset of the per-workgroup LDS copy, or -1
+    int32_t c32;                // the LDS copy is compact: uint32 counts, int32 sums (below)
+    int64_t lG;                 // groups [0, lG) have LDS cells, laid out [which][group]
 };
 
+// Add v to accumulator `which` (0: COUNT, 1 + k: SUM slot k) of group gid.
+// A compact LDS table keeps 32-bit cells: counts cannot wrap (a workgroup
+// counts fewer than 2^31 rows); a SUM term that fits int32 is added to its
+// cell, and when the add wraps the cell past the int32 range (signs of the
+// old value and the term agree, the new value's differs) the lost 2^32 goes
+// to the global table; a wider term goes to the global table directly.  The
+// cell plus the global corrections is the exact 64-bit sum.
 __device__ __forceinline__ void table_add(const Table& t, int which, int64_t gid, int64_t v) {
-    if (t.loff >= 0)
+    if (t.loff >= 0 && t.c32 && gid < t.lG) {
+        uint32_t* cell = (uint32_t*)(ccq_lds + t.loff) + (which * t.lG + gid);
+        if (which == 0) {
+            atomicAdd(cell, (uint32_t)v);
+        } else if (v == (int64_t)(int32_t)v) {
+            const uint32_t add = (uint32_t)(int32_t)v;
+            const int32_t o = (int32_t)atomicAdd(cell, add);
+            const int32_t n = (int32_t)((uint32_t)o + add);
+            if (((o ^ n) & ((int32_t)v ^ n)) < 0)
+                atomicAdd((unsigned long long*)&t.g[which * t.G + gid],
+                          (unsigned long long)(v > 0 ? (int64_t(1) << 32) : -(int64_t(1) << 32)));
+        } else {
+            atomicAdd((unsigned long long*)&t.g[which * t.G + gid], (unsigned long long)v);
+        }
+    } else if (t.loff >= 0 && !t.c32) {
         atomicAdd((unsigned long long*)(ccq_lds + t.loff) + (which * t.G + gid), (unsigned long long)v);
-    else
+    } else {
         atomicAdd((unsigned long long*)&t.g[which * t.G + gid], (unsigned long long)v);
+    }
 }
 
 
@@ -238,9 +262,6 @@ struct WaveLds {
     int32_t* run_end;   // [run_cap] run end - tile start, capped at 2^30
     int64_t* run_val;   // [run_cap] run value; for a key column that is not summed, its group-id part
                         // (key value times its radix weight, -1 outside the key's domain)
-    uint16_t* rows;     // generic row mode: surviving rows of the tile, compacted
-    uint32_t* pts;      // row mode: 64-word point bitmap per Index column
-    int32_t* ptpre;     // row mode: exclusive popcount prefix per bitmap word
     uint32_t* tog;      // 64-word toggle bitmap per RLE column
     uint32_t* bnd;      // staged paths: 64-word run-boundary bitmap per RLE column
     int32_t* bpre;      // staged paths: exclusive prefix of boundary popcounts per word
@@ -679,44 +700,6 @@ __device__ __forceinline__ uint32_t idx_pred_mask(const DevPlan& P, const WaveLd
         pm &= ic.zero_pass ? ~x : x;
     }
     return pm;
-}
-
-// Point bitmaps of the tile (one bit per row carrying an Index point) with
-// exclusive prefix counts per word; pbase[j] = index of the tile's first point.
-__device__ __forceinline__ void tile_points(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
-                                            int64_t (&pcur)[kMaxIdx], int64_t (&pbase)[kMaxIdx]) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int j = 0; j < kMaxIdx; ++j) {
-        pbase[j] = 0;
-        if (j >= P.n_idx) continue;
-        const IdxCol& ic = P.idx[j];
-        uint32_t* bm = W.pts + j * 64;
-        bm[lane] = 0;
-        wave_lds_sync();
-        int64_t p0 = pcur[j];
-        pbase[j] = p0;
-        for (;;) {
-            const int64_t i = p0 + lane;
-            const bool valid = i < ic.n;
-            const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
-            const bool in = valid && pos < t0 + L;
-            const uint64_t m = wave_ballot(in);
-            if (in) {
-                const int32_t rel = (int32_t)(pos - t0);
-                atomicOr(&bm[rel >> 5], 1u << (rel & 31));
-            }
-            const int c = __builtin_popcountll(m);
-            p0 += c;
-            if (c < 64) break;
-        }
-        pcur[j] = p0;
-        wave_lds_sync();
-        int tot;
-        const int ex = wave_exclusive_sum(__builtin_popcount(bm[lane]), &tot);
-        W.ptpre[j * 64 + lane] = ex;
-        wave_lds_sync();
-    }
 }
 
 // code table lookup (table at LDS byte offset `off`): uint8 tables use
@@ -1452,183 +1435,234 @@ __device__ __forceinline__ void fast_flush(const DevPlan& P, int64_t* table, int
     }
 }
 
-// Generic row mode: any number of bit-packed columns of any width, RLE values
-// per row.  Surviving rows are compacted into an LDS list; the packed words
-// they read are staged in LDS.
-// sum of a 64-bit value over the wave (every lane gets it)
-__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+// ---- generic row path
+//
+// Row mode when the fast path does not apply: several bit-packed columns of
+// any width, RLE values per row (an RLE key or SUM next to a bit-packed
+// column), the row clause, Index predicates.  The tile's runs are staged and
+// masked by stage_tile; the packed words under lanes with surviving rows are
+// staged in LDS.  Lane l then walks its own rows 32l .. 32l + 31, all lanes
+// on row j together:
+//   - a bit-packed column's code is two staged words funnel-shifted, looked
+//     up in the column's code table, which folds its predicates and key slot
+//     (a4, the RLE x Plain AND of Section 5.1 per row);
+//   - an RLE column's staged run advances by one at each bit of the lane's
+//     boundary word, so the run holding the row needs no search (a2);
+//   - group id and SUM terms follow (a6); rows of one group that follow each
+//     other in a lane add up in registers and reach the table when the group
+//     changes (a7), so an RLE key reaches it about once per run.
+// Index SUMs are taken per point: each lane takes one of the tile's points
+// and, if its row survives, adds the point's value to that row's group.
+
+// consecutive rows of one group in a lane, per SUM slot
+struct SlotAcc {
+    int64_t gid;          // -1: empty
+    int64_t cnt;
+    int64_t sum[kMaxAggs];
+};
+
+__device__ __forceinline__ void slotacc_init(SlotAcc& a) {
+    a.gid = -1;
+    a.cnt = 0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int k = 0; k < kMaxAggs; ++k) a.sum[k] = 0;
 }
 
-constexpr int kPeelRounds = 16;
+__device__ __forceinline__ void slotacc_flush(const DevPlan& P, const Table& tb, SlotAcc& a) {
+    if (a.gid >= 0 && a.cnt > 0) {
+        table_add(tb, 0, a.gid, a.cnt);
+#pragma unroll
+        for (int k = 0; k < kMaxAggs; ++k)
+            if (k < P.n_sums && a.sum[k] != 0) table_add(tb, 1 + k, a.gid, a.sum[k]);
+    }
+    a.gid = -1;
+    a.cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxAggs; ++k) a.sum[k] = 0;
+}
+
+// Tile row r (whose lane has staged words): the bit-packed predicates and
+// the row clause, the group id from the key columns (ridx: the staged run of
+// each RLE column holding r) and the decoded bit-packed values.  False if
+// the row fails, or (status raised) if a key is outside its domain.
+template <int KMAX>
+__device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int32_t r,
+                                         const int32_t (&ridx)[KMAX], const int32_t (&luts)[kMaxBp],
+                                         int32_t* status, int64_t* gid_out, int64_t (&bpv)[kMaxBp]) {
+    bool pass = true;
+    bool dom = false;
+    int64_t gid = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxBp; ++j) {
+        bpv[j] = 0;
+        if (j >= P.n_bp) continue;
+        const BpCol& bc = P.bp[j];
+        const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
+        // tiles start at multiples of 32 rows, so the tile's first staged
+        // word starts with row 0 and row r sits at bit r * w
+        const uint32_t bit = (uint32_t)r * (uint32_t)bc.w;
+        const uint32_t q = bit >> 5;
+        const uint32_t mask = bc.w == 32 ? 0xFFFFFFFFu : ((1u << bc.w) - 1u);
+        const uint32_t code = __builtin_amdgcn_alignbit(st[q + 1], st[q], bit & 31) & mask;
+        bpv[j] = bc.base + (int64_t)code;
+        if (luts[j] >= 0) {
+            const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
+            if (e == kLutReject) pass = false;
+            else if (e == kLutDomain) dom = true;
+            else if (bc.key >= 0) gid += (int64_t)e * bc.key_stride;
+        } else {
+            pass = pass && pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, bpv[j]);
+            if (bc.key >= 0) {
+                const int64_t kv = bpv[j] >> bc.key_shift;
+                if (kv < 0 || kv >= bc.key_card) dom = true;
+                else gid += (kv - bc.key_lo) * bc.key_stride;
+            }
+        }
+    }
+    if (pass && W.rcl) {
+        // the row clause (Section 5.2, RLE mask OR Plain mask): its RLE rows,
+        // or a bit-packed part holding on this row's value
+        bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
+#pragma unroll
+        for (int j = 0; j < kMaxBp; ++j)
+            if (j < P.n_bp && P.bp[j].or_pred != kPredNone)
+                in = in || pred_pass(P.bp[j].or_pred, P.bp[j].or_lo, P.bp[j].or_hi, P.bp[j].or_set,
+                                     P.bp[j].or_set_len, bpv[j]);
+        pass = in;
+    }
+    if (pass && P.any_rle_row) {
+        int64_t g2;
+        if (rle_key_part<KMAX>(P, W, ridx, &g2, status)) gid += g2;
+        else pass = false;
+    }
+    if (pass && dom) {
+        raise_status(status, -4);
+        pass = false;
+    }
+    *gid_out = gid;
+    return pass;
+}
+
+// OR of a word over the wave
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x |= (uint32_t)__shfl_xor((int)x, o, 64);
+    return x;
+}
 
 template <int KMAX>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
                                                  uint32_t pm, const Table& tb, int32_t* status,
-                                                 int64_t (&pcur)[kMaxIdx], const int32_t (&luts)[kMaxBp]) {
+                                                 int64_t (&pcur)[kMaxIdx], const int32_t (&luts)[kMaxBp],
+                                                 SlotAcc& acc) {
     const int lane = lane_id();
-    const int32_t s0 = lane * kRowSpan;
-    int64_t pbase[kMaxIdx];
-    tile_points(P, W, t0, L, pcur, pbase);
-
-    // a3: compact the surviving rows into the wave's row list
-    int total;
-    const int first = wave_exclusive_sum(__builtin_popcount(pm), &total);
-    {
-        uint32_t m = pm;
-        int q = first;
-        while (m) {
-            const int b = __builtin_ctz(m);
-            m &= m - 1;
-            W.rows[q++] = (uint16_t)(s0 + b);
-        }
-    }
-    if (total == 0) {
-        wave_lds_sync();
-        return;
-    }
+    const uint32_t any = wave_or32(pm);
+    if (P.n_idx > 0) W.pmw[lane] = pm;
 
     // a4: stage only the packed words read by lanes that have surviving rows
     const uint64_t need_lanes = wave_ballot(pm != 0);
+    if (any) {
 #pragma unroll
-    for (int j = 0; j < kMaxBp; ++j) {
-        if (j >= P.n_bp) continue;
-        const BpCol& bc = P.bp[j];
-        const int64_t wbase = (t0 * (int64_t)bc.w) >> 5;
-        const int32_t nwords = (int32_t)((((t0 + L) * (int64_t)bc.w - 1) >> 5) + 2 - wbase);
-        const uint32_t magic = ((1u << 20) + (uint32_t)bc.w - 1u) / (uint32_t)bc.w;   // ceil(2^20 / w)
-        uint32_t* st = (uint32_t*)(W.base + bc.stage_off);
-        for (int q = lane; q < nwords; q += 64) {
-            // word q is read by lane floor(q / w) and at most two lanes before it
-            const int f = (int)(((uint32_t)q * magic) >> 20);
-            const int l0 = f >= 2 ? f - 2 : 0;
-            const int l1 = f < 63 ? f : 63;
-            const uint64_t lanes = l1 >= l0 ? (((2ull << (l1 - l0)) - 1ull) << l0) : 0ull;
-            if (need_lanes & lanes) st[q] = gld(bc.packed, wbase + q);
+        for (int j = 0; j < kMaxBp; ++j) {
+            if (j >= P.n_bp) continue;
+            const BpCol& bc = P.bp[j];
+            const int64_t wbase = (t0 * (int64_t)bc.w) >> 5;
+            const int32_t nwords = (int32_t)((((t0 + L) * (int64_t)bc.w - 1) >> 5) + 2 - wbase);
+            const uint32_t magic = ((1u << 20) + (uint32_t)bc.w - 1u) / (uint32_t)bc.w;   // ceil(2^20 / w)
+            uint32_t* st = (uint32_t*)(W.base + bc.stage_off);
+            for (int q = lane; q < nwords; q += 64) {
+                // word q is read by lane floor(q / w) and at most two lanes before it
+                const int f = (int)(((uint32_t)q * magic) >> 20);
+                const int l0 = f >= 2 ? f - 2 : 0;
+                const int l1 = f < 63 ? f : 63;
+                const uint64_t lanes = l1 >= l0 ? (((2ull << (l1 - l0)) - 1ull) << l0) : 0ull;
+                if (need_lanes & lanes) st[q] = gld(bc.packed, wbase + q);
+            }
         }
     }
     wave_lds_sync();
 
-    for (int i0 = 0; i0 < total; i0 += 64) {
-        // a8 per row: the row's group and its SUM terms (add[slot])
-        const int i = i0 + lane;
-        bool ok = i < total;
-        const int32_t r = ok ? W.rows[i] : 0;
-        int64_t gid = 0;
-        int64_t add[kMaxAggs];
+    // the lane's rows, row j of every lane together
+    if (any) {
+        int32_t ridx[KMAX];
+        uint32_t bw[KMAX];
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k) add[k] = 0;
-        if (ok) {
-            bool pass = true;
-            bool dom = false;
+        for (int c = 0; c < KMAX; ++c) {
+            ridx[c] = 0;
+            bw[c] = 0;
+            if (c < P.k_rle && P.any_rle_row && (P.rle[c].key_on || P.rle[c].sum_slot >= 0)) {
+                bw[c] = W.bnd[c * 64 + lane];
+                ridx[c] = W.bpre[c * 64 + lane];
+            }
+        }
+        const int32_t s0 = lane * kRowSpan;
+        for (int j = 0; j < kRowSpan; ++j) {
+            // the staged run holding row s0 + j: boundaries at rows <= s0 + j
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) ridx[c] += (int32_t)((bw[c] >> j) & 1u);
+            if (!((any >> j) & 1u)) continue;
+            if (!((pm >> j) & 1u)) continue;
             int64_t bpv[kMaxBp];
+            int64_t gid;
+            if (!row_eval<KMAX>(P, W, s0 + j, ridx, luts, status, &gid, bpv)) continue;
+            if (gid != acc.gid) {
+                slotacc_flush(P, tb, acc);
+                acc.gid = gid;
+            }
+            acc.cnt += 1;
+            // SUM terms by slot (static indices keep the accumulators in registers)
 #pragma unroll
-            for (int j = 0; j < kMaxBp; ++j) {
-                bpv[j] = 0;
-                if (j >= P.n_bp) continue;
-                const BpCol& bc = P.bp[j];
-                const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
-                const int64_t bit = ((t0 * (int64_t)bc.w) & 31) + (int64_t)r * bc.w;
-                const int32_t q = (int32_t)(bit >> 5);
-                const uint32_t sh = (uint32_t)(bit & 31);
-                const uint64_t two = (uint64_t)st[q] | ((uint64_t)st[q + 1] << 32);
-                const uint64_t mask = bc.w == 32 ? 0xFFFFFFFFull : ((1ull << bc.w) - 1ull);
-                const uint32_t code = (uint32_t)((two >> sh) & mask);
-                bpv[j] = bc.base + (int64_t)code;
-                if (luts[j] >= 0) {
-                    const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
-                    if (e == kLutReject) pass = false;
-                    else if (e == kLutDomain) dom = true;
-                    else if (bc.key >= 0) gid += (int64_t)e * bc.key_stride;
-                } else {
-                    pass = pass && pred_pass(bc.pred, bc.lo, bc.hi, bc.set, bc.set_len, bpv[j]);
-                    if (bc.key >= 0) {
-                        const int64_t kv = bpv[j] >> bc.key_shift;
-                        if (kv < 0 || kv >= bc.key_card) dom = true;
-                        else gid += kv * bc.key_stride;
-                    }
-                }
-            }
-            if (pass && W.rcl) {
-                // the row clause (Section 5.2, RLE mask OR Plain mask): its RLE
-                // rows, or a bit-packed part holding on this row's value
-                bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
-#pragma unroll
-                for (int j = 0; j < kMaxBp; ++j)
-                    if (j < P.n_bp && P.bp[j].or_pred != kPredNone)
-                        in = in || pred_pass(P.bp[j].or_pred, P.bp[j].or_lo, P.bp[j].or_hi, P.bp[j].or_set,
-                                             P.bp[j].or_set_len, bpv[j]);
-                pass = in;
-            }
-            int64_t rv[KMAX];
-            int32_t ridx[KMAX];
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) {
-                rv[c] = 0;
-                ridx[c] = 0;
-                if (pass && P.any_rle_row && c < P.k_rle) {
-                    ridx[c] = bm_run(W, c, r);
-                    if (P.rle[c].sum_slot >= 0) rv[c] = W.run_val[stage_base(P, c) + ridx[c]];
-                }
-            }
-            if (pass && P.any_rle_row) {
-                int64_t g2;
-                if (rle_key_part<KMAX>(P, W, ridx, &g2, status)) gid += g2;
-                else pass = false;
-            }
-            if (pass && dom) {
-                raise_status(status, -4);
-                pass = false;
-            }
-            ok = pass;
-            if (ok) {
+            for (int k = 0; k < kMaxAggs; ++k) {
+                if (k >= P.n_sums) continue;
+                int64_t term = 0;
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c)
-                    if (c < P.k_rle && P.rle[c].sum_slot >= 0) add[P.rle[c].sum_slot] = rv[c];
+                    if (c < P.k_rle && P.rle[c].sum_slot == k) term = W.run_val[stage_base(P, c) + ridx[c]];
 #pragma unroll
-                for (int j = 0; j < kMaxBp; ++j)
-                    if (j < P.n_bp && P.bp[j].sum_slot >= 0) add[P.bp[j].sum_slot] = bpv[j];
+                for (int b = 0; b < kMaxBp; ++b)
+                    if (b < P.n_bp && P.bp[b].sum_slot == k) term = bpv[b];
+                acc.sum[k] += term;
+            }
+        }
+    }
+
+    // a5: Index points of the tile (every column's cursor moves past them);
+    // a SUM adds each surviving point's value to its row's group
+    if (P.n_idx > 0) {
+        wave_lds_sync();
 #pragma unroll
-                for (int j = 0; j < kMaxIdx; ++j) {
-                    if (j < P.n_idx && P.idx[j].sum_slot >= 0) {
-                        const uint32_t word = W.pts[j * 64 + (r >> 5)];
-                        if (word & (1u << (r & 31))) {
-                            const int64_t rank =
-                                W.ptpre[j * 64 + (r >> 5)] + __builtin_popcount(word & ((1u << (r & 31)) - 1u));
-                            add[P.idx[j].sum_slot] = ld_val(P.idx[j].vals, P.idx[j].vtype, pbase[j] + rank);
+        for (int j = 0; j < kMaxIdx; ++j) {
+            if (j >= P.n_idx) continue;
+            const IdxCol& ic = P.idx[j];
+            int64_t p0 = pcur[j];
+            for (;;) {
+                const int64_t i = p0 + lane;
+                const bool valid = i < ic.n;
+                const int64_t pos = valid ? ld_val(ic.pos, ic.ptype, i) : INT64_MAX;
+                const bool in = valid && pos < t0 + L;
+                const uint64_t m = wave_ballot(in);
+                if (in && ic.sum_slot >= 0) {
+                    const int32_t rel = (int32_t)(pos - t0);
+                    if ((W.pmw[rel >> 5] >> (rel & 31)) & 1u) {
+                        int32_t idx[KMAX];
+#pragma unroll
+                        for (int c = 0; c < KMAX; ++c) {
+                            idx[c] = 0;
+                            if (c < P.k_rle && P.rle[c].key_on) idx[c] = bm_run(W, c, rel);
+                        }
+                        int64_t bpv[kMaxBp];
+                        int64_t gid;
+                        if (row_eval<KMAX>(P, W, rel, idx, luts, status, &gid, bpv)) {
+                            const int64_t v = ld_val(ic.vals, ic.vtype, i);
+                            if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
                         }
                     }
                 }
+                const int c = __builtin_popcountll(m);
+                p0 += c;
+                if (c < 64) break;
             }
-        }
-        // Groups holding two or more of these 64 rows (Zipf-hot keys) are
-        // summed across the wave and added once, by the lowest lane holding
-        // them, in at most kPeelRounds rounds; every other row adds itself.
-        // This keeps hot groups from serialising the table's atomics.
-        uint64_t todo = wave_ballot(ok);
-        for (int round = 0; round < kPeelRounds && todo; ++round) {
-            const int leader = __builtin_ctzll(todo);
-            const int64_t g0 = __shfl(gid, leader, 64);
-            const bool mine = ((todo >> lane) & 1ull) && gid == g0;
-            const uint64_t same = wave_ballot(mine);
-            if (__builtin_popcountll(same) >= 2) {
-                if (lane == leader) table_add(tb, 0, g0, __builtin_popcountll(same));
-                for (int k = 0; k < P.n_sums; ++k) {
-                    const int64_t tot = wave_sum64(mine ? add[k] : 0);
-                    if (lane == leader && tot != 0) table_add(tb, 1 + k, g0, tot);
-                }
-                if (mine) ok = false;
-                todo &= ~same;
-            } else {
-                todo &= todo - 1;     // the leader's group has this row only: it adds itself
-            }
-        }
-        if (ok) {
-            table_add(tb, 0, gid, 1);
-            for (int k = 0; k < P.n_sums; ++k)
-                if (add[k] != 0) table_add(tb, 1 + k, gid, add[k]);
+            pcur[j] = p0;
         }
     }
     wave_lds_sync();
@@ -1665,8 +1699,9 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
         uint32_t* z = (uint32_t*)(ccq_lds + P.fast_sum_off);
         for (int i = threadIdx.x; i < P.fast_bytes / 4; i += blockDim.x) z[i] = 0;
     } else if (P.table_lds) {
-        unsigned long long* l = (unsigned long long*)(ccq_lds + P.table_lds_off);
-        const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
+        // int64 cells, or 32-bit cells (compact table), cleared as 32-bit words
+        uint32_t* l = (uint32_t*)(ccq_lds + P.table_lds_off);
+        const int64_t n = (int64_t)(1 + P.n_sums) * P.table_lds_groups * (P.table_c32 ? 1 : 2);
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) l[i] = 0;
     }
     __syncthreads();
@@ -1681,9 +1716,6 @@ __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
     W.cur = (int64_t*)(W.base + 128);
     W.run_end = (int32_t*)(W.base + P.off_run_end);
     W.run_val = (int64_t*)(W.base + P.off_run_val);
-    W.rows = (uint16_t*)(W.base + P.off_rows);
-    W.pts = (uint32_t*)(W.base + P.off_pts);
-    W.ptpre = (int32_t*)(W.base + P.off_ptpre);
     W.tog = (uint32_t*)(W.base + P.off_tog);
     W.bnd = (uint32_t*)(W.base + P.off_bnd);
     W.bpre = (int32_t*)(W.base + P.off_bpre);
@@ -1695,7 +1727,7 @@ __device__ __forceinline__ WaveLds wave_lds(const DevPlan& P) {
 // One wavefront over rows [w0, w1) of the plan's window.
 template <int KMAX, int W0, bool BIG>
 __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, int64_t w0, int64_t w1,
-                                           const Table& tb, int32_t* status, RegAcc<KMAX>& acc,
+                                           const Table& tb, int32_t* status,
                                            const int32_t (&luts)[kMaxBp], const uint8_t* s_lut, uint32_t* cnt) {
     if (w0 >= w1) return;
     if constexpr (W0 > 0) {
@@ -1727,16 +1759,34 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
         }
         // tiles start at multiples of 32 rows (lane words); the first one may
         // start before the window, whose rows are then masked out
+        // (one loop per mode, so each keeps only its own accumulator live)
         int64_t t0 = w0 & ~(int64_t)31;
-        while (t0 < w1) {
-            int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
-            uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
-            const int32_t L = (int32_t)(t1 - t0);
-            pm = idx_pred_mask(P, W, t0, L, pcur, pm);
-            if (P.row_mode) tile_row_generic<KMAX>(P, W, t0, L, pm, tb, status, pcur, luts);
-            else tile_run_bits<KMAX>(P, W, t0, L, pm, tb, status, acc, pcur);
-            tile_bitmaps_clear(P, W);
-            t0 = t1;
+        if (P.row_mode) {
+            SlotAcc sacc;
+            slotacc_init(sacc);
+            while (t0 < w1) {
+                int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
+                uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
+                const int32_t L = (int32_t)(t1 - t0);
+                pm = idx_pred_mask(P, W, t0, L, pcur, pm);
+                tile_row_generic<KMAX>(P, W, t0, L, pm, tb, status, pcur, luts, sacc);
+                tile_bitmaps_clear(P, W);
+                t0 = t1;
+            }
+            slotacc_flush(P, tb, sacc);
+        } else {
+            RegAcc<KMAX> acc;
+            regacc_init(acc);
+            while (t0 < w1) {
+                int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
+                uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
+                const int32_t L = (int32_t)(t1 - t0);
+                pm = idx_pred_mask(P, W, t0, L, pcur, pm);
+                tile_run_bits<KMAX>(P, W, t0, L, pm, tb, status, acc, pcur);
+                tile_bitmaps_clear(P, W);
+                t0 = t1;
+            }
+            regacc_flush<KMAX>(P, tb, acc);
         }
     }
 }
@@ -1748,6 +1798,20 @@ __device__ __forceinline__ void wg_flush(const DevPlan& P, int64_t* table, int32
     __syncthreads();
     if constexpr (W0 > 0) {
         fast_flush(P, table, status, !BIG && P.bp[0].sum_slot >= 0, cnt, BIG);
+    } else if (P.table_lds && P.table_c32) {
+        // compact cells: counts as uint32, sums as int32 (their wraps already
+        // went to the global table)
+        const uint32_t* l = (const uint32_t*)(ccq_lds + P.table_lds_off);
+        const int64_t lg = P.table_lds_groups;
+        const int64_t n = (int64_t)(1 + P.n_sums) * lg;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t v = l[i];
+            if (v) {
+                const int64_t which = i / lg, g = i - which * lg;
+                const int64_t x = which == 0 ? (int64_t)v : (int64_t)(int32_t)v;
+                atomicAdd((unsigned long long*)&table[which * P.n_groups + g], (unsigned long long)x);
+            }
+        }
     } else if (P.table_lds) {
         const unsigned long long* l = (const unsigned long long*)(ccq_lds + P.table_lds_off);
         const int64_t n = (int64_t)(1 + P.n_sums) * P.n_groups;
@@ -1792,6 +1856,8 @@ __global__ __launch_bounds__(kThreads, kFastWaves(W0)) void k_fused(const DevPla
     tb.g = table;
     tb.G = P.n_groups;
     tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
+    tb.c32 = P.table_c32;
+    tb.lG = P.table_lds_groups;
 
     const int64_t gw = (int64_t)blockIdx.x * kWaves + wave_id();
     const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
@@ -1800,10 +1866,7 @@ __global__ __launch_bounds__(kThreads, kFastWaves(W0)) void k_fused(const DevPla
     const int64_t w1 = min(P.row_end, (first_tile + (gw + 1) * tiles_per_wave) << kTileShift);
 
     const WaveLds W = wave_lds(P);
-    RegAcc<KMAX> acc;
-    regacc_init(acc);
-    wave_range<KMAX, W0, BIG>(P, W, w0, w1, tb, status, acc, luts, s_lut, cnt);
-    regacc_flush<KMAX>(P, tb, acc);
+    wave_range<KMAX, W0, BIG>(P, W, w0, w1, tb, status, luts, s_lut, cnt);
     wg_flush<KMAX, W0, BIG>(P, table, status, cnt);
 }
 
@@ -1823,11 +1886,20 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int32_t item = s_item;
+        const int32_t item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= grp.n_items) break;
         const BatchItem it = grp.items[item];
-        const DevPlan& P = *B->plans[it.query];
+        // The plans do not change during a launch.  Reading a plan through a
+        // wave-uniform pointer in the constant address space lets its fields
+        // load into scalar registers, as the single-query kernel's plan
+        // argument does; through a plain pointer every field would be a flat
+        // load into vector registers (and would count against the LDS wait
+        // counter as well).
+        const uint64_t pbits = (uint64_t)(uintptr_t)B->plans[it.query];
+        const uint64_t ubits = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(pbits >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pbits);
+        const DevPlan& P = *(const DevPlan*)(const __attribute__((address_space(4))) DevPlan*)(uintptr_t)ubits;
         int32_t* status = (int32_t*)(ws + B->region[it.query]);
         int64_t* table = (int64_t*)(ws + B->region[it.query] + 256);
         int32_t luts[kMaxBp];
@@ -1838,6 +1910,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         tb.g = table;
         tb.G = P.n_groups;
         tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
+        tb.c32 = P.table_c32;
+        tb.lG = P.table_lds_groups;
 
         // this wave's share of the item's tiles
         const int wave = wave_id();
@@ -1849,10 +1923,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         const int64_t w1 = min(P.row_end, b << kTileShift);
 
         const WaveLds W = wave_lds(P);
-        RegAcc<KMAX> acc;
-        regacc_init(acc);
-        wave_range<KMAX, W0, BIG>(P, W, w0, w1, tb, status, acc, luts, s_lut, cnt);
-        regacc_flush<KMAX>(P, tb, acc);
+        wave_range<KMAX, W0, BIG>(P, W, w0, w1, tb, status, luts, s_lut, cnt);
         wg_flush<KMAX, W0, BIG>(P, table, status, cnt);
     }
 }

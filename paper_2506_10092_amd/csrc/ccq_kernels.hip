@@ -250,9 +250,47 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 hipError_t scratch_address(void** out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
 
+// A launch's static plus dynamic LDS must fit the workgroup's LDS: checked
+// against the kernel's own attributes before every persistent launch, so a
+// plan that asks for too much fails with an error instead of being
+// dispatched.  (Attributes and the device limit are looked up once.)
+static hipError_t check_lds(const void* fn, size_t dyn) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> stat;
+    static std::map<int, size_t> limit;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    size_t st, lim;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = stat.find({dev, fn});
+        if (it == stat.end()) {
+            hipFuncAttributes a;
+            e = hipFuncGetAttributes(&a, fn);
+            if (e != hipSuccess) return e;
+            it = stat.emplace(std::make_pair(dev, fn), (size_t)a.sharedSizeBytes).first;
+        }
+        st = it->second;
+        auto jt = limit.find(dev);
+        if (jt == limit.end()) {
+            int v = 0;
+            e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+            if (e != hipSuccess) return e;
+            jt = limit.emplace(dev, (size_t)v).first;
+        }
+        lim = jt->second;
+    }
+    return st + dyn <= lim ? hipSuccess : hipErrorInvalidConfiguration;
+}
+
 hipError_t launch_query(const DevPlan& p, const DevPlan* dp, void* ws, hipStream_t stream, int64_t* out_keys,
                         int64_t* out_counts, int64_t* out_aggs, int64_t* out_n_groups, int32_t* out_status,
                         int grid_fused, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    if (p.n_tiles > 0) {
+        const hipError_t le = check_lds((const void*)fused_kernel(p), (size_t)p.lds_dyn_bytes);
+        if (le != hipSuccess) return le;
+    }
     const WsLayout L = workspace_layout(p);
     unsigned char* base = (unsigned char*)ws;
     int32_t* header = (int32_t*)base;
@@ -322,6 +360,11 @@ hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan
                         const DevPlan* const* plans_dev, const int64_t* region, const BatchOut* outs,
                         unsigned char* ws, const int* group_grid, const int* group_lds, const int32_t* big,
                         int32_t n_big, hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    for (int g = 0; g < host.n_groups_used; ++g) {
+        const BatchGroup& grp = host.groups[g];
+        const hipError_t le = check_lds((const void*)batch_kernel(grp.kmax, grp.w0, grp.big), (size_t)group_lds[g]);
+        if (le != hipSuccess) return le;
+    }
     const int clear_grid = (int)std::min<int64_t>(std::max<int64_t>(host.n, 1), 4096);
     hipLaunchKernelGGL(k_batch_clear, dim3(clear_grid), dim3(kThreads), 0, stream, dev, ws);
     if (ev_begin) {

@@ -128,6 +128,10 @@ struct DevPlan {
     int32_t row_mode;       // 1 when a bit-packed column is referenced
     int32_t k_rle, n_bp, n_idx, n_keys, n_aggs, n_sums;
     int32_t table_lds;      // 1: per-workgroup LDS table, added to the global one at the end
+    int32_t table_c32;      // the LDS table is compact: uint32 counts, int32 sums whose wraps go to
+                            // the global table (generic row path)
+    int64_t table_lds_groups;   // groups [0, this) have LDS cells ([which][group]); the rest add to
+                                // the global table
     int32_t any_rle_row;    // row mode: some key or SUM reads an RLE value per row
     int32_t kmax;           // kernel instance: bound on RLE columns (2, 4 or 8)
     int32_t w0;             // kernel instance: width of the fast row path's column (0: none)
@@ -137,7 +141,7 @@ struct DevPlan {
     int32_t lds_shared_bytes;   // code tables + group table, before the wave slices
     int32_t lds_wave_bytes;     // one wave slice
     int32_t table_lds_off;  // byte offset of the LDS group table
-    int32_t off_run_end, off_run_val, off_rows, off_pts, off_ptpre;   // inside a wave slice
+    int32_t off_run_end, off_run_val, off_pts;   // inside a wave slice
     // fast row path: uint32 counts [(G + 2) << rep_shift] in static LDS; in
     // dynamic LDS uint64 code sums [G << rep_shift] and Index sums [n_idx * G]
     int32_t fast_rep_shift, fast_sum_off, fast_isum_off, fast_bytes;
@@ -182,11 +186,18 @@ struct BatchGroup {
 
 // kernel instance variants besides KMAX: staged paths, fast row path of width
 // 14 or 20, each of those with a large table
-constexpr int kVariants = 5;
+// Variant 5 runs the staged paths' kernel too, for plans that need more
+// than kBatchLdsSplit bytes of LDS per workgroup (large group tables in
+// LDS), so they do not lower the occupancy of the other staged plans'
+// launch.
+constexpr int kVariants = 6;
 constexpr int kMaxInstances = 3 * kVariants;     // KMAX in {2, 4, 8}
-inline int variant_of(int w0, int big) { return w0 == 0 ? 0 : (w0 == 14 ? 1 : 2) + (big ? 2 : 0); }
-inline int variant_w0(int v) { return v == 0 ? 0 : (v == 1 || v == 3) ? 14 : 20; }
-inline int variant_big(int v) { return v >= 3 ? 1 : 0; }
+constexpr int kBatchLdsSplit = 48 * 1024;
+inline int variant_of(int w0, int big, int lds_bytes) {
+    return w0 == 0 ? (lds_bytes > kBatchLdsSplit ? 5 : 0) : (w0 == 14 ? 1 : 2) + (big ? 2 : 0);
+}
+inline int variant_w0(int v) { return v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20; }
+inline int variant_big(int v) { return v == 3 || v == 4 ? 1 : 0; }
 
 // Where each query's result goes.
 struct BatchOut {
@@ -273,6 +284,14 @@ hipError_t launch_validate_idx(const void* pos, int32_t ptype, int64_t n, int64_
 
 // Persistent-grid size for the fused kernel with the plan's LDS use.
 int fused_grid_limit(const DevPlan& p, int cus);
+
+// Static LDS of a k_fused / k_batch instance (s_lut, s_cnt, s_item), with
+// slack for alignment: a plan's dynamic LDS must stay within the
+// workgroup's LDS minus this.
+constexpr int kernel_static_lds(int w0, int big) {
+    return ((w0 > 0 && w0 <= kLutMaxBits && !big) ? (1 << w0) + 16 : 16) + 4 * ((w0 > 0 && !big) ? kFastCntWords : 4) +
+           4 + 256;
+}
 
 // Bit widths that have a fast row-mode kernel instance.
 bool fast_row_width(int w);

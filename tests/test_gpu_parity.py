@@ -538,3 +538,47 @@ def test_dictionary_plan_rules(ctx):
         with pytest.raises(ccq.CcqError) as e:
             ccq.Plan(tb, bad)
         assert e.value.status == status
+
+
+def _generic_table(n, seed=21):
+    """Columns that send queries down the generic row path: RLE int32 r
+    (predicates, keys), RLE int64 m with values far beyond int32, a 32-bit
+    packed column q spanning the whole int32 range (SUM terms that wrap a
+    32-bit accumulator often), Zipf dictionary codes d (14 bits, 12000
+    codes) and a 20-bit packed column p."""
+    cols = {
+        "r": datagen.rle_column(seed, 5010, n, "lognormal", 64, 0, 1 << 16),
+        "m": datagen.rle_column(seed, 5020, n, "lognormal", 200, -(1 << 40), 1 << 40, np.int64),
+        "q": datagen.packed_column(seed, 5030, n, 32, "uniform", 1 << 32, base=-(1 << 31)),
+        "d": datagen.packed_column(seed, 5040, n, 14, "zipf", 12000, s=1.1),
+        "p": datagen.packed_column(seed, 5050, n, 20, "uniform", 1 << 20, base=-(1 << 19)),
+    }
+    return {"name": "generic_%d" % n, "n_rows": n, "columns": cols}
+
+
+GENERIC_CASES = {
+    # SUM terms that wrap int32 cells (q) and terms wider than int32 (m)
+    "wrap_and_wide": {"preds": [("r", "range", 1000, 60000)], "keys": [("d", 0, 12000)],
+                      "aggs": [("sum", "q"), ("sum", "m"), ("count",)]},
+    # four SUMs over 12000 groups: only part of the table fits in LDS
+    "partial_table": {"preds": [("p", "range", -300000, 400000)], "keys": [("d", 0, 12000)],
+                      "aggs": [("sum", "q"), ("sum", "m"), ("sum", "p"), ("sum", "r"), ("count",)]},
+    # a range on the key column itself: no code table, slot = key - lowest key
+    "range_key_no_table": {"preds": [("d", "range", 3, 9000), ("r", "range", 0, 50000)],
+                           "keys": [("d", 0, 12000)], "aggs": [("sum", "p"), ("count",)]},
+    # an RLE key with 8192 groups next to a packed SUM: register runs, global table
+    "rle_key_global": {"preds": [("p", "range", -400000, 300000)], "keys": [("r", 3, 8192)],
+                       "aggs": [("sum", "q"), ("sum", "m"), ("count",)]},
+    # two keys: RLE then dictionary
+    "two_keys": {"preds": [("q", "range", -(1 << 30), 1 << 30)], "keys": [("r", 12, 16), ("d", 0, 12000)],
+                 "aggs": [("sum", "p"), ("count",)]},
+}
+
+
+@pytest.mark.parametrize("case", sorted(GENERIC_CASES))
+def test_generic_row_path_tables(ctx, case):
+    t = _generic_table(3_000_017)
+    q = dict(GENERIC_CASES[case], window=(12_345, 3_000_017 - 999))
+    say("generic case:", case)
+    got = check(ctx, t, q)
+    assert len(got["keys"]) > 1
