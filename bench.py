@@ -17,6 +17,7 @@ host's cores as the CPU baseline.
 --config c2 | c3 | c1: one query per step (single-launch path), the
 1e9-row mixed-encoding GROUP BY d query, the 1e10-row four-key RLE GROUP
 BY, or the 1e6-row two-column query.  --config c5: the serving loop.
+--config encode: the device Plain -> RLE encoder on a 1e9-row column.
 
 Prints one JSON line: logical rows/s; the persistent kernels' achieved
 compressed-bytes bandwidth against the 8 TB/s HBM peak (bytes = the encoded
@@ -424,6 +425,58 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_encode(args):
+    """The device encoder: Plain -> RLE of an int32 column (the mixed-encoding
+    table's r0, decoded: lognormal runs of mean 64) of --rows rows (default
+    1e9).  A step is one ccq_plain_to_rle (count, scan, write); the output is
+    checked against the CPU oracle's runs."""
+    import numpy as np
+    import torch
+    import datagen
+    from oracle import encode as E
+    from paper_2506_10092_amd import ccq
+
+    n = args.rows or 1_000_000_000
+    src = datagen.rle_column(2, 2010, n, "lognormal", 64, 0, 1 << 16)
+    x = E.decode_rle(src["values"], src["run_ends"])
+    ctx = ccq.Context(0)
+    d = torch.from_numpy(x).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        out = ccq.plain_to_rle(ctx, d, stream)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        out = ccq.plain_to_rle(ctx, d, stream)
+    torch.cuda.synchronize()
+    ms = (time.time() - t0) * 1e3 / args.steps
+    runs = out["values"].numel()
+    # the oracle's maximal runs (the generator's runs need not be maximal:
+    # neighbouring runs may draw the same value)
+    t1 = time.time()
+    ev, ee = E.plain_to_rle(x)
+    cpu_s = time.time() - t1
+    if not (np.array_equal(out["run_ends"].cpu().numpy(), ee) and np.array_equal(out["values"].cpu().numpy(), ev)):
+        raise SystemExit("encoded runs differ from the oracle's")
+    alg = 4 * n + 12 * runs       # the column read once, the runs written once
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = {"value": n / cpu_s, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": "numpy plain_to_rle over the whole column (%d rows), %.1f s, one thread; its runs "
+                         "equal the GPU's" % (n, cpu_s)}
+    achieved = alg / (ms * 1e-3) / 1e9
+    out = {"metric": METRIC, "value": n / (ms * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "encode_plain_to_rle_%g" % n, "rows": n, "runs": runs,
+                      "step": "one ccq_plain_to_rle (count, scan, host read of the run count, write)"},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_enc_count + k_enc_scan + k_enc_write (wall time of the call)"},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def describe_query(wl, query, flt):
     """A short text of a single-launch workload's filter and grouping."""
     if wl["name"].startswith("c2"):
@@ -439,7 +492,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "encode"])
     ap.add_argument("--queries", type=int, default=4096, help="c4: queries per batch")
     ap.add_argument("--serve-queries", type=int, default=10000, help="c5: queries per arrival rate (after warm-up)")
     ap.add_argument("--serve-warmup", type=int, default=500, help="c5: leading queries left out of the statistics")
@@ -483,6 +536,9 @@ def main():
         return
     if args.config == "c5":
         bench_serve(args)
+        return
+    if args.config == "encode":
+        bench_encode(args)
         return
 
     t_gen = time.time()

@@ -253,6 +253,75 @@ ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_b
 #define CCQ_NOALLOC_WORKSPACE_BYTES ((size_t)32 << 20)
 ccq_status ccq_execute_noalloc(const ccq_plan* p, void* stream, const ccq_result* result);
 
+/* ---- encoding Plain data on the device (Table 1: plain_to_rle,
+ * plain_to_rle+index, plain_to_plain+index) and choosing an encoding
+ * (Section 9, the evaluation's encoding heuristics) ----
+ *
+ * Input: a device array of n_rows values (value_type CCQ_I32 or CCQ_I64), in
+ * row order.  Every call needs a device workspace of at least
+ * ccq_encode_workspace_bytes(n_rows) bytes, 256-byte aligned, not shared with
+ * a concurrent call.  Each call enqueues its kernels on `stream` and
+ * synchronises it (the output sizes are read back before anything is
+ * written); outputs are device arrays owned by the caller.  Errors:
+ * CCQ_E_INVALID (arguments), CCQ_E_CAPACITY (workspace or an output too
+ * small: nothing is written, the sizes needed are still returned),
+ * CCQ_E_HIP. */
+enum { CCQ_CHOOSE_PLAIN = 1, CCQ_CHOOSE_RLE = 2, CCQ_CHOOSE_RLE_INDEX = 3, CCQ_CHOOSE_PLAIN_INDEX = 4 };
+
+typedef struct {
+    int64_t n_rows;
+    int64_t runs;            /* maximal runs of equal values */
+    int64_t single_runs;     /* of them, runs of one row */
+    int64_t min_value, max_value;
+    int64_t lo_cut, hi_cut;  /* the values at sorted ranks floor(n/20) and n - 1 - floor(n/20)
+                                (the top and bottom 5% cut) */
+    int32_t choice;          /* CCQ_CHOOSE_*: under 1e6 rows Plain; else RLE when
+                                n * sizeof(value) / (runs * (sizeof(value) + 16)) > 20 (a run as
+                                value, start, end); else RLE+Index when there are single-row runs
+                                and (n - single runs) * sizeof(value) / (longer runs *
+                                (sizeof(value) + 16)) > 20; else Plain+Index when the cut range
+                                needs fewer bits than the full range; else Plain (RLE when even
+                                Plain would need more than 32 bits) */
+    int32_t bit_width;       /* PLAIN, PLAIN_INDEX: code width (1..32); 0 for the other choices */
+    int64_t base;            /* PLAIN, PLAIN_INDEX: value = base + code (PLAIN: the minimum;
+                                PLAIN_INDEX: centered, the cut range's midpoint rounded up minus
+                                2^(bit_width - 1), at least INT64_MIN) */
+    int64_t rle_runs;        /* RLE: runs; RLE_INDEX: runs of two or more rows */
+    int64_t index_points;    /* RLE_INDEX: single-row runs; PLAIN_INDEX: rows outside
+                                [base, base + 2^bit_width) */
+} ccq_encoding_choice;
+
+size_t ccq_encode_workspace_bytes(int64_t n_rows);
+
+/* Column statistics and the encoding the heuristics choose. */
+ccq_status ccq_encode_choose(ccq_context* ctx, const void* values, int32_t value_type, int64_t n_rows, void* ws,
+                             size_t ws_bytes, void* stream, ccq_encoding_choice* out);
+
+/* Plain -> RLE: maximal runs.  run_values: value_type[capacity], run_ends:
+ * int64[capacity] (exclusive ends; the form ccq_table_create takes);
+ * *n_runs (host) receives the number of runs. */
+ccq_status ccq_plain_to_rle(ccq_context* ctx, const void* values, int32_t value_type, int64_t n_rows, void* ws,
+                            size_t ws_bytes, void* stream, void* run_values, int64_t* run_ends, int64_t capacity,
+                            int64_t* n_runs);
+
+/* Plain -> RLE+Index (Section 3.2, composite encodings): runs of two or
+ * more rows as RLE (values, starts, exclusive ends; gaps where points are),
+ * rows whose run is a single row as Index points (int64 positions,
+ * value_type values).  Runs and points are disjoint and cover every row. */
+ccq_status ccq_plain_to_rle_index(ccq_context* ctx, const void* values, int32_t value_type, int64_t n_rows,
+                                  void* ws, size_t ws_bytes, void* stream, void* run_values, int64_t* run_starts,
+                                  int64_t* run_ends, int64_t run_capacity, int64_t* idx_positions, void* idx_values,
+                                  int64_t idx_capacity, int64_t* n_runs, int64_t* n_points);
+
+/* Plain -> Plain+Index (Section 3.2): codes value - base of bit_width bits,
+ * packed as a BITPACKED column (>= ceil(n*w/32) + 2 words; rows outside
+ * [base, base + 2^bit_width) hold code 0 there) and those rows as Index
+ * points (int64 positions, value_type values). */
+ccq_status ccq_plain_to_plain_index(ccq_context* ctx, const void* values, int32_t value_type, int64_t n_rows,
+                                    int32_t bit_width, int64_t base, void* ws, size_t ws_bytes, void* stream,
+                                    uint32_t* packed, int64_t packed_words, int64_t* idx_positions, void* idx_values,
+                                    int64_t idx_capacity, int64_t* n_points);
+
 /* ---- batched execution: many queries, one launch sequence ----
  *
  * A batch runs n compiled plans (over any tables of one device) together:

@@ -102,6 +102,16 @@ class ResultDesc(ctypes.Structure):
                 ("n_groups", ctypes.c_void_p), ("status", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
 
 
+class EncodingChoice(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("runs", ctypes.c_int64), ("single_runs", ctypes.c_int64),
+                ("min_value", ctypes.c_int64), ("max_value", ctypes.c_int64), ("lo_cut", ctypes.c_int64),
+                ("hi_cut", ctypes.c_int64), ("choice", ctypes.c_int32), ("bit_width", ctypes.c_int32),
+                ("base", ctypes.c_int64), ("rle_runs", ctypes.c_int64), ("index_points", ctypes.c_int64)]
+
+
+CHOICE_NAMES = {1: "plain", 2: "rle", 3: "rle+index", 4: "plain+index"}
+
+
 # every function include/ccq.h declares: name -> (restype, argtypes)
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 SIGNATURES = {
@@ -134,6 +144,13 @@ SIGNATURES = {
     "ccq_server_poll": (_i32, [_vp, ctypes.POINTER(Completion), _i32, ctypes.POINTER(_i32)]),
     "ccq_server_drain": (_i32, [_vp, ctypes.c_double]),
     "ccq_server_destroy": (None, [_vp]),
+    "ccq_encode_workspace_bytes": (_sz, [_i64]),
+    "ccq_encode_choose": (_i32, [_vp, _vp, _i32, _i64, _vp, _sz, _vp, ctypes.POINTER(EncodingChoice)]),
+    "ccq_plain_to_rle": (_i32, [_vp, _vp, _i32, _i64, _vp, _sz, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
+    "ccq_plain_to_rle_index": (_i32, [_vp, _vp, _i32, _i64, _vp, _sz, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64,
+                                      ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "ccq_plain_to_plain_index": (_i32, [_vp, _vp, _i32, _i64, _i32, _i64, _vp, _sz, _vp, _vp, _i64, _vp, _vp, _i64,
+                                        ctypes.POINTER(_i64)]),
 }
 
 _lib = None
@@ -506,3 +523,98 @@ def to_device(columns, device="cuda:0"):
                 d[k] = v
         out[name] = d
     return out
+
+
+# ---- encoding Plain data on the device (ccq_encode_*, ccq_plain_to_*)
+
+def _enc_ws(values):
+    import torch
+    n = values.numel()
+    return torch.empty(max(int(lib().ccq_encode_workspace_bytes(n)), 256), dtype=torch.uint8, device=values.device)
+
+
+def encode_choose(ctx, values, stream=None):
+    """Column statistics and the chosen encoding (dict) of a device tensor."""
+    values = values.contiguous()
+    ws = _enc_ws(values)
+    out = EncodingChoice()
+    _check(lib().ccq_encode_choose(ctx.h, ctypes.c_void_p(values.data_ptr()), _dtype_code(values), values.numel(),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream),
+                                   ctypes.byref(out)))
+    d = {k: getattr(out, k) for k, _ in EncodingChoice._fields_}
+    d["choice"] = CHOICE_NAMES[d["choice"]]
+    return d
+
+
+def plain_to_rle(ctx, values, stream=None):
+    """Device Plain -> RLE column dict (run values, exclusive run ends)."""
+    import torch
+    values = values.contiguous()
+    ws = _enc_ws(values)
+    n = ctypes.c_int64()
+    L = lib()
+    args = lambda rv, re_, cap: (ctx.h, ctypes.c_void_p(values.data_ptr()), _dtype_code(values), values.numel(),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), rv, re_, cap,
+                                 ctypes.byref(n))
+    st = L.ccq_plain_to_rle(*args(None, None, 0))
+    if st != E_CAPACITY:
+        _check(st)
+    rv = torch.empty(max(n.value, 1), dtype=values.dtype, device=values.device)
+    re_ = torch.empty(max(n.value, 1), dtype=torch.int64, device=values.device)
+    _check(L.ccq_plain_to_rle(*args(ctypes.c_void_p(rv.data_ptr()), ctypes.c_void_p(re_.data_ptr()), n.value)))
+    return {"enc": "rle", "values": rv[:n.value], "run_ends": re_[:n.value]}
+
+
+def plain_to_rle_index(ctx, values, stream=None):
+    """Device Plain -> RLE+Index: {"runs": {values, starts, ends}, "points": {positions, values}}."""
+    import torch
+    values = values.contiguous()
+    ws = _enc_ws(values)
+    nr, npt = ctypes.c_int64(), ctypes.c_int64()
+    L = lib()
+    dev = values.device
+
+    def call(bufs, rc, pc):
+        p = [ctypes.c_void_p(b.data_ptr()) if b is not None else None for b in bufs]
+        return L.ccq_plain_to_rle_index(ctx.h, ctypes.c_void_p(values.data_ptr()), _dtype_code(values),
+                                        values.numel(), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream_ptr(stream), p[0], p[1], p[2], rc, p[3], p[4], pc,
+                                        ctypes.byref(nr), ctypes.byref(npt))
+    st = call([None] * 5, 0, 0)
+    if st != E_CAPACITY and st != OK:
+        _check(st)
+    r, q = nr.value, npt.value
+    bufs = [torch.empty(max(r, 1), dtype=values.dtype, device=dev), torch.empty(max(r, 1), dtype=torch.int64, device=dev),
+            torch.empty(max(r, 1), dtype=torch.int64, device=dev), torch.empty(max(q, 1), dtype=torch.int64, device=dev),
+            torch.empty(max(q, 1), dtype=values.dtype, device=dev)]
+    _check(call(bufs, r, q))
+    return {"runs": {"values": bufs[0][:r], "starts": bufs[1][:r], "ends": bufs[2][:r]},
+            "points": {"positions": bufs[3][:q], "values": bufs[4][:q]}}
+
+
+def plain_to_plain_index(ctx, values, bit_width, base, stream=None):
+    """Device Plain -> Plain+Index: a bit-packed column dict (codes value -
+    base; rows outside [base, base + 2^w) hold 0) and the outliers as points."""
+    import torch
+    values = values.contiguous()
+    ws = _enc_ws(values)
+    n = values.numel()
+    words = (n * int(bit_width) + 31) // 32 + 2
+    packed = torch.empty(words, dtype=torch.int32, device=values.device)
+    npt = ctypes.c_int64()
+    L = lib()
+
+    def call(pos, vals, cap):
+        return L.ccq_plain_to_plain_index(ctx.h, ctypes.c_void_p(values.data_ptr()), _dtype_code(values), n,
+                                          int(bit_width), int(base), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream_ptr(stream), ctypes.c_void_p(packed.data_ptr()), words,
+                                          pos, vals, cap, ctypes.byref(npt))
+    st = call(None, None, 0)
+    if st != E_CAPACITY and st != OK:
+        _check(st)
+    q = npt.value
+    pos = torch.empty(max(q, 1), dtype=torch.int64, device=values.device)
+    vals = torch.empty(max(q, 1), dtype=values.dtype, device=values.device)
+    _check(call(ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vals.data_ptr()), q))
+    return {"column": {"enc": "bitpacked", "packed": packed, "w": int(bit_width), "base": int(base)},
+            "points": {"positions": pos[:q], "values": vals[:q]}}

@@ -662,6 +662,14 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             f.iv = m.second;
             fold_classify(f);
             put_pred(f, b.or_pred, b.or_lo, b.or_hi, b.or_set, b.or_set_len);
+            if (b.w <= kLutMaxBits) {
+                // one bit per code: the code's value passes this column's part of the clause
+                std::vector<uint32_t> bits(((size_t(1) << b.w) + 31) / 32, 0u);
+                for (int64_t code = 0; code < (int64_t(1) << b.w); ++code)
+                    if (fold_pass(f, b.base + code)) bits[code >> 5] |= 1u << (code & 31);
+                b.or_bits_words = (int32_t)bits.size();
+                fix_ptr(&b.or_bits, blob_put(bits.data(), bits.size() * 4));
+            }
         }
     }
 
@@ -853,6 +861,10 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             P.bp[s].lut_lds_off = (int32_t)sh;
             sh = align16(sh + (size_t)P.bp[s].lut_bytes);
         }
+        if (P.bp[s].or_bits_words > 0) {
+            P.bp[s].or_bits_lds_off = (int32_t)sh;
+            sh = align16(sh + 4 * (size_t)P.bp[s].or_bits_words);
+        }
     }
     if (P.w0 && P.fast_big) {
         // one uint32 count per slot (G, G + 1: out of domain, rejected) in
@@ -959,7 +971,16 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         // kLdsTableBytes stays global (keeping occupancy).
         bool bp_keyed = false;
         for (int k = 0; k < P.n_keys; ++k) bp_keyed = bp_keyed || P.keys[k].src_kind == kKeyBp;
-        const size_t cell_row = sizeof(uint32_t) * (size_t)(1 + P.n_sums);
+        // LDS columns: COUNT and the SUMs added per row; an Index SUM (a few
+        // points per tile) adds to the global table directly
+        uint64_t map = 0;
+        int cols = 0;
+        for (int w = 0; w <= P.n_sums; ++w) {
+            bool idx_sum = false;
+            for (int j = 0; j < P.n_idx; ++j) idx_sum = idx_sum || (w > 0 && P.idx[j].sum_slot == w - 1);
+            map |= (uint64_t)(idx_sum ? 15 : cols++) << (4 * w);
+        }
+        const size_t cell_row = sizeof(uint32_t) * (size_t)cols;
         const int64_t min_blocks = std::max<int64_t>(1, std::min<int64_t>((P.n_tiles + 3) / 4, t->ctx->cus));
         const int64_t rows_per_wg = ((P.n_tiles + 4 * min_blocks - 1) / (4 * min_blocks)) * 4 * P.tile_rows;
         // dynamic LDS left: the workgroup's LDS minus the kernel's static LDS
@@ -973,6 +994,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             P.table_lds = 1;
             P.table_c32 = 1;
             P.table_lds_groups = lg;
+            P.table_lds_map = map;
+            P.table_lds_cols = cols;
             P.table_lds_off = (int32_t)sh;
             sh = align16(sh + (size_t)lg * cell_row);
         }

@@ -219,7 +219,8 @@ struct Table {
     int64_t G;
     int32_t loff;               // byte offset of the per-workgroup LDS copy, or -1
     int32_t c32;                // the LDS copy is compact: uint32 counts, int32 sums (below)
-    int64_t lG;                 // groups [0, lG) have LDS cells, laid out [which][group]
+    int64_t lG;                 // groups [0, lG) have LDS cells
+    uint64_t amap;              // compact table: LDS column of each accumulator (4 bits; 15: none)
 };
 
 // Add v to accumulator `which` (0: COUNT, 1 + k: SUM slot k) of group gid.
@@ -230,8 +231,9 @@ struct Table {
 // to the global table; a wider term goes to the global table directly.  The
 // cell plus the global corrections is the exact 64-bit sum.
 __device__ __forceinline__ void table_add(const Table& t, int which, int64_t gid, int64_t v) {
-    if (t.loff >= 0 && t.c32 && gid < t.lG) {
-        uint32_t* cell = (uint32_t*)(ccq_lds + t.loff) + (which * t.lG + gid);
+    const int lc = (int)((t.amap >> (4 * which)) & 15u);
+    if (t.loff >= 0 && t.c32 && gid < t.lG && lc != 15) {
+        uint32_t* cell = (uint32_t*)(ccq_lds + t.loff) + (lc * t.lG + gid);
         if (which == 0) {
             atomicAdd(cell, (uint32_t)v);
         } else if (v == (int64_t)(int32_t)v) {
@@ -1492,9 +1494,11 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
     bool pass = true;
     bool dom = false;
     int64_t gid = 0;
+    uint32_t codes[kMaxBp];
 #pragma unroll
     for (int j = 0; j < kMaxBp; ++j) {
         bpv[j] = 0;
+        codes[j] = 0;
         if (j >= P.n_bp) continue;
         const BpCol& bc = P.bp[j];
         const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
@@ -1504,6 +1508,7 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
         const uint32_t q = bit >> 5;
         const uint32_t mask = bc.w == 32 ? 0xFFFFFFFFu : ((1u << bc.w) - 1u);
         const uint32_t code = __builtin_amdgcn_alignbit(st[q + 1], st[q], bit & 31) & mask;
+        codes[j] = code;
         bpv[j] = bc.base + (int64_t)code;
         if (luts[j] >= 0) {
             const uint32_t e = lut_get(luts[j], bc.lut_u8, code);
@@ -1524,10 +1529,16 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
         // or a bit-packed part holding on this row's value
         bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
 #pragma unroll
-        for (int j = 0; j < kMaxBp; ++j)
-            if (j < P.n_bp && P.bp[j].or_pred != kPredNone)
+        for (int j = 0; j < kMaxBp; ++j) {
+            if (j >= P.n_bp || P.bp[j].or_pred == kPredNone) continue;
+            if (P.bp[j].or_bits_words > 0) {
+                const uint32_t* ob = (const uint32_t*)(ccq_lds + P.bp[j].or_bits_lds_off);
+                in = in || ((ob[codes[j] >> 5] >> (codes[j] & 31)) & 1u) != 0;
+            } else {
                 in = in || pred_pass(P.bp[j].or_pred, P.bp[j].or_lo, P.bp[j].or_hi, P.bp[j].or_set,
                                      P.bp[j].or_set_len, bpv[j]);
+            }
+        }
         pass = in;
     }
     if (pass && P.any_rle_row) {
@@ -1689,6 +1700,11 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
                 const int n = P.bp[j].lut_bytes / 4;
                 for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = gld(src, i);
             }
+            if (W0 == 0 && j < P.n_bp && P.bp[j].or_bits_words > 0) {
+                uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].or_bits_lds_off);
+                const uint32_t* src = P.bp[j].or_bits;
+                for (int i = threadIdx.x; i < P.bp[j].or_bits_words; i += blockDim.x) dst[i] = gld(src, i);
+            }
         }
     }
 #pragma unroll
@@ -1701,7 +1717,8 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
     } else if (P.table_lds) {
         // int64 cells, or 32-bit cells (compact table), cleared as 32-bit words
         uint32_t* l = (uint32_t*)(ccq_lds + P.table_lds_off);
-        const int64_t n = (int64_t)(1 + P.n_sums) * P.table_lds_groups * (P.table_c32 ? 1 : 2);
+        const int64_t n =
+            P.table_c32 ? (int64_t)P.table_lds_cols * P.table_lds_groups : (int64_t)(1 + P.n_sums) * P.n_groups * 2;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) l[i] = 0;
     }
     __syncthreads();
@@ -1803,13 +1820,15 @@ __device__ __forceinline__ void wg_flush(const DevPlan& P, int64_t* table, int32
         // went to the global table)
         const uint32_t* l = (const uint32_t*)(ccq_lds + P.table_lds_off);
         const int64_t lg = P.table_lds_groups;
-        const int64_t n = (int64_t)(1 + P.n_sums) * lg;
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t v = l[i];
-            if (v) {
-                const int64_t which = i / lg, g = i - which * lg;
-                const int64_t x = which == 0 ? (int64_t)v : (int64_t)(int32_t)v;
-                atomicAdd((unsigned long long*)&table[which * P.n_groups + g], (unsigned long long)x);
+        for (int w = 0; w <= P.n_sums; ++w) {
+            const int lc = (int)((P.table_lds_map >> (4 * w)) & 15u);
+            if (lc == 15) continue;
+            for (int64_t g = threadIdx.x; g < lg; g += blockDim.x) {
+                const uint32_t v = l[lc * lg + g];
+                if (v) {
+                    const int64_t x = w == 0 ? (int64_t)v : (int64_t)(int32_t)v;
+                    atomicAdd((unsigned long long*)&table[(int64_t)w * P.n_groups + g], (unsigned long long)x);
+                }
             }
         }
     } else if (P.table_lds) {
@@ -1858,6 +1877,7 @@ __global__ __launch_bounds__(kThreads, kFastWaves(W0)) void k_fused(const DevPla
     tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
     tb.c32 = P.table_c32;
     tb.lG = P.table_lds_groups;
+    tb.amap = P.table_lds_map;
 
     const int64_t gw = (int64_t)blockIdx.x * kWaves + wave_id();
     const int64_t tiles_per_wave = (P.n_tiles + n_waves_total - 1) / n_waves_total;
@@ -1912,6 +1932,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
         tb.c32 = P.table_c32;
         tb.lG = P.table_lds_groups;
+        tb.amap = P.table_lds_map;
 
         // this wave's share of the item's tiles
         const int wave = wave_id();

@@ -86,6 +86,12 @@ struct BpCol {
     int32_t or_set_len;
     int64_t or_lo, or_hi;
     const int64_t* or_set;
+    // widths up to kLutMaxBits: that part as one bit per code (device), kept
+    // in LDS at or_bits_lds_off (or_bits_words words), instead of testing
+    // the value per row
+    const uint32_t* or_bits;
+    int32_t or_bits_words;
+    int32_t or_bits_lds_off;
 };
 
 struct IdxCol {
@@ -130,8 +136,12 @@ struct DevPlan {
     int32_t table_lds;      // 1: per-workgroup LDS table, added to the global one at the end
     int32_t table_c32;      // the LDS table is compact: uint32 counts, int32 sums whose wraps go to
                             // the global table (generic row path)
-    int64_t table_lds_groups;   // groups [0, this) have LDS cells ([which][group]); the rest add to
+    int64_t table_lds_groups;   // groups [0, this) have LDS cells ([column][group]); the rest add to
                                 // the global table
+    uint64_t table_lds_map;     // compact table: LDS column of accumulator `which` (0: COUNT, 1 + k:
+                                // SUM slot k) in bits [4 which, 4 which + 4); 15: no LDS column
+                                // (an Index SUM, added to the global table)
+    int32_t table_lds_cols;     // LDS columns of the compact table
     int32_t any_rle_row;    // row mode: some key or SUM reads an RLE value per row
     int32_t kmax;           // kernel instance: bound on RLE columns (2, 4 or 8)
     int32_t w0;             // kernel instance: width of the fast row path's column (0: none)
