@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 3
+#define CCQ_ABI_VERSION 4
 
 typedef int32_t ccq_status;
 enum {
@@ -138,10 +138,22 @@ typedef struct {
     int64_t card;              /* the key must lie in [0, card) */
 } ccq_key;
 
-enum { CCQ_COUNT_STAR = 1, CCQ_SUM = 2 };
+/* Aggregates (Section 7.2, aggregating phase): COUNT(*), SUM, MIN, MAX of a
+ * column, or of the row-wise sum, difference or product of two columns
+ * (Section 6: arithmetic on columns after aligning their runs).  Arithmetic
+ * is int64 and wraps (equal to the exact value whenever that fits in int64).
+ * For an ungrouped query with no qualifying row every aggregate is 0.
+ * AVG, STD and VAR are post-processing of COUNT, SUM(x) and SUM(x * x)
+ * (ccq_avg_var).  MIN, MAX and the two-column forms take RLE and BITPACKED
+ * columns (an INDEX column: CCQ_E_UNSUPPORTED); SUM of one column takes any
+ * encoding. */
+enum { CCQ_COUNT_STAR = 1, CCQ_SUM = 2, CCQ_MIN = 3, CCQ_MAX = 4 };
+enum { CCQ_OP_NONE = 0, CCQ_OP_ADD = 1, CCQ_OP_SUB = 2, CCQ_OP_MUL = 3 };
 typedef struct {
-    int32_t func;              /* CCQ_COUNT_STAR or CCQ_SUM */
-    int32_t col;               /* CCQ_SUM: any column; ignored for COUNT(*) */
+    int32_t func;              /* CCQ_COUNT_STAR, CCQ_SUM, CCQ_MIN or CCQ_MAX */
+    int32_t col;               /* the column (ignored for COUNT(*)) */
+    int32_t op;                /* CCQ_OP_NONE: the column; else col op col2, row by row */
+    int32_t col2;              /* second column when op != CCQ_OP_NONE */
 } ccq_agg;
 
 typedef struct {
@@ -252,6 +264,14 @@ ccq_status ccq_execute_ex(const ccq_plan* p, void* workspace, size_t workspace_b
  * codes of ccq_execute; results are identical to ccq_execute's. */
 #define CCQ_NOALLOC_WORKSPACE_BYTES ((size_t)32 << 20)
 ccq_status ccq_execute_noalloc(const ccq_plan* p, void* stream, const ccq_result* result);
+
+/* AVG and population VAR per result row from COUNT, SUM(x) and SUM(x * x)
+ * (Section 7.2: computed after SUM and COUNT): each exact int64 is rounded
+ * to the nearest double, then avg = s / n and var = (ss - s * s / n) / n in
+ * IEEE double arithmetic, in that order (0 and 0 when n = 0).  Host arrays of
+ * n_rows entries; returns CCQ_E_INVALID for NULL arrays or n_rows < 0. */
+ccq_status ccq_avg_var(const int64_t* count, const int64_t* sum, const int64_t* sum_sq, int64_t n_rows, double* avg,
+                       double* var);
 
 /* ---- encoding Plain data on the device (Table 1: plain_to_rle,
  * plain_to_rle+index, plain_to_plain+index) and choosing an encoding

@@ -16,8 +16,11 @@
  *      Section 6): a clause is one predicate, or the OR of the predicates
  *      that share a clause id (OR, Section 5.2); a negated predicate holds
  *      where the plain one fails (NOT, Section 5.3);
- *   3. qualifying rows are grouped by their key tuple and COUNT(*) / SUM(col)
- *      are accumulated per group (Section 7, grouping and aggregating phases);
+ *   3. qualifying rows are grouped by their key tuple and COUNT(*), SUM, MIN
+ *      and MAX are accumulated per group (Section 7, grouping and aggregating
+ *      phases); an aggregate's argument is a column or the row-wise sum,
+ *      difference or product of two columns (Section 6, arithmetic on
+ *      aligned columns);
  *   4. groups are emitted in ascending key order (torch.unique returns sorted
  *      unique values, Section 2.2); an ungrouped query emits one row.
  * No NULLs exist (Appendix "Query Optimization Rules").
@@ -29,7 +32,10 @@
  *   - range predicates are half open, lo <= v < hi; IN has set semantics;
  *   - a group key is v >> shift and must lie in the declared [0, card);
  *   - the bit-packed stream is LSB first in little-endian uint32 words;
- *   - sums are exact int64; any overflow is reported as an error.
+ *   - sums, differences and products are exact int64; any overflow is
+ *     reported as an error;
+ *   - an ungrouped query over no qualifying row reports 0 for every
+ *     aggregate (MIN and MAX included).
  *
  * Work is split into chunks of at most 2^20 rows handed to std::threads; each
  * thread keeps its own std::map, and the maps are added together at the end
@@ -51,7 +57,8 @@ extern "C" {
 enum { ORC_RLE = 1, ORC_INDEX = 2, ORC_BITPACKED = 3 };
 enum { ORC_I32 = 1, ORC_I64 = 2 };
 enum { ORC_RANGE = 1, ORC_IN = 2, ORC_NOT_RANGE = 3, ORC_NOT_IN = 4 };
-enum { ORC_COUNT = 1, ORC_SUM = 2 };
+enum { ORC_COUNT = 1, ORC_SUM = 2, ORC_MIN = 3, ORC_MAX = 4 };
+enum { ORC_OP_NONE = 0, ORC_OP_ADD = 1, ORC_OP_SUB = 2, ORC_OP_MUL = 3 };
 
 typedef struct {
     int32_t enc;
@@ -86,6 +93,8 @@ typedef struct {
 typedef struct {
     int32_t func;
     int32_t col;
+    int32_t op;     /* ORC_OP_NONE: the column; else col op col2, row by row */
+    int32_t col2;
 } orc_agg;
 
 }  // extern "C"
@@ -196,6 +205,23 @@ struct Query {
     std::vector<int> slot;        /* column id -> index into the decoded chunk */
 };
 
+std::vector<int64_t> initial_vals(const Query& q) {
+    std::vector<int64_t> v(q.aggs.size(), 0);
+    for (size_t a = 0; a < q.aggs.size(); a++) {
+        if (q.aggs[a].func == ORC_MIN) v[a] = INT64_MAX;
+        if (q.aggs[a].func == ORC_MAX) v[a] = INT64_MIN;
+    }
+    return v;
+}
+
+/* fold x into accumulator v of aggregate a; false on overflow */
+bool fold(const orc_agg& a, int64_t& v, int64_t x) {
+    if (a.func == ORC_MIN) v = std::min(v, x);
+    else if (a.func == ORC_MAX) v = std::max(v, x);
+    else return !__builtin_add_overflow(v, x, &v);
+    return true;
+}
+
 struct ThreadState {
     std::map<std::vector<int64_t>, Acc> groups;
     std::string error;
@@ -244,7 +270,7 @@ void run_chunks(const Query& q, std::atomic<int64_t>& next_chunk, int64_t n_chun
                 auto it = st.groups.find(key);
                 if (it == st.groups.end()) {
                     Acc a;
-                    a.vals.assign(q.aggs.size(), 0);
+                    a.vals = initial_vals(q);
                     it = st.groups.emplace(key, a).first;
                 }
                 last = &it->second;
@@ -252,8 +278,19 @@ void run_chunks(const Query& q, std::atomic<int64_t>& next_chunk, int64_t n_chun
             }
             last->count += 1;
             for (size_t a = 0; a < q.aggs.size(); a++) {
-                int64_t add = q.aggs[a].func == ORC_COUNT ? 1 : x[q.slot[q.aggs[a].col]][r];
-                if (__builtin_add_overflow(last->vals[a], add, &last->vals[a])) {
+                const orc_agg& ag = q.aggs[a];
+                int64_t v = 1;
+                bool ok = true;
+                if (ag.func != ORC_COUNT) {
+                    v = x[q.slot[ag.col]][r];
+                    if (ag.op != ORC_OP_NONE) {
+                        const int64_t w = x[q.slot[ag.col2]][r];
+                        if (ag.op == ORC_OP_ADD) ok = !__builtin_add_overflow(v, w, &v);
+                        else if (ag.op == ORC_OP_SUB) ok = !__builtin_sub_overflow(v, w, &v);
+                        else ok = !__builtin_mul_overflow(v, w, &v);
+                    }
+                }
+                if (!ok || !fold(ag, last->vals[a], v)) {
                     st.error = "int64 overflow in an aggregate";
                     return;
                 }
@@ -303,8 +340,10 @@ Result* execute(Query& q, int n_threads) {
         if (k.card <= 0 || k.shift < 0 || k.shift > 62) { res->error = "bad key domain"; return res; }
     }
     for (auto& a : q.aggs) {
-        if (a.func == ORC_SUM) {
+        if (a.func == ORC_SUM || a.func == ORC_MIN || a.func == ORC_MAX) {
             if (!use(a.col)) { res->error = "aggregate column out of range"; return res; }
+            if (a.op < ORC_OP_NONE || a.op > ORC_OP_MUL) { res->error = "unknown operator"; return res; }
+            if (a.op != ORC_OP_NONE && !use(a.col2)) { res->error = "aggregate column out of range"; return res; }
         } else if (a.func != ORC_COUNT) {
             res->error = "unknown aggregate";
             return res;
@@ -328,7 +367,7 @@ Result* execute(Query& q, int n_threads) {
             if (it == all.end()) { all.emplace(kv.first, kv.second); continue; }
             it->second.count += kv.second.count;
             for (size_t a = 0; a < q.aggs.size(); a++)
-                if (__builtin_add_overflow(it->second.vals[a], kv.second.vals[a], &it->second.vals[a])) {
+                if (!fold(q.aggs[a], it->second.vals[a], kv.second.vals[a])) {
                     res->error = "int64 overflow in an aggregate";
                     return res;
                 }
@@ -339,7 +378,7 @@ Result* execute(Query& q, int n_threads) {
         Acc a;
         a.vals.assign(q.aggs.size(), 0);
         auto it = all.find(std::vector<int64_t>{});
-        if (it != all.end()) a = it->second;
+        if (it != all.end() && it->second.count > 0) a = it->second;
         res->keys.push_back({});
         res->counts.push_back(a.count);
         res->aggs.push_back(a.vals);

@@ -25,7 +25,8 @@ _lib = None
 RLE, INDEX, BITPACKED = 1, 2, 3
 I32, I64 = 1, 2
 RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
-COUNT, SUM = 1, 2
+COUNT, SUM, MIN, MAX = 1, 2, 3, 4
+OPS = {"+": 1, "-": 2, "*": 3}
 
 
 class OrcColumn(ctypes.Structure):
@@ -46,7 +47,7 @@ class OrcKey(ctypes.Structure):
 
 
 class OrcAgg(ctypes.Structure):
-    _fields_ = [("func", ctypes.c_int32), ("col", ctypes.c_int32)]
+    _fields_ = [("func", ctypes.c_int32), ("col", ctypes.c_int32), ("op", ctypes.c_int32), ("col2", ctypes.c_int32)]
 
 
 def build(force: bool = True) -> str:
@@ -187,14 +188,23 @@ def run(table, query, n_threads=None):
                 raise OracleError("a key on a dictionary column needs shift 0 and card <= the dictionary size")
         dicts.append(d)
     for a in query["aggs"]:
-        if a[0] == "sum" and table["columns"].get(a[1], {}).get("dict") is not None:
-            raise OracleError("SUM over a dictionary-encoded column")
+        if a[0] in ("sum", "min", "max"):
+            args = a[1] if isinstance(a[1], tuple) else (a[1],)
+            if any(table["columns"].get(c, {}).get("dict") is not None for c in args[::2]):
+                raise OracleError("aggregate over a dictionary-encoded column")
     aggs = (OrcAgg * max(len(query["aggs"]), 1))()
     for i, a in enumerate(query["aggs"]):
         if a[0] == "count":
             aggs[i].func, aggs[i].col = COUNT, -1
-        elif a[0] == "sum":
-            aggs[i].func, aggs[i].col = SUM, col_id(a[1])
+        elif a[0] in ("sum", "min", "max"):
+            aggs[i].func = {"sum": SUM, "min": MIN, "max": MAX}[a[0]]
+            if isinstance(a[1], tuple):        # (col, op, col2): the row-wise col op col2
+                c1, op, c2 = a[1]
+                if op not in OPS:
+                    raise OracleError("unknown operator %r" % (op,))
+                aggs[i].col, aggs[i].op, aggs[i].col2 = col_id(c1), OPS[op], col_id(c2)
+            else:
+                aggs[i].col = col_id(a[1])
         else:
             raise OracleError("unknown aggregate %r" % (a[0],))
     rb, re_ = query.get("window", (0, n_rows))
@@ -319,3 +329,17 @@ def idx_in_idx(pos1, pos2):
     ok = b >= 0
     ok[ok] = pos2[b[ok]] == pos1[ok]
     return [int(x) for x in pos1[ok]]
+
+
+# ---- AVG and VAR as post-processing of SUM and COUNT (Section 7.2,
+# aggregating phase: AVG divides SUM by COUNT; STD and VAR need the sum of
+# the squared values too).  The exact integer aggregates are rounded to the
+# nearest double each, then combined in IEEE double arithmetic in this
+# order (population variance): avg = s / n; var = (ss - s * s / n) / n.
+# A group with n = 0 (the empty ungrouped row) gives 0.0 for both.
+
+def avg_var(count, s, ss):
+    n, s_, ss_ = float(count), float(s), float(ss)
+    if count == 0:
+        return 0.0, 0.0
+    return s_ / n, (ss_ - s_ * s_ / n) / n

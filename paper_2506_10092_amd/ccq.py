@@ -35,7 +35,8 @@ OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_KEY_DOMAIN, E_HIP, E_BUDGET, E_BUSY,
 RLE, INDEX, BITPACKED = 1, 2, 3
 I32, I64 = 1, 2
 RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
-COUNT_STAR, SUM = 1, 2
+COUNT_STAR, SUM, MIN, MAX = 1, 2, 3, 4
+OPS = {"+": 1, "-": 2, "*": 3}
 HOST_ONLY = -1
 # size of the fixed device scratch ccq_execute_noalloc uses as the workspace (include/ccq.h)
 NOALLOC_WORKSPACE_BYTES = 32 << 20
@@ -68,7 +69,7 @@ class Key(ctypes.Structure):
 
 
 class Agg(ctypes.Structure):
-    _fields_ = [("func", ctypes.c_int32), ("col", ctypes.c_int32)]
+    _fields_ = [("func", ctypes.c_int32), ("col", ctypes.c_int32), ("op", ctypes.c_int32), ("col2", ctypes.c_int32)]
 
 
 class QueryDesc(ctypes.Structure):
@@ -144,6 +145,7 @@ SIGNATURES = {
     "ccq_server_poll": (_i32, [_vp, ctypes.POINTER(Completion), _i32, ctypes.POINTER(_i32)]),
     "ccq_server_drain": (_i32, [_vp, ctypes.c_double]),
     "ccq_server_destroy": (None, [_vp]),
+    "ccq_avg_var": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "ccq_encode_workspace_bytes": (_sz, [_i64]),
     "ccq_encode_choose": (_i32, [_vp, _vp, _i32, _i64, _vp, _sz, _vp, ctypes.POINTER(EncodingChoice)]),
     "ccq_plain_to_rle": (_i32, [_vp, _vp, _i32, _i64, _vp, _sz, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
@@ -299,8 +301,14 @@ def query_desc(table, query):
     for i, a in enumerate(query["aggs"]):
         if a[0] == "count":
             aggs[i].func, aggs[i].col = COUNT_STAR, -1
-        elif a[0] == "sum":
-            aggs[i].func, aggs[i].col = SUM, col(a[1])
+        elif a[0] in ("sum", "min", "max"):
+            aggs[i].func = {"sum": SUM, "min": MIN, "max": MAX}[a[0]]
+            if isinstance(a[1], tuple):        # (col, op, col2): the row-wise col op col2
+                if a[1][1] not in OPS:
+                    raise CcqError(E_INVALID, "unknown operator %r" % (a[1][1],))
+                aggs[i].col, aggs[i].op, aggs[i].col2 = col(a[1][0]), OPS[a[1][1]], col(a[1][2])
+            else:
+                aggs[i].col = col(a[1])
         else:
             raise CcqError(E_INVALID, "unknown aggregate %r" % (a[0],))
     rb, re_ = query.get("window", (0, table.n_rows))
@@ -618,3 +626,14 @@ def plain_to_plain_index(ctx, values, bit_width, base, stream=None):
     _check(call(ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vals.data_ptr()), q))
     return {"column": {"enc": "bitpacked", "packed": packed, "w": int(bit_width), "base": int(base)},
             "points": {"positions": pos[:q], "values": vals[:q]}}
+
+
+def avg_var(count, s, ss):
+    """AVG and VAR per result row from COUNT, SUM(x), SUM(x * x) (host
+    lists or arrays of int64), through ccq_avg_var."""
+    c = np.ascontiguousarray(np.asarray(count, dtype=np.int64))
+    a = np.ascontiguousarray(np.asarray(s, dtype=np.int64))
+    q = np.ascontiguousarray(np.asarray(ss, dtype=np.int64))
+    avg, var = np.zeros(len(c)), np.zeros(len(c))
+    _check(lib().ccq_avg_var(c.ctypes.data, a.ctypes.data, q.ctypes.data, len(c), avg.ctypes.data, var.ctypes.data))
+    return avg.tolist(), var.tolist()

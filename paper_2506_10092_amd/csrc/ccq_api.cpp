@@ -346,10 +346,15 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     for (int i = 0; i < q->n_keys; ++i)
         if (ccq_status s = use(q->keys[i].col)) return s;
     for (int i = 0; i < q->n_aggs; ++i) {
-        if (q->aggs[i].func == CCQ_SUM) {
-            if (ccq_status s = use(q->aggs[i].col)) return s;
-        } else if (q->aggs[i].func != CCQ_COUNT_STAR) {
-            return fail(CCQ_E_INVALID, "aggregate %d: unknown function %d", i, q->aggs[i].func);
+        const ccq_agg& ag = q->aggs[i];
+        if (ag.func == CCQ_SUM || ag.func == CCQ_MIN || ag.func == CCQ_MAX) {
+            if (ag.op < CCQ_OP_NONE || ag.op > CCQ_OP_MUL)
+                return fail(CCQ_E_INVALID, "aggregate %d: unknown operator %d", i, ag.op);
+            if (ccq_status s = use(ag.col)) return s;
+            if (ag.op != CCQ_OP_NONE)
+                if (ccq_status s = use(ag.col2)) return s;
+        } else if (ag.func != CCQ_COUNT_STAR) {
+            return fail(CCQ_E_INVALID, "aggregate %d: unknown function %d", i, ag.func);
         }
     }
 
@@ -673,10 +678,55 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
     }
 
-    // aggregates
+    // aggregates.  A plan with MIN, MAX or a two-column expression gives
+    // every aggregate but COUNT and an Index column's SUM an ExtAcc
+    // (accumulators [0, n_ext)), evaluated per row on the generic row path.
     P.n_aggs = q->n_aggs;
+    bool ext = false;
+    for (int a = 0; a < q->n_aggs; ++a)
+        ext = ext || q->aggs[a].func == CCQ_MIN || q->aggs[a].func == CCQ_MAX || q->aggs[a].op != CCQ_OP_NONE;
+    std::vector<char> placed(q->n_aggs, 0);
+    for (int a = 0; ext && a < q->n_aggs; ++a) {
+        const ccq_agg& ag = q->aggs[a];
+        AggDesc& ad = P.aggs[a];
+        ad.fin = kFinValue;
+        if (ag.func == CCQ_COUNT_STAR) {
+            ad.kind = kAggCount;
+            ad.sum_slot = -1;
+            placed[a] = 1;
+            continue;
+        }
+        if (ag.func == CCQ_SUM && ag.op == CCQ_OP_NONE && t->cols[ag.col].encoding == CCQ_INDEX) continue;
+        const int opnd[2] = {ag.col, ag.op != CCQ_OP_NONE ? ag.col2 : ag.col};
+        for (int k = 0; k < 2; ++k) {
+            const ccq_column_desc& c = t->cols[opnd[k]];
+            if (c.encoding == CCQ_INDEX)
+                return fail(CCQ_E_UNSUPPORTED, "aggregate %d: MIN, MAX and expressions take RLE and BITPACKED columns",
+                            a);
+            if (c.dict_values)
+                return fail(CCQ_E_UNSUPPORTED, "aggregate %d: over a dictionary-encoded column", a);
+        }
+        const int slot = P.n_sums++;
+        ExtAcc& e = P.ext[slot];
+        e.kind = ag.func == CCQ_MIN ? kExtMin : ag.func == CCQ_MAX ? kExtMax : kExtSum;
+        e.op = ag.op;
+        e.a_rle = t->cols[opnd[0]].encoding == CCQ_RLE ? 1 : 0;
+        e.a_src = kind_slot[opnd[0]];
+        e.b_rle = t->cols[opnd[1]].encoding == CCQ_RLE ? 1 : 0;
+        e.b_src = kind_slot[opnd[1]];
+        if (e.a_rle) P.rle[e.a_src].keep_value = 1;
+        if (e.b_rle) P.rle[e.b_src].keep_value = 1;
+        ad.kind = kAggExt;
+        ad.src = slot;
+        ad.sum_slot = slot;
+        ad.fin = e.kind == kExtMin ? kFinMin : e.kind == kExtMax ? kFinMax : kFinValue;
+        placed[a] = 1;
+    }
+    P.n_ext = P.n_sums;
     for (int a = 0; a < q->n_aggs; ++a) {
         AggDesc& ad = P.aggs[a];
+        if (placed[a]) continue;
+        ad.fin = kFinValue;
         if (q->aggs[a].func == CCQ_COUNT_STAR) {
             ad.kind = kAggCount;
             ad.sum_slot = -1;
@@ -696,8 +746,10 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     }
 
     // mode and tiling
-    P.row_mode = P.n_bp > 0 ? 1 : 0;
+    P.row_mode = (P.n_bp > 0 || P.n_ext > 0) ? 1 : 0;
     P.any_rle_row = 0;
+    for (int k = 0; k < P.n_ext; ++k)
+        if (P.ext[k].a_rle || P.ext[k].b_rle) P.any_rle_row = 1;
     if (P.row_mode) {
         for (int k = 0; k < P.n_keys; ++k)
             if (P.keys[k].src_kind == kKeyRle) P.any_rle_row = 1;
@@ -748,7 +800,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.fast_big = 0;
     {
         bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
-                    !idx_pred && !row_clause;
+                    !idx_pred && !row_clause && P.n_ext == 0;
         BpCol& b = P.bp[0];
         const Fold& f = fold[bp_cols.empty() ? 0 : bp_cols[0]];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
@@ -978,7 +1030,9 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         for (int w = 0; w <= P.n_sums; ++w) {
             bool idx_sum = false;
             for (int j = 0; j < P.n_idx; ++j) idx_sum = idx_sum || (w > 0 && P.idx[j].sum_slot == w - 1);
-            map |= (uint64_t)(idx_sum ? 15 : cols++) << (4 * w);
+            // MIN and MAX keep 64-bit encoded values: the global table, through the registers
+            const bool minmax = w > 0 && w - 1 < P.n_ext && P.ext[w - 1].kind != kExtSum;
+            map |= (uint64_t)((idx_sum || minmax) ? 15 : cols++) << (4 * w);
         }
         const size_t cell_row = sizeof(uint32_t) * (size_t)cols;
         const int64_t min_blocks = std::max<int64_t>(1, std::min<int64_t>((P.n_tiles + 3) / 4, t->ctx->cus));
@@ -1128,3 +1182,27 @@ ccq_status ccq_execute_noalloc(const ccq_plan* p, void* stream, const ccq_result
 }  // extern "C"
 
 static_assert(ccq::kScratchBytes == CCQ_NOALLOC_WORKSPACE_BYTES, "fixed scratch size differs from the header's");
+
+static_assert(kOpNone == CCQ_OP_NONE && kOpAdd == CCQ_OP_ADD && kOpSub == CCQ_OP_SUB && kOpMul == CCQ_OP_MUL,
+              "ExtOp values follow the ABI");
+
+extern "C" ccq_status ccq_avg_var(const int64_t* count, const int64_t* sum, const int64_t* sum_sq, int64_t n_rows,
+                                  double* avg, double* var) {
+    if (n_rows < 0 || (n_rows > 0 && (!count || !sum || !sum_sq || !avg || !var)))
+        return ccq::fail(CCQ_E_INVALID, "bad arguments");
+    for (int64_t i = 0; i < n_rows; ++i) {
+        if (count[i] == 0) {
+            avg[i] = var[i] = 0.0;
+            continue;
+        }
+        // each exact integer rounded once, then the formula in this order
+        const volatile double n = (double)count[i], s = (double)sum[i], ss = (double)sum_sq[i];
+        const volatile double a = s / n;
+        const volatile double sq = s * s;
+        const volatile double m = sq / n;
+        const volatile double d = ss - m;
+        avg[i] = a;
+        var[i] = d / n;
+    }
+    return ccq::ok();
+}

@@ -365,7 +365,7 @@ __device__ __forceinline__ uint32_t stage_tile(const DevPlan& P, const WaveLds& 
                 W.run_end[off + n + lane] = (int32_t)(rel < (1 << 30) ? rel : (1 << 30));
                 // a key column that is not summed keeps its group-id part instead of its value
                 int64_t keep = v;
-                if (rc.key_on && rc.sum_slot < 0) {
+                if (rc.key_on && rc.sum_slot < 0 && !rc.keep_value) {
                     const int64_t kv = v >> rc.key_shift;
                     keep = (kv >= 0 && kv < rc.key_card) ? kv * rc.key_stride : -1;
                 }
@@ -460,7 +460,7 @@ __device__ __forceinline__ bool rle_key_part(const DevPlan& P, const WaveLds& W,
         if (c < P.k_rle && P.rle[c].key_on) {
             const RleCol& rc = P.rle[c];
             int64_t part = W.run_val[stage_base(P, c) + idx[c]];   // staged as the part
-            if (rc.sum_slot >= 0) {                                 // staged as the value
+            if (rc.sum_slot >= 0 || rc.keep_value) {                // staged as the value
                 const int64_t kv = part >> rc.key_shift;
                 part = (kv >= 0 && kv < rc.key_card) ? kv * rc.key_stride : -1;
             }
@@ -1474,8 +1474,13 @@ __device__ __forceinline__ void slotacc_flush(const DevPlan& P, const Table& tb,
     if (a.gid >= 0 && a.cnt > 0) {
         table_add(tb, 0, a.gid, a.cnt);
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k)
-            if (k < P.n_sums && a.sum[k] != 0) table_add(tb, 1 + k, a.gid, a.sum[k]);
+        for (int k = 0; k < kMaxAggs; ++k) {
+            if (k >= P.n_sums || a.sum[k] == 0) continue;
+            if (k < P.n_ext && P.ext[k].kind != kExtSum)     // MIN / MAX: encoded, unsigned maximum
+                atomicMax((unsigned long long*)&tb.g[(int64_t)(1 + k) * tb.G + a.gid], (unsigned long long)a.sum[k]);
+            else
+                table_add(tb, 1 + k, a.gid, a.sum[k]);
+        }
     }
     a.gid = -1;
     a.cnt = 0;
@@ -1601,7 +1606,8 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
         for (int c = 0; c < KMAX; ++c) {
             ridx[c] = 0;
             bw[c] = 0;
-            if (c < P.k_rle && P.any_rle_row && (P.rle[c].key_on || P.rle[c].sum_slot >= 0)) {
+            if (c < P.k_rle && P.any_rle_row &&
+                (P.rle[c].key_on || P.rle[c].sum_slot >= 0 || P.rle[c].keep_value)) {
                 bw[c] = W.bnd[c * 64 + lane];
                 ridx[c] = W.bpre[c * 64 + lane];
             }
@@ -1625,6 +1631,35 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 #pragma unroll
             for (int k = 0; k < kMaxAggs; ++k) {
                 if (k >= P.n_sums) continue;
+                if (k < P.n_ext) {
+                    // MIN, MAX or an expression: the row's operands, then the fold
+                    const ExtAcc& e = P.ext[k];
+                    int64_t va = 0, vb = 0;
+#pragma unroll
+                    for (int c = 0; c < KMAX; ++c) {
+                        if (c >= P.k_rle) continue;
+                        if (e.a_rle && e.a_src == c) va = W.run_val[stage_base(P, c) + ridx[c]];
+                        if (e.b_rle && e.b_src == c) vb = W.run_val[stage_base(P, c) + ridx[c]];
+                    }
+#pragma unroll
+                    for (int b = 0; b < kMaxBp; ++b) {
+                        if (b >= P.n_bp) continue;
+                        if (!e.a_rle && e.a_src == b) va = bpv[b];
+                        if (!e.b_rle && e.b_src == b) vb = bpv[b];
+                    }
+                    // wrapping int64 arithmetic (equal to the exact value whenever it fits)
+                    const uint64_t ua = (uint64_t)va, ub = (uint64_t)vb;
+                    const int64_t x = e.op == kOpAdd ? (int64_t)(ua + ub)
+                                      : e.op == kOpSub ? (int64_t)(ua - ub)
+                                      : e.op == kOpMul ? (int64_t)(ua * ub) : va;
+                    if (e.kind == kExtSum) {
+                        acc.sum[k] += x;
+                    } else {
+                        const uint64_t enc = e.kind == kExtMin ? min_enc(x) : max_enc(x);
+                        if (enc > (uint64_t)acc.sum[k]) acc.sum[k] = (int64_t)enc;
+                    }
+                    continue;
+                }
                 int64_t term = 0;
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c)

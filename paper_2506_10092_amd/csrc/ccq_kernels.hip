@@ -40,7 +40,14 @@ __device__ void write_group(const DevPlan& P, int64_t g, int64_t row, const int6
     counts[row] = cnt;
     for (int a = 0; a < P.n_aggs; ++a) {
         const AggDesc& ad = P.aggs[a];
-        aggs[row * P.n_aggs + a] = ad.kind == kAggCount ? cnt : table[(int64_t)(1 + ad.sum_slot) * G + g];
+        int64_t v = 0;
+        if (ad.kind == kAggCount) {
+            v = cnt;
+        } else if (cnt > 0) {          // an empty (ungrouped) row reports 0 for every aggregate
+            const int64_t c = table[(int64_t)(1 + ad.sum_slot) * G + g];
+            v = ad.fin == kFinMin ? min_dec((uint64_t)c) : ad.fin == kFinMax ? max_dec((uint64_t)c) : c;
+        }
+        aggs[row * P.n_aggs + a] = v;
     }
 }
 

@@ -27,7 +27,7 @@ constexpr int kFastCntWords = 2048;    // fast row path: static LDS counts, (G +
 
 enum PredKind : int32_t { kPredNone = 0, kPredRange = 1, kPredSet = 2, kPredFalse = 3, kPredIntervals = 4,
                           kPredNotRange = 5 };   // kPredNotRange: v < lo or v >= hi
-enum AggKind : int32_t { kAggCount = 0, kAggSumRle = 1, kAggSumBp = 2, kAggSumIdx = 3 };
+enum AggKind : int32_t { kAggCount = 0, kAggSumRle = 1, kAggSumBp = 2, kAggSumIdx = 3, kAggExt = 4 };
 enum KeySrc : int32_t { kKeyRle = 0, kKeyBp = 1 };
 
 // code table entries (uint16 per code of a bit-packed column)
@@ -51,6 +51,8 @@ struct RleCol {
     int64_t key_stride;
     int32_t stage_base;     // staged paths: first run slot of this column in a wave slice
     int32_t stage_cap;      // and its capacity (>= 64)
+    int32_t keep_value;     // staged runs keep the value (a SUM or an expression reads it per row),
+                            // not the key's group-id part
     int32_t or_next;        // 1: this column's pass mask is ORed with the next column's (one OR
                             // clause spans consecutive columns); 0: the clause ends here and is ANDed
     int32_t row_clause;     // 1: the clause is the row clause (its mask goes to the row test instead)
@@ -122,8 +124,28 @@ struct KeyDesc {
 struct AggDesc {
     int32_t kind;           // AggKind
     int32_t src;            // column slot within its kind
-    int32_t sum_slot;       // index among SUM accumulators (-1 for COUNT)
-    int32_t pad_;
+    int32_t sum_slot;       // index among the accumulators (-1 for COUNT)
+    int32_t fin;            // how the finalize reads the accumulator: kFinValue, kFinMin, kFinMax
+};
+
+// MIN and MAX accumulate as an unsigned maximum of an order-preserving
+// encoding whose neutral element is 0, so every table starts cleared to 0:
+// MIN keeps INT64_MAX - m (larger for smaller m), MAX keeps m ^ 2^63.
+enum FinKind : int32_t { kFinValue = 0, kFinMin = 1, kFinMax = 2 };
+__host__ __device__ inline uint64_t min_enc(int64_t m) { return (uint64_t)INT64_MAX - (uint64_t)m; }
+__host__ __device__ inline int64_t min_dec(uint64_t c) { return (int64_t)((uint64_t)INT64_MAX - c); }
+__host__ __device__ inline uint64_t max_enc(int64_t m) { return (uint64_t)m ^ (uint64_t(1) << 63); }
+__host__ __device__ inline int64_t max_dec(uint64_t c) { return (int64_t)(c ^ (uint64_t(1) << 63)); }
+
+// An accumulator over a column or a two-column expression, evaluated per
+// row on the generic row path (plans with MIN, MAX or an expression).
+enum ExtKind : int32_t { kExtNone = 0, kExtSum = 1, kExtMin = 2, kExtMax = 3 };
+enum ExtOp : int32_t { kOpNone = 0, kOpAdd = 1, kOpSub = 2, kOpMul = 3 };   // the ABI's CCQ_OP_* values
+struct ExtAcc {
+    int32_t kind;           // ExtKind
+    int32_t op;             // ExtOp
+    int32_t a_rle, a_src;   // first operand: RLE (1) or bit-packed (0) column slot
+    int32_t b_rle, b_src;   // second operand (op != CCQ_OP_NONE)
 };
 
 struct DevPlan {
@@ -169,6 +191,9 @@ struct DevPlan {
     // run mode with a global group table: per-wave LDS slots that merge the
     // pieces of one group segment before they reach the table
     int32_t seg_slots, off_slots;
+    int32_t n_ext;          // accumulators [0, n_ext) are ExtAcc (MIN, MAX, expressions); 0 otherwise
+    int32_t pad_ext_;
+    ExtAcc ext[kMaxAggs];
     RleCol rle[kMaxRle];
     BpCol bp[kMaxBp];
     IdxCol idx[kMaxIdx];

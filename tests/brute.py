@@ -35,6 +35,16 @@ def decode_rows(col, n_rows):
     raise ValueError(enc)
 
 
+def agg_value(rows, a, r):
+    """Row r's argument of aggregate a: a column, or (col, op, col2) row-wise."""
+    if a[0] == "count":
+        return 1
+    if isinstance(a[1], tuple):
+        x, op, y = rows[a[1][0]][r], a[1][1], rows[a[1][2]][r]
+        return x + y if op == "+" else x - y if op == "-" else x * y
+    return rows[a[1]][r]
+
+
 def run(table, query):
     n = int(table["n_rows"])
     rows = {name: decode_rows(c, n) for name, c in table["columns"].items()}
@@ -61,10 +71,17 @@ def run(table, query):
                 raise ValueError("key outside domain")
             key.append(k)
         key = tuple(key)
-        acc = groups.setdefault(key, [0] + [0] * len(query["aggs"]))
+        acc = groups.setdefault(key, [0] + [None] * len(query["aggs"]))
         acc[0] += 1
         for i, a in enumerate(query["aggs"]):
-            acc[1 + i] += 1 if a[0] == "count" else rows[a[1]][r]
+            v = agg_value(rows, a, r)
+            old = acc[1 + i]
+            if a[0] == "min":
+                acc[1 + i] = v if old is None else min(old, v)
+            elif a[0] == "max":
+                acc[1 + i] = v if old is None else max(old, v)
+            else:
+                acc[1 + i] = v if old is None else old + v
     if not query["keys"]:
         acc = groups.get((), [0] + [0] * len(query["aggs"]))
         return {"keys": [()], "counts": [acc[0]], "aggs": [tuple(acc[1:])]}
@@ -96,7 +113,12 @@ def run_sqlite(table, query):
     where += [sql_pred(p) for p in query["preds"]]
     where += ["(%s)" % " OR ".join(sql_pred(p) for p in clause) for clause in query.get("or", ())]
     keys = ['("%s" >> %d)' % (c, s) for (c, s, _) in query["keys"]]
-    aggs = ["COUNT(*)"] + ["COUNT(*)" if a[0] == "count" else 'COALESCE(SUM("%s"), 0)' % a[1]
+    def sql_arg(a):
+        if isinstance(a[1], tuple):
+            return '("%s" %s "%s")' % (a[1][0], a[1][1], a[1][2])
+        return '"%s"' % a[1]
+
+    aggs = ["COUNT(*)"] + ["COUNT(*)" if a[0] == "count" else "COALESCE(%s(%s), 0)" % (a[0].upper(), sql_arg(a))
                            for a in query["aggs"]]
     sql = "SELECT %s FROM t WHERE %s" % (", ".join(keys + aggs), " AND ".join(where))
     if keys:

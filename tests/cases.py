@@ -137,3 +137,22 @@ def tiny_query_with_index_pred(rng, n, wd):
     else:
         q["preds"] = q["preds"] + preds
     return q
+
+
+def tiny_query_with_exprs(rng, n, wd):
+    """tiny_query whose aggregates include MIN, MAX and SUM / MIN / MAX of
+    the row-wise sum, difference or product of two RLE or bit-packed
+    columns."""
+    q = tiny_query(rng, n, wd)
+    cols = ["r0", "r1", "r2", "d", "p"]
+    aggs = [a for a in q["aggs"] if a[0] == "count" or a[1] != "s"]
+    for _ in range(int(rng.integers(1, 4))):
+        f = ["sum", "min", "max"][int(rng.integers(0, 3))]
+        a = cols[int(rng.integers(0, len(cols)))]
+        if rng.random() < 0.5:
+            aggs.append((f, a))
+        else:
+            b = cols[int(rng.integers(0, len(cols)))]
+            aggs.append((f, (a, "+-*"[int(rng.integers(0, 3))], b)))
+    q["aggs"] = aggs
+    return q

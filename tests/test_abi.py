@@ -35,7 +35,7 @@ def test_header_functions_are_exported():
 
 
 def test_abi_version():
-    assert ccq.lib().ccq_abi_version() == 3
+    assert ccq.lib().ccq_abi_version() == 4
 
 
 def _host_table(columns, n_rows):
@@ -89,6 +89,9 @@ def test_host_only_context_checks_plans():
     # five two-column OR clauses need ten RLE column uses (at most eight)
     ({"or": [[("a", "range", 0, 2 + i), ("m", "range", 0, 5)] for i in range(5)]}, ccq.E_UNSUPPORTED),
     ({"or": [[]]}, ccq.E_INVALID),
+    # MIN / MAX / expressions take RLE and bit-packed columns
+    ({"aggs": [("min", "s")]}, ccq.E_UNSUPPORTED),
+    ({"aggs": [("sum", ("a", "+", "s"))]}, ccq.E_UNSUPPORTED),
 ])
 def test_plan_check_rejects(bad, code):
     tb = _host_table(_cols(), 1000)
@@ -184,3 +187,29 @@ def test_work_item_size_is_capped():
     cfg = ccq.ServerConfig(1 << 30, 8, 0, 1, 1, (1 << 19) + 1, 0)
     assert L.ccq_server_create(ctx.h, ccq.ctypes.byref(cfg), ccq.ctypes.byref(h)) == ccq.E_INVALID
     assert b"tiles_per_item" in L.ccq_last_error()
+
+
+def test_avg_var_matches_the_oracle_bit_for_bit():
+    """ccq_avg_var (host code of the library) against the oracle's
+    post-processing: identical doubles on random exact aggregates."""
+    from oracle import oracle
+    rng = np.random.default_rng(11)
+    n = rng.integers(0, 1 << 40, size=500)
+    n[:5] = 0
+    s = rng.integers(-(1 << 60), 1 << 60, size=500)
+    ss = rng.integers(0, 1 << 62, size=500)
+    avg, var = ccq.avg_var(n, s, ss)
+    for i in range(500):
+        a, v = oracle.avg_var(int(n[i]), int(s[i]), int(ss[i]))
+        assert avg[i] == a and var[i] == v, i
+
+
+def test_expression_plans_check_on_host():
+    tb = _host_table(_cols(), 1000)
+    q = {"preds": [("d", "in", [1, 2])], "keys": [("d", 0, 10000)],
+         "aggs": [("min", "a"), ("max", ("a", "*", "p")), ("sum", "s"), ("count",)], "window": (0, 1000)}
+    g, ws = ccq.plan_check(tb, q)
+    assert g == 2 and ws >= 256 + 8 * 5 * 2
+    with pytest.raises(ccq.CcqError) as e:
+        ccq.plan_check(tb, dict(q, aggs=[("sum", ("a", "%", "p"))]))
+    assert e.value.status == ccq.E_INVALID

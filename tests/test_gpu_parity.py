@@ -72,7 +72,8 @@ def test_paper_examples(ctx, name):
     table = {"n_rows": g["n_rows"], "columns": {k: _np_col(v) for k, v in g["columns"].items()}}
     for q in g["queries"]:
         query = {"preds": [tuple(p) for p in q["preds"]], "keys": [tuple(k) for k in q["keys"]],
-                 "aggs": [tuple(a) for a in q["aggs"]], "window": (0, g["n_rows"])}
+                 "aggs": [tuple(tuple(x) if isinstance(x, list) else x for x in a) for a in q["aggs"]],
+                 "window": (0, g["n_rows"])}
         got = check(ctx, table, query)
         assert got["counts"] == q["expect"]["counts"]
         assert [list(a) for a in got["aggs"]] == q["expect"]["aggs"]
@@ -582,3 +583,55 @@ def test_generic_row_path_tables(ctx, case):
     say("generic case:", case)
     got = check(ctx, t, q)
     assert len(got["keys"]) > 1
+
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_tiny_random_tables_with_min_max_expressions(ctx, seed):
+    """MIN, MAX and SUM / MIN / MAX of a + b, a - b, a * b over RLE and
+    bit-packed columns (the generic row path), equal to the oracle."""
+    from tests.cases import tiny_query_with_exprs
+    rng = np.random.default_rng(7000 + seed)
+    n = int(rng.integers(1, 5000))
+    t, wd = tiny_table(rng, n)
+    for _ in range(3):
+        q = tiny_query_with_exprs(rng, n, wd)
+        say("expr seed", seed, "n", n, "query", q)
+        check(ctx, t, q)
+
+
+@pytest.mark.parametrize("q", [
+    # over the mixed-encoding table: RLE x RLE, RLE x packed, packed x packed; dictionary / RLE / no keys
+    {"preds": [("r0", "range", 0, 40000)], "keys": [("d", 0, 10000)],
+     "aggs": [("min", "r1"), ("max", ("r1", "-", "p")), ("sum", ("r0", "*", "r1")), ("count",), ("sum", "s")]},
+    {"preds": [("p", "range", -200000, 300000)], "keys": [("r2", 10, 64)],
+     "aggs": [("sum", ("p", "+", "r0")), ("min", ("p", "*", "r1")), ("max", "p")]},
+    {"preds": [], "keys": [], "aggs": [("min", "r0"), ("max", "r0"), ("sum", ("r0", "+", "r1")), ("count",)]},
+    {"preds": [("d", "in", [0, 1, 2, 3, 4])], "keys": [("d", 0, 10000)],
+     "aggs": [("min", "p"), ("max", "p"), ("sum", ("p", "*", "p"))]},
+])
+def test_min_max_expressions_2m_rows(ctx, q):
+    t = datagen.config_c2(seed=33, n_rows=2_000_003, columns=datagen.C2_COLS)
+    q = dict(q, window=(777, 2_000_003 - 55))
+    say("expr 2M:", q["aggs"])
+    got = check(ctx, t, q)
+    assert len(got["keys"]) >= 1
+
+
+def test_min_max_expressions_in_a_batch(ctx):
+    from paper_2506_10092_amd import ccq
+    n = 1_000_003
+    t = datagen.config_c2(seed=34, n_rows=n, columns=datagen.C2_COLS)
+    qs = [{"preds": [("r1", "range", 1000, 50000)], "keys": [("d", 0, 10000)],
+           "aggs": [("max", ("r0", "+", "p")), ("count",)], "window": (0, n)},
+          {"preds": [], "keys": [], "aggs": [("min", "p"), ("sum", ("r2", "*", "r2"))], "window": (100, n // 2)},
+          {"preds": [("r0", "range", 0, 30000)], "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)],
+           "window": (0, n)}]
+    tb = ccq.Table(ctx, n, ccq.to_device(t["columns"]))
+    b = ccq.Batch(ctx, [ccq.Plan(tb, q) for q in qs], tiles_per_item=16)
+    b.execute(b.new_workspace())
+    for q, g in zip(qs, b.to_python()):
+        exp = oracle.run(t, q)
+        assert g["status"] == 0
+        for k in ("keys", "counts", "aggs"):
+            assert g[k] == exp[k], k

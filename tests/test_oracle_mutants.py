@@ -31,8 +31,11 @@ MUTANTS = {
                                "uint64_t two = (uint64_t)c.packed[word];"),
     "key_ignores_shift": ("int64_t v = x[q.slot[q.keys[k].col]][r] >> q.keys[k].shift;",
                           "int64_t v = x[q.slot[q.keys[k].col]][r];"),
-    "sum_counts_rows": ("int64_t add = q.aggs[a].func == ORC_COUNT ? 1 : x[q.slot[q.aggs[a].col]][r];",
-                        "int64_t add = 1;"),
+    "sum_counts_rows": ("v = x[q.slot[ag.col]][r];", "v = 1;"),
+    "min_as_max": ("if (a.func == ORC_MIN) v = std::min(v, x);", "if (a.func == ORC_MIN) v = std::max(v, x);"),
+    "add_as_sub": ("if (ag.op == ORC_OP_ADD) ok = !__builtin_add_overflow(v, w, &v);",
+                   "if (ag.op == ORC_OP_ADD) ok = !__builtin_sub_overflow(v, w, &v);"),
+    "mul_as_add": ("else ok = !__builtin_mul_overflow(v, w, &v);", "else ok = !__builtin_add_overflow(v, w, &v);"),
     "window_ignores_begin": ("int64_t c0 = q.row_begin + ch * CH;", "int64_t c0 = ch * CH;"),
     "groups_descending": ("for (auto& kv : all) {   /* std::map", "for (auto& kv : std::map<std::vector<int64_t>, Acc, std::greater<std::vector<int64_t>>>(all.begin(), all.end())) {   /* std::map"),
     "thread_merge_drops_counts": ("it->second.count += kv.second.count;", "it->second.count = kv.second.count;"),

@@ -37,7 +37,8 @@ def _as_np_column(c):
 
 def _as_query(q, n_rows):
     return {"preds": [tuple(p) for p in q["preds"]], "keys": [tuple(k) for k in q["keys"]],
-            "aggs": [tuple(a) for a in q["aggs"]], "window": tuple(q.get("window", (0, n_rows)))}
+            "aggs": [tuple(tuple(x) if isinstance(x, list) else x for x in a) for a in q["aggs"]],
+            "window": tuple(q.get("window", (0, n_rows)))}
 
 
 def _norm(res):
@@ -587,3 +588,62 @@ def test_dictionary_rules():
         oracle.run(t, dict(base, keys=[("v", 0, len(dic) + 1)]))       # domain beyond the dictionary
     with pytest.raises(oracle.OracleError):
         oracle.run(t, dict(base, keys=[], aggs=[("sum", "v")]))        # SUM over dictionary codes
+
+
+# ------------------------------------------------------------------ MIN, MAX, column arithmetic, AVG / VAR
+
+@pytest.mark.parametrize("seed", range(40))
+def test_min_max_and_expressions_match_brute_force_and_sqlite(seed):
+    from tests.cases import tiny_query_with_exprs
+    rng = np.random.default_rng(4000 + seed)
+    n = int(rng.integers(1, 300))
+    t, wd = _tiny_table(rng, n)
+    for _ in range(4):
+        q = tiny_query_with_exprs(rng, n, wd)
+        got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
+        assert got == _norm(brute.run(t, q)), q
+        assert got == _norm(brute.run_sqlite(t, q)), q
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_expression_invariants(seed):
+    """SUM(a + b) = SUM(a) + SUM(b), SUM(a - b) = SUM(a) - SUM(b); the
+    ungrouped MIN / MAX are the extremes of the per-group ones."""
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(50, 400))
+    t, wd = _tiny_table(rng, n)
+    base = {"preds": [("r0", "range", -3, 12)], "window": (0, n)}
+    r = oracle.run(t, dict(base, keys=[], aggs=[("sum", ("r1", "+", "p")), ("sum", "r1"), ("sum", "p"),
+                                                 ("sum", ("r1", "-", "p")), ("min", "r1"), ("max", "r1")]))
+    a = r["aggs"][0]
+    assert a[0] == a[1] + a[2] and a[3] == a[1] - a[2]
+    g = oracle.run(t, dict(base, keys=[("d", 0, 1 << wd)], aggs=[("min", "r1"), ("max", "r1")]))
+    if g["keys"]:
+        assert a[4] == min(x[0] for x in g["aggs"]) and a[5] == max(x[1] for x in g["aggs"])
+
+
+def test_avg_var_post_processing():
+    """AVG and VAR from COUNT, SUM and SUM(x * x): exact on small cases,
+    within a few ulps of the exact rational otherwise."""
+    from fractions import Fraction
+    assert oracle.avg_var(4, 4, 8) == (1.0, 1.0)          # values 0, 2, 0, 2
+    assert oracle.avg_var(3, 21, 147) == (7.0, 0.0)        # a constant 7
+    assert oracle.avg_var(0, 0, 0) == (0.0, 0.0)
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        x = rng.integers(-10**6, 10**6, size=int(rng.integers(1, 500)))
+        n, s, ss = len(x), int(x.sum()), int((x.astype(object) ** 2).sum())
+        avg, var = oracle.avg_var(n, s, ss)
+        ea = Fraction(s, n)
+        ev = Fraction(ss, n) - ea * ea
+        assert abs(Fraction(avg) - ea) <= abs(ea) * Fraction(1, 2**50) + Fraction(1, 2**60)
+        assert abs(Fraction(var) - ev) <= abs(Fraction(ss, n)) * Fraction(1, 2**45) + Fraction(1, 2**40)
+    # on a table: VAR of r1 from one query's COUNT, SUM(r1) and SUM(r1 * r1)
+    rng = np.random.default_rng(10)
+    t, wd = _tiny_table(rng, 300)
+    r = oracle.run(t, {"preds": [], "keys": [], "aggs": [("count",), ("sum", "r1"), ("sum", ("r1", "*", "r1"))],
+                       "window": (0, 300)})
+    vals = np.array(brute.decode_rows(t["columns"]["r1"], 300), dtype=np.float64)
+    avg, var = oracle.avg_var(*r["aggs"][0])
+    assert abs(avg - vals.mean()) < 1e-12 * max(1.0, abs(vals.mean()))
+    assert abs(var - vals.var()) < 1e-9 * max(1.0, vals.var())
