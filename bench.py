@@ -332,7 +332,8 @@ def bench_serve(args):
 
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(args.serve_budget_gb * 1e9, free - 4e9))
-    levels = [float(x) for x in args.qps.split(",")]
+    # arrival rates; "max" submits every query at once (the saturation throughput)
+    levels = [float("inf") if x.strip() == "max" else float(x) for x in args.qps.split(",")]
     warm = min(args.serve_warmup, n_q // 2)
     report = {}
     answers = {}
@@ -342,7 +343,10 @@ def bench_serve(args):
         for qps in levels:
             srv = ccq.Server(ctx, budget, max_inflight=args.serve_inflight, n_streams=2, batching=batching,
                              tiles_per_item=args.serve_tpi)
-            arr = np.cumsum(np.random.default_rng([6, int(qps)]).exponential(1.0 / qps, size=n_q))
+            if math.isinf(qps):
+                arr = np.zeros(n_q)
+            else:
+                arr = np.cumsum(np.random.default_rng([6, int(qps)]).exponential(1.0 / qps, size=n_q))
             base = ccq.now() + 0.005
             sched = {}
             for k in range(n_q):
@@ -500,7 +504,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0, help="c5: HBM budget of the servers")
     ap.add_argument("--serve-inflight", type=int, default=512, help="c5: queries admitted or running at once")
     ap.add_argument("--serve-tpi", type=int, default=64, help="c5: batch work-item size in tiles")
-    ap.add_argument("--qps", default="200,1000,5000", help="c5: Poisson arrival rates")
+    ap.add_argument("--qps", default="200,1000,5000,max",
+                    help="c5: Poisson arrival rates; max submits every query at once (saturation)")
     ap.add_argument("--serve-check", type=int, default=1000, help="c5: served answers checked against the oracle")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
     ap.add_argument("--filter", default="and", choices=["and", "not", "or", "or_dict"],

@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 4
+#define CCQ_ABI_VERSION 5
 
 typedef int32_t ccq_status;
 enum {
@@ -408,8 +408,12 @@ typedef struct {
     int32_t max_batch;         /* queries per launch (0: max_inflight) */
     int32_t n_streams;         /* launch streams (0: 2) */
     int32_t batching;          /* 1: one batched launch per dispatch; 0: one ccq_execute per query */
-    int32_t tiles_per_item;    /* batch work-item size (0: 64) */
-    int32_t pad_;
+    int32_t tiles_per_item;    /* largest batch work item in 2048-row tiles (0: 64); a dispatch with
+                                  few tiles in all uses smaller items so they spread over the GPU */
+    int32_t no_graphs;         /* 0: each batched dispatch replays a hipGraph captured once per launch
+                                  shape (kernel instances, grids, LDS, query count rounded up to a
+                                  power of two), its per-query descriptors copied to device memory
+                                  first; 1: launch every dispatch directly */
 } ccq_server_config;
 
 typedef struct {

@@ -90,7 +90,7 @@ class BatchOpts(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("batching", ctypes.c_int32),
-                ("tiles_per_item", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("tiles_per_item", ctypes.c_int32), ("no_graphs", ctypes.c_int32)]
 
 
 class Completion(ctypes.Structure):
@@ -470,10 +470,10 @@ class Server:
     completion has been polled."""
 
     def __init__(self, ctx, hbm_budget_bytes, max_inflight=64, max_batch=0, n_streams=2, batching=True,
-                 tiles_per_item=0):
+                 tiles_per_item=0, graphs=True):
         self.ctx = ctx
         cfg = ServerConfig(int(hbm_budget_bytes), int(max_inflight), int(max_batch), int(n_streams),
-                           1 if batching else 0, int(tiles_per_item), 0)
+                           1 if batching else 0, int(tiles_per_item), 0 if graphs else 1)
         h = ctypes.c_void_p()
         _check(lib().ccq_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h

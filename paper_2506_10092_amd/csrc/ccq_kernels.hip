@@ -153,6 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fin(const BatchDev* __restri
                                                          const unsigned char* __restrict__ ws) {
     __shared__ int s_wave[kWaves];
     const int32_t q = blockIdx.x;
+    if (q >= B->n) return;      // a grid rounded up for a reusable launch shape
     const DevPlan& P = *B->plans[q];
     const int32_t* status = (const int32_t*)(ws + B->region[q]);
     const int64_t* table = (const int64_t*)(ws + B->region[q] + 256);
@@ -366,13 +367,18 @@ int batch_grid_limit(int kmax, int w0, int big, int lds_bytes, int cus) {
 hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan* const* plans_host,
                         const DevPlan* const* plans_dev, const int64_t* region, const BatchOut* outs,
                         unsigned char* ws, const int* group_grid, const int* group_lds, const int32_t* big,
-                        int32_t n_big, hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end) {
+                        int32_t n_big, hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end,
+                        int32_t fin_grid) {
     for (int g = 0; g < host.n_groups_used; ++g) {
         const BatchGroup& grp = host.groups[g];
         const hipError_t le = check_lds((const void*)batch_kernel(grp.kmax, grp.w0, grp.big), (size_t)group_lds[g]);
         if (le != hipSuccess) return le;
     }
-    const int clear_grid = (int)std::min<int64_t>(std::max<int64_t>(host.n, 1), 4096);
+    // fin_grid > 0: a fixed launch shape (for graph replay): every group
+    // launches its full persistent grid and the per-query kernels a grid of
+    // fin_grid blocks; surplus workgroups exit at once
+    const int clear_grid = fin_grid > 0 ? std::min(fin_grid, 4096)
+                                        : (int)std::min<int64_t>(std::max<int64_t>(host.n, 1), 4096);
     hipLaunchKernelGGL(k_batch_clear, dim3(clear_grid), dim3(kThreads), 0, stream, dev, ws);
     if (ev_begin) {
         hipError_t e = hipEventRecord(ev_begin, stream);
@@ -380,8 +386,8 @@ hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan
     }
     for (int g = 0; g < host.n_groups_used; ++g) {
         const BatchGroup& grp = host.groups[g];
-        if (grp.n_items == 0) continue;
-        const int blocks = std::max(1, std::min(group_grid[g], grp.n_items));
+        if (grp.n_items == 0 && fin_grid <= 0) continue;
+        const int blocks = fin_grid > 0 ? std::max(1, group_grid[g]) : std::max(1, std::min(group_grid[g], grp.n_items));
         hipLaunchKernelGGL(batch_kernel(grp.kmax, grp.w0, grp.big), dim3(blocks), dim3(kThreads), group_lds[g], stream, dev,
                            g, ws);
     }
@@ -389,7 +395,8 @@ hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan
         hipError_t e = hipEventRecord(ev_end, stream);
         if (e != hipSuccess) return e;
     }
-    if (host.n > 0) hipLaunchKernelGGL(k_batch_fin, dim3(host.n), dim3(kThreads), 0, stream, dev, ws);
+    if (host.n > 0)
+        hipLaunchKernelGGL(k_batch_fin, dim3(fin_grid > 0 ? fin_grid : host.n), dim3(kThreads), 0, stream, dev, ws);
     for (int i = 0; i < n_big; ++i) {
         // group tables too large for one workgroup: the multi-block finalize
         const int32_t q = big[i];

@@ -266,7 +266,7 @@ hipError_t launch_batch(const BatchDev& host, const BatchDev* dev, const DevPlan
                         const DevPlan* const* plans_dev, const int64_t* region, const BatchOut* outs,
                         unsigned char* ws, const int* group_grid, const int* group_lds, const int32_t* big,
                         int32_t n_big, hipStream_t stream, hipEvent_t ev_begin = nullptr,
-                        hipEvent_t ev_end = nullptr);
+                        hipEvent_t ev_end = nullptr, int32_t fin_grid = 0);
 
 // Persistent-grid size and dynamic LDS of a batch kernel instance.
 int batch_grid_limit(int kmax, int w0, int big, int lds_bytes, int cus);

@@ -6,6 +6,15 @@
 // one ccq_execute per query (the single-launch path).  Completion is seen
 // through one event per launch; latency = completion - submission on the
 // host's steady clock.
+//
+// A batched dispatch writes its per-query descriptors (plans, workspace
+// regions, outputs, work items) into the stream's descriptor buffer in
+// device memory and replays a hipGraph of the launch sequence.  The graph's
+// kernel arguments are only that buffer and the arena, so one graph serves
+// every dispatch of the same launch shape: the kernel instances with their
+// grids and LDS sizes, and the query count rounded up to a power of two.
+// Graphs are captured the first time a shape is seen (at most kMaxGraphs
+// per stream; the cache is cleared when full).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -80,6 +89,8 @@ struct Req {
     size_t off, bytes;
 };
 
+constexpr size_t kMaxGraphs = 256;
+
 struct Lane {                     // one launch stream
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -88,7 +99,13 @@ struct Lane {                     // one launch stream
     unsigned char* desc_dev = nullptr;    // device copy (inside the arena)
     size_t desc_bytes = 0;
     bool busy = false;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;   // launch shape -> captured sequence
 };
+
+void drop_graphs(Lane& L) {
+    for (auto& kv : L.graphs) (void)hipGraphExecDestroy(kv.second);
+    L.graphs.clear();
+}
 
 }  // namespace
 
@@ -153,10 +170,26 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
     }
     reqs.assign(s->admitted.begin(), s->admitted.begin() + take);
     s->admitted.erase(s->admitted.begin(), s->admitted.begin() + take);
+    // work-item size for this dispatch: small enough that the dispatch's
+    // tiles make about four items per compute unit (a lone small query then
+    // spreads over the GPU as a single launch would), at most tiles_per_item,
+    // and large enough for the descriptor buffer
+    int64_t all_tiles = 0;
+    for (auto& r : reqs) all_tiles += r.plan->host.n_tiles;
+    int32_t tpi_d = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tpi0, (all_tiles + 4 * s->ctx->cus - 1) /
+                                                                         std::max(1, 4 * s->ctx->cus)));
+    for (;;) {
+        size_t it = 0;
+        for (auto& r : reqs) it += (size_t)items_of(r.plan, tpi_d);
+        if (tpi_d >= tpi0 || desc_size(reqs.size(), it) <= L.desc_bytes) break;
+        tpi_d = std::min<int32_t>(tpi0, tpi_d * 2);
+    }
     const double t = now_s();
     for (auto& r : reqs) r.t_start = t;
     hipError_t e = hipSuccess;
-    if (!s->cfg.batching) {
+    // A dispatch of one query gains nothing from a batch: its own
+    // single-query kernels spread it over the whole GPU at once.
+    if (!s->cfg.batching || reqs.size() == 1) {
         for (auto& r : reqs) {
             e = launch_query(r.plan->host, r.plan->dev, s->arena_base + r.off, L.stream, r.result.keys,
                              r.result.counts, r.result.aggs, r.result.n_groups, r.result.status, r.plan->grid_fused,
@@ -166,7 +199,7 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
     } else {
         // descriptor: BatchDev | counters | plans | regions | clear sizes | outs | items per group
         const int n = (int)reqs.size();
-        const int32_t tpi = s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : 64;
+        const int32_t tpi = tpi_d;
         int group_of[3][kVariants];
         for (auto& row : group_of)
             for (int& g : row) g = -1;
@@ -249,9 +282,35 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
         for (int g = 0; g < n_groups; ++g)
             if (!items[g].empty()) memcpy(h + o_items[g], items[g].data(), sizeof(BatchItem) * items[g].size());
         e = hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, L.stream);
-        if (e == hipSuccess)
+        if (e == hipSuccess && !s->cfg.no_graphs && big.empty()) {
+            // the launch shape: query count rounded up to a power of two, then
+            // each group's kernel instance, grid and LDS
+            int32_t nb = 1;
+            while (nb < n) nb <<= 1;
+            std::vector<int64_t> key = {nb, n_groups};
+            for (int g = 0; g < n_groups; ++g) key.insert(key.end(), {gk[g], gw[g], gb[g], ggrid[g], glds[g]});
+            auto it = L.graphs.find(key);
+            if (it == L.graphs.end()) {
+                if (L.graphs.size() >= kMaxGraphs) drop_graphs(L);
+                hipGraph_t graph = nullptr;
+                hipGraphExec_t exec = nullptr;
+                e = hipStreamBeginCapture(L.stream, hipStreamCaptureModeRelaxed);
+                if (e == hipSuccess) {
+                    const hipError_t le = launch_batch(H, (const BatchDev*)d, plans_host.data(), plans_dev.data(),
+                                                       region.data(), outs.data(), s->arena_base, ggrid.data(),
+                                                       glds.data(), nullptr, 0, L.stream, nullptr, nullptr, nb);
+                    e = hipStreamEndCapture(L.stream, &graph);
+                    if (le != hipSuccess) e = le;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (e == hipSuccess) it = L.graphs.emplace(key, exec).first;
+            }
+            if (e == hipSuccess) e = hipGraphLaunch(it->second, L.stream);
+        } else if (e == hipSuccess) {
             e = launch_batch(H, (const BatchDev*)d, plans_host.data(), plans_dev.data(), region.data(), outs.data(),
                              s->arena_base, ggrid.data(), glds.data(), big.data(), (int32_t)big.size(), L.stream);
+        }
     }
     if (e == hipSuccess) e = hipEventRecord(L.done, L.stream);
     L.running = std::move(reqs);
@@ -444,6 +503,7 @@ void ccq_server_destroy(ccq_server* s) {
         if (L.stream) (void)hipStreamDestroy(L.stream);
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.desc_host) (void)hipHostFree(L.desc_host);
+        drop_graphs(L);
     }
     if (s->arena_base) (void)hipFree(s->arena_base);
     delete s;

@@ -109,3 +109,24 @@ def test_server_rejects_bad_config(setup):
         ccq.Server(setup["ctx"], 1024, max_inflight=4)
     with pytest.raises(ccq.CcqError):
         ccq.Server(setup["ctx"], 256 << 20, max_inflight=0)
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_server_graph_replays_across_rounds(setup, graphs):
+    """Batches of at most 8 queries, so launch shapes repeat and each captured
+    graph is replayed many times; three rounds with unrelated GPU work and
+    synchronisations between them; every answer of every round equals the
+    oracle's."""
+    import torch
+    from paper_2506_10092_amd import ccq
+    s = ccq.Server(setup["ctx"], 256 << 20, max_inflight=16, max_batch=8, n_streams=2, batching=True,
+                   tiles_per_item=64, graphs=graphs)
+    for rnd in range(3):
+        comps, got = _serve(setup, s, setup["plans"])
+        assert all(c["status"] == 0 for c in comps)
+        assert got == setup["expect"], "round %d differs from the oracle (graphs=%s)" % (rnd, graphs)
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        torch.cuda.synchronize()
+        say("graph replay round", rnd, "graphs", graphs, "ok")
+    s.close()
