@@ -3,48 +3,37 @@
 // (templates; instantiated per RLE-column bound in ccq_inst.hip).  Internal
 // to libccq.
 //
-//
 // One query runs as a short launch sequence on one stream:
 //   k_prepare   clear the group table and the status word;
-//   k_fused     the hot path (every step below), persistent; each wavefront
-//               is an independent worker;
-//   finalize    compact the non-empty groups in key order into the result
+//   k_fused     the hot path, persistent; each wavefront is an independent
+//               worker over a contiguous slice of the window;
+//   finalize    the non-empty groups in key order into the result
 //               (k_fin_single for ungrouped queries, else count/scan/write).
 //
-// k_fused, per wavefront: the wave owns a contiguous slice of the logical
-// row window and walks it tile by tile (2048 rows when bit-packed columns
-// take part, otherwise 64 * span rows with span chosen from run density).
-// Per tile:
-//   stage   the runs of every RLE column that overlap the tile are loaded
-//           64 at a time (coalesced) into the wave's LDS slice; a column
-//           whose runs overflow its share of the slice ends the tile early,
-//           so every tile fits and there is no slow path;
-//   a1      run predicates are evaluated on run values, once per run and
-//           lane (several predicates on one column are folded into one range
-//           or one set on the host, as the paper's composite-predicate rule
-//           does);
-//   a2      each lane owns a span of rows and merges the run ends of all RLE
-//           columns inside it: a boundary of any column starts a new aligned
-//           run (Section 6 alignment; Algorithm 1 restricted to the runs that
-//           survive the predicates, extended to k columns);
-//   a3      run mode: surviving aligned runs are consumed in place;
-//           row mode: surviving rows are compacted with a wavefront scan into
-//           an LDS row list;
-//   a4      row mode: only the bit-packed words under surviving rows are
-//           staged in LDS; each listed row unpacks its code and looks it up in
-//           an LDS code table that folds the column's predicates and its
-//           group-key slot (the RLE x Plain AND of Section 5.1 done per tile);
-//   a5      Index points: in row mode a point bitmap says which listed rows
-//           carry a point (Plain x Index); in run mode each point finds its
-//           runs by binary search over the staged run ends (idx_in_rle,
-//           Algorithm 3);
-//   a6      group id = mixed radix over key slots, first key most
-//           significant, so id order is ascending key order;
-//   a7      COUNT += run length and SUM += value * run length per aligned run
-//           (Section 7, Aggregating Phase), or +1 / +value per row; runs of
-//           one group that follow each other in a lane are added in registers
-//           first; small tables live in LDS per workgroup and are added to the
-//           global table once at the end.
+// Every path works on 2048-row tiles starting at multiples of 32 rows; lane
+// l of a wave owns rows [32l, 32l + 32) of the tile, one 32-bit word of
+// every row bitmap.  Three paths share that layout:
+//   fast row path   one bit-packed column of width 14 or 20 (no RLE value
+//                   per row): run batches are read straight from HBM, their
+//                   predicate outcomes (a1) become toggle bitmaps whose
+//                   prefix XOR is each column's pass mask (a2, a3); active
+//                   lane-words are gathered into full batches and counted
+//                   through an LDS code table into lane-replicated LDS
+//                   counts (a4, a6, a7); Index points probe the pass bits
+//                   (a5).  A software pipeline keeps the next tile's words
+//                   and run batches in flight.
+//   staged paths    the tile's runs are staged in LDS (stage_tile) with a
+//                   run-boundary bitmap per column; the staged run holding
+//                   row r is a prefix count plus a popcount (no search), the
+//                   union of the columns' bitmaps is the aligned boundary
+//                   set (a2), and toggles give the pass masks (a1, a3).
+//     run mode      no bit-packed column: a lane cuts its word at the key
+//                   and SUM columns' boundaries; each piece is an aligned
+//                   run adding COUNT += rows and SUM += value * rows (a7).
+//     generic rows  each lane walks its 32 rows; packed codes come from LDS-
+//                   staged words (a4), RLE values from the advancing staged
+//                   run, and rows of one group add up in registers before
+//                   reaching a compact LDS group table (a6, a7).
 #pragma once
 
 #include "ccq_plan.h"
