@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 5
+#define CCQ_ABI_VERSION 6
 
 typedef int32_t ccq_status;
 enum {
@@ -341,6 +341,61 @@ ccq_status ccq_plain_to_plain_index(ccq_context* ctx, const void* values, int32_
                                     int32_t bit_width, int64_t base, void* ws, size_t ws_bytes, void* stream,
                                     uint32_t* packed, int64_t packed_words, int64_t* idx_positions, void* idx_values,
                                     int64_t idx_capacity, int64_t* n_points);
+
+/* ---- joins on encoded columns (Section 8: Get Join Index, Apply Join Index) ----
+ *
+ * An equi-join of column left_col of `left` (rows [left_begin, left_end))
+ * with column right_col of `right` (rows [right_begin, right_end)), on the
+ * columns' integer values (a bit-packed column's base + code; a dictionary
+ * column joins on its codes).  The join works on entries: an RLE run (its
+ * value and its rows, clipped to the window), a listed point of an Index
+ * column (rows an Index column does not list take no part), or one row of a
+ * bit-packed column.  Each pair of equal-valued entries gives one block, the
+ * cross product of the two entries' row ranges: an RLE side keeps its join
+ * index as row ranges, the other encodings as single rows (Table 6).  The
+ * join's row pairs are the blocks' pairs, block by block with the left row
+ * outer; blocks of one left entry are adjacent and left entries come in row
+ * order, but the order of the blocks within one left entry is unspecified
+ * (the Join Index is unsorted).
+ *
+ * Both tables need device contexts on one device.  Workspace: device memory
+ * of ccq_join_workspace_bytes(...) bytes (same arguments), 256-byte
+ * aligned, not shared with a concurrent call.  ccq_join_index enqueues its
+ * kernels on `stream` and synchronises it twice (entry counts, then the
+ * number of blocks); `blocks` is a device array of `capacity` blocks owned by
+ * the caller.  *n_blocks and *n_pairs (host) receive the number of blocks and
+ * of row pairs (the join's output rows; below 2^63 assumed) also when the
+ * capacity is too small (CCQ_E_CAPACITY, nothing written).  Errors:
+ * CCQ_E_INVALID (NULL pointers, column or window out of range, host-only
+ * context, misaligned workspace), CCQ_E_CAPACITY, CCQ_E_HIP.  Run ends and
+ * positions must satisfy ccq_table_validate. */
+typedef struct {
+    int64_t left_start, left_len;    /* rows [left_start, left_start + left_len) of the left table */
+    int64_t right_start, right_len;  /* rows [right_start, right_start + right_len) of the right table */
+} ccq_join_block;
+
+size_t ccq_join_workspace_bytes(const ccq_table* left, int32_t left_col, int64_t left_begin, int64_t left_end,
+                                const ccq_table* right, int32_t right_col, int64_t right_begin, int64_t right_end);
+ccq_status ccq_join_index(const ccq_table* left, int32_t left_col, int64_t left_begin, int64_t left_end,
+                          const ccq_table* right, int32_t right_col, int64_t right_begin, int64_t right_end, void* ws,
+                          size_t ws_bytes, void* stream, ccq_join_block* blocks, int64_t capacity, int64_t* n_blocks,
+                          int64_t* n_pairs);
+
+/* Apply Join Index: out[p] = the value of column `col` of table t at the
+ * side's row of the join's p-th pair (side 0: left rows, 1: right rows), in
+ * the pair order above; an Index column holds 0 at rows it does not list;
+ * a bit-packed column gives base + code.  blocks: device array of n_blocks
+ * (from ccq_join_index over t as that side, or any blocks whose side rows
+ * lie in t, with pairs per block below 2^63).  Workspace: device memory of
+ * ccq_join_apply_workspace_bytes(n_blocks) bytes, 256-byte aligned.
+ * Synchronises `stream` once (the number of pairs), then enqueues the gather;
+ * out: device int64[capacity]; *n_out (host) receives the number of pairs
+ * also on CCQ_E_CAPACITY (nothing written).  CCQ_E_INVALID for a block with a
+ * negative length or side rows outside the table (checked on the device
+ * before anything is written). */
+size_t ccq_join_apply_workspace_bytes(int64_t n_blocks);
+ccq_status ccq_join_apply(const ccq_table* t, int32_t col, const ccq_join_block* blocks, int64_t n_blocks, int32_t side,
+                          void* ws, size_t ws_bytes, void* stream, int64_t* out, int64_t capacity, int64_t* n_out);
 
 /* ---- batched execution: many queries, one launch sequence ----
  *

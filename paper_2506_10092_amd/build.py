@@ -25,7 +25,7 @@ HIPCC_FLAGS = [
 # (source, extra defines, object name)
 UNITS = [("ccq_api.cpp", [], "ccq_api"), ("ccq_batch.cpp", [], "ccq_batch"),
          ("ccq_server.cpp", [], "ccq_server"), ("ccq_kernels.hip", [], "ccq_kernels"),
-         ("ccq_encode.hip", [], "ccq_encode")]
+         ("ccq_encode.hip", [], "ccq_encode"), ("ccq_join.hip", [], "ccq_join")]
 UNITS += [("ccq_inst.hip", ["-DCCQ_KMAX=%d" % k, "-DCCQ_BATCH=%d" % b], "ccq_inst_k%d_%s" % (k, "batch" if b else "fused"))
           for k in (2, 4, 8) for b in (0, 1)]
 

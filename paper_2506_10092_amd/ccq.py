@@ -153,6 +153,11 @@ SIGNATURES = {
                                       ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "ccq_plain_to_plain_index": (_i32, [_vp, _vp, _i32, _i64, _i32, _i64, _vp, _sz, _vp, _vp, _i64, _vp, _vp, _i64,
                                         ctypes.POINTER(_i64)]),
+    "ccq_join_workspace_bytes": (_sz, [_vp, _i32, _i64, _i64, _vp, _i32, _i64, _i64]),
+    "ccq_join_index": (_i32, [_vp, _i32, _i64, _i64, _vp, _i32, _i64, _i64, _vp, _sz, _vp, _vp, _i64,
+                              ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "ccq_join_apply_workspace_bytes": (_sz, [_i64]),
+    "ccq_join_apply": (_i32, [_vp, _i32, _vp, _i64, _i32, _vp, _sz, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
 }
 
 _lib = None
@@ -626,6 +631,66 @@ def plain_to_plain_index(ctx, values, bit_width, base, stream=None):
     _check(call(ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vals.data_ptr()), q))
     return {"column": {"enc": "bitpacked", "packed": packed, "w": int(bit_width), "base": int(base)},
             "points": {"positions": pos[:q], "values": vals[:q]}}
+
+
+# ---- joins (ccq_join_*)
+
+def _col_index(table, col):
+    return table.names.index(col) if isinstance(col, str) else int(col)
+
+
+def join_index(left, left_col, right, right_col, left_window=None, right_window=None, stream=None):
+    """Get Join Index of two tables' columns: (blocks, n_pairs), blocks an
+    int64 device tensor [n, 4] of (left_start, left_len, right_start,
+    right_len) rows."""
+    import torch
+    lw = left_window or (0, left.n_rows)
+    rw = right_window or (0, right.n_rows)
+    L = lib()
+    lc, rc = _col_index(left, left_col), _col_index(right, right_col)
+    wsb = L.ccq_join_workspace_bytes(left.h, lc, lw[0], lw[1], right.h, rc, rw[0], rw[1])
+    if wsb == 0:          # the size call fails only on invalid arguments
+        raise CcqError(E_INVALID, L.ccq_last_error().decode())
+    dev = torch.device("cuda", left.ctx.device)
+    ws = torch.empty(max(int(wsb), 256), dtype=torch.uint8, device=dev)
+    nb, npairs = ctypes.c_int64(), ctypes.c_int64()
+
+    def call(buf, cap):
+        return L.ccq_join_index(left.h, lc, lw[0], lw[1], right.h, rc, rw[0], rw[1], ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream_ptr(stream), buf, cap, ctypes.byref(nb), ctypes.byref(npairs))
+    st = call(None, 0)
+    if st != E_CAPACITY and st != OK:
+        _check(st)
+    blocks = torch.empty((max(nb.value, 1), 4), dtype=torch.int64, device=dev)
+    if nb.value:
+        _check(call(ctypes.c_void_p(blocks.data_ptr()), nb.value))
+    return blocks[:nb.value], npairs.value
+
+
+def join_apply(table, col, blocks, side, stream=None):
+    """Apply Join Index: the column's values at the `side` ("left"/0 or
+    "right"/1) rows of the blocks' pairs, an int64 device tensor."""
+    import torch
+    blocks = blocks.contiguous()
+    sd = {"left": 0, "right": 1}.get(side, side)
+    L = lib()
+    n = blocks.shape[0]
+    dev = torch.device("cuda", table.ctx.device)
+    ws = torch.empty(max(int(L.ccq_join_apply_workspace_bytes(n)), 256), dtype=torch.uint8, device=dev)
+    n_out = ctypes.c_int64()
+    ci = _col_index(table, col)
+
+    def call(buf, cap):
+        return L.ccq_join_apply(table.h, ci, ctypes.c_void_p(blocks.data_ptr()) if n else None, n, sd,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), buf, cap,
+                                ctypes.byref(n_out))
+    st = call(None, 0)
+    if st != E_CAPACITY and st != OK:
+        _check(st)
+    out = torch.empty(max(n_out.value, 1), dtype=torch.int64, device=dev)
+    if n_out.value:
+        _check(call(ctypes.c_void_p(out.data_ptr()), n_out.value))
+    return out[:n_out.value]
 
 
 def avg_var(count, s, ss):

@@ -35,7 +35,7 @@ def test_header_functions_are_exported():
 
 
 def test_abi_version():
-    assert ccq.lib().ccq_abi_version() == 5
+    assert ccq.lib().ccq_abi_version() == 6
 
 
 def _host_table(columns, n_rows):
