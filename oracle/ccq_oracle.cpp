@@ -11,7 +11,11 @@
  *   1. every referenced column is decompressed to one int64 value per logical
  *      row (Section 3.1 "Basic Encodings": RLE runs (value, start, end), Index
  *      (value, position); Section 3.2 bit-width reduction with a global
- *      reference value, value = base + code);
+ *      reference value, value = base + code; Section 3.2 composite encodings:
+ *      RLE + Index is pure runs (value, start, end) and Index points on the
+ *      rows no run covers, disjoint and together covering every row; Plain +
+ *      Index is the bit-packed codes with the outlier rows listed as Index
+ *      points, whose codes are never read);
  *   2. a row qualifies when every clause holds on its values (selection,
  *      Section 6): a clause is one predicate, or the OR of the predicates
  *      that share a clause id (OR, Section 5.2); a negated predicate holds
@@ -54,7 +58,7 @@
 
 extern "C" {
 
-enum { ORC_RLE = 1, ORC_INDEX = 2, ORC_BITPACKED = 3 };
+enum { ORC_RLE = 1, ORC_INDEX = 2, ORC_BITPACKED = 3, ORC_RLE_INDEX = 4, ORC_PLAIN_INDEX = 5 };
 enum { ORC_I32 = 1, ORC_I64 = 2 };
 enum { ORC_RANGE = 1, ORC_IN = 2, ORC_NOT_RANGE = 3, ORC_NOT_IN = 4 };
 enum { ORC_COUNT = 1, ORC_SUM = 2, ORC_MIN = 3, ORC_MAX = 4 };
@@ -71,6 +75,12 @@ typedef struct {
     int32_t w;                  /* BITPACKED bit width */
     int32_t ptype;              /* INDEX position type: ORC_I32 or ORC_I64 */
     int64_t base;               /* BITPACKED: value = base + code */
+    /* composite encodings (Section 3.2) */
+    const int64_t* run_starts;  /* RLE_INDEX: first row of each pure run (its end exclusive in run_ends) */
+    int64_t pt_n;               /* RLE_INDEX, PLAIN_INDEX: listed points */
+    const void* pt_positions;   /* strictly increasing, pt_ptype */
+    const void* pt_values;      /* pt_vtype */
+    int32_t pt_ptype, pt_vtype;
 } orc_column;
 
 typedef struct {
@@ -122,6 +132,38 @@ int64_t position_at(const orc_column& c, int64_t i) {
     return c.ptype == ORC_I32 ? (int64_t)((const int32_t*)c.positions)[i] : ((const int64_t*)c.positions)[i];
 }
 
+int64_t point_position(const orc_column& c, int64_t i) {
+    return c.pt_ptype == ORC_I32 ? (int64_t)((const int32_t*)c.pt_positions)[i]
+                                 : ((const int64_t*)c.pt_positions)[i];
+}
+
+int64_t point_value(const orc_column& c, int64_t i) {
+    return c.pt_vtype == ORC_I32 ? (int64_t)((const int32_t*)c.pt_values)[i] : ((const int64_t*)c.pt_values)[i];
+}
+
+/* first point of a composite column whose position is >= r */
+int64_t first_composite_point(const orc_column& c, int64_t r) {
+    int64_t lo = 0, hi = c.pt_n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (point_position(c, mid) < r) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+std::string validate_points(const orc_column& c, int64_t n_rows) {
+    if (c.pt_ptype != ORC_I32 && c.pt_ptype != ORC_I64) return "point position type must be int32 or int64";
+    if (c.pt_vtype != ORC_I32 && c.pt_vtype != ORC_I64) return "point value type must be int32 or int64";
+    if (c.pt_n < 0 || (c.pt_n > 0 && (!c.pt_positions || !c.pt_values))) return "point arrays missing";
+    int64_t prev = -1;
+    for (int64_t i = 0; i < c.pt_n; i++) {
+        int64_t p = point_position(c, i);
+        if (p <= prev || p >= n_rows) return "point positions must be strictly increasing in [0, rows)";
+        prev = p;
+    }
+    return "";
+}
+
 /* first listed point whose position is >= r (binary search over positions) */
 int64_t first_point_at_or_after(const orc_column& c, int64_t r) {
     int64_t lo = 0, hi = c.n;
@@ -152,10 +194,30 @@ std::string validate_column(const orc_column& c, int64_t n_rows) {
             if (p <= prev || p >= n_rows) return "Index positions must be strictly increasing in [0, rows)";
             prev = p;
         }
-    } else if (c.enc == ORC_BITPACKED) {
+    } else if (c.enc == ORC_BITPACKED || c.enc == ORC_PLAIN_INDEX) {
         if (c.w < 1 || c.w > 32) return "bit width must be in 1..32";
         if (!c.packed) return "packed stream missing";
         if (c.n != n_rows) return "bit-packed column must hold one code per row";
+        if (c.enc == ORC_PLAIN_INDEX) return validate_points(c, n_rows);
+    } else if (c.enc == ORC_RLE_INDEX) {
+        if (c.vtype != ORC_I32 && c.vtype != ORC_I64) return "RLE value type must be int32 or int64";
+        if (c.n < 0 || (c.n > 0 && (!c.values || !c.run_starts || !c.run_ends))) return "RLE part arrays missing";
+        std::string e = validate_points(c, n_rows);
+        if (!e.empty()) return e;
+        /* pure runs in order, disjoint; points on none of them; together every row */
+        int64_t prev_end = 0, covered = 0;
+        for (int64_t i = 0; i < c.n; i++) {
+            if (c.run_starts[i] < prev_end || c.run_ends[i] <= c.run_starts[i] || c.run_ends[i] > n_rows)
+                return "RLE part runs must be non-empty, ordered, disjoint and inside the rows";
+            covered += c.run_ends[i] - c.run_starts[i];
+            prev_end = c.run_ends[i];
+        }
+        for (int64_t k = 0; k < c.pt_n; k++) {
+            int64_t p = point_position(c, k);
+            int64_t i = std::upper_bound(c.run_ends, c.run_ends + c.n, p) - c.run_ends;
+            if (i < c.n && c.run_starts[i] <= p) return "a point lies inside a pure run";
+        }
+        if (covered + c.pt_n != n_rows) return "runs and points must cover every row";
     } else {
         return "unknown encoding";
     }
@@ -180,6 +242,13 @@ void decode(const orc_column& c, int64_t r0, int64_t r1, int64_t* out) {
         for (int64_t k = 0; k < len; k++) out[k] = 0;
         for (int64_t i = first_point_at_or_after(c, r0); i < c.n && position_at(c, i) < r1; i++)
             out[position_at(c, i) - r0] = value_at(c, i);
+    } else if (c.enc == ORC_RLE_INDEX) {
+        /* pure runs first (rows between them are points, filled below) */
+        for (int64_t i = std::upper_bound(c.run_ends, c.run_ends + c.n, r0) - c.run_ends;
+             i < c.n && c.run_starts[i] < r1; i++) {
+            int64_t v = value_at(c, i);
+            for (int64_t r = std::max(c.run_starts[i], r0); r < std::min(c.run_ends[i], r1); r++) out[r - r0] = v;
+        }
     } else {
         const uint64_t mask = c.w == 32 ? 0xFFFFFFFFull : ((1ull << c.w) - 1);
         for (int64_t r = r0; r < r1; r++) {
@@ -190,6 +259,10 @@ void decode(const orc_column& c, int64_t r0, int64_t r1, int64_t* out) {
             out[r - r0] = c.base + (int64_t)code;
         }
     }
+    /* composite: the Index part's rows take the points' values */
+    if (c.enc == ORC_RLE_INDEX || c.enc == ORC_PLAIN_INDEX)
+        for (int64_t i = first_composite_point(c, r0); i < c.pt_n && point_position(c, i) < r1; i++)
+            out[point_position(c, i) - r0] = point_value(c, i);
 }
 
 struct Query {

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.environ.get("CCQ_ORACLE_LIB") or os.path.join(_HERE, "libccq_oracle.so")
 _lib = None
 
-RLE, INDEX, BITPACKED = 1, 2, 3
+RLE, INDEX, BITPACKED, RLE_INDEX, PLAIN_INDEX = 1, 2, 3, 4, 5
 I32, I64 = 1, 2
 RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
 COUNT, SUM, MIN, MAX = 1, 2, 3, 4
@@ -33,7 +33,9 @@ class OrcColumn(ctypes.Structure):
     _fields_ = [("enc", ctypes.c_int32), ("vtype", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("values", ctypes.c_void_p), ("run_ends", ctypes.c_void_p), ("positions", ctypes.c_void_p),
                 ("packed", ctypes.c_void_p), ("w", ctypes.c_int32), ("ptype", ctypes.c_int32),
-                ("base", ctypes.c_int64)]
+                ("base", ctypes.c_int64), ("run_starts", ctypes.c_void_p), ("pt_n", ctypes.c_int64),
+                ("pt_positions", ctypes.c_void_p), ("pt_values", ctypes.c_void_p), ("pt_ptype", ctypes.c_int32),
+                ("pt_vtype", ctypes.c_int32)]
 
 
 class OrcPred(ctypes.Structure):
@@ -115,7 +117,7 @@ def _column(c, n_rows, keep):
         keep += [v, p]
         oc.enc, oc.vtype, oc.n, oc.ptype = INDEX, _vtype(v), len(p), _vtype(p)
         oc.values, oc.positions = v.ctypes.data, p.ctypes.data
-    elif c["enc"] == "bitpacked":
+    elif c["enc"] in ("bitpacked", "plain+index"):
         pk = np.ascontiguousarray(c["packed"], dtype=np.uint32)
         w = int(c["w"])
         if len(pk) < (n_rows * w + 31) // 32 + 2:
@@ -123,9 +125,35 @@ def _column(c, n_rows, keep):
         keep.append(pk)
         oc.enc, oc.n, oc.w, oc.base = BITPACKED, n_rows, w, int(c.get("base", 0))
         oc.packed = pk.ctypes.data
+        if c["enc"] == "plain+index":
+            oc.enc = PLAIN_INDEX
+            _points(oc, c, keep)
+    elif c["enc"] == "rle+index":
+        # Section 3.2 form: pure runs (values, starts, exclusive ends) and
+        # points on the remaining rows
+        v = np.ascontiguousarray(c["values"])
+        s0 = np.ascontiguousarray(c["run_starts"], dtype=np.int64)
+        e = np.ascontiguousarray(c["run_ends"], dtype=np.int64)
+        if not len(v) == len(s0) == len(e):
+            raise OracleError("RLE part values, run_starts and run_ends differ in length")
+        keep += [v, s0, e]
+        oc.enc, oc.vtype, oc.n = RLE_INDEX, _vtype(v), len(e)
+        oc.values, oc.run_starts, oc.run_ends = v.ctypes.data, s0.ctypes.data, e.ctypes.data
+        _points(oc, c, keep)
     else:
         raise OracleError("unknown encoding %r" % (c["enc"],))
     return oc
+
+
+def _points(oc, c, keep):
+    """The Index part of a composite column (positions, point_values)."""
+    p = np.ascontiguousarray(c["positions"])
+    v = np.ascontiguousarray(c["point_values"])
+    if len(p) != len(v):
+        raise OracleError("point positions and values differ in length")
+    keep += [p, v]
+    oc.pt_n, oc.pt_ptype, oc.pt_vtype = len(p), _vtype(p), _vtype(v)
+    oc.pt_positions, oc.pt_values = p.ctypes.data, v.ctypes.data
 
 
 def decode(column, n_rows, r0=0, r1=None):

@@ -25,13 +25,27 @@ def decode_rows(col, n_rows):
         for p, v in zip(col["positions"], col["values"]):
             out[int(p)] = int(v)
         return out
-    if enc == "bitpacked":
+    if enc in ("bitpacked", "plain+index"):
         w = int(col["w"])
         big = 0
         for i, word in enumerate(col["packed"]):
             big |= int(word) << (32 * i)
         mask = (1 << w) - 1
-        return [int(col.get("base", 0)) + ((big >> (r * w)) & mask) for r in range(n_rows)]
+        out = [int(col.get("base", 0)) + ((big >> (r * w)) & mask) for r in range(n_rows)]
+        if enc == "plain+index":
+            for p, v in zip(col["positions"], col["point_values"]):
+                out[int(p)] = int(v)
+        return out
+    if enc == "rle+index":
+        out = [None] * n_rows
+        for v, s, e in zip(col["values"], col["run_starts"], col["run_ends"]):
+            for r in range(int(s), int(e)):
+                out[r] = int(v)
+        for p, v in zip(col["positions"], col["point_values"]):
+            assert out[int(p)] is None
+            out[int(p)] = int(v)
+        assert None not in out
+        return out
     raise ValueError(enc)
 
 

@@ -156,3 +156,104 @@ def tiny_query_with_exprs(rng, n, wd):
             aggs.append((f, (a, "+-*"[int(rng.integers(0, 3))], b)))
     q["aggs"] = aggs
     return q
+
+
+def composite_columns(rng, n):
+    """Two composite columns over n rows (Section 3.2): x as RLE + Index
+    (pure runs of two or more rows, single rows as points) and y as Plain +
+    Index (values outside [base, base + 2^w) as points; the
+    codes at those rows are random, since they are never read)."""
+    # segments: pure runs of 2-6 rows and single rows (points), in random order
+    p_single = float(rng.choice([0.0, 0.3, 0.9]))
+    rv, rs, re_, pp, pv = [], [], [], [], []
+    r = 0
+    while r < n:
+        v = int(rng.integers(-5, 20))
+        if rng.random() < p_single or r + 2 > n:
+            pp.append(r)
+            pv.append(v)
+            r += 1
+        else:
+            e = min(n, r + int(rng.integers(2, 7)))
+            rv.append(v)
+            rs.append(r)
+            re_.append(e)
+            r = e
+    xs = np.zeros(n, dtype=np.int64)
+    for v, a, b in zip(rv, rs, re_):
+        xs[a:b] = v
+    xs[np.asarray(pp, dtype=np.int64)] = pv
+    x = {"enc": "rle+index", "values": np.asarray(rv, dtype=np.int64), "run_starts": np.asarray(rs, dtype=np.int64),
+         "run_ends": np.asarray(re_, dtype=np.int64), "positions": np.asarray(pp, dtype=np.int32),
+         "point_values": np.asarray(pv, dtype=np.int64)}
+    w = int(rng.integers(1, 12))
+    base = int(rng.integers(-50, 50))
+    ys = base + rng.integers(0, 1 << w, size=n)
+    out = rng.random(n) < rng.choice([0.0, 0.05, 0.3])
+    ys = np.where(out, rng.choice([-1, 1], size=n) * rng.integers(1 << 20, 1 << 40, size=n), ys).astype(np.int64)
+    inside = (ys >= base) & (ys < base + (1 << w))
+    codes = np.where(inside, ys - base, rng.integers(0, 1 << w, size=n)).astype(np.uint32)
+    pos = np.flatnonzero(~inside).astype(np.int32)
+    y = {"enc": "plain+index", "packed": datagen.pack_codes(codes, w), "w": w, "base": base,
+         "positions": pos, "point_values": ys[pos].copy()}
+    return x, y, xs, ys
+
+
+def abi_column(col, n_rows):
+    """The library's form of a column.  RLE + Index takes the RLE part as
+    run ends only: run i covers the rows from the previous end to its own
+    that no point lists, and the last run ends at n_rows (a column of points
+    only gets one run, whose value is never read)."""
+    if col["enc"] != "rle+index":
+        return col
+    v, e = col["values"], np.asarray(col["run_ends"], dtype=np.int64).copy()
+    if len(e) == 0:
+        v, e = np.zeros(1, dtype=np.asarray(v).dtype), np.array([n_rows], dtype=np.int64)
+    e[-1] = n_rows
+    return {"enc": "rle+index", "values": v, "run_ends": e, "positions": col["positions"],
+            "point_values": col["point_values"]}
+
+
+def composite_table(rng, n):
+    """tiny_table's columns plus the composites x and y."""
+    t, wd = tiny_table(rng, n)
+    x, y, _, _ = composite_columns(rng, n)
+    t["columns"]["x"] = x
+    t["columns"]["y"] = y
+    return t, wd
+
+
+def tiny_query_with_composites(rng, n, wd):
+    """Predicates, SUM, MIN, MAX and expressions over the composite columns
+    x and y beside the plain columns; keys on the other columns."""
+    preds = []
+    lo = int(rng.integers(-6, 20))
+    kind = rng.choice(["range", "not_range", "in"])
+    if rng.random() < 0.7:
+        if kind == "in":
+            preds.append(("x", "in", sorted(set(int(v) for v in rng.integers(-5, 20, size=int(rng.integers(0, 6)))))))
+        else:
+            preds.append(("x", str(kind), lo, lo + int(rng.integers(1, 15))))
+    if rng.random() < 0.5:
+        a = int(rng.integers(-100, 100))
+        preds.append(("y", str(rng.choice(["range", "not_range"])), a, a + int(rng.integers(1, 400))))
+    if rng.random() < 0.4:
+        lo = int(rng.integers(-6, 20))
+        preds.append(("r0", "range", lo, lo + int(rng.integers(1, 20))))
+    if rng.random() < 0.3:
+        preds.append(("d", "in", sorted(set(int(v) for v in rng.integers(0, 1 << wd, size=int(rng.integers(0, 6)))))))
+    keys = []
+    if rng.random() < 0.4:
+        keys.append(("d", 0, 1 << wd))
+    if rng.random() < 0.3:
+        keys.append(("r2", 0, 20))
+        preds.append(("r2", "range", 0, 20))
+    aggs = [("count",)]
+    pool = [("sum", "x"), ("sum", "y"), ("min", "x"), ("max", "y"), ("max", "x"), ("min", "y"), ("sum", "s"),
+            ("sum", ("x", "+", "y")), ("sum", ("x", "*", "r0")), ("min", ("y", "-", "x")), ("sum", "r1")]
+    for i in rng.permutation(len(pool))[:int(rng.integers(1, 5))]:
+        aggs.append(pool[i])
+    a = int(rng.integers(0, n))
+    b = int(rng.integers(a, n + 1))
+    win = (a, b) if rng.random() < 0.3 else (0, n)
+    return {"preds": preds, "keys": keys, "aggs": aggs, "window": win}

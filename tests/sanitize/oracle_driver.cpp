@@ -4,7 +4,8 @@
 //
 // It links oracle/ccq_oracle.cpp directly, builds seeded random tables (RLE
 // with int32 and int64 values, Index with int32 and int64 positions,
-// bit-packed columns of every width), runs queries with range / IN / NOT
+// bit-packed columns of every width, RLE + Index and Plain + Index
+// composites), runs queries with range / IN / NOT
 // predicates, OR clauses, keys, SUM / MIN / MAX and two-column expressions
 // over several thread counts and windows, and checks every answer against
 // its own row-by-row evaluation.  Any sanitizer report aborts the process.
@@ -25,6 +26,11 @@ typedef struct {
     const uint32_t* packed;
     int32_t w, ptype;
     int64_t base;
+    const int64_t* run_starts;
+    int64_t pt_n;
+    const void* pt_positions;
+    const void* pt_values;
+    int32_t pt_ptype, pt_vtype;
 } orc_column;
 typedef struct {
     int32_t col, op;
@@ -56,7 +62,7 @@ int64_t uni(int64_t lo, int64_t hi) { return lo + (int64_t)(rng() % (uint64_t)(h
 struct Col {
     orc_column d{};
     std::vector<int32_t> v32, p32;
-    std::vector<int64_t> v64, ends, p64;
+    std::vector<int64_t> v64, ends, p64, starts, pv;
     std::vector<uint32_t> packed;
     std::vector<int64_t> rows;   // the decoded column, for the driver's own evaluation
 };
@@ -119,6 +125,58 @@ Col make_packed(int64_t n, int w, int64_t base) {
     return c;
 }
 
+// RLE + Index: pure runs of 2-8 rows and single rows listed as points
+Col make_rle_index(int64_t n, bool wide_pos) {
+    Col c;
+    c.rows.assign(n, 0);
+    int64_t r = 0;
+    while (r < n) {
+        const int64_t v = uni(-6, 20);
+        if (rng() % 3 == 0 || r + 2 > n) {
+            if (wide_pos) c.p64.push_back(r); else c.p32.push_back((int32_t)r);
+            c.pv.push_back(v);
+            c.rows[r++] = v;
+        } else {
+            const int64_t e = std::min(n, r + uni(2, 9));
+            c.v64.push_back(v);
+            c.starts.push_back(r);
+            c.ends.push_back(e);
+            for (; r < e; ++r) c.rows[r] = v;
+        }
+    }
+    c.d.enc = 4;
+    c.d.vtype = 2;
+    c.d.n = (int64_t)c.ends.size();
+    c.d.values = c.v64.data();
+    c.d.run_starts = c.starts.data();
+    c.d.run_ends = c.ends.data();
+    c.d.pt_n = (int64_t)c.pv.size();
+    c.d.pt_ptype = wide_pos ? 2 : 1;
+    c.d.pt_vtype = 2;
+    c.d.pt_positions = wide_pos ? (const void*)c.p64.data() : (const void*)c.p32.data();
+    c.d.pt_values = c.pv.data();
+    return c;
+}
+
+// Plain + Index: 6-bit codes, about one row in five an outlier point
+Col make_plain_index(int64_t n) {
+    Col c = make_packed(n, 6, -10);
+    for (int64_t r = 0; r < n; ++r)
+        if (rng() % 5 == 0) {
+            const int64_t v = uni(-1000, 1000);
+            c.p32.push_back((int32_t)r);
+            c.pv.push_back(v);
+            c.rows[r] = v;
+        }
+    c.d.enc = 5;
+    c.d.pt_n = (int64_t)c.pv.size();
+    c.d.pt_ptype = 1;
+    c.d.pt_vtype = 2;
+    c.d.pt_positions = c.p32.data();
+    c.d.pt_values = c.pv.data();
+    return c;
+}
+
 }  // namespace
 
 int main() {
@@ -131,6 +189,8 @@ int main() {
         cols.push_back(make_index(n, t % 3 == 0));
         const int w = 1 + t % 32;
         cols.push_back(make_packed(n, w, t % 2 ? -(int64_t(1) << (w - 1)) : 0));
+        cols.push_back(make_rle_index(n, t % 2 == 0));
+        cols.push_back(make_plain_index(n));
         std::vector<orc_column> d;
         for (auto& c : cols) d.push_back(c.d);
         for (int qi = 0; qi < 6; ++qi) {
@@ -139,7 +199,7 @@ int main() {
             const int np = (int)uni(0, 4);
             for (int i = 0; i < np; ++i) {
                 orc_pred p{};
-                p.col = (int)uni(0, 4);
+                p.col = (int)uni(0, 6);
                 p.op = (int)uni(1, 5);
                 p.lo = uni(-10, 15);
                 p.hi = p.lo + uni(0, 20);
@@ -155,7 +215,8 @@ int main() {
             if (rng() % 2) keys.push_back({1, 0, 32});       // values of column 1 lie in [-6, 20): some out of
                                                            // the domain, which the oracle reports as an error
             std::vector<orc_agg> aggs = {{1, -1, 0, 0}, {2, 2, 0, 0}, {3, 0, 0, 0}, {4, 3, 0, 0},
-                                         {2, 0, 1, 1}, {3, 3, 3, 1}, {4, 0, 2, 2}};
+                                         {2, 0, 1, 1}, {3, 3, 3, 1}, {4, 0, 2, 2}, {2, 4, 1, 5}};
+            if (rng() % 2) aggs.back() = {3, 5, 0, 0};
             const int64_t rb = uni(0, n), re = uni(rb, n + 1);
             const int threads = 1 + (int)uni(0, 4);
             void* h = orc_query(d.data(), (int32_t)d.size(), n, preds.data(), (int32_t)preds.size(), keys.data(),

@@ -22,8 +22,9 @@ MUTANTS = {
                              "any = holds(q.clauses[c][0]);"),
     "rle_run_one_row_long": ("int64_t stop = std::min(c.run_ends[i], r1);",
                              "int64_t stop = std::min(c.run_ends[i] + 1, r1);"),
-    "rle_value_of_next_run": ("int64_t v = value_at(c, i);",
-                              "int64_t v = value_at(c, i + 1 < c.n ? i + 1 : i);"),
+    "rle_value_of_next_run": ("int64_t stop = std::min(c.run_ends[i], r1);\n            int64_t v = value_at(c, i);",
+                              "int64_t stop = std::min(c.run_ends[i], r1);\n"
+                              "            int64_t v = value_at(c, i + 1 < c.n ? i + 1 : i);"),
     "index_value_shifted": ("out[position_at(c, i) - r0] = value_at(c, i);",
                             "out[position_at(c, i) - r0] = value_at(c, i > 0 ? i - 1 : i);"),
     "bitpacked_drops_base": ("out[r - r0] = c.base + (int64_t)code;", "out[r - r0] = (int64_t)code;"),
@@ -41,6 +42,12 @@ MUTANTS = {
     "thread_merge_drops_counts": ("it->second.count += kv.second.count;", "it->second.count = kv.second.count;"),
     "in_list_first_only": ("q.in_sets[p].insert(q.preds[p].in_list[i]);",
                            "if (i == 0) q.in_sets[p].insert(q.preds[p].in_list[i]);"),
+    "composite_points_ignored": ("out[point_position(c, i) - r0] = point_value(c, i);", "(void)0;"),
+    "composite_point_value_shifted": ("out[point_position(c, i) - r0] = point_value(c, i);",
+                                      "out[point_position(c, i) - r0] = point_value(c, i + 1 < c.pt_n ? i + 1 : i);"),
+    "composite_run_value_of_next_run": (
+        "int64_t v = value_at(c, i);\n            for (int64_t r = std::max(c.run_starts[i], r0)",
+        "int64_t v = value_at(c, i + 1 < c.n ? i + 1 : i);\n            for (int64_t r = std::max(c.run_starts[i], r0)"),
 }
 
 
@@ -59,6 +66,7 @@ def test_pins_reject_mutant(name, tmp_path):
     _build(src.replace(old, new), so)
     env = dict(os.environ, CCQ_ORACLE_LIB=so)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_composite.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
