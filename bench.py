@@ -18,6 +18,8 @@ host's cores as the CPU baseline.
 1e9-row mixed-encoding GROUP BY d query, the 1e10-row four-key RLE GROUP
 BY, or the 1e6-row two-column query.  --config c5: the serving loop.
 --config encode: the device Plain -> RLE encoder on a 1e9-row column.
+--config join: a 1e8-row RLE fact column joined with a 65,536-row dimension
+key, and a dimension attribute applied over the join.
 
 Prints one JSON line: logical rows/s; the persistent kernels' achieved
 compressed-bytes bandwidth against the 8 TB/s HBM peak (bytes = the encoded
@@ -481,6 +483,115 @@ def bench_encode(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_join(args):
+    """Joins (Get / Apply Join Index): a fact column joined with a dimension
+    key.  Left: the mixed-encoding table's RLE int32 column r0 (lognormal runs
+    of mean 64, values uniform in [0, 2^16)) over --rows rows (default 1e8).
+    Right: a 65,536-row dimension table, its key a seeded permutation of
+    [0, 2^16) bit-packed to 16 bits, and an attribute uniform in [0, 2^20)
+    bit-packed to 20 bits.  A step is one ccq_join_index (one block per left
+    run) and one ccq_join_apply of the attribute over the blocks (one value
+    per left row).  Blocks and values are checked in full against the
+    dimension arrays, and a window of the left column against the CPU
+    oracle."""
+    import ctypes
+    import numpy as np
+    import torch
+    import datagen
+    from oracle import join as J
+    from paper_2506_10092_amd import ccq
+
+    n = args.rows or 100_000_000
+    nd = 1 << 16
+    left = datagen.rle_column(2, 2010, n, "lognormal", 64, 0, 1 << 16)
+    rng = np.random.default_rng([2, 7001])
+    key = rng.permutation(nd).astype(np.uint32)
+    attr = rng.integers(0, 1 << 20, size=nd).astype(np.uint32)
+    right = {"k": {"enc": "bitpacked", "packed": datagen.pack_codes(key, 16), "w": 16, "base": 0},
+             "a": {"enc": "bitpacked", "packed": datagen.pack_codes(attr, 20), "w": 20, "base": 0}}
+    ctx = ccq.Context(0)
+    tl = ccq.Table(ctx, n, ccq.to_device({"r0": left}))
+    tr = ccq.Table(ctx, nd, ccq.to_device(right))
+    L = ccq.lib()
+    runs = len(left["values"])
+    wsb = L.ccq_join_workspace_bytes(tl.h, 0, 0, n, tr.h, 0, 0, nd)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    blocks = torch.empty((runs, 4), dtype=torch.int64, device="cuda")
+    ws2b = L.ccq_join_apply_workspace_bytes(runs, n)
+    ws2 = torch.empty(ws2b, dtype=torch.uint8, device="cuda")
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    nb, npairs, nout = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    stream = ccq._stream_ptr(None)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def step():
+        ccq._check(L.ccq_join_index(tl.h, 0, 0, n, tr.h, 0, 0, nd, vp(ws), wsb, stream, vp(blocks), runs,
+                                    ctypes.byref(nb), ctypes.byref(npairs)))
+        ccq._check(L.ccq_join_apply(tr.h, 1, vp(blocks), nb.value, 1, vp(ws2), ws2b, stream, vp(out), n,
+                                    ctypes.byref(nout)))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.time() - t0) * 1e3 / args.steps
+    # index calls alone, for the split
+    t1 = time.time()
+    for _ in range(args.steps):
+        ccq._check(L.ccq_join_index(tl.h, 0, 0, n, tr.h, 0, 0, nd, vp(ws), wsb, stream, vp(blocks), runs,
+                                    ctypes.byref(nb), ctypes.byref(npairs)))
+    torch.cuda.synchronize()
+    ms_index = (time.time() - t1) * 1e3 / args.steps
+    # full check: one block per left run, in left order (one right entry per value)
+    inv = np.empty(nd, dtype=np.int64)
+    inv[key.astype(np.int64)] = np.arange(nd)
+    ends = left["run_ends"]
+    starts = np.r_[0, ends[:-1]]
+    lv = left["values"].astype(np.int64)
+    want = np.stack([starts, ends - starts, inv[lv], np.ones(runs, dtype=np.int64)], axis=1)
+    if nb.value != runs or npairs.value != n or not np.array_equal(blocks.cpu().numpy(), want):
+        raise SystemExit("join blocks differ from the dimension arrays")
+    if nout.value != n or not np.array_equal(out.cpu().numpy(), np.repeat(attr.astype(np.int64)[inv[lv]],
+                                                                        ends - starts)):
+        raise SystemExit("applied values differ from the dimension arrays")
+    # oracle on a window of the left column (bounded sample)
+    w = min(n, 10_000_000)
+    t2 = time.time()
+    ob = J.join_blocks(J.entries(left, n, 0, w), J.entries(right["k"], nd, 0, nd))
+    ov = J.apply(ob, right["a"], nd, "right")
+    cpu_s = time.time() - t2
+    gb, gp = ccq.join_index(tl, 0, tr, 0, (0, w))
+    if sorted(map(tuple, gb.cpu().numpy().tolist())) != sorted(ob) or gp != len(ov):
+        raise SystemExit("join blocks differ from the CPU oracle")
+    if not np.array_equal(ccq.join_apply(tr, 1, torch.tensor(ob, dtype=torch.int64, device="cuda"), "right")
+                          .cpu().numpy(), ov):
+        raise SystemExit("applied values differ from the CPU oracle")
+    # algorithmic bytes: the left runs and both right columns read, the
+    # blocks written once and read once, the applied values written
+    alg = runs * 12 + nd * 2 + nd * 20 // 8 + runs * 32 * 2 + n * 8
+    achieved = alg / (ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = {"value": w / cpu_s, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": "oracle join_blocks + apply over the first %d left rows (%d runs), %.1f s, one thread; "
+                         "equal to the GPU's" % (w, len(ob), cpu_s)}
+    line = {"metric": METRIC, "value": n / (ms * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": "join_rle_fact_%g_x_dim_%d" % (n, nd), "rows": n, "left_runs": runs,
+                       "blocks": nb.value, "pairs": npairs.value, "ms_join_index": ms_index,
+                       "step": "one ccq_join_index (bounds, build, count, scan, write) and one ccq_join_apply "
+                               "(pair counts, scan, gather) with their host reads of the sizes"},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "every kernel of both calls (wall time of the calls)"},
+            "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
 def describe_query(wl, query, flt):
     """A short text of a single-launch workload's filter and grouping."""
     if wl["name"].startswith("c2"):
@@ -496,7 +607,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "encode"])
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "encode", "join"])
     ap.add_argument("--queries", type=int, default=4096, help="c4: queries per batch")
     ap.add_argument("--serve-queries", type=int, default=10000, help="c5: queries per arrival rate (after warm-up)")
     ap.add_argument("--serve-warmup", type=int, default=500, help="c5: leading queries left out of the statistics")
@@ -544,6 +655,9 @@ def main():
         return
     if args.config == "encode":
         bench_encode(args)
+        return
+    if args.config == "join":
+        bench_join(args)
         return
 
     t_gen = time.time()

@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 6
+#define CCQ_ABI_VERSION 7
 
 typedef int32_t ccq_status;
 enum {
@@ -75,14 +75,32 @@ typedef struct ccq_context ccq_context;
 typedef struct ccq_table ccq_table;
 typedef struct ccq_plan ccq_plan;
 
-/* ---- encodings (Section 3.1 Basic Encodings; Section 3.2 bit widths) ---- */
-enum { CCQ_RLE = 1, CCQ_INDEX = 2, CCQ_BITPACKED = 3 };
+/* ---- encodings (Section 3.1 Basic Encodings; Section 3.2 bit widths and
+ * composite encodings) ----
+ * CCQ_RLE_INDEX (Section 3.2, RLE + Index): pure runs plus Index points on
+ * the rows no pure run covers.  The RLE part is values / run_ends /
+ * n_entries with run_ends as for CCQ_RLE (strictly increasing, last ==
+ * rows): run i stands for the rows of [run_ends[i-1], run_ends[i]) (0 for
+ * i = 0) that no point lists, so a pure run's start is implicit.  From
+ * runs given with starts and ends (ccq_plain_to_rle_index), keep the ends
+ * and set the last one to the row count; a column of points only takes one
+ * run over every row, whose value is never read.
+ * CCQ_PLAIN_INDEX (Section 3.2, Plain + Index): a BITPACKED column (packed,
+ * bit_width, base) whose rows listed as points take the points' values; the
+ * codes at those rows are never read.
+ * Both composites list their points in positions (position_type) and
+ * point_values (value_type), n_points of them, positions strictly increasing
+ * in [0, rows).  A query may name at most two composite columns, in
+ * predicates (alone in their OR clauses), SUM, MIN, MAX and expression
+ * operands, not in group keys; such queries take the generic row path. */
+enum { CCQ_RLE = 1, CCQ_INDEX = 2, CCQ_BITPACKED = 3, CCQ_RLE_INDEX = 4, CCQ_PLAIN_INDEX = 5 };
 enum { CCQ_I32 = 1, CCQ_I64 = 2 };
 
 typedef struct {
-    int32_t encoding;          /* CCQ_RLE, CCQ_INDEX or CCQ_BITPACKED */
-    int32_t value_type;        /* RLE, INDEX: CCQ_I32 or CCQ_I64 */
-    int64_t n_entries;         /* RLE: runs; INDEX: listed points; BITPACKED: rows (== table rows) */
+    int32_t encoding;          /* CCQ_RLE, CCQ_INDEX, CCQ_BITPACKED, CCQ_RLE_INDEX or CCQ_PLAIN_INDEX */
+    int32_t value_type;        /* RLE, INDEX and the composites: CCQ_I32 or CCQ_I64 */
+    int64_t n_entries;         /* RLE, RLE_INDEX: runs; INDEX: listed points; BITPACKED, PLAIN_INDEX:
+                                  rows (== table rows) */
     const void* values;        /* RLE, INDEX: device value_type[n_entries] */
     const int64_t* run_ends;   /* RLE: device int64[n_entries], exclusive, strictly
                                   increasing, first > 0, last == table rows */
@@ -99,6 +117,9 @@ typedef struct {
                                   Such a key needs shift 0 and card <= dict_size; SUM over the column is
                                   CCQ_E_UNSUPPORTED.  Borrowed like the other column buffers. */
     int64_t dict_size;         /* entries of dict_values (>= 1 when dict_values is set, else 0) */
+    const void* point_values;  /* RLE_INDEX, PLAIN_INDEX: device value_type[n_points], the Index part's
+                                  values (positions in `positions`) */
+    int64_t n_points;          /* RLE_INDEX, PLAIN_INDEX: listed points (>= 0); 0 for the other encodings */
 } ccq_column_desc;
 
 /* ---- query (Sections 5-7) ----
@@ -387,13 +408,16 @@ ccq_status ccq_join_index(const ccq_table* left, int32_t left_col, int64_t left_
  * a bit-packed column gives base + code.  blocks: device array of n_blocks
  * (from ccq_join_index over t as that side, or any blocks whose side rows
  * lie in t, with pairs per block below 2^63).  Workspace: device memory of
- * ccq_join_apply_workspace_bytes(n_blocks) bytes, 256-byte aligned.
+ * ccq_join_apply_workspace_bytes(n_blocks, n_pairs) bytes, 256-byte aligned,
+ * n_pairs the blocks' pairs (ccq_join_index reports it; a call with a
+ * workspace for n_pairs = 0 and capacity 0 reports it in *n_out with
+ * CCQ_E_CAPACITY).
  * Synchronises `stream` once (the number of pairs), then enqueues the gather;
  * out: device int64[capacity]; *n_out (host) receives the number of pairs
  * also on CCQ_E_CAPACITY (nothing written).  CCQ_E_INVALID for a block with a
  * negative length or side rows outside the table (checked on the device
  * before anything is written). */
-size_t ccq_join_apply_workspace_bytes(int64_t n_blocks);
+size_t ccq_join_apply_workspace_bytes(int64_t n_blocks, int64_t n_pairs);
 ccq_status ccq_join_apply(const ccq_table* t, int32_t col, const ccq_join_block* blocks, int64_t n_blocks, int32_t side,
                           void* ws, size_t ws_bytes, void* stream, int64_t* out, int64_t capacity, int64_t* n_out);
 

@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libccq.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_KEY_DOMAIN, E_HIP, E_BUDGET, E_BUSY, E_NOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8
-RLE, INDEX, BITPACKED = 1, 2, 3
+RLE, INDEX, BITPACKED, RLE_INDEX, PLAIN_INDEX = 1, 2, 3, 4, 5
 I32, I64 = 1, 2
 RANGE, IN, NOT_RANGE, NOT_IN = 1, 2, 3, 4
 COUNT_STAR, SUM, MIN, MAX = 1, 2, 3, 4
@@ -55,7 +55,8 @@ class ColumnDesc(ctypes.Structure):
     _fields_ = [("encoding", ctypes.c_int32), ("value_type", ctypes.c_int32), ("n_entries", ctypes.c_int64),
                 ("values", ctypes.c_void_p), ("run_ends", ctypes.c_void_p), ("positions", ctypes.c_void_p),
                 ("packed", ctypes.c_void_p), ("bit_width", ctypes.c_int32), ("position_type", ctypes.c_int32),
-                ("base", ctypes.c_int64), ("dict_values", ctypes.c_void_p), ("dict_size", ctypes.c_int64)]
+                ("base", ctypes.c_int64), ("dict_values", ctypes.c_void_p), ("dict_size", ctypes.c_int64),
+                ("point_values", ctypes.c_void_p), ("n_points", ctypes.c_int64)]
 
 
 class Pred(ctypes.Structure):
@@ -156,7 +157,7 @@ SIGNATURES = {
     "ccq_join_workspace_bytes": (_sz, [_vp, _i32, _i64, _i64, _vp, _i32, _i64, _i64]),
     "ccq_join_index": (_i32, [_vp, _i32, _i64, _i64, _vp, _i32, _i64, _i64, _vp, _sz, _vp, _vp, _i64,
                               ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
-    "ccq_join_apply_workspace_bytes": (_sz, [_i64]),
+    "ccq_join_apply_workspace_bytes": (_sz, [_i64, _i64]),
     "ccq_join_apply": (_i32, [_vp, _i32, _vp, _i64, _i32, _vp, _sz, _vp, _vp, _i64, ctypes.POINTER(_i64)]),
 }
 
@@ -211,7 +212,25 @@ class Context:
 
 
 def _column_desc(c, n_rows):
+    """Column dict -> ccq_column_desc.  Composites: "rle+index" {values,
+    run_ends (the last equal to n_rows; a run stands for the rows from the
+    previous end that no point lists), positions, point_values}; "plain+index"
+    {packed, w, base, positions, point_values}."""
     d = ColumnDesc()
+    if c["enc"] in ("rle+index", "plain+index"):
+        base = dict(c, enc="rle" if c["enc"] == "rle+index" else "bitpacked")
+        for k in ("positions", "point_values"):
+            base.pop(k, None)
+        d = _column_desc(base, n_rows)
+        d.encoding = RLE_INDEX if c["enc"] == "rle+index" else PLAIN_INDEX
+        pv = c["point_values"]
+        if c["enc"] == "plain+index":
+            d.value_type = _dtype_code(pv)
+        elif _dtype_code(pv) != d.value_type:
+            raise CcqError(E_INVALID, "run values and point values must share one type")
+        d.position_type = _dtype_code(c["positions"])
+        d.positions, d.point_values, d.n_points = c["positions"].data_ptr(), pv.data_ptr(), pv.numel()
+        return d
     if c["enc"] == "rle":
         d.encoding, d.value_type, d.n_entries = RLE, _dtype_code(c["values"]), c["run_ends"].numel()
         d.values, d.run_ends = c["values"].data_ptr(), c["run_ends"].data_ptr()
@@ -676,21 +695,24 @@ def join_apply(table, col, blocks, side, stream=None):
     L = lib()
     n = blocks.shape[0]
     dev = torch.device("cuda", table.ctx.device)
-    ws = torch.empty(max(int(L.ccq_join_apply_workspace_bytes(n)), 256), dtype=torch.uint8, device=dev)
     n_out = ctypes.c_int64()
     ci = _col_index(table, col)
 
-    def call(buf, cap):
+    def call(ws, buf, cap):
         return L.ccq_join_apply(table.h, ci, ctypes.c_void_p(blocks.data_ptr()) if n else None, n, sd,
                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream), buf, cap,
                                 ctypes.byref(n_out))
-    st = call(None, 0)
+    # first call: the number of pairs (the workspace grows with it)
+    ws = torch.empty(max(int(L.ccq_join_apply_workspace_bytes(n, 0)), 256), dtype=torch.uint8, device=dev)
+    st = call(ws, None, 0)
     if st != E_CAPACITY and st != OK:
         _check(st)
-    out = torch.empty(max(n_out.value, 1), dtype=torch.int64, device=dev)
-    if n_out.value:
-        _check(call(ctypes.c_void_p(out.data_ptr()), n_out.value))
-    return out[:n_out.value]
+    total = n_out.value
+    out = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+    if total:
+        ws = torch.empty(max(int(L.ccq_join_apply_workspace_bytes(n, total)), 256), dtype=torch.uint8, device=dev)
+        _check(call(ws, ctypes.c_void_p(out.data_ptr()), total))
+    return out[:total]
 
 
 def avg_var(count, s, ss):

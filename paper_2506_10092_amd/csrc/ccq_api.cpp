@@ -105,7 +105,24 @@ ccq_status ccq_table_create(ccq_context* ctx, int64_t n_rows, const ccq_column_d
     if (n_cols < 0 || (n_cols > 0 && !cols)) return fail(CCQ_E_INVALID, "bad column array");
     for (int i = 0; i < n_cols; ++i) {
         const ccq_column_desc& c = cols[i];
-        if (c.encoding == CCQ_RLE) {
+        const bool comp = c.encoding == CCQ_RLE_INDEX || c.encoding == CCQ_PLAIN_INDEX;
+        if (comp) {
+            // the Index part of a composite column
+            if (c.position_type != CCQ_I32 && c.position_type != CCQ_I64)
+                return fail(CCQ_E_INVALID, "column %d: point position_type must be CCQ_I32 or CCQ_I64", i);
+            if (c.value_type != CCQ_I32 && c.value_type != CCQ_I64)
+                return fail(CCQ_E_INVALID, "column %d: value_type must be CCQ_I32 or CCQ_I64", i);
+            if (c.n_points < 0 || c.n_points > n_rows)
+                return fail(CCQ_E_INVALID, "column %d: n_points out of range", i);
+            if (c.position_type == CCQ_I32 && n_rows > (int64_t)INT32_MAX + 1)
+                return fail(CCQ_E_INVALID, "column %d: int32 positions cannot address %lld rows", i,
+                            (long long)n_rows);
+            if (c.n_points > 0 && (!c.point_values || !c.positions))
+                return fail(CCQ_E_INVALID, "column %d: point values / positions missing", i);
+        } else if (c.n_points != 0) {
+            return fail(CCQ_E_INVALID, "column %d: n_points is for composite columns only", i);
+        }
+        if (c.encoding == CCQ_RLE || c.encoding == CCQ_RLE_INDEX) {
             if (c.value_type != CCQ_I32 && c.value_type != CCQ_I64)
                 return fail(CCQ_E_INVALID, "column %d: RLE value_type must be CCQ_I32 or CCQ_I64", i);
             if (n_rows > 0 && c.n_entries < 1) return fail(CCQ_E_INVALID, "column %d: RLE column needs runs", i);
@@ -124,7 +141,7 @@ ccq_status ccq_table_create(ccq_context* ctx, int64_t n_rows, const ccq_column_d
                             (long long)n_rows);
             if (c.n_entries > 0 && (!c.values || !c.positions))
                 return fail(CCQ_E_INVALID, "column %d: INDEX values / positions missing", i);
-        } else if (c.encoding == CCQ_BITPACKED) {
+        } else if (c.encoding == CCQ_BITPACKED || c.encoding == CCQ_PLAIN_INDEX) {
             if (c.bit_width < 1 || c.bit_width > 32)
                 return fail(CCQ_E_INVALID, "column %d: bit_width must be in 1..32", i);
             if (c.n_entries != n_rows) return fail(CCQ_E_INVALID, "column %d: BITPACKED n_entries must equal n_rows", i);
@@ -162,9 +179,12 @@ ccq_status ccq_table_validate(ccq_table* t, void* stream) {
     e = hipMemcpyAsync(flag, host.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s);
     for (size_t i = 0; i < t->cols.size() && e == hipSuccess; ++i) {
         const ccq_column_desc& c = t->cols[i];
-        if (c.encoding == CCQ_RLE && c.n_entries > 0) e = launch_validate_rle(c.run_ends, c.n_entries, t->n_rows, flag + i, s);
+        if ((c.encoding == CCQ_RLE || c.encoding == CCQ_RLE_INDEX) && c.n_entries > 0)
+            e = launch_validate_rle(c.run_ends, c.n_entries, t->n_rows, flag + i, s);
         if (c.encoding == CCQ_INDEX && c.n_entries > 0)
             e = launch_validate_idx(c.positions, c.position_type, c.n_entries, t->n_rows, flag + i, s);
+        if (e == hipSuccess && c.n_points > 0)
+            e = launch_validate_idx(c.positions, c.position_type, c.n_points, t->n_rows, flag + i, s);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(host.data(), flag, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -323,15 +343,25 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.row_end = q->row_end;
 
     // referenced columns, grouped by encoding, in order of first use
+    // a composite column (Section 3.2) takes the slot of its base part (RLE
+    // or bit-packed) plus a CompCol for its points
+    auto base_enc = [&](int c) {
+        const int enc = t->cols[c].encoding;
+        return enc == CCQ_RLE_INDEX ? CCQ_RLE : enc == CCQ_PLAIN_INDEX ? CCQ_BITPACKED : enc;
+    };
+    auto is_comp = [&](int c) {
+        return t->cols[c].encoding == CCQ_RLE_INDEX || t->cols[c].encoding == CCQ_PLAIN_INDEX;
+    };
     std::vector<int> kind_slot(ncol, -1);
-    std::vector<int> rle_cols, bp_cols, idx_cols;
+    std::vector<int> rle_cols, bp_cols, idx_cols, comp_cols;
     auto use = [&](int c) -> ccq_status {
         if (c < 0 || c >= ncol) return fail(CCQ_E_INVALID, "column index %d out of range", c);
         if (kind_slot[c] >= 0) return CCQ_OK;
-        int enc = t->cols[c].encoding;
+        int enc = base_enc(c);
         std::vector<int>& v = enc == CCQ_RLE ? rle_cols : enc == CCQ_BITPACKED ? bp_cols : idx_cols;
         kind_slot[c] = (int)v.size();
         v.push_back(c);
+        if (is_comp(c)) comp_cols.push_back(c);
         return CCQ_OK;
     };
     for (int i = 0; i < q->n_preds; ++i) {
@@ -433,6 +463,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
         bool mixed = false;
         for (size_t j : live) {
+            if (is_comp(cl.cols[j]))
+                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes no composite column", cl.id);
             if (t->cols[cl.cols[j]].encoding == CCQ_INDEX)
                 return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes no INDEX column", cl.id);
             mixed = mixed || t->cols[cl.cols[j]].encoding == CCQ_BITPACKED;
@@ -473,7 +505,14 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     if ((int)bp_cols.size() > kMaxBp)
         return fail(CCQ_E_UNSUPPORTED, "at most %d bit-packed columns per query", kMaxBp);
     if ((int)idx_cols.size() > kMaxIdx) return fail(CCQ_E_UNSUPPORTED, "at most %d Index columns per query", kMaxIdx);
+    if ((int)comp_cols.size() > kMaxComp)
+        return fail(CCQ_E_UNSUPPORTED, "at most %d composite columns per query", kMaxComp);
     for (auto& f : fold) fold_classify(f);
+    // a composite column's predicates are tested per row on its value (the
+    // point's or the base part's), so its base part gets none
+    Fold no_pred;
+    fold_classify(no_pred);
+    auto base_fold = [&](int c) -> const Fold& { return is_comp(c) ? no_pred : fold[c]; };
 
     // device blob contents, laid out after the DevPlan
     std::vector<unsigned char>& blob = out.blob;
@@ -523,7 +562,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         const bool own = s < (int)rle_cols.size();
         const OrSlot* o = own ? nullptr : &or_slots[s - rle_cols.size()];
         const ccq_column_desc& c = t->cols[own ? rle_cols[s] : o->col];
-        const Fold& f = own ? fold[rle_cols[s]] : o->f;
+        const Fold& f = own ? base_fold(rle_cols[s]) : o->f;
         RleCol& r = P.rle[s];
         r.or_next = (o && o->or_next) ? 1 : 0;
         r.row_clause = (o && o->row_clause) ? 1 : 0;
@@ -559,6 +598,8 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     for (int k = 0; k < q->n_keys; ++k) {
         const ccq_key& key = q->keys[k];
         const ccq_column_desc& c = t->cols[key.col];
+        if (is_comp(key.col))
+            return fail(CCQ_E_UNSUPPORTED, "key %d: group keys on composite columns are not supported", k);
         if (key.shift < 0 || key.shift > 62) return fail(CCQ_E_INVALID, "key %d: shift must be in 0..62", k);
         if (key.card < 1) return fail(CCQ_E_INVALID, "key %d: card must be >= 1", k);
         KeyDesc& kd = P.keys[k];
@@ -622,7 +663,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     std::vector<std::vector<uint16_t>> lut16(P.n_bp);
     for (int s = 0; s < P.n_bp; ++s) {
         const ccq_column_desc& c = t->cols[bp_cols[s]];
-        const Fold& f = fold[bp_cols[s]];
+        const Fold& f = base_fold(bp_cols[s]);
         BpCol& b = P.bp[s];
         b.packed = c.packed;
         b.base = c.base;
@@ -710,9 +751,9 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         ExtAcc& e = P.ext[slot];
         e.kind = ag.func == CCQ_MIN ? kExtMin : ag.func == CCQ_MAX ? kExtMax : kExtSum;
         e.op = ag.op;
-        e.a_rle = t->cols[opnd[0]].encoding == CCQ_RLE ? 1 : 0;
+        e.a_rle = base_enc(opnd[0]) == CCQ_RLE ? 1 : 0;
         e.a_src = kind_slot[opnd[0]];
-        e.b_rle = t->cols[opnd[1]].encoding == CCQ_RLE ? 1 : 0;
+        e.b_rle = base_enc(opnd[1]) == CCQ_RLE ? 1 : 0;
         e.b_src = kind_slot[opnd[1]];
         if (e.a_rle) P.rle[e.a_src].keep_value = 1;
         if (e.b_rle) P.rle[e.b_src].keep_value = 1;
@@ -733,7 +774,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             continue;
         }
         const int col = q->aggs[a].col;
-        const int enc = t->cols[col].encoding;
+        const int enc = base_enc(col);
         if (t->cols[col].dict_values)
             return fail(CCQ_E_UNSUPPORTED, "aggregate %d: SUM over a dictionary-encoded column", a);
         ad.kind = enc == CCQ_RLE ? kAggSumRle : enc == CCQ_BITPACKED ? kAggSumBp : kAggSumIdx;
@@ -745,11 +786,30 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         ad.sum_slot = slot;
     }
 
+    // composite columns: the points, and the predicate tested per row
+    P.n_comp = (int32_t)comp_cols.size();
+    for (int i = 0; i < P.n_comp; ++i) {
+        const int col = comp_cols[i];
+        const ccq_column_desc& c = t->cols[col];
+        CompCol& cc = P.comp[i];
+        cc.rle = base_enc(col) == CCQ_RLE ? 1 : 0;
+        cc.src = kind_slot[col];
+        cc.pos = c.positions;
+        cc.vals = c.point_values;
+        cc.n = c.n_points;
+        cc.ptype = c.position_type;
+        cc.vtype = c.value_type;
+        put_pred(fold[col], cc.pred, cc.lo, cc.hi, cc.set, cc.set_len);
+        if (cc.rle) P.rle[cc.src].keep_value = 1;     // the run's value, read per row
+    }
+
     // mode and tiling
-    P.row_mode = (P.n_bp > 0 || P.n_ext > 0) ? 1 : 0;
+    P.row_mode = (P.n_bp > 0 || P.n_ext > 0 || P.n_comp > 0) ? 1 : 0;
     P.any_rle_row = 0;
     for (int k = 0; k < P.n_ext; ++k)
         if (P.ext[k].a_rle || P.ext[k].b_rle) P.any_rle_row = 1;
+    for (int i = 0; i < P.n_comp; ++i)
+        if (P.comp[i].rle) P.any_rle_row = 1;
     if (P.row_mode) {
         for (int k = 0; k < P.n_keys; ++k)
             if (P.keys[k].src_kind == kKeyRle) P.any_rle_row = 1;
@@ -800,7 +860,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     P.fast_big = 0;
     {
         bool fast = P.row_mode && P.n_bp == 1 && P.n_idx <= 1 && !P.any_rle_row && fast_row_width(P.bp[0].w) &&
-                    !idx_pred && !row_clause && P.n_ext == 0;
+                    !idx_pred && !row_clause && P.n_ext == 0 && P.n_comp == 0;
         BpCol& b = P.bp[0];
         const Fold& f = fold[bp_cols.empty() ? 0 : bp_cols[0]];
         if (fast && b.key < 0 && P.n_keys > 0) fast = false;
@@ -1005,6 +1065,12 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         for (int s = 0; s < P.n_bp; ++s) {
             P.bp[s].stage_off = (int32_t)wv;
             wv = align16(wv + 4 * (size_t)(64 * P.bp[s].w + 2));
+        }
+        // composite columns: the tile's listed rows (one word per lane) and
+        // the exclusive prefix of their popcounts
+        for (int i = 0; i < P.n_comp; ++i) {
+            P.comp[i].lds_off = (int32_t)wv;
+            wv = align16(wv + 2 * 256);
         }
     }
     P.off_pts = 0;

@@ -53,7 +53,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int kidx(int kmax) { return kmax <= 2 ? 0 : kmax <= 4 ? 1 : 2; }
-int widx(const DevPlan& p) { return variant_of(p.w0, p.fast_big, p.lds_dyn_bytes); }
+int widx(const DevPlan& p) { return variant_of(kernel_w0(p), p.fast_big, p.lds_dyn_bytes); }
 
 void drop_graph(ccq_batch* b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);

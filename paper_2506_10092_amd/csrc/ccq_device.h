@@ -1481,10 +1481,11 @@ __device__ __forceinline__ void slotacc_flush(const DevPlan& P, const Table& tb,
 // the row clause, the group id from the key columns (ridx: the staged run of
 // each RLE column holding r) and the decoded bit-packed values.  False if
 // the row fails, or (status raised) if a key is outside its domain.
-template <int KMAX>
+template <int KMAX, bool COMP>
 __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int32_t r,
                                          const int32_t (&ridx)[KMAX], const int32_t (&luts)[kMaxBp],
-                                         int32_t* status, int64_t* gid_out, int64_t (&bpv)[kMaxBp]) {
+                                         int32_t* status, int64_t* gid_out, int64_t (&bpv)[kMaxBp],
+                                         const int64_t (&cfirst)[kMaxComp], int64_t (&cv)[kMaxComp]) {
     bool pass = true;
     bool dom = false;
     int64_t gid = 0;
@@ -1518,6 +1519,38 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
             }
         }
     }
+    // composite columns (Section 3.2): a row the Index part lists takes the
+    // point's value (the tile's bitmap of listed rows and its word prefixes
+    // give the point's index), any other row its base part's; the column's
+    // predicate is tested on that value
+#pragma unroll
+    for (int i = 0; i < kMaxComp; ++i) {
+        cv[i] = 0;
+        if (!COMP || i >= P.n_comp) continue;
+        const CompCol& cc = P.comp[i];
+        const uint32_t* lm = (const uint32_t*)(W.base + cc.lds_off);
+        const uint32_t w = lm[r >> 5];
+        int64_t v = 0;
+        if ((w >> (r & 31)) & 1u) {
+            const int32_t pre = ((const int32_t*)(lm + 64))[r >> 5];
+            v = ld_val(cc.vals, cc.vtype, cfirst[i] + pre + __builtin_popcount(w & ((1u << (r & 31)) - 1u)));
+        } else if (cc.rle) {
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c)
+                if (c < P.k_rle && c == cc.src) v = W.run_val[stage_base(P, c) + ridx[c]];
+        } else {
+#pragma unroll
+            for (int b = 0; b < kMaxBp; ++b)
+                if (b < P.n_bp && b == cc.src) v = bpv[b];
+        }
+        if (!cc.rle) {
+#pragma unroll
+            for (int b = 0; b < kMaxBp; ++b)
+                if (b < P.n_bp && b == cc.src) bpv[b] = v;
+        }
+        cv[i] = v;
+        pass = pass && pred_pass(cc.pred, cc.lo, cc.hi, cc.set, cc.set_len, v);
+    }
     if (pass && W.rcl) {
         // the row clause (Section 5.2, RLE mask OR Plain mask): its RLE rows,
         // or a bit-packed part holding on this row's value
@@ -1548,6 +1581,20 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
     return pass;
 }
 
+// the value of RLE column c at the row: its staged run's, or a composite
+// column's point value where its Index part lists the row
+template <int KMAX, bool COMP>
+__device__ __forceinline__ int64_t rle_row_val(const DevPlan& P, const WaveLds& W, int c,
+                                               const int32_t (&ridx)[KMAX], const int64_t (&cv)[kMaxComp]) {
+    int64_t v = W.run_val[stage_base(P, c) + ridx[c]];
+    if constexpr (COMP) {
+#pragma unroll
+        for (int i = 0; i < kMaxComp; ++i)
+            if (i < P.n_comp && P.comp[i].rle && P.comp[i].src == c) v = cv[i];
+    }
+    return v;
+}
+
 // OR of a word over the wave
 __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
 #pragma unroll
@@ -1555,11 +1602,11 @@ __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
     return x;
 }
 
-template <int KMAX>
+template <int KMAX, bool COMP>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
                                                  uint32_t pm, const Table& tb, int32_t* status,
-                                                 int64_t (&pcur)[kMaxIdx], const int32_t (&luts)[kMaxBp],
-                                                 SlotAcc& acc) {
+                                                 int64_t (&pcur)[kMaxIdx], int64_t (&ccur)[kMaxComp],
+                                                 const int32_t (&luts)[kMaxBp], SlotAcc& acc) {
     const int lane = lane_id();
     const uint32_t any = wave_or32(pm);
     if (P.n_idx > 0) W.pmw[lane] = pm;
@@ -1585,6 +1632,38 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
             }
         }
     }
+    // composite columns: the tile's listed rows as a bitmap, one word per
+    // lane, and the exclusive prefix of the words' popcounts; the tile's
+    // points follow the cursor, which moves past them
+    int64_t cfirst[kMaxComp];
+#pragma unroll
+    for (int i = 0; i < kMaxComp; ++i) {
+        cfirst[i] = 0;
+        if (!COMP || i >= P.n_comp) continue;
+        const CompCol& cc = P.comp[i];
+        uint32_t* lm = (uint32_t*)(W.base + cc.lds_off);
+        lm[lane] = 0;
+        wave_lds_sync();
+        int64_t p0 = ccur[i];
+        cfirst[i] = p0;
+        for (;;) {
+            const int64_t k = p0 + lane;
+            const bool valid = k < cc.n;
+            const int64_t pos = valid ? ld_val(cc.pos, cc.ptype, k) : INT64_MAX;
+            const bool in = valid && pos < t0 + L;      // the cursor is at the first point >= t0
+            if (in) {
+                const int32_t rel = (int32_t)(pos - t0);
+                atomicOr(&lm[rel >> 5], 1u << (rel & 31));
+            }
+            const int c = __builtin_popcountll(wave_ballot(in));
+            p0 += c;
+            if (c < 64) break;
+        }
+        ccur[i] = p0;
+        wave_lds_sync();
+        int tot;
+        ((int32_t*)(lm + 64))[lane] = wave_exclusive_sum(__builtin_popcount(lm[lane]), &tot);
+    }
     wave_lds_sync();
 
     // the lane's rows, row j of every lane together
@@ -1609,8 +1688,9 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
             if (!((any >> j) & 1u)) continue;
             if (!((pm >> j) & 1u)) continue;
             int64_t bpv[kMaxBp];
+            int64_t cv[kMaxComp];
             int64_t gid;
-            if (!row_eval<KMAX>(P, W, s0 + j, ridx, luts, status, &gid, bpv)) continue;
+            if (!row_eval<KMAX, COMP>(P, W, s0 + j, ridx, luts, status, &gid, bpv, cfirst, cv)) continue;
             if (gid != acc.gid) {
                 slotacc_flush(P, tb, acc);
                 acc.gid = gid;
@@ -1627,8 +1707,8 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 #pragma unroll
                     for (int c = 0; c < KMAX; ++c) {
                         if (c >= P.k_rle) continue;
-                        if (e.a_rle && e.a_src == c) va = W.run_val[stage_base(P, c) + ridx[c]];
-                        if (e.b_rle && e.b_src == c) vb = W.run_val[stage_base(P, c) + ridx[c]];
+                        if (e.a_rle && e.a_src == c) va = rle_row_val<KMAX, COMP>(P, W, c, ridx, cv);
+                        if (e.b_rle && e.b_src == c) vb = rle_row_val<KMAX, COMP>(P, W, c, ridx, cv);
                     }
 #pragma unroll
                     for (int b = 0; b < kMaxBp; ++b) {
@@ -1652,7 +1732,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
                 int64_t term = 0;
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c)
-                    if (c < P.k_rle && P.rle[c].sum_slot == k) term = W.run_val[stage_base(P, c) + ridx[c]];
+                    if (c < P.k_rle && P.rle[c].sum_slot == k) term = rle_row_val<KMAX, COMP>(P, W, c, ridx, cv);
 #pragma unroll
                 for (int b = 0; b < kMaxBp; ++b)
                     if (b < P.n_bp && P.bp[b].sum_slot == k) term = bpv[b];
@@ -1683,11 +1763,12 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 #pragma unroll
                         for (int c = 0; c < KMAX; ++c) {
                             idx[c] = 0;
-                            if (c < P.k_rle && P.rle[c].key_on) idx[c] = bm_run(W, c, rel);
+                            if (c < P.k_rle && (P.rle[c].key_on || P.rle[c].keep_value)) idx[c] = bm_run(W, c, rel);
                         }
                         int64_t bpv[kMaxBp];
+                        int64_t cv[kMaxComp];
                         int64_t gid;
-                        if (row_eval<KMAX>(P, W, rel, idx, luts, status, &gid, bpv)) {
+                        if (row_eval<KMAX, COMP>(P, W, rel, idx, luts, status, &gid, bpv, cfirst, cv)) {
                             const int64_t v = ld_val(ic.vals, ic.vtype, i);
                             if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
                         }
@@ -1718,13 +1799,13 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
         }
 #pragma unroll
         for (int j = 0; j < kMaxBp; ++j) {
-            if (W0 == 0 && j < P.n_bp && P.bp[j].lut) {
+            if (W0 <= 0 && j < P.n_bp && P.bp[j].lut) {
                 uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].lut_lds_off);
                 const uint32_t* src = (const uint32_t*)P.bp[j].lut;
                 const int n = P.bp[j].lut_bytes / 4;
                 for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = gld(src, i);
             }
-            if (W0 == 0 && j < P.n_bp && P.bp[j].or_bits_words > 0) {
+            if (W0 <= 0 && j < P.n_bp && P.bp[j].or_bits_words > 0) {
                 uint32_t* dst = (uint32_t*)(ccq_lds + P.bp[j].or_bits_lds_off);
                 const uint32_t* src = P.bp[j].or_bits;
                 for (int i = threadIdx.x; i < P.bp[j].or_bits_words; i += blockDim.x) dst[i] = gld(src, i);
@@ -1732,7 +1813,7 @@ __device__ __forceinline__ void wg_setup(const DevPlan& P, uint8_t* s_lut, uint3
         }
     }
 #pragma unroll
-    for (int j = 0; j < kMaxBp; ++j) luts[j] = (W0 == 0 && j < P.n_bp && P.bp[j].lut) ? P.bp[j].lut_lds_off : -1;
+    for (int j = 0; j < kMaxBp; ++j) luts[j] = (W0 <= 0 && j < P.n_bp && P.bp[j].lut) ? P.bp[j].lut_lds_off : -1;
     if constexpr (W0 > 0) {
         if constexpr (!BIG)
             for (int i = threadIdx.x; i < kFastCntWords; i += blockDim.x) s_cnt[i] = 0;
@@ -1791,6 +1872,10 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
 #pragma unroll
         for (int j = 0; j < kMaxIdx; ++j)
             pcur[j] = j < P.n_idx ? wave_lower_bound_pos(P.idx[j].pos, P.idx[j].ptype, P.idx[j].n, w0) : 0;
+        int64_t ccur[kMaxComp];
+#pragma unroll
+        for (int j = 0; j < kMaxComp; ++j)
+            ccur[j] = j < P.n_comp ? wave_lower_bound_pos(P.comp[j].pos, P.comp[j].ptype, P.comp[j].n, w0) : 0;
         wave_lds_sync();
         for (int c = 0; c < P.k_rle; ++c) W.bnd[c * 64 + lane_id()] = 0;
         if (P.off_tog >= 0) W.tog[lane_id()] = 0;
@@ -1810,7 +1895,7 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
                 uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
                 const int32_t L = (int32_t)(t1 - t0);
                 pm = idx_pred_mask(P, W, t0, L, pcur, pm);
-                tile_row_generic<KMAX>(P, W, t0, L, pm, tb, status, pcur, luts, sacc);
+                tile_row_generic<KMAX, (W0 < 0)>(P, W, t0, L, pm, tb, status, pcur, ccur, luts, sacc);
                 tile_bitmaps_clear(P, W);
                 t0 = t1;
             }
@@ -1898,7 +1983,7 @@ __global__ __launch_bounds__(kThreads, kFastWaves(W0)) void k_fused(const DevPla
     Table tb;
     tb.g = table;
     tb.G = P.n_groups;
-    tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
+    tb.loff = (W0 <= 0 && P.table_lds) ? P.table_lds_off : -1;
     tb.c32 = P.table_c32;
     tb.lG = P.table_lds_groups;
     tb.amap = P.table_lds_map;
@@ -1953,7 +2038,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(const BatchDev* __restrict__
         Table tb;
         tb.g = table;
         tb.G = P.n_groups;
-        tb.loff = (W0 == 0 && P.table_lds) ? P.table_lds_off : -1;
+        tb.loff = (W0 <= 0 && P.table_lds) ? P.table_lds_off : -1;
         tb.c32 = P.table_c32;
         tb.lG = P.table_lds_groups;
         tb.amap = P.table_lds_map;

@@ -32,6 +32,7 @@ namespace ccq {
 namespace {
 
 constexpr int kJThreads = 256;
+constexpr int64_t kMaxGrid = 8192;        // workgroups of the grid-stride kernels
 constexpr int64_t kEmpty = INT64_MIN;     // empty slot marker (the value INT64_MIN uses slot cap)
 
 struct JCol {                  // one side's column and window
@@ -185,8 +186,10 @@ __global__ void k_join_build(JTable T, JCol r, int64_t n_right) {
     }
 }
 
-// per left entry: its blocks (counts[k]) and, added up, the pairs
-__global__ void k_join_count(JTable T, JCol l, int64_t n_left, int64_t* counts, unsigned long long* pairs) {
+// per left entry: its blocks (counts[k]); per workgroup: its entries' pairs (ppart[block])
+__global__ __launch_bounds__(kJThreads) void k_join_count(JTable T, JCol l, int64_t n_left, int64_t* counts,
+                                                          unsigned long long* ppart) {
+    __shared__ unsigned long long sw[kJThreads / 64];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long p = 0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_left; k += stride) {
@@ -197,7 +200,29 @@ __global__ void k_join_count(JTable T, JCol l, int64_t n_left, int64_t* counts, 
         if (slot >= 0) p += (unsigned long long)len * T.rows[slot];
     }
     for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
-    if ((threadIdx.x & 63) == 0 && p) atomicAdd(pairs, p);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kJThreads / 64; ++w) t += sw[w];
+        ppart[blockIdx.x] = t;
+    }
+}
+
+// the sum of n partials into *total (one workgroup)
+__global__ __launch_bounds__(kJThreads) void k_sum_parts(const unsigned long long* part, int64_t n,
+                                                         unsigned long long* total) {
+    __shared__ unsigned long long sw[kJThreads / 64];
+    unsigned long long p = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kJThreads) p += part[i];
+    for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kJThreads / 64; ++w) t += sw[w];
+        *total = t;
+    }
 }
 
 __global__ void k_join_write(JTable T, JCol l, JCol r, int64_t n_left, const int64_t* offsets,
@@ -313,21 +338,121 @@ __device__ __forceinline__ int64_t value_at_row(const JCol& c, int64_t r) {
     return packed_value(c, r);
 }
 
-__global__ void k_join_apply(const ccq_join_block* b, int64_t nb, const int64_t* off, int64_t total, JCol c,
-                             int32_t side, int64_t* out) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += stride) {
-        int64_t lo = 0, hi = nb;      // last block with off <= p
-        while (hi - lo > 1) {
-            const int64_t m = (lo + hi) >> 1;
-            if (off[m] <= p) lo = m; else hi = m;
-        }
-        // the block holding pair p (blocks of no pairs share the next one's offset and are never last)
-        const ccq_join_block& bb = b[lo];
-        const int64_t q = p - off[lo];
-        const int64_t row = side == 0 ? bb.left_start + q / bb.right_len : bb.right_start + q % bb.right_len;
-        out[p] = value_at_row(c, row);
+constexpr int kApplyPer = 16;                               // consecutive outputs per thread
+constexpr int64_t kApplyChunk = (int64_t)kJThreads * kApplyPer;  // outputs per workgroup
+
+// last block m in [lo, hi] with off[m] <= p (off[lo] <= p)
+__device__ __forceinline__ int64_t block_of(const int64_t* off, int64_t lo, int64_t hi, int64_t p) {
+    while (lo < hi) {
+        const int64_t m = (lo + hi + 1) >> 1;
+        if (off[m] <= p) lo = m; else hi = m - 1;
     }
+    return lo;
+}
+
+// reads a column at rows that mostly step by one: an RLE cursor keeps the
+// current run, an Index cursor the next listed point
+struct RowCursor {
+    int64_t i = -1, lo = 0, hi = 0;    // RLE: run i covers [lo, hi); Index: point i is the first >= hi - 1
+    int64_t v = 0;
+};
+
+__device__ __forceinline__ int64_t read_row(const JCol& c, int64_t r, RowCursor& k) {
+    if (c.enc == CCQ_RLE) {
+        if (k.i < 0 || r < k.lo || r >= k.hi) {
+            if (k.i >= 0 && r == k.hi) ++k.i; else k.i = upper_bound_dev(c.ends, c.n, r);
+            k.lo = k.i > 0 ? c.ends[k.i - 1] : 0;
+            k.hi = c.ends[k.i];
+            k.v = jld(c.vals, c.vtype, k.i);
+        }
+        return k.v;
+    }
+    if (c.enc == CCQ_INDEX) {
+        // k.lo: the row last read; k.i: the first point at or after it
+        if (k.i < 0 || r != k.lo + 1) k.i = lower_bound_pos(c.pos, c.ptype, c.n, r);
+        else if (k.i < c.n && jld(c.pos, c.ptype, k.i) < r) ++k.i;
+        k.lo = r;
+        return (k.i < c.n && jld(c.pos, c.ptype, k.i) == r) ? jld(c.vals, c.vtype, k.i) : 0;
+    }
+    return packed_value(c, r);
+}
+
+// the block holding each chunk's first output (one thread per chunk, all
+// searches in flight together); entry n_chunks holds the last output's block
+__global__ void k_chunk_first(const int64_t* off, int64_t nb, int64_t total, int64_t n_chunks, int64_t* first) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= n_chunks; c += stride)
+        first[c] = block_of(off, 0, nb - 1, min(c * kApplyChunk, total - 1));
+}
+
+constexpr int kApplyLds = 2048;            // block offsets a workgroup stages in LDS
+
+// one workgroup per chunk of kApplyChunk outputs; each thread takes
+// kApplyPer consecutive ones (one block search and one division, the rows,
+// then all their loads), stages them in LDS, and the chunk is written with
+// coalesced stores
+__global__ __launch_bounds__(kJThreads) void k_join_apply(const ccq_join_block* b, int64_t nb, const int64_t* off,
+                                                          int64_t total, const int64_t* first, JCol c, int32_t side,
+                                                          int64_t* out) {
+    // padded by one slot per kApplyPer: a thread's run starts 17 slots after its neighbour's
+    __shared__ int64_t sout[kApplyChunk + kApplyChunk / kApplyPer];
+    __shared__ int64_t soff[kApplyLds];
+    const int64_t c0 = (int64_t)blockIdx.x * kApplyChunk;
+    const int64_t c1 = min(total, c0 + kApplyChunk);
+    // the chunk's blocks lie in [lo, hi]
+    const int64_t lo = first[blockIdx.x], hi = first[blockIdx.x + 1];
+    const bool staged = hi - lo < kApplyLds;
+    if (staged)
+        for (int64_t i = threadIdx.x; i <= hi - lo; i += kJThreads) soff[i] = off[lo + i];
+    __syncthreads();
+    const int64_t p0 = c0 + (int64_t)threadIdx.x * kApplyPer;
+    if (p0 < c1) {
+        int64_t k;
+        if (staged) {
+            int32_t a = 0, z = (int32_t)(hi - lo);
+            while (a < z) {
+                const int32_t m = (a + z + 1) >> 1;
+                if (soff[m] <= p0) a = m; else z = m - 1;
+            }
+            k = lo + a;
+        } else {
+            k = block_of(off, lo, hi, p0);
+        }
+        // k holds pair p0: blocks of no pairs share the next one's offset and are never last
+        ccq_join_block bb = b[k];
+        const int64_t q = p0 - off[k];
+        int64_t a = q / bb.right_len, r = q % bb.right_len;
+        const int n = (int)min<int64_t>(kApplyPer, c1 - p0);
+        int64_t rows[kApplyPer];
+#pragma unroll
+        for (int j = 0; j < kApplyPer; ++j) {
+            rows[j] = side == 0 ? bb.left_start + a : bb.right_start + r;
+            if (++r == bb.right_len) {
+                r = 0;
+                if (++a == bb.left_len && j + 1 < n) {
+                    // next block with pairs (one exists: pair p0 + j + 1 < total)
+                    do {
+                        bb = b[++k];
+                    } while (bb.left_len == 0 || bb.right_len == 0);
+                    a = 0;
+                }
+            }
+        }
+        int64_t* dst = sout + threadIdx.x * (kApplyPer + 1);
+        if (c.enc == CCQ_BITPACKED) {
+            // independent loads, all in flight together
+#pragma unroll
+            for (int j = 0; j < kApplyPer; ++j)
+                if (j < n) dst[j] = packed_value(c, rows[j]);
+        } else {
+            RowCursor cur;
+#pragma unroll
+            for (int j = 0; j < kApplyPer; ++j)
+                if (j < n) dst[j] = read_row(c, rows[j], cur);
+        }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < c1 - c0; i += kJThreads) out[c0 + i] = sout[i + i / kApplyPer];
 }
 
 // ---- host helpers
@@ -337,6 +462,8 @@ ccq_status jcol(const ccq_table* t, int32_t col, int64_t begin, int64_t end, JCo
     if (col < 0 || col >= (int32_t)t->cols.size()) return fail(CCQ_E_INVALID, "column %d out of range", col);
     if (begin < 0 || end > t->n_rows || begin > end) return fail(CCQ_E_INVALID, "window outside the table");
     const ccq_column_desc& d = t->cols[col];
+    if (d.encoding != CCQ_RLE && d.encoding != CCQ_INDEX && d.encoding != CCQ_BITPACKED)
+        return fail(CCQ_E_UNSUPPORTED, "column %d: joins take RLE, INDEX and BITPACKED columns", col);
     memset(c, 0, sizeof *c);
     c->enc = d.encoding;
     c->vtype = d.value_type;
@@ -370,6 +497,7 @@ struct JWs {
     int64_t* counts;         // [n_left]
     int64_t* offsets;        // [n_left]
     int64_t* part;           // [chunks + 1]
+    unsigned long long* ppart;  // [count grid] pairs per workgroup
     size_t total;
 };
 
@@ -393,11 +521,14 @@ JWs join_ws(unsigned char* base, int64_t n_left, int64_t n_right) {
     w.counts = (int64_t*)take(8 * (size_t)std::max<int64_t>(n_left, 1));
     w.offsets = (int64_t*)take(8 * (size_t)std::max<int64_t>(n_left, 1));
     w.part = (int64_t*)take(8 * (size_t)((n_left + kScanPer - 1) / kScanPer + 2));
+    w.ppart = (unsigned long long*)take(8 * (size_t)kMaxGrid);
     w.total = o;
     return w;
 }
 
-unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kJThreads - 1) / kJThreads, 8192)); }
+unsigned grid_for(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kJThreads - 1) / kJThreads, kMaxGrid));
+}
 
 // exclusive scan of in[n] into out[n]; the total lands at part[chunks]
 void scan(const int64_t* in, int64_t n, int64_t* part, int64_t* out, hipStream_t s) {
@@ -454,7 +585,9 @@ ccq_status ccq_join_index(const ccq_table* left, int32_t left_col, int64_t left_
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
     if (nr > 0) hipLaunchKernelGGL(k_join_build, dim3(grid_for(nr)), dim3(kJThreads), 0, s, w.T, r, nr);
     if (nl > 0) {
-        hipLaunchKernelGGL(k_join_count, dim3(grid_for(nl)), dim3(kJThreads), 0, s, w.T, l, nl, w.counts, w.pairs);
+        const unsigned g = grid_for(nl);
+        hipLaunchKernelGGL(k_join_count, dim3(g), dim3(kJThreads), 0, s, w.T, l, nl, w.counts, w.ppart);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kJThreads), 0, s, w.ppart, (int64_t)g, w.pairs);
         scan(w.counts, nl, w.part, w.offsets, s);
     }
     int64_t tot = 0;
@@ -476,9 +609,11 @@ ccq_status ccq_join_index(const ccq_table* left, int32_t left_col, int64_t left_
     return ok();
 }
 
-size_t ccq_join_apply_workspace_bytes(int64_t n_blocks) {
+size_t ccq_join_apply_workspace_bytes(int64_t n_blocks, int64_t n_pairs) {
     const int64_t n = std::max<int64_t>(n_blocks, 1);
-    return 256 + a256(8 * (size_t)n) * 2 + a256(8 * (size_t)((n + kScanPer - 1) / kScanPer + 2));
+    const int64_t chunks = std::max<int64_t>(n_pairs, 0) / kApplyChunk + 2;
+    return 256 + a256(8 * (size_t)n) * 2 + a256(8 * (size_t)((n + kScanPer - 1) / kScanPer + 2)) +
+           a256(8 * (size_t)chunks);
 }
 
 ccq_status ccq_join_apply(const ccq_table* t, int32_t col, const ccq_join_block* blocks, int64_t n_blocks, int32_t side,
@@ -491,7 +626,7 @@ ccq_status ccq_join_apply(const ccq_table* t, int32_t col, const ccq_join_block*
     if (side != 0 && side != 1) return fail(CCQ_E_INVALID, "side must be 0 (left) or 1 (right)");
     if (n_blocks < 0 || (n_blocks > 0 && !blocks)) return fail(CCQ_E_INVALID, "bad block list");
     if (!ws || ((uintptr_t)ws & 255)) return fail(CCQ_E_INVALID, "workspace must be 256-byte aligned");
-    if (ws_bytes < ccq_join_apply_workspace_bytes(n_blocks)) return fail(CCQ_E_CAPACITY, "workspace too small");
+    if (ws_bytes < ccq_join_apply_workspace_bytes(n_blocks, 0)) return fail(CCQ_E_CAPACITY, "workspace too small");
     if (n_blocks == 0) return ok();
     hipError_t e = hipSetDevice(t->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -502,6 +637,7 @@ ccq_status ccq_join_apply(const ccq_table* t, int32_t col, const ccq_join_block*
     int64_t* pc = (int64_t*)(w + 256);
     int64_t* off = (int64_t*)(w + 256 + a256(8 * (size_t)n));
     int64_t* part = (int64_t*)(w + 256 + 2 * a256(8 * (size_t)n));
+    int64_t* cfirst = (int64_t*)(w + 256 + 2 * a256(8 * (size_t)n) + a256(8 * (size_t)((n + kScanPer - 1) / kScanPer + 2)));
     e = hipMemsetAsync(bad, 0, 4, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
     hipLaunchKernelGGL(k_pair_counts, dim3(grid_for(n)), dim3(kJThreads), 0, s, blocks, n, side, t->n_rows, pc, bad);
@@ -516,10 +652,17 @@ ccq_status ccq_join_apply(const ccq_table* t, int32_t col, const ccq_join_block*
     if (flag) return fail(CCQ_E_INVALID, "a block's rows lie outside the table");
     *n_out = total;
     if (total > capacity) return fail(CCQ_E_CAPACITY, "%lld values, capacity %lld", (long long)total, (long long)capacity);
+    if (ws_bytes < ccq_join_apply_workspace_bytes(n_blocks, total))
+        return fail(CCQ_E_CAPACITY, "workspace of %zu bytes, %zu needed for %lld pairs", ws_bytes,
+                    ccq_join_apply_workspace_bytes(n_blocks, total), (long long)total);
     if (total > 0) {
         if (!out) return fail(CCQ_E_INVALID, "out is NULL");
-        hipLaunchKernelGGL(k_join_apply, dim3(grid_for(total)), dim3(kJThreads), 0, s, blocks, n, off, total, c, side,
-                           out);
+        const int64_t chunks_out = (total + kApplyChunk - 1) / kApplyChunk;
+        if (chunks_out > INT32_MAX) return fail(CCQ_E_UNSUPPORTED, "more than 2^31 chunks of output");
+        hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(chunks_out + 1)), dim3(kJThreads), 0, s, off, n, total,
+                           chunks_out, cfirst);
+        hipLaunchKernelGGL(k_join_apply, dim3((unsigned)chunks_out), dim3(kJThreads), 0, s, blocks, n, off, total,
+                           cfirst, c, side, out);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "join apply");

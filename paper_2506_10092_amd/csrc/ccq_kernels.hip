@@ -234,9 +234,9 @@ WsLayout workspace_layout(const DevPlan& p) {
 // bit width of the fast row path (0: run mode or generic row mode)
 static FusedFn fused_kernel(const DevPlan& p) {
     const bool big = p.fast_big != 0;
-    if (p.kmax <= 2) return fused_kernel_k2(p.w0, big);
-    if (p.kmax <= 4) return fused_kernel_k4(p.w0, big);
-    return fused_kernel_k8(p.w0, big);
+    if (p.kmax <= 2) return fused_kernel_k2(kernel_w0(p), big);
+    if (p.kmax <= 4) return fused_kernel_k4(kernel_w0(p), big);
+    return fused_kernel_k8(kernel_w0(p), big);
 }
 
 bool fast_row_width(int w) { return w == 14 || w == 20; }

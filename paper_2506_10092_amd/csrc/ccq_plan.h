@@ -15,6 +15,7 @@ constexpr int kTileShift = 11;            // log2(kRowTile)
 constexpr int kMaxRle = 8;
 constexpr int kMaxBp = 4;
 constexpr int kMaxIdx = 2;
+constexpr int kMaxComp = 2;           // composite columns per query
 constexpr int kMaxKeys = 8;
 constexpr int kMaxAggs = 8;
 constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
@@ -109,6 +110,25 @@ struct IdxCol {
     int32_t zero_pass;      // 1 when the value 0 passes the predicate
 };
 
+// A composite column (Section 3.2: RLE + Index, Plain + Index): its base
+// part is an ordinary RLE or bit-packed slot without predicates; rows its
+// points list take the points' values, and its predicate is tested per row
+// on that value (generic row path).
+struct CompCol {
+    int32_t rle;            // 1: the base part is RLE slot `src`; 0: bit-packed slot `src`
+    int32_t src;
+    const void* pos;        // points, strictly increasing
+    const void* vals;
+    int64_t n;
+    int32_t ptype, vtype;
+    int32_t pred;           // PredKind on the row's value
+    int32_t set_len;
+    int64_t lo, hi;
+    const int64_t* set;
+    int32_t lds_off;        // in a wave slice: 64 words of listed rows, then 64 int32 prefixes
+    int32_t pad_;
+};
+
 struct KeyDesc {
     int32_t src_kind;       // KeySrc
     int32_t src;            // column slot within its kind
@@ -147,6 +167,11 @@ struct ExtAcc {
     int32_t a_rle, a_src;   // first operand: RLE (1) or bit-packed (0) column slot
     int32_t b_rle, b_src;   // second operand (op != CCQ_OP_NONE)
 };
+
+struct DevPlan;
+// the kernel instance's width parameter: -1 for the staged paths with
+// composite columns, else the plan's w0
+inline int kernel_w0(const DevPlan& p);
 
 struct DevPlan {
     int64_t row_begin, row_end;
@@ -192,7 +217,8 @@ struct DevPlan {
     // pieces of one group segment before they reach the table
     int32_t seg_slots, off_slots;
     int32_t n_ext;          // accumulators [0, n_ext) are ExtAcc (MIN, MAX, expressions); 0 otherwise
-    int32_t pad_ext_;
+    int32_t n_comp;         // composite columns (comp[0, n_comp))
+    CompCol comp[kMaxComp];
     ExtAcc ext[kMaxAggs];
     RleCol rle[kMaxRle];
     BpCol bp[kMaxBp];
@@ -220,18 +246,22 @@ struct BatchGroup {
 };
 
 // kernel instance variants besides KMAX: staged paths, fast row path of width
-// 14 or 20, each of those with a large table
+// 14 or 20, each of those with a large table; variant 6 is the staged paths'
+// kernel with composite columns (instance w0 = -1), kept apart so the
+// per-row point lookups cost the other plans no registers
 // Variant 5 runs the staged paths' kernel too, for plans that need more
 // than kBatchLdsSplit bytes of LDS per workgroup (large group tables in
 // LDS), so they do not lower the occupancy of the other staged plans'
 // launch.
-constexpr int kVariants = 6;
+constexpr int kVariants = 7;
 constexpr int kMaxInstances = 3 * kVariants;     // KMAX in {2, 4, 8}
 constexpr int kBatchLdsSplit = 48 * 1024;
+inline int kernel_w0(const DevPlan& p) { return p.n_comp > 0 ? -1 : p.w0; }
 inline int variant_of(int w0, int big, int lds_bytes) {
+    if (w0 < 0) return 6;
     return w0 == 0 ? (lds_bytes > kBatchLdsSplit ? 5 : 0) : (w0 == 14 ? 1 : 2) + (big ? 2 : 0);
 }
-inline int variant_w0(int v) { return v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20; }
+inline int variant_w0(int v) { return v == 6 ? -1 : v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20; }
 inline int variant_big(int v) { return v == 3 || v == 4 ? 1 : 0; }
 
 // Where each query's result goes.

@@ -212,14 +212,14 @@ hipError_t launch_lane(ccq_server* s, Lane& L) {
         std::vector<int32_t> big;
         for (int i = 0; i < n; ++i) {
             const DevPlan& p = reqs[i].plan->host;
-            const int ki = p.kmax <= 2 ? 0 : p.kmax <= 4 ? 1 : 2, wi = variant_of(p.w0, p.fast_big, p.lds_dyn_bytes);
+            const int ki = p.kmax <= 2 ? 0 : p.kmax <= 4 ? 1 : 2, wi = variant_of(kernel_w0(p), p.fast_big, p.lds_dyn_bytes);
             int& g = group_of[ki][wi];
             if (g < 0) {
                 g = n_groups++;
                 items.emplace_back();
                 glds.push_back(0);
                 gk.push_back(p.kmax);
-                gw.push_back(p.w0);
+                gw.push_back(kernel_w0(p));
                 gb.push_back(p.fast_big);
             }
             glds[g] = std::max(glds[g], p.lds_dyn_bytes);

@@ -158,13 +158,13 @@ def tiny_query_with_exprs(rng, n, wd):
     return q
 
 
-def composite_columns(rng, n):
+def composite_columns(rng, n, p_single=None):
     """Two composite columns over n rows (Section 3.2): x as RLE + Index
     (pure runs of two or more rows, single rows as points) and y as Plain +
     Index (values outside [base, base + 2^w) as points; the
     codes at those rows are random, since they are never read)."""
     # segments: pure runs of 2-6 rows and single rows (points), in random order
-    p_single = float(rng.choice([0.0, 0.3, 0.9]))
+    p_single = float(rng.choice([0.0, 0.3, 0.9])) if p_single is None else p_single
     rv, rs, re_, pp, pv = [], [], [], [], []
     r = 0
     while r < n:

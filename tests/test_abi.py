@@ -35,7 +35,7 @@ def test_header_functions_are_exported():
 
 
 def test_abi_version():
-    assert ccq.lib().ccq_abi_version() == 6
+    assert ccq.lib().ccq_abi_version() == 7
 
 
 def _host_table(columns, n_rows):
@@ -213,3 +213,53 @@ def test_expression_plans_check_on_host():
     with pytest.raises(ccq.CcqError) as e:
         ccq.plan_check(tb, dict(q, aggs=[("sum", ("a", "%", "p"))]))
     assert e.value.status == ccq.E_INVALID
+
+
+def _composite_cols(n=1000):
+    t = lambda a, dt: torch.tensor(a, dtype=dt)
+    cols = _cols(n)
+    cols["x"] = {"enc": "rle+index", "values": t([4, 9], torch.int64), "run_ends": t([600, n], torch.int64),
+                 "positions": t([7, 650], torch.int32), "point_values": t([-1, 3], torch.int64)}
+    cols["y"] = {"enc": "plain+index", "packed": torch.zeros((n * 6 + 31) // 32 + 2, dtype=torch.int32), "w": 6,
+                 "base": -3, "positions": t([0, 999], torch.int32), "point_values": t([1 << 40, -(1 << 40)], torch.int64)}
+    return cols
+
+
+def test_composite_plans_check_on_host():
+    """Composite columns (Section 3.2) in predicates, SUM, MIN, MAX and
+    expressions; not as keys, not in an OR across columns, at most two."""
+    tb = _host_table(_composite_cols(), 1000)
+    q = {"preds": [("x", "range", 0, 5), ("y", "not_range", 0, 9), ("d", "in", [1, 2])], "keys": [("d", 0, 1 << 14)],
+         "aggs": [("sum", "x"), ("min", "y"), ("max", ("x", "+", "y")), ("sum", "s"), ("count",)], "window": (0, 1000)}
+    g, _ = ccq.plan_check(tb, q)
+    assert g == 2
+    ccq.plan_check(tb, dict(q, preds=[], **{"or": [[("x", "range", 0, 2), ("x", "in", [9])]]}))   # one column
+    for bad in ({"keys": [("x", 0, 16)]}, {"keys": [("y", 0, 64)]},
+                {"or": [[("x", "range", 0, 2), ("a", "in", [1])]]},
+                {"or": [[("y", "range", 0, 2), ("d", "in", [1])]]}):
+        with pytest.raises(ccq.CcqError) as e:
+            ccq.plan_check(tb, dict(q, **bad))
+        assert e.value.status == ccq.E_UNSUPPORTED, bad
+    cols = _composite_cols()
+    cols["z"] = dict(cols["x"])
+    tb = _host_table(cols, 1000)
+    with pytest.raises(ccq.CcqError) as e:
+        ccq.plan_check(tb, dict(q, preds=[("x", "range", 0, 5), ("y", "range", 0, 5), ("z", "range", 0, 5)]))
+    assert e.value.status == ccq.E_UNSUPPORTED
+
+
+def test_composite_table_create_rejects():
+    cols = _composite_cols()
+    cols["x"]["point_values"] = cols["x"]["point_values"].to(torch.int32)     # run values are int64
+    with pytest.raises(ccq.CcqError, match="share one type"):
+        _host_table(cols, 1000)
+    L = ccq.lib()
+    d = ccq._column_desc(_composite_cols()["a"], 1000)
+    d.n_points = 3                                  # points on a plain RLE column
+    h = ccq.ctypes.c_void_p()
+    ctx = ccq.Context(ccq.HOST_ONLY)
+    assert L.ccq_table_create(ctx.h, 1000, ccq.ctypes.byref(d), 1, ccq.ctypes.byref(h)) == ccq.E_INVALID
+    assert b"n_points" in L.ccq_last_error()
+    d = ccq._column_desc(_composite_cols()["y"], 1000)
+    d.point_values = None
+    assert L.ccq_table_create(ctx.h, 1000, ccq.ctypes.byref(d), 1, ccq.ctypes.byref(h)) == ccq.E_INVALID
