@@ -1459,13 +1459,15 @@ __device__ __forceinline__ void slotacc_init(SlotAcc& a) {
     for (int k = 0; k < kMaxAggs; ++k) a.sum[k] = 0;
 }
 
+template <bool FULL>
 __device__ __forceinline__ void slotacc_flush(const DevPlan& P, const Table& tb, SlotAcc& a) {
+    constexpr int NS = FULL ? kMaxAggs : kSmallSums;
     if (a.gid >= 0 && a.cnt > 0) {
         table_add(tb, 0, a.gid, a.cnt);
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k) {
+        for (int k = 0; k < NS; ++k) {
             if (k >= P.n_sums || a.sum[k] == 0) continue;
-            if (k < P.n_ext && P.ext[k].kind != kExtSum)     // MIN / MAX: encoded, unsigned maximum
+            if (FULL && k < P.n_ext && P.ext[k].kind != kExtSum)     // MIN / MAX: encoded, unsigned maximum
                 atomicMax((unsigned long long*)&tb.g[(int64_t)(1 + k) * tb.G + a.gid], (unsigned long long)a.sum[k]);
             else
                 table_add(tb, 1 + k, a.gid, a.sum[k]);
@@ -1481,17 +1483,18 @@ __device__ __forceinline__ void slotacc_flush(const DevPlan& P, const Table& tb,
 // the row clause, the group id from the key columns (ridx: the staged run of
 // each RLE column holding r) and the decoded bit-packed values.  False if
 // the row fails, or (status raised) if a key is outside its domain.
-template <int KMAX, bool COMP>
+template <int KMAX, bool FULL>
 __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int32_t r,
                                          const int32_t (&ridx)[KMAX], const int32_t (&luts)[kMaxBp],
                                          int32_t* status, int64_t* gid_out, int64_t (&bpv)[kMaxBp],
                                          const int64_t (&cfirst)[kMaxComp], int64_t (&cv)[kMaxComp]) {
+    constexpr int NB = FULL ? kMaxBp : kSmallBp;
     bool pass = true;
     bool dom = false;
     int64_t gid = 0;
     uint32_t codes[kMaxBp];
 #pragma unroll
-    for (int j = 0; j < kMaxBp; ++j) {
+    for (int j = 0; j < NB; ++j) {
         bpv[j] = 0;
         codes[j] = 0;
         if (j >= P.n_bp) continue;
@@ -1526,7 +1529,7 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
 #pragma unroll
     for (int i = 0; i < kMaxComp; ++i) {
         cv[i] = 0;
-        if (!COMP || i >= P.n_comp) continue;
+        if (!FULL || i >= P.n_comp) continue;
         const CompCol& cc = P.comp[i];
         const uint32_t* lm = (const uint32_t*)(W.base + cc.lds_off);
         const uint32_t w = lm[r >> 5];
@@ -1540,12 +1543,12 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
                 if (c < P.k_rle && c == cc.src) v = W.run_val[stage_base(P, c) + ridx[c]];
         } else {
 #pragma unroll
-            for (int b = 0; b < kMaxBp; ++b)
+            for (int b = 0; b < NB; ++b)
                 if (b < P.n_bp && b == cc.src) v = bpv[b];
         }
         if (!cc.rle) {
 #pragma unroll
-            for (int b = 0; b < kMaxBp; ++b)
+            for (int b = 0; b < NB; ++b)
                 if (b < P.n_bp && b == cc.src) bpv[b] = v;
         }
         cv[i] = v;
@@ -1556,7 +1559,7 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
         // or a bit-packed part holding on this row's value
         bool in = ((W.rcl[r >> 5] >> (r & 31)) & 1u) != 0;
 #pragma unroll
-        for (int j = 0; j < kMaxBp; ++j) {
+        for (int j = 0; j < NB; ++j) {
             if (j >= P.n_bp || P.bp[j].or_pred == kPredNone) continue;
             if (P.bp[j].or_bits_words > 0) {
                 const uint32_t* ob = (const uint32_t*)(ccq_lds + P.bp[j].or_bits_lds_off);
@@ -1583,11 +1586,11 @@ __device__ __forceinline__ bool row_eval(const DevPlan& P, const WaveLds& W, int
 
 // the value of RLE column c at the row: its staged run's, or a composite
 // column's point value where its Index part lists the row
-template <int KMAX, bool COMP>
+template <int KMAX, bool FULL>
 __device__ __forceinline__ int64_t rle_row_val(const DevPlan& P, const WaveLds& W, int c,
                                                const int32_t (&ridx)[KMAX], const int64_t (&cv)[kMaxComp]) {
     int64_t v = W.run_val[stage_base(P, c) + ridx[c]];
-    if constexpr (COMP) {
+    if constexpr (FULL) {
 #pragma unroll
         for (int i = 0; i < kMaxComp; ++i)
             if (i < P.n_comp && P.comp[i].rle && P.comp[i].src == c) v = cv[i];
@@ -1602,11 +1605,13 @@ __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
     return x;
 }
 
-template <int KMAX, bool COMP>
+template <int KMAX, bool FULL>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
                                                  uint32_t pm, const Table& tb, int32_t* status,
                                                  int64_t (&pcur)[kMaxIdx], int64_t (&ccur)[kMaxComp],
                                                  const int32_t (&luts)[kMaxBp], SlotAcc& acc) {
+    constexpr int NB = FULL ? kMaxBp : kSmallBp;
+    constexpr int NS = FULL ? kMaxAggs : kSmallSums;
     const int lane = lane_id();
     const uint32_t any = wave_or32(pm);
     if (P.n_idx > 0) W.pmw[lane] = pm;
@@ -1615,7 +1620,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
     const uint64_t need_lanes = wave_ballot(pm != 0);
     if (any) {
 #pragma unroll
-        for (int j = 0; j < kMaxBp; ++j) {
+        for (int j = 0; j < NB; ++j) {
             if (j >= P.n_bp) continue;
             const BpCol& bc = P.bp[j];
             const int64_t wbase = (t0 * (int64_t)bc.w) >> 5;
@@ -1639,7 +1644,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
 #pragma unroll
     for (int i = 0; i < kMaxComp; ++i) {
         cfirst[i] = 0;
-        if (!COMP || i >= P.n_comp) continue;
+        if (!FULL || i >= P.n_comp) continue;
         const CompCol& cc = P.comp[i];
         uint32_t* lm = (uint32_t*)(W.base + cc.lds_off);
         lm[lane] = 0;
@@ -1690,28 +1695,28 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
             int64_t bpv[kMaxBp];
             int64_t cv[kMaxComp];
             int64_t gid;
-            if (!row_eval<KMAX, COMP>(P, W, s0 + j, ridx, luts, status, &gid, bpv, cfirst, cv)) continue;
+            if (!row_eval<KMAX, FULL>(P, W, s0 + j, ridx, luts, status, &gid, bpv, cfirst, cv)) continue;
             if (gid != acc.gid) {
-                slotacc_flush(P, tb, acc);
+                slotacc_flush<FULL>(P, tb, acc);
                 acc.gid = gid;
             }
             acc.cnt += 1;
             // SUM terms by slot (static indices keep the accumulators in registers)
 #pragma unroll
-            for (int k = 0; k < kMaxAggs; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 if (k >= P.n_sums) continue;
-                if (k < P.n_ext) {
+                if (FULL && k < P.n_ext) {
                     // MIN, MAX or an expression: the row's operands, then the fold
                     const ExtAcc& e = P.ext[k];
                     int64_t va = 0, vb = 0;
 #pragma unroll
                     for (int c = 0; c < KMAX; ++c) {
                         if (c >= P.k_rle) continue;
-                        if (e.a_rle && e.a_src == c) va = rle_row_val<KMAX, COMP>(P, W, c, ridx, cv);
-                        if (e.b_rle && e.b_src == c) vb = rle_row_val<KMAX, COMP>(P, W, c, ridx, cv);
+                        if (e.a_rle && e.a_src == c) va = rle_row_val<KMAX, FULL>(P, W, c, ridx, cv);
+                        if (e.b_rle && e.b_src == c) vb = rle_row_val<KMAX, FULL>(P, W, c, ridx, cv);
                     }
 #pragma unroll
-                    for (int b = 0; b < kMaxBp; ++b) {
+                    for (int b = 0; b < NB; ++b) {
                         if (b >= P.n_bp) continue;
                         if (!e.a_rle && e.a_src == b) va = bpv[b];
                         if (!e.b_rle && e.b_src == b) vb = bpv[b];
@@ -1732,9 +1737,9 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
                 int64_t term = 0;
 #pragma unroll
                 for (int c = 0; c < KMAX; ++c)
-                    if (c < P.k_rle && P.rle[c].sum_slot == k) term = rle_row_val<KMAX, COMP>(P, W, c, ridx, cv);
+                    if (c < P.k_rle && P.rle[c].sum_slot == k) term = rle_row_val<KMAX, FULL>(P, W, c, ridx, cv);
 #pragma unroll
-                for (int b = 0; b < kMaxBp; ++b)
+                for (int b = 0; b < NB; ++b)
                     if (b < P.n_bp && P.bp[b].sum_slot == k) term = bpv[b];
                 acc.sum[k] += term;
             }
@@ -1768,7 +1773,7 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
                         int64_t bpv[kMaxBp];
                         int64_t cv[kMaxComp];
                         int64_t gid;
-                        if (row_eval<KMAX, COMP>(P, W, rel, idx, luts, status, &gid, bpv, cfirst, cv)) {
+                        if (row_eval<KMAX, FULL>(P, W, rel, idx, luts, status, &gid, bpv, cfirst, cv)) {
                             const int64_t v = ld_val(ic.vals, ic.vtype, i);
                             if (v != 0) table_add(tb, 1 + ic.sum_slot, gid, v);
                         }
@@ -1899,7 +1904,7 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
                 tile_bitmaps_clear(P, W);
                 t0 = t1;
             }
-            slotacc_flush(P, tb, sacc);
+            slotacc_flush<(W0 < 0)>(P, tb, sacc);
         } else {
             RegAcc<KMAX> acc;
             regacc_init(acc);

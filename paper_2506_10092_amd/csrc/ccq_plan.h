@@ -16,6 +16,11 @@ constexpr int kMaxRle = 8;
 constexpr int kMaxBp = 4;
 constexpr int kMaxIdx = 2;
 constexpr int kMaxComp = 2;           // composite columns per query
+// the common staged-path instance is compiled for at most this many
+// bit-packed columns and accumulators, without MIN / MAX / expression and
+// composite code; larger plans take the full instance
+constexpr int kSmallBp = 2;
+constexpr int kSmallSums = 4;
 constexpr int kMaxKeys = 8;
 constexpr int kMaxAggs = 8;
 constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
@@ -169,8 +174,10 @@ struct ExtAcc {
 };
 
 struct DevPlan;
-// the kernel instance's width parameter: -1 for the staged paths with
-// composite columns, else the plan's w0
+// the kernel instance's width parameter: the fast row path's width; for
+// the staged paths 0 (the common instance) or -1 (the full instance:
+// composite columns, MIN / MAX / expressions, more than kSmallBp bit-packed
+// columns or kSmallSums accumulators)
 inline int kernel_w0(const DevPlan& p);
 
 struct DevPlan {
@@ -247,8 +254,8 @@ struct BatchGroup {
 
 // kernel instance variants besides KMAX: staged paths, fast row path of width
 // 14 or 20, each of those with a large table; variant 6 is the staged paths'
-// kernel with composite columns (instance w0 = -1), kept apart so the
-// per-row point lookups cost the other plans no registers
+// full instance (w0 = -1: composite columns, MIN / MAX / expressions, wide
+// plans), kept apart so its code costs the common plans no registers
 // Variant 5 runs the staged paths' kernel too, for plans that need more
 // than kBatchLdsSplit bytes of LDS per workgroup (large group tables in
 // LDS), so they do not lower the occupancy of the other staged plans'
@@ -256,7 +263,10 @@ struct BatchGroup {
 constexpr int kVariants = 7;
 constexpr int kMaxInstances = 3 * kVariants;     // KMAX in {2, 4, 8}
 constexpr int kBatchLdsSplit = 48 * 1024;
-inline int kernel_w0(const DevPlan& p) { return p.n_comp > 0 ? -1 : p.w0; }
+inline int kernel_w0(const DevPlan& p) {
+    if (p.w0 > 0) return p.w0;
+    return (p.n_comp > 0 || p.n_ext > 0 || p.n_bp > kSmallBp || p.n_sums > kSmallSums) ? -1 : 0;
+}
 inline int variant_of(int w0, int big, int lds_bytes) {
     if (w0 < 0) return 6;
     return w0 == 0 ? (lds_bytes > kBatchLdsSplit ? 5 : 0) : (w0 == 14 ? 1 : 2) + (big ? 2 : 0);
