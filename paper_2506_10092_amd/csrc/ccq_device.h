@@ -1605,6 +1605,165 @@ __device__ __forceinline__ uint32_t wave_or32(uint32_t x) {
     return x;
 }
 
+// The common instance's pass over the lane's 32 rows, in two phases.
+// Phase 1 goes column by column, so each column's plan fields are read
+// once per tile: a bit-packed column's code decides, for every row of the
+// lane, the row's pass bit (a code-table reject or a failed predicate), its
+// key slot and its part of the row clause; an RLE key column adds its staged
+// run's group-id part (the run holding row r is the lane's first run plus
+// the boundaries at rows <= r).  Phase 2 adds the surviving rows to the group
+// table, consecutive rows of one group through the register accumulator.
+template <int KMAX>
+__device__ __forceinline__ void lane_rows_two_phase(const DevPlan& P, const WaveLds& W, uint32_t pm,
+                                                    const int32_t (&luts)[kMaxBp], const Table& tb,
+                                                    int32_t* status, SlotAcc& acc) {
+    const int lane = lane_id();
+    uint32_t live = pm;
+    uint32_t dom = 0;
+    int32_t gid[kRowSpan];
+#pragma unroll
+    for (int r = 0; r < kRowSpan; ++r) gid[r] = 0;
+    const bool rcl = W.rcl != nullptr;
+    uint32_t orin = rcl ? W.rcl[lane] : 0u;
+
+    // phase 1, bit-packed columns (tiles start at multiples of 32 rows, so
+    // the lane's row s0 = 32 lane sits at bit s0 w of the staged words: word
+    // lane w, bit 0)
+#pragma unroll
+    for (int j = 0; j < kSmallBp; ++j) {
+        if (j >= P.n_bp) continue;
+        const BpCol& bc = P.bp[j];
+        const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
+        const uint32_t w = (uint32_t)bc.w;
+        const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+        const uint32_t q0 = (uint32_t)lane * w;
+        const int64_t base = bc.base;
+        const bool key = bc.key >= 0;
+        const int32_t stride = (int32_t)bc.key_stride;
+        const bool or_on = rcl && bc.or_pred != kPredNone;
+        const bool or_bits = or_on && bc.or_bits_words > 0;
+        const uint32_t* ob = (const uint32_t*)(ccq_lds + bc.or_bits_lds_off);
+        const int lut = luts[j];
+        if (lut >= 0) {
+            const int32_t u8 = bc.lut_u8;
+#pragma unroll
+            for (int r = 0; r < kRowSpan; ++r) {
+                const uint32_t b = (uint32_t)r * w;
+                const uint32_t q = q0 + (b >> 5);
+                const uint32_t code = __builtin_amdgcn_alignbit(st[q + 1], st[q], b & 31) & mask;
+                const uint32_t e = lut_get(lut, u8, code);
+                if (e == kLutReject) live &= ~(1u << r);
+                else if (e == kLutDomain) dom |= 1u << r;
+                else if (key) gid[r] += (int32_t)e * stride;
+                if (or_bits) {
+                    if ((ob[code >> 5] >> (code & 31)) & 1u) orin |= 1u << r;
+                } else if (or_on && pred_pass(bc.or_pred, bc.or_lo, bc.or_hi, bc.or_set, bc.or_set_len,
+                                              base + (int64_t)code)) {
+                    orin |= 1u << r;
+                }
+            }
+        } else {
+            const int32_t pk = bc.pred;
+            const int64_t lo = bc.lo, hi = bc.hi;
+            const int32_t shift = bc.key_shift;
+            const int64_t card = bc.key_card, klo = bc.key_lo;
+#pragma unroll
+            for (int r = 0; r < kRowSpan; ++r) {
+                const uint32_t b = (uint32_t)r * w;
+                const uint32_t q = q0 + (b >> 5);
+                const uint32_t code = __builtin_amdgcn_alignbit(st[q + 1], st[q], b & 31) & mask;
+                const int64_t v = base + (int64_t)code;
+                if (!pred_pass(pk, lo, hi, bc.set, bc.set_len, v)) live &= ~(1u << r);
+                if (key) {
+                    const int64_t kv = v >> shift;
+                    if (kv < 0 || kv >= card) dom |= 1u << r;
+                    else gid[r] += (int32_t)(kv - klo) * stride;
+                }
+                if (or_bits) {
+                    if ((ob[code >> 5] >> (code & 31)) & 1u) orin |= 1u << r;
+                } else if (or_on && pred_pass(bc.or_pred, bc.or_lo, bc.or_hi, bc.or_set, bc.or_set_len, v)) {
+                    orin |= 1u << r;
+                }
+            }
+        }
+    }
+
+    // phase 1, RLE key columns
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        if (c >= P.k_rle || !P.any_rle_row || !P.rle[c].key_on) continue;
+        const RleCol& rc = P.rle[c];
+        const uint32_t bw = W.bnd[c * 64 + lane];
+        const int32_t i0 = W.bpre[c * 64 + lane];
+        const int64_t* rv = W.run_val + stage_base(P, c);
+        const bool val = rc.sum_slot >= 0 || rc.keep_value;      // staged as the value, not the part
+        const int32_t shift = rc.key_shift;
+        const int64_t card = rc.key_card, stride = rc.key_stride;
+#pragma unroll
+        for (int r = 0; r < kRowSpan; ++r) {
+            int64_t part = rv[i0 + __builtin_popcount(bw & bits_le(r))];
+            if (val) {
+                const int64_t kv = part >> shift;
+                part = (kv >= 0 && kv < card) ? kv * stride : -1;
+            }
+            if (part < 0) dom |= 1u << r;
+            else gid[r] += (int32_t)part;
+        }
+    }
+    if (rcl) live &= orin;
+    dom &= live;
+    if (dom) {
+        raise_status(status, -4);
+        live &= ~dom;
+    }
+
+    // phase 2: the surviving rows into the table
+    if (!live) return;
+    uint32_t sbw[KMAX];
+    int32_t si0[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) {
+        sbw[c] = 0;
+        si0[c] = 0;
+        if (c < P.k_rle && P.rle[c].sum_slot >= 0) {
+            sbw[c] = W.bnd[c * 64 + lane];
+            si0[c] = W.bpre[c * 64 + lane];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRowSpan; ++r) {
+        if (!((live >> r) & 1u)) continue;
+        const int64_t g = gid[r];
+        if (g != acc.gid) {
+            slotacc_flush<false>(P, tb, acc);
+            acc.gid = g;
+        }
+        acc.cnt += 1;
+#pragma unroll
+        for (int k = 0; k < kSmallSums; ++k) {
+            if (k >= P.n_sums) continue;
+            int64_t term = 0;
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c)
+                if (c < P.k_rle && P.rle[c].sum_slot == k)
+                    term = W.run_val[stage_base(P, c) + si0[c] + __builtin_popcount(sbw[c] & bits_le(r))];
+#pragma unroll
+            for (int b = 0; b < kSmallBp; ++b) {
+                if (b < P.n_bp && P.bp[b].sum_slot == k) {
+                    const BpCol& bc = P.bp[b];
+                    const uint32_t* st = (const uint32_t*)(W.base + bc.stage_off);
+                    const uint32_t w = (uint32_t)bc.w;
+                    const uint32_t bb = (uint32_t)r * w;
+                    const uint32_t q = (uint32_t)lane * w + (bb >> 5);
+                    const uint32_t mask = w == 32 ? 0xFFFFFFFFu : ((1u << w) - 1u);
+                    term = bc.base + (int64_t)(__builtin_amdgcn_alignbit(st[q + 1], st[q], bb & 31) & mask);
+                }
+            }
+            acc.sum[k] += term;
+        }
+    }
+}
+
 template <int KMAX, bool FULL>
 __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds& W, int64_t t0, int32_t L,
                                                  uint32_t pm, const Table& tb, int32_t* status,
@@ -1671,8 +1830,10 @@ __device__ __forceinline__ void tile_row_generic(const DevPlan& P, const WaveLds
     }
     wave_lds_sync();
 
-    // the lane's rows, row j of every lane together
-    if (any) {
+    // the lane's rows: the common instance column by column, then row by
+    // row (lane_rows_two_phase); the full instance row j of every lane together
+    if (!FULL && any) lane_rows_two_phase<KMAX>(P, W, pm, luts, tb, status, acc);
+    if (FULL && any) {
         int32_t ridx[KMAX];
         uint32_t bw[KMAX];
 #pragma unroll
