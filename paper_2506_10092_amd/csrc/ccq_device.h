@@ -2054,19 +2054,23 @@ __device__ __forceinline__ void wave_range(const DevPlan& P, const WaveLds& W, i
         // (one loop per mode, so each keeps only its own accumulator live)
         int64_t t0 = w0 & ~(int64_t)31;
         if (P.row_mode) {
-            SlotAcc sacc;
-            slotacc_init(sacc);
-            while (t0 < w1) {
-                int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
-                uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
-                const int32_t L = (int32_t)(t1 - t0);
-                pm = idx_pred_mask(P, W, t0, L, pcur, pm);
-                tile_row_generic<KMAX, (W0 < 0)>(P, W, t0, L, pm, tb, status, pcur, ccur, luts, sacc);
-                tile_bitmaps_clear(P, W);
-                t0 = t1;
+            // row mode: the common instance (-2) or the full one (-1)
+            if constexpr (W0 != 0) {
+                SlotAcc sacc;
+                slotacc_init(sacc);
+                while (t0 < w1) {
+                    int64_t t1 = min(((t0 >> kTileShift) + 1) << kTileShift, w1);
+                    uint32_t pm = stage_tile<KMAX>(P, W, t0, &t1, w0);
+                    const int32_t L = (int32_t)(t1 - t0);
+                    pm = idx_pred_mask(P, W, t0, L, pcur, pm);
+                    tile_row_generic<KMAX, (W0 == -1)>(P, W, t0, L, pm, tb, status, pcur, ccur, luts, sacc);
+                    tile_bitmaps_clear(P, W);
+                    t0 = t1;
+                }
+                slotacc_flush<(W0 == -1)>(P, tb, sacc);
             }
-            slotacc_flush<(W0 < 0)>(P, tb, sacc);
-        } else {
+        } else if constexpr (W0 != -2) {
+            // run mode: its own instance (0) or the full one (-1)
             RegAcc<KMAX> acc;
             regacc_init(acc);
             while (t0 < w1) {

@@ -175,9 +175,9 @@ struct ExtAcc {
 
 struct DevPlan;
 // the kernel instance's width parameter: the fast row path's width; for
-// the staged paths 0 (the common instance) or -1 (the full instance:
-// composite columns, MIN / MAX / expressions, more than kSmallBp bit-packed
-// columns or kSmallSums accumulators)
+// the staged paths 0 (run mode), -2 (the common generic row path) or -1 (the
+// full instance, both modes: composite columns, MIN / MAX / expressions,
+// more than kSmallBp bit-packed columns or kSmallSums accumulators)
 inline int kernel_w0(const DevPlan& p);
 
 struct DevPlan {
@@ -252,26 +252,32 @@ struct BatchGroup {
     int32_t big;            // fast path with a large table
 };
 
-// kernel instance variants besides KMAX: staged paths, fast row path of width
-// 14 or 20, each of those with a large table; variant 6 is the staged paths'
-// full instance (w0 = -1: composite columns, MIN / MAX / expressions, wide
-// plans), kept apart so its code costs the common plans no registers
+// kernel instance variants besides KMAX: run mode (0, and 5 for plans with
+// more than kBatchLdsSplit bytes of LDS), fast row path of width 14 or 20,
+// each of those with a large table (1-4), the staged paths' full instance
+// (6; w0 = -1: composite columns, MIN / MAX / expressions, wide plans), the
+// common generic row path (7, and 8 with large LDS; w0 = -2).  Each instance
+// is compiled for its own path, so one path's registers cost no other.
 // Variant 5 runs the staged paths' kernel too, for plans that need more
 // than kBatchLdsSplit bytes of LDS per workgroup (large group tables in
 // LDS), so they do not lower the occupancy of the other staged plans'
 // launch.
-constexpr int kVariants = 7;
+constexpr int kVariants = 9;
 constexpr int kMaxInstances = 3 * kVariants;     // KMAX in {2, 4, 8}
 constexpr int kBatchLdsSplit = 48 * 1024;
 inline int kernel_w0(const DevPlan& p) {
     if (p.w0 > 0) return p.w0;
-    return (p.n_comp > 0 || p.n_ext > 0 || p.n_bp > kSmallBp || p.n_sums > kSmallSums) ? -1 : 0;
+    if (p.n_comp > 0 || p.n_ext > 0 || p.n_bp > kSmallBp || p.n_sums > kSmallSums) return -1;
+    return p.row_mode ? -2 : 0;
 }
 inline int variant_of(int w0, int big, int lds_bytes) {
-    if (w0 < 0) return 6;
+    if (w0 == -1) return 6;
+    if (w0 == -2) return lds_bytes > kBatchLdsSplit ? 8 : 7;
     return w0 == 0 ? (lds_bytes > kBatchLdsSplit ? 5 : 0) : (w0 == 14 ? 1 : 2) + (big ? 2 : 0);
 }
-inline int variant_w0(int v) { return v == 6 ? -1 : v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20; }
+inline int variant_w0(int v) {
+    return v == 6 ? -1 : (v == 7 || v == 8) ? -2 : v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20;
+}
 inline int variant_big(int v) { return v == 3 || v == 4 ? 1 : 0; }
 
 // Where each query's result goes.
