@@ -194,8 +194,12 @@ def bench_batch(args):
 
     batch = ccq.Batch(ctx, plans, use_graph=True)
     ws = batch.new_workspace()
+    if args.tune_cache:
+        log("tuning cache %s: %d entries loaded" % (args.tune_cache, ctx.tune_cache_load(args.tune_cache)))
     best, tuned_ms = batch.autotune(ws, candidates=(8, 32, 128, 512), reps=3, stream=stream)
     log("autotuned tiles_per_item=%d (%.3f ms)" % (best, tuned_ms))
+    if args.tune_cache:
+        ctx.tune_cache_save(args.tune_cache)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             batch.execute(ws, stream)
@@ -619,6 +623,8 @@ def main():
                     help="c5: Poisson arrival rates; max submits every query at once (saturation)")
     ap.add_argument("--serve-check", type=int, default=1000, help="c5: served answers checked against the oracle")
     ap.add_argument("--rows", type=int, default=0, help="override the logical row count")
+    ap.add_argument("--tune-cache", default="",
+                    help="c4: a tuning-cache file, loaded before the autotune and saved after it")
     ap.add_argument("--filter", default="and", choices=["and", "not", "or", "or_dict"],
                     help="c2: the workload's filter (and), or the same table under a filter with NOT "
                          "(r0 outside a middle range), an OR of the two RLE ranges (or), or an OR of the "

@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define CCQ_ABI_VERSION 7
+#define CCQ_ABI_VERSION 8
 
 typedef int32_t ccq_status;
 enum {
@@ -459,10 +459,28 @@ ccq_status ccq_batch_execute_ex(ccq_batch* b, void* workspace, size_t workspace_
                                 const ccq_exec_opts* opts);
 
 /* Time each candidate work-item size (reps executions each, after one warm-up;
- * synchronises `stream`), keep the fastest by median, report it and its time. */
+ * synchronises `stream`), keep the fastest by median, report it and its time.
+ * The result is kept in the context's tuning cache, keyed by the batch's
+ * shape: the device's architecture and CU count, the candidate list, and per
+ * query its kernel instance, nominal tiles, group count, accumulators and
+ * LDS bytes.  A batch whose key is cached (from an earlier autotune or a
+ * loaded cache file) takes the cached size and time without executing
+ * anything. */
 ccq_status ccq_batch_autotune(ccq_batch* b, void* workspace, size_t workspace_bytes, void* stream,
                               const int32_t* candidates, int32_t n_candidates, int32_t reps, int32_t* best,
                               float* best_ms);
+
+/* The tuning cache as a text file: a header line, then one line per entry
+ * (the key in hex, the work-item size, the median time in ms).
+ * ccq_tune_cache_load merges a file into the context's cache (a missing file
+ * loads nothing and succeeds); ccq_tune_cache_save writes the whole cache to
+ * `path` (through a temporary file renamed over it).  Host paths; *n_entries
+ * (may be NULL) receives the entries read or written.  CCQ_E_INVALID for a
+ * NULL context or path, a file that is not a tuning cache (nothing merged),
+ * or an I/O error (the message carries the system's).  Safe to call while
+ * other threads autotune batches of the same context. */
+ccq_status ccq_tune_cache_load(ccq_context* ctx, const char* path, int64_t* n_entries);
+ccq_status ccq_tune_cache_save(ccq_context* ctx, const char* path, int64_t* n_entries);
 
 /* ---- serving: continuous batching under an HBM budget ----
  *

@@ -154,6 +154,8 @@ SIGNATURES = {
                                       ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "ccq_plain_to_plain_index": (_i32, [_vp, _vp, _i32, _i64, _i32, _i64, _vp, _sz, _vp, _vp, _i64, _vp, _vp, _i64,
                                         ctypes.POINTER(_i64)]),
+    "ccq_tune_cache_load": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64)]),
+    "ccq_tune_cache_save": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64)]),
     "ccq_join_workspace_bytes": (_sz, [_vp, _i32, _i64, _i64, _vp, _i32, _i64, _i64]),
     "ccq_join_index": (_i32, [_vp, _i32, _i64, _i64, _vp, _i32, _i64, _i64, _vp, _sz, _vp, _vp, _i64,
                               ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
@@ -204,6 +206,18 @@ class Context:
         _check(lib().ccq_context_create(int(device), ctypes.byref(h)))
         self.h = h
         self.device = device
+
+    def tune_cache_load(self, path):
+        """Merge a tuning-cache file into this context's cache; returns the entries read."""
+        n = ctypes.c_int64()
+        _check(lib().ccq_tune_cache_load(self.h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
+    def tune_cache_save(self, path):
+        """Write this context's tuning cache to `path`; returns the entries written."""
+        n = ctypes.c_int64()
+        _check(lib().ccq_tune_cache_save(self.h, os.fsencode(path), ctypes.byref(n)))
+        return n.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -66,6 +66,7 @@ ccq_status ccq_context_create(int32_t device, ccq_context** out) {
         c->cus = 256;
         c->lds_per_block = 160 * 1024;
         c->scratch = nullptr;
+        c->arch = "host";
         *out = c;
         return ok();
     }
@@ -90,6 +91,7 @@ ccq_status ccq_context_create(int32_t device, ccq_context** out) {
     c->cus = prop.multiProcessorCount;
     c->lds_per_block = prop.sharedMemPerBlock;
     c->scratch = scratch;
+    c->arch = prop.gcnArchName;
     *out = c;
     return ok();
 }

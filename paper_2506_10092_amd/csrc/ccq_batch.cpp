@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cerrno>
+#include <cinttypes>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <new>
@@ -53,6 +56,41 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int kidx(int kmax) { return kmax <= 2 ? 0 : kmax <= 4 ? 1 : 2; }
+
+// FNV-1a over the words that decide a batch's launch shapes
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(uint64_t x) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (x >> (8 * i)) & 0xFF;
+            h *= 1099511628211ull;
+        }
+    }
+};
+
+// The tuning cache's key of a batch: the device (architecture, CUs), the
+// candidate list, and per query its kernel instance, nominal tiles, groups,
+// accumulators and LDS bytes.
+uint64_t tune_key(const ccq_batch* b, const int32_t* cand, int32_t n_cand) {
+    Fnv f;
+    for (char c : b->ctx->arch) f.add((uint64_t)(unsigned char)c);
+    f.add((uint64_t)b->ctx->cus);
+    f.add((uint64_t)n_cand);
+    for (int i = 0; i < n_cand; ++i) f.add((uint64_t)(uint32_t)cand[i]);
+    f.add((uint64_t)b->plans.size());
+    for (const ccq_plan* p : b->plans) {
+        const DevPlan& d = p->host;
+        f.add((uint64_t)(uint32_t)d.kmax);
+        f.add((uint64_t)(int64_t)kernel_w0(d));
+        f.add((uint64_t)(uint32_t)d.fast_big);
+        f.add((uint64_t)d.n_tiles);
+        f.add((uint64_t)d.n_groups);
+        f.add((uint64_t)(uint32_t)d.n_sums);
+        f.add((uint64_t)(uint32_t)d.lds_dyn_bytes);
+    }
+    return f.h;
+}
+
 int widx(const DevPlan& p) { return variant_of(kernel_w0(p), p.fast_big, p.lds_dyn_bytes); }
 
 void drop_graph(ccq_batch* b) {
@@ -307,6 +345,19 @@ ccq_status ccq_batch_autotune(ccq_batch* b, void* workspace, size_t workspace_by
                               const int32_t* candidates, int32_t n_candidates, int32_t reps, int32_t* best,
                               float* best_ms) {
     if (!b || !candidates || n_candidates < 1 || reps < 1) return fail(CCQ_E_INVALID, "bad autotune arguments");
+    // the context's tuning cache first
+    const uint64_t key = tune_key(b, candidates, n_candidates);
+    {
+        std::lock_guard<std::mutex> g(b->ctx->tune_mu);
+        auto it = b->ctx->tune.find(key);
+        if (it != b->ctx->tune.end() &&
+            std::find(candidates, candidates + n_candidates, it->second.first) != candidates + n_candidates) {
+            if (ccq_status st = ccq_batch_set_tiles_per_item(b, it->second.first)) return st;
+            if (best) *best = it->second.first;
+            if (best_ms) *best_ms = it->second.second;
+            return ok();
+        }
+    }
     hipError_t e = hipSetDevice(b->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -344,8 +395,75 @@ ccq_status ccq_batch_autotune(ccq_batch* b, void* workspace, size_t workspace_by
     (void)hipEventDestroy(e1);
     if (st) return st;
     if ((st = ccq_batch_set_tiles_per_item(b, arg_best))) return st;
+    {
+        std::lock_guard<std::mutex> g(b->ctx->tune_mu);
+        b->ctx->tune[key] = {arg_best, t_best};
+    }
     if (best) *best = arg_best;
     if (best_ms) *best_ms = t_best;
+    return ok();
+}
+
+static const char kTuneHeader[] = "ccq-tune-cache 1";
+
+ccq_status ccq_tune_cache_load(ccq_context* ctx, const char* path, int64_t* n_entries) {
+    if (n_entries) *n_entries = 0;
+    if (!ctx || !path) return fail(CCQ_E_INVALID, "context or path is NULL");
+    FILE* f = fopen(path, "r");
+    if (!f) {
+        if (errno == ENOENT) return ok();        // no cache yet
+        return fail(CCQ_E_INVALID, "cannot open %s: %s", path, strerror(errno));
+    }
+    char line[256];
+    std::vector<std::pair<uint64_t, std::pair<int32_t, float>>> got;
+    bool header = false, bad = false;
+    while (fgets(line, sizeof line, f)) {
+        if (!header) {
+            header = strncmp(line, kTuneHeader, sizeof kTuneHeader - 1) == 0;
+            if (!header) bad = true;
+            if (bad) break;
+            continue;
+        }
+        uint64_t key = 0;
+        int32_t tpi = 0;
+        float ms = 0;
+        char extra = 0;
+        const int n = sscanf(line, "%" SCNx64 " %" SCNd32 " %f %c", &key, &tpi, &ms, &extra);
+        if (n != 3 || tpi < 1 || tpi >= kMaxTilesPerItem || !(ms >= 0)) {
+            bad = true;
+            break;
+        }
+        got.push_back({key, {tpi, ms}});
+    }
+    fclose(f);
+    if (bad || !header) return fail(CCQ_E_INVALID, "%s is not a tuning cache (line: %.60s)", path, line);
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    for (const auto& x : got) ctx->tune[x.first] = x.second;
+    if (n_entries) *n_entries = (int64_t)got.size();
+    return ok();
+}
+
+ccq_status ccq_tune_cache_save(ccq_context* ctx, const char* path, int64_t* n_entries) {
+    if (n_entries) *n_entries = 0;
+    if (!ctx || !path) return fail(CCQ_E_INVALID, "context or path is NULL");
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(CCQ_E_INVALID, "cannot write %s: %s", tmp.c_str(), strerror(errno));
+    int64_t n = 0;
+    bool okw = fprintf(f, "%s\n", kTuneHeader) > 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        for (const auto& x : ctx->tune) {
+            okw = okw && fprintf(f, "%016" PRIx64 " %" PRId32 " %.6g\n", x.first, x.second.first, x.second.second) > 0;
+            ++n;
+        }
+    }
+    okw = (fclose(f) == 0) && okw;
+    if (!okw || rename(tmp.c_str(), path) != 0) {
+        (void)remove(tmp.c_str());
+        return fail(CCQ_E_INVALID, "cannot write %s: %s", path, strerror(errno));
+    }
+    if (n_entries) *n_entries = n;
     return ok();
 }
 

@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/ccq.h"
@@ -24,6 +27,10 @@ struct ccq_context {
     int cus;
     size_t lds_per_block;
     void* scratch;          // device address of the fixed scratch on this device (null: host only)
+    std::string arch;       // gcnArchName ("host" for a host-only context)
+    // tuning cache: batch shape key -> (work-item size, median ms)
+    std::mutex tune_mu;
+    std::map<uint64_t, std::pair<int32_t, float>> tune;
 };
 
 struct ccq_table {

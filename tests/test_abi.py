@@ -35,7 +35,7 @@ def test_header_functions_are_exported():
 
 
 def test_abi_version():
-    assert ccq.lib().ccq_abi_version() == 7
+    assert ccq.lib().ccq_abi_version() == 8
 
 
 def _host_table(columns, n_rows):
@@ -263,3 +263,31 @@ def test_composite_table_create_rejects():
     d = ccq._column_desc(_composite_cols()["y"], 1000)
     d.point_values = None
     assert L.ccq_table_create(ctx.h, 1000, ccq.ctypes.byref(d), 1, ccq.ctypes.byref(h)) == ccq.E_INVALID
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """The tuning cache's text file: a missing file loads nothing, a written
+    file reloads the same entries, malformed files are rejected and merge
+    nothing."""
+    ctx = ccq.Context(ccq.HOST_ONLY)
+    path = str(tmp_path / "tune.txt")
+    assert ctx.tune_cache_load(path) == 0                      # no file yet
+    assert ctx.tune_cache_save(path) == 0
+    assert open(path).read().splitlines() == ["ccq-tune-cache 1"]
+    with open(path, "a") as f:
+        f.write("00000000000000ab 32 12.5\n0123456789abcdef 512 355.25\n")
+    assert ctx.tune_cache_load(path) == 2
+    out = str(tmp_path / "out.txt")
+    assert ctx.tune_cache_save(out) == 2
+    lines = open(out).read().splitlines()
+    assert lines[0] == "ccq-tune-cache 1"
+    assert sorted(lines[1:]) == sorted(["00000000000000ab 32 12.5", "0123456789abcdef 512 355.25"])
+    for bad in ("not a cache\n", "ccq-tune-cache 1\nzz 1 2\n", "ccq-tune-cache 1\n00ab 0 1.0\n",
+                "ccq-tune-cache 1\n00ab 8 1.0 extra\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        other = ccq.Context(ccq.HOST_ONLY)
+        with pytest.raises(ccq.CcqError) as e:
+            other.tune_cache_load(str(p))
+        assert e.value.status == ccq.E_INVALID
+        assert other.tune_cache_save(str(tmp_path / "empty.txt")) == 0      # nothing merged

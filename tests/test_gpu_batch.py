@@ -97,3 +97,37 @@ def test_batch_autotune_keeps_results(setup):
     b.execute(ws, stream)
     stream.synchronize()
     assert b.to_python() == eager
+
+
+def test_autotune_tuning_cache(setup, tmp_path):
+    """A second autotune of a batch of the same shape takes the context's
+    cached result without timing (the same size and the same time); a fresh
+    context that loads the saved cache does the same; a different candidate
+    list is a different key and is timed."""
+    import torch
+    from paper_2506_10092_amd import ccq
+    plans = setup["plans"]
+    stream = torch.cuda.Stream()
+    b = ccq.Batch(setup["ctx"], plans)
+    ws = b.new_workspace()
+    cand = (4, 32, 256)
+    best, ms = b.autotune(ws, candidates=cand, reps=2, stream=stream)
+    say("tuned", best, ms)
+    b2 = ccq.Batch(setup["ctx"], plans)
+    assert b2.autotune(b2.new_workspace(), candidates=cand, reps=2, stream=stream) == (best, ms)
+    path = str(tmp_path / "tune.txt")
+    assert setup["ctx"].tune_cache_save(path) >= 1
+    ctx2 = ccq.Context(0)
+    assert ctx2.tune_cache_load(path) >= 1
+    t2 = ccq.Table(ctx2, setup["table"].n_rows, setup["table"].columns)
+    plans2 = [ccq.Plan(t2, q) for q in setup["qs"]]
+    b3 = ccq.Batch(ctx2, plans2)
+    ws3 = b3.new_workspace()
+    best3, ms3 = b3.autotune(ws3, candidates=cand, reps=2, stream=stream)
+    assert best3 == best and abs(ms3 - ms) <= 1e-5 * max(ms, 1.0)     # the file keeps 6 significant digits
+    # the cached size is the one that runs, and the answers are unchanged
+    b3.execute(ws3, stream)
+    stream.synchronize()
+    assert b3.to_python() == _single(plans)
+    other = b3.autotune(ws3, candidates=(8, 64), reps=1, stream=stream)
+    assert other[0] in (8, 64)
