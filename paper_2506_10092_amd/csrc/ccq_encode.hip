@@ -6,15 +6,15 @@
 //
 // Every encoder is a stream compaction: a per-row flag says whether the row
 // starts a run, ends one, or is an outlier; output slots are the flag's rank
-// among all rows.  Rows are split into chunks of kEncChunk rows; a
-// workgroup takes a contiguous range of chunks, stages each chunk's values in
-// LDS (one coalesced read, plus the rows just before and after it so every
-// row sees its neighbours) and ranks its flags with wavefront prefix sums.
-// Launch sequence per encoder: count (per-workgroup flag totals), scan (one
-// workgroup: exclusive offsets), write (the same pass again, writing at the
-// offsets).  The order statistics of the choice come from a radix select:
-// eight passes of 8-bit digit histograms over the order-preserving 64-bit
-// keys, each pass keeping the digit that holds the wanted rank.
+// among all rows.  A wavefront takes 1024-row chunks: each lane loads 16
+// rows, one coalesced wave load each (row r0 + 64 k + lane), finds its
+// rows' neighbours with lane shuffles, and ballots rank the chunk's flags,
+// with no LDS and no barrier.  Launch sequence per encoder: count (flag
+// totals per chunk), a three-kernel scan (exclusive offsets per chunk),
+// write (the same pass again, writing at the offsets).  The order
+// statistics of the choice come from a radix select: eight passes of 8-bit
+// digit histograms over the order-preserving 64-bit keys, each pass keeping
+// the digit that holds the wanted rank.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -30,8 +30,6 @@ namespace {
 
 constexpr int kEncThreads = 256;
 constexpr int kEncRowsPerThread = 16;
-constexpr int kEncChunk = kEncThreads * kEncRowsPerThread;   // 4096 rows
-constexpr int kEncMaxBlocks = 4096;
 constexpr int64_t kChooseMinRows = 1000000;   // columns under this many rows stay Plain
 constexpr double kChooseRatio = 20.0;          // compression ratio that selects RLE / RLE+Index
 
@@ -65,25 +63,14 @@ __device__ __forceinline__ int64_t block_inclusive_sum(int64_t x, int64_t* s_wav
     return x + before;
 }
 
-// the chunks of workgroup b: [c0, c1)
-__device__ __forceinline__ void block_chunks(int64_t n, int64_t* c0, int64_t* c1) {
-    const int64_t chunks = (n + kEncChunk - 1) / kEncChunk;
-    const int64_t per = (chunks + gridDim.x - 1) / gridDim.x;
-    *c0 = min(chunks, (int64_t)blockIdx.x * per);
-    *c1 = min(chunks, *c0 + per);
-}
-
-// Stage rows [r0, r0 + kEncChunk) (clipped to n) plus the row before and the
-// row after into s[1 .. kEncChunk], s[0], s[kEncChunk + 1].
-__device__ __forceinline__ void stage_chunk(const void* v, int32_t vtype, int64_t n, int64_t r0, int64_t* s) {
-    for (int k = threadIdx.x; k < kEncChunk + 2; k += kEncThreads) {
-        const int64_t i = r0 - 1 + k;
-        s[k] = (i >= 0 && i < n) ? load_value(v, vtype, i) : 0;
-    }
-    __syncthreads();
-}
-
 enum EncMode : int32_t { kModeRle = 0, kModeRleIndex = 1, kModePlainIndex = 2 };
+
+// Rows go in wave chunks of kWaveChunk rows: lane l holds rows
+// r0 + 64 k + l for k < kEncRowsPerThread, so each of a lane's loads is one
+// coalesced wave load, a row's neighbours come from the next or previous
+// lane (or, across lanes 0 and 63, the neighbouring k or chunk), and row
+// order within the chunk is (k, lane), in which ballots rank the flags.
+constexpr int kWaveChunk = 64 * kEncRowsPerThread;      // 1024 rows
 
 struct EncArgs {
     const void* values;
@@ -100,138 +87,160 @@ struct EncArgs {
     int64_t* run_ends;      // RLE, RLE+Index: exclusive run ends
     int64_t* idx_pos;       // RLE+Index, Plain+Index: point positions
     void* idx_vals;         // point values
-    int64_t* block_tot;     // [2][gridDim.x]: per-workgroup totals of flags 0 and 1
-    const int64_t* block_off;   // [2][gridDim.x]: exclusive offsets
+    int32_t* cnt;           // [2][n_wc]: flags 0 and 1 per wave chunk
+    const int64_t* off;     // [2][n_wc + 1]: exclusive offsets per wave chunk
+    int64_t n_wc;
 };
 
-// Row i's two flags in the given mode (s: staged chunk, j: row's slot in s;
-// i < n).  Flag 0 ranks runs (RLE: every run start; RLE+Index: starts of runs
-// of two or more rows; Plain+Index: outliers).  Flag 1 ranks the points of
-// RLE+Index (rows that form a run of their own).
-__device__ __forceinline__ void row_flags(const EncArgs& A, const int64_t* s, int j, int64_t i, bool* f0,
-                                          bool* f1, bool* start, bool* end) {
-    const int64_t x = s[j];
-    *start = i == 0 || x != s[j - 1];
-    *end = i == A.n - 1 || x != s[j + 1];
-    if (A.mode == kModeRle) {
-        *f0 = *start;
-        *f1 = false;
-    } else if (A.mode == kModeRleIndex) {
-        *f0 = *start && !*end;
-        *f1 = *start && *end;
-    } else {
-        // outside [base, base + 2^w); once x >= base the wrapped difference is exact
-        const uint64_t code = (uint64_t)x - (uint64_t)A.base;
-        *f0 = x < A.base || (code >> A.w) != 0;
-        *f1 = false;
+// One wave chunk: the lane's rows, their two flags (flag 0 ranks runs --
+// RLE: every run start; RLE+Index: starts of runs of two or more rows;
+// Plain+Index: outliers -- flag 1 the points of RLE+Index, rows that form a
+// run of their own) and, with WRITE, the outputs at the ranks from o0, o1.
+// Returns the chunk's flag counts (wave-uniform).
+template <bool WRITE>
+__device__ __forceinline__ void wave_chunk(const EncArgs& A, int64_t wc, int64_t o0, int64_t o1, int32_t* c0,
+                                           int32_t* c1) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r0 = wc * kWaveChunk;
+    int64_t x[kEncRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kEncRowsPerThread; ++k) {
+        const int64_t i = r0 + 64 * k + lane;
+        x[k] = i < A.n ? load_value(A.values, A.vtype, i) : 0;
     }
-}
-
-__global__ __launch_bounds__(kEncThreads) void k_enc_count(EncArgs A) {
-    __shared__ int64_t s[kEncChunk + 2];
-    __shared__ int64_t s_wave[kEncThreads / 64];
-    int64_t c0, c1;
-    block_chunks(A.n, &c0, &c1);
-    int64_t t0 = 0, t1 = 0;
-    for (int64_t c = c0; c < c1; ++c) {
-        const int64_t r0 = c * kEncChunk;
-        stage_chunk(A.values, A.vtype, A.n, r0, s);
-        int64_t a = 0, b = 0;
-        for (int k = 0; k < kEncRowsPerThread; ++k) {
-            const int j = threadIdx.x * kEncRowsPerThread + k;
-            const int64_t i = r0 + j;
-            if (i >= A.n) break;
-            bool f0, f1, st, en;
-            row_flags(A, s, j + 1, i, &f0, &f1, &st, &en);
-            a += f0;
-            b += f1;
+    const int64_t before = r0 > 0 ? load_value(A.values, A.vtype, r0 - 1) : 0;
+    const int64_t after = r0 + kWaveChunk < A.n ? load_value(A.values, A.vtype, r0 + kWaveChunk) : 0;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t n0 = 0, n1 = 0;
+#pragma unroll
+    for (int k = 0; k < kEncRowsPerThread; ++k) {
+        const int64_t i = r0 + 64 * k + lane;
+        const int64_t xi = x[k];
+        int64_t prev = __shfl_up(xi, 1, 64);
+        int64_t next = __shfl_down(xi, 1, 64);
+        const int64_t last_prev = k > 0 ? __shfl(x[k - 1], 63, 64) : before;
+        const int64_t first_next = k + 1 < kEncRowsPerThread ? __shfl(x[k + 1 < kEncRowsPerThread ? k + 1 : k], 0, 64)
+                                                              : after;
+        if (lane == 0) prev = last_prev;
+        if (lane == 63) next = first_next;
+        const bool valid = i < A.n;
+        const bool start = valid && (i == 0 || xi != prev);
+        const bool end = valid && (i == A.n - 1 || xi != next);
+        bool f0, f1;
+        if (A.mode == kModeRle) {
+            f0 = start;
+            f1 = false;
+        } else if (A.mode == kModeRleIndex) {
+            f0 = start && !end;
+            f1 = start && end;
+        } else {
+            // outside [base, base + 2^w); once x >= base the wrapped difference is exact
+            const uint64_t code = (uint64_t)xi - (uint64_t)A.base;
+            f0 = valid && (xi < A.base || (code >> A.w) != 0);
+            f1 = false;
         }
-        int64_t ta, tb;
-        block_inclusive_sum(a, s_wave, &ta);
-        block_inclusive_sum(b, s_wave, &tb);
-        t0 += ta;
-        t1 += tb;
-    }
-    if (threadIdx.x == 0) {
-        A.block_tot[blockIdx.x] = t0;
-        A.block_tot[gridDim.x + blockIdx.x] = t1;
-    }
-}
-
-// exclusive offsets of the per-workgroup totals, and the two grand totals at
-// off[2 * nb], off[2 * nb + 1] (one workgroup)
-__global__ __launch_bounds__(kEncThreads) void k_enc_scan(const int64_t* tot, int64_t* off, int32_t nb) {
-    __shared__ int64_t s_wave[kEncThreads / 64];
-    for (int f = 0; f < 2; ++f) {
-        int64_t carry = 0;
-        for (int b0 = 0; b0 < nb; b0 += kEncThreads) {
-            const int b = b0 + (int)threadIdx.x;
-            const int64_t x = b < nb ? tot[f * nb + b] : 0;
-            int64_t all;
-            const int64_t inc = block_inclusive_sum(x, s_wave, &all);
-            if (b < nb) off[f * nb + b] = carry + inc - x;
-            carry += all;
-        }
-        if (threadIdx.x == 0) off[2 * nb + f] = carry;
-    }
-}
-
-__global__ __launch_bounds__(kEncThreads) void k_enc_write(EncArgs A) {
-    __shared__ int64_t s[kEncChunk + 2];
-    __shared__ int64_t s_wave[kEncThreads / 64];
-    int64_t c0, c1;
-    block_chunks(A.n, &c0, &c1);
-    int64_t o0 = A.block_off[blockIdx.x], o1 = A.block_off[gridDim.x + blockIdx.x];
-    for (int64_t c = c0; c < c1; ++c) {
-        const int64_t r0 = c * kEncChunk;
-        stage_chunk(A.values, A.vtype, A.n, r0, s);
-        const int jb = threadIdx.x * kEncRowsPerThread;
-        int64_t a = 0, b = 0;
-        for (int k = 0; k < kEncRowsPerThread; ++k) {
-            const int64_t i = r0 + jb + k;
-            if (i >= A.n) break;
-            bool f0, f1, st, en;
-            row_flags(A, s, jb + k + 1, i, &f0, &f1, &st, &en);
-            a += f0;
-            b += f1;
-        }
-        int64_t ta, tb;
-        const int64_t ea = block_inclusive_sum(a, s_wave, &ta) - a;
-        const int64_t eb = block_inclusive_sum(b, s_wave, &tb) - b;
-        int64_t ra = o0 + ea, rb = o1 + eb;   // rank of this thread's first flag of each kind
-        for (int k = 0; k < kEncRowsPerThread; ++k) {
-            const int64_t i = r0 + jb + k;
-            if (i >= A.n) break;
-            const int j = jb + k + 1;
-            bool f0, f1, st, en;
-            row_flags(A, s, j, i, &f0, &f1, &st, &en);
-            const int64_t x = s[j];
+        const uint64_t m0 = __ballot(f0), m1 = __ballot(f1);
+        if constexpr (WRITE) {
+            const int64_t ra = o0 + n0 + __builtin_popcountll(m0 & below);   // rank of this row's flag 0
+            const int64_t rb = o1 + n1 + __builtin_popcountll(m1 & below);
             if (A.mode == kModeRle) {
-                // run ra - 1 after this start holds row i
-                if (f0) store_value(A.run_values, A.out_vtype, ra, x);
-                if (f0) ++ra;
-                if (en) A.run_ends[ra - 1] = i + 1;
+                if (f0) store_value(A.run_values, A.out_vtype, ra, xi);
+                // the run holding row i is the last one started at or before it
+                if (end) A.run_ends[ra + (f0 ? 1 : 0) - 1] = i + 1;
             } else if (A.mode == kModeRleIndex) {
                 if (f0) {
-                    store_value(A.run_values, A.out_vtype, ra, x);
+                    store_value(A.run_values, A.out_vtype, ra, xi);
                     A.run_starts[ra] = i;
-                    ++ra;
                 }
-                if (en && !st) A.run_ends[ra - 1] = i + 1;   // the end of a run of two or more rows
+                if (end && !start) A.run_ends[ra - 1] = i + 1;   // the end of a run of two or more rows
                 if (f1) {
                     A.idx_pos[rb] = i;
-                    store_value(A.idx_vals, A.out_vtype, rb, x);
-                    ++rb;
+                    store_value(A.idx_vals, A.out_vtype, rb, xi);
                 }
             } else if (f0) {
                 A.idx_pos[ra] = i;
-                store_value(A.idx_vals, A.out_vtype, ra, x);
-                ++ra;
+                store_value(A.idx_vals, A.out_vtype, ra, xi);
             }
         }
-        o0 += ta;
-        o1 += tb;
-        __syncthreads();    // every read of s before the next chunk is staged
+        n0 += __builtin_popcountll(m0);
+        n1 += __builtin_popcountll(m1);
+    }
+    *c0 = n0;
+    *c1 = n1;
+}
+
+// flag counts per wave chunk (a wave per chunk, grid-stride)
+__global__ __launch_bounds__(kEncThreads) void k_enc_count(EncArgs A) {
+    const int64_t waves = (int64_t)gridDim.x * (kEncThreads / 64);
+    for (int64_t wc = (int64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6); wc < A.n_wc; wc += waves) {
+        int32_t c0, c1;
+        wave_chunk<false>(A, wc, 0, 0, &c0, &c1);
+        if ((threadIdx.x & 63) == 0) {
+            A.cnt[wc] = c0;
+            A.cnt[A.n_wc + wc] = c1;
+        }
+    }
+}
+
+// ---- exclusive scan of the per-chunk counts (int32) into int64 offsets
+
+constexpr int64_t kEncScanPer = 4096;
+
+// per part of kEncScanPer counts: its total (flag f = blockIdx.y)
+__global__ __launch_bounds__(kEncThreads) void k_enc_scan_part(const int32_t* cnt, int64_t n, int64_t* part,
+                                                               int64_t n_parts) {
+    __shared__ int64_t s_wave[kEncThreads / 64];
+    const int32_t* c = cnt + blockIdx.y * n;
+    const int64_t p0 = (int64_t)blockIdx.x * kEncScanPer;
+    int64_t x = 0;
+    for (int64_t i = p0 + threadIdx.x; i < min(n, p0 + kEncScanPer); i += kEncThreads) x += c[i];
+    int64_t t;
+    block_inclusive_sum(x, s_wave, &t);
+    if (threadIdx.x == 0) part[blockIdx.y * (n_parts + 1) + blockIdx.x] = t;
+}
+
+// exclusive scan of the part totals in place, the grand total at part[n_parts] (one workgroup per flag)
+__global__ __launch_bounds__(kEncThreads) void k_enc_scan_parts(int64_t* part, int64_t n_parts) {
+    __shared__ int64_t s_wave[kEncThreads / 64];
+    int64_t* p = part + blockIdx.y * (n_parts + 1);
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < n_parts; b0 += kEncThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        const int64_t x = b < n_parts ? p[b] : 0;
+        int64_t all;
+        const int64_t inc = block_inclusive_sum(x, s_wave, &all);
+        if (b < n_parts) p[b] = carry + inc - x;
+        carry += all;
+    }
+    if (threadIdx.x == 0) p[n_parts] = carry;
+}
+
+// off[f][i] = the part's offset plus the in-part exclusive scan; off[f][n] = the total
+__global__ __launch_bounds__(kEncThreads) void k_enc_scan_final(const int32_t* cnt, int64_t n, const int64_t* part,
+                                                                int64_t n_parts, int64_t* off) {
+    __shared__ int64_t s_wave[kEncThreads / 64];
+    const int32_t* c = cnt + blockIdx.y * n;
+    const int64_t* p = part + blockIdx.y * (n_parts + 1);
+    int64_t* o = off + blockIdx.y * (n + 1);
+    const int64_t p0 = (int64_t)blockIdx.x * kEncScanPer;
+    int64_t carry = p[blockIdx.x];
+    for (int64_t b0 = p0; b0 < min(n, p0 + kEncScanPer); b0 += kEncThreads) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t x = i < n ? c[i] : 0;
+        int64_t all;
+        const int64_t inc = block_inclusive_sum(x, s_wave, &all);
+        if (i < n) o[i] = carry + inc - x;
+        carry += all;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) o[n] = p[n_parts];
+}
+
+// the outputs, each wave chunk at its offsets
+__global__ __launch_bounds__(kEncThreads) void k_enc_write(EncArgs A) {
+    const int64_t waves = (int64_t)gridDim.x * (kEncThreads / 64);
+    for (int64_t wc = (int64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6); wc < A.n_wc; wc += waves) {
+        int32_t c0, c1;
+        wave_chunk<true>(A, wc, A.off[wc], A.off[A.n_wc + 1 + wc], &c0, &c1);
     }
 }
 
@@ -274,45 +283,39 @@ struct EncStats {
 };
 
 __global__ __launch_bounds__(kEncThreads) void k_enc_stats(const void* v, int32_t vtype, int64_t n, EncStats* out) {
-    __shared__ int64_t s[kEncChunk + 2];
-    __shared__ int64_t s_wave[kEncThreads / 64];
-    int64_t c0, c1;
-    block_chunks(n, &c0, &c1);
+    // runs and single-row runs: flags 0 and 1 of RLE+Index, per wave chunk
+    EncArgs A = {};
+    A.values = v;
+    A.vtype = vtype;
+    A.mode = kModeRleIndex;
+    A.n = n;
+    A.n_wc = (n + kWaveChunk - 1) / kWaveChunk;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (kEncThreads / 64);
     int64_t runs = 0, singles = 0, lo = INT64_MAX, hi = INT64_MIN;
-    for (int64_t c = c0; c < c1; ++c) {
-        const int64_t r0 = c * kEncChunk;
-        stage_chunk(v, vtype, n, r0, s);
+    for (int64_t wc = (int64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6); wc < A.n_wc; wc += waves) {
+        int32_t c0, c1;
+        wave_chunk<false>(A, wc, 0, 0, &c0, &c1);
+        runs += c0 + c1;
+        singles += c1;
         for (int k = 0; k < kEncRowsPerThread; ++k) {
-            const int j = threadIdx.x * kEncRowsPerThread + k;
-            const int64_t i = r0 + j;
-            if (i >= n) break;
-            const int64_t x = s[j + 1];
-            const bool st = i == 0 || x != s[j];
-            const bool en = i == n - 1 || x != s[j + 2];
-            runs += st;
-            singles += st && en;
-            lo = min(lo, x);
-            hi = max(hi, x);
+            const int64_t i = wc * kWaveChunk + 64 * k + lane;
+            if (i < n) {
+                const int64_t x = load_value(v, vtype, i);
+                lo = min(lo, x);
+                hi = max(hi, x);
+            }
         }
-        __syncthreads();
     }
-    int64_t t;
-    const int64_t rr = block_inclusive_sum(runs, s_wave, &t);
-    (void)rr;
-    const int64_t truns = t;
-    block_inclusive_sum(singles, s_wave, &t);
-    const int64_t tsingles = t;
     for (int o = 32; o > 0; o >>= 1) {
         lo = min(lo, (int64_t)__shfl_xor(lo, o, 64));
         hi = max(hi, (int64_t)__shfl_xor(hi, o, 64));
     }
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         atomicMin(&out->vmin, (long long)lo);
         atomicMax(&out->vmax, (long long)hi);
-    }
-    if (threadIdx.x == 0) {
-        atomicAdd(&out->runs, (unsigned long long)truns);
-        atomicAdd(&out->singles, (unsigned long long)tsingles);
+        atomicAdd(&out->runs, (unsigned long long)runs);      // wave-uniform counts, one add per wave
+        atomicAdd(&out->singles, (unsigned long long)singles);
     }
 }
 
@@ -350,35 +353,43 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_hist(const void* v, int32_t
 int bits_for(uint64_t x) { return x == 0 ? 1 : 64 - __builtin_clzll(x); }
 
 struct EncWs {
-    int64_t nb;
-    int64_t* tot;       // [2][nb]
-    int64_t* off;       // [2][nb] + 2 totals
+    int64_t n_wc;               // wave chunks
+    int64_t n_parts;            // scan parts
+    unsigned grid;              // workgroups of the chunk kernels
+    int32_t* cnt;               // [2][n_wc]
+    int64_t* off;               // [2][n_wc + 1]
+    int64_t* part;              // [2][n_parts + 1]
     EncStats* stats;
     unsigned long long* hist;   // [2][256]
 };
 
-int64_t enc_blocks(int64_t n) {
-    const int64_t chunks = (n + kEncChunk - 1) / kEncChunk;
-    return std::max<int64_t>(1, std::min<int64_t>(chunks, kEncMaxBlocks));
-}
-
-size_t enc_ws_bytes(int64_t n) {
-    const int64_t nb = enc_blocks(n);
-    return 256 * (size_t)(4 + (16 * nb + 255) / 256 + (16 * nb + 16 + 255) / 256 + 16);
-}
+size_t a256e(size_t x) { return (x + 255) & ~size_t(255); }
 
 EncWs enc_ws(void* ws, int64_t n) {
     EncWs w;
-    w.nb = enc_blocks(n);
+    w.n_wc = std::max<int64_t>(1, (n + kWaveChunk - 1) / kWaveChunk);
+    w.n_parts = (w.n_wc + kEncScanPer - 1) / kEncScanPer;
+    w.grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((w.n_wc + 3) / 4, 8192));
     unsigned char* p = (unsigned char*)ws;
-    w.stats = (EncStats*)p;
-    p += 256;
-    w.hist = (unsigned long long*)p;
-    p += 4096;
-    w.tot = (int64_t*)p;
-    p += 256 * ((16 * w.nb + 255) / 256);
-    w.off = (int64_t*)p;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* q = p ? p + o : nullptr;
+        o += a256e(bytes);
+        return q;
+    };
+    w.stats = (EncStats*)take(sizeof(EncStats));
+    w.hist = (unsigned long long*)take(4096);
+    w.cnt = (int32_t*)take(4 * 2 * (size_t)w.n_wc);
+    w.off = (int64_t*)take(8 * 2 * (size_t)(w.n_wc + 1));
+    w.part = (int64_t*)take(8 * 2 * (size_t)(w.n_parts + 1));
     return w;
+}
+
+size_t enc_ws_bytes(int64_t n) {
+    // the layout's size: enc_ws over a null base, the last piece's end
+    const EncWs w = enc_ws(nullptr, n);
+    return a256e(sizeof(EncStats)) + 4096 + a256e(4 * 2 * (size_t)w.n_wc) + a256e(8 * 2 * (size_t)(w.n_wc + 1)) +
+           a256e(8 * 2 * (size_t)(w.n_parts + 1));
 }
 
 ccq_status enc_check(ccq_context* ctx, const void* values, int32_t vtype, int64_t n, void* ws, size_t ws_bytes) {
@@ -396,12 +407,18 @@ ccq_status enc_check(ccq_context* ctx, const void* values, int32_t vtype, int64_
 
 // count + scan for one mode; returns the two flag totals (synchronises)
 ccq_status enc_count(EncArgs& A, const EncWs& w, hipStream_t s, int64_t* t0, int64_t* t1) {
-    A.block_tot = w.tot;
-    A.block_off = w.off;
-    hipLaunchKernelGGL(k_enc_count, dim3((unsigned)w.nb), dim3(kEncThreads), 0, s, A);
-    hipLaunchKernelGGL(k_enc_scan, dim3(1), dim3(kEncThreads), 0, s, w.tot, w.off, (int32_t)w.nb);
+    A.cnt = w.cnt;
+    A.off = w.off;
+    A.n_wc = w.n_wc;
+    hipLaunchKernelGGL(k_enc_count, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    hipLaunchKernelGGL(k_enc_scan_part, dim3((unsigned)w.n_parts, 2), dim3(kEncThreads), 0, s, w.cnt, w.n_wc, w.part,
+                       w.n_parts);
+    hipLaunchKernelGGL(k_enc_scan_parts, dim3(1, 2), dim3(kEncThreads), 0, s, w.part, w.n_parts);
+    hipLaunchKernelGGL(k_enc_scan_final, dim3((unsigned)w.n_parts, 2), dim3(kEncThreads), 0, s, w.cnt, w.n_wc,
+                       w.part, w.n_parts, w.off);
     int64_t h[2];
-    hipError_t e = hipMemcpyAsync(h, w.off + 2 * w.nb, sizeof h, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(&h[0], w.off + w.n_wc, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h[1], w.off + 2 * w.n_wc + 1, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "encode count");
     *t0 = h[0];
@@ -432,7 +449,7 @@ ccq_status ccq_encode_choose(ccq_context* ctx, const void* values, int32_t value
     }
     const EncWs w = enc_ws(ws, n_rows);
     hipLaunchKernelGGL(k_enc_stats_init, dim3(1), dim3(1), 0, s, w.stats);
-    hipLaunchKernelGGL(k_enc_stats, dim3((unsigned)w.nb), dim3(kEncThreads), 0, s, values, value_type, n_rows,
+    hipLaunchKernelGGL(k_enc_stats, dim3(w.grid), dim3(kEncThreads), 0, s, values, value_type, n_rows,
                        w.stats);
     EncStats st;
     hipError_t e = hipMemcpyAsync(&st, w.stats, sizeof st, hipMemcpyDeviceToHost, s);
@@ -532,7 +549,7 @@ ccq_status ccq_plain_to_rle(ccq_context* ctx, const void* values, int32_t value_
     if (!run_values || !run_ends) return fail(CCQ_E_INVALID, "output arrays missing");
     A.run_values = run_values;
     A.run_ends = run_ends;
-    hipLaunchKernelGGL(k_enc_write, dim3((unsigned)w.nb), dim3(kEncThreads), 0, s, A);
+    hipLaunchKernelGGL(k_enc_write, dim3(w.grid), dim3(kEncThreads), 0, s, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "encode write");
     return ok();
@@ -568,7 +585,7 @@ ccq_status ccq_plain_to_rle_index(ccq_context* ctx, const void* values, int32_t 
     A.run_ends = run_ends;
     A.idx_pos = idx_positions;
     A.idx_vals = idx_values;
-    hipLaunchKernelGGL(k_enc_write, dim3((unsigned)w.nb), dim3(kEncThreads), 0, s, A);
+    hipLaunchKernelGGL(k_enc_write, dim3(w.grid), dim3(kEncThreads), 0, s, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "encode write");
     return ok();
@@ -608,7 +625,7 @@ ccq_status ccq_plain_to_plain_index(ccq_context* ctx, const void* values, int32_
     if (points && (!idx_positions || !idx_values)) return fail(CCQ_E_INVALID, "output arrays missing");
     A.idx_pos = idx_positions;
     A.idx_vals = idx_values;
-    if (points) hipLaunchKernelGGL(k_enc_write, dim3((unsigned)w.nb), dim3(kEncThreads), 0, s, A);
+    if (points) hipLaunchKernelGGL(k_enc_write, dim3(w.grid), dim3(kEncThreads), 0, s, A);
     const int64_t lanes = (n_rows + 31) / 32;
     hipLaunchKernelGGL(k_enc_pack, dim3((unsigned)((lanes + kEncThreads - 1) / kEncThreads)), dim3(kEncThreads), 0, s,
                        values, value_type, n_rows, base, bit_width, packed, need);
