@@ -97,30 +97,33 @@ struct EncArgs {
 // Plain+Index: outliers -- flag 1 the points of RLE+Index, rows that form a
 // run of their own) and, with WRITE, the outputs at the ranks from o0, o1.
 // Returns the chunk's flag counts (wave-uniform).
-template <bool WRITE>
+// T: the column's value type (int32_t or int64_t), so int32 columns shuffle
+// and compare 32-bit values.
+template <typename T, bool WRITE>
 __device__ __forceinline__ void wave_chunk(const EncArgs& A, int64_t wc, int64_t o0, int64_t o1, int32_t* c0,
                                            int32_t* c1) {
     const int lane = threadIdx.x & 63;
     const int64_t r0 = wc * kWaveChunk;
-    int64_t x[kEncRowsPerThread];
+    const T* v = (const T*)A.values;
+    T x[kEncRowsPerThread];
 #pragma unroll
     for (int k = 0; k < kEncRowsPerThread; ++k) {
         const int64_t i = r0 + 64 * k + lane;
-        x[k] = i < A.n ? load_value(A.values, A.vtype, i) : 0;
+        x[k] = i < A.n ? v[i] : T(0);
     }
-    const int64_t before = r0 > 0 ? load_value(A.values, A.vtype, r0 - 1) : 0;
-    const int64_t after = r0 + kWaveChunk < A.n ? load_value(A.values, A.vtype, r0 + kWaveChunk) : 0;
+    const T before = r0 > 0 ? v[r0 - 1] : T(0);
+    const T after = r0 + kWaveChunk < A.n ? v[r0 + kWaveChunk] : T(0);
     const uint64_t below = (1ull << lane) - 1ull;
     int32_t n0 = 0, n1 = 0;
 #pragma unroll
     for (int k = 0; k < kEncRowsPerThread; ++k) {
         const int64_t i = r0 + 64 * k + lane;
-        const int64_t xi = x[k];
-        int64_t prev = __shfl_up(xi, 1, 64);
-        int64_t next = __shfl_down(xi, 1, 64);
-        const int64_t last_prev = k > 0 ? __shfl(x[k - 1], 63, 64) : before;
-        const int64_t first_next = k + 1 < kEncRowsPerThread ? __shfl(x[k + 1 < kEncRowsPerThread ? k + 1 : k], 0, 64)
-                                                              : after;
+        const T xi = x[k];
+        T prev = __shfl_up(xi, 1, 64);
+        T next = __shfl_down(xi, 1, 64);
+        const T last_prev = k > 0 ? __shfl(x[k - 1], 63, 64) : before;
+        const T first_next = k + 1 < kEncRowsPerThread ? __shfl(x[k + 1 < kEncRowsPerThread ? k + 1 : k], 0, 64)
+                                                        : after;
         if (lane == 0) prev = last_prev;
         if (lane == 63) next = first_next;
         const bool valid = i < A.n;
@@ -135,8 +138,8 @@ __device__ __forceinline__ void wave_chunk(const EncArgs& A, int64_t wc, int64_t
             f1 = start && end;
         } else {
             // outside [base, base + 2^w); once x >= base the wrapped difference is exact
-            const uint64_t code = (uint64_t)xi - (uint64_t)A.base;
-            f0 = valid && (xi < A.base || (code >> A.w) != 0);
+            const uint64_t code = (uint64_t)(int64_t)xi - (uint64_t)A.base;
+            f0 = valid && ((int64_t)xi < A.base || (code >> A.w) != 0);
             f1 = false;
         }
         const uint64_t m0 = __ballot(f0), m1 = __ballot(f1);
@@ -170,11 +173,12 @@ __device__ __forceinline__ void wave_chunk(const EncArgs& A, int64_t wc, int64_t
 }
 
 // flag counts per wave chunk (a wave per chunk, grid-stride)
+template <typename T>
 __global__ __launch_bounds__(kEncThreads) void k_enc_count(EncArgs A) {
     const int64_t waves = (int64_t)gridDim.x * (kEncThreads / 64);
     for (int64_t wc = (int64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6); wc < A.n_wc; wc += waves) {
         int32_t c0, c1;
-        wave_chunk<false>(A, wc, 0, 0, &c0, &c1);
+        wave_chunk<T, false>(A, wc, 0, 0, &c0, &c1);
         if ((threadIdx.x & 63) == 0) {
             A.cnt[wc] = c0;
             A.cnt[A.n_wc + wc] = c1;
@@ -236,11 +240,12 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_scan_final(const int32_t* c
 }
 
 // the outputs, each wave chunk at its offsets
+template <typename T>
 __global__ __launch_bounds__(kEncThreads) void k_enc_write(EncArgs A) {
     const int64_t waves = (int64_t)gridDim.x * (kEncThreads / 64);
     for (int64_t wc = (int64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6); wc < A.n_wc; wc += waves) {
         int32_t c0, c1;
-        wave_chunk<true>(A, wc, A.off[wc], A.off[A.n_wc + 1 + wc], &c0, &c1);
+        wave_chunk<T, true>(A, wc, A.off[wc], A.off[A.n_wc + 1 + wc], &c0, &c1);
     }
 }
 
@@ -282,6 +287,7 @@ struct EncStats {
     long long vmin, vmax;
 };
 
+template <typename T>
 __global__ __launch_bounds__(kEncThreads) void k_enc_stats(const void* v, int32_t vtype, int64_t n, EncStats* out) {
     // runs and single-row runs: flags 0 and 1 of RLE+Index, per wave chunk
     EncArgs A = {};
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(kEncThreads) void k_enc_stats(const void* v, int32_
     int64_t runs = 0, singles = 0, lo = INT64_MAX, hi = INT64_MIN;
     for (int64_t wc = (int64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6); wc < A.n_wc; wc += waves) {
         int32_t c0, c1;
-        wave_chunk<false>(A, wc, 0, 0, &c0, &c1);
+        wave_chunk<T, false>(A, wc, 0, 0, &c0, &c1);
         runs += c0 + c1;
         singles += c1;
         for (int k = 0; k < kEncRowsPerThread; ++k) {
@@ -405,12 +411,18 @@ ccq_status enc_check(ccq_context* ctx, const void* values, int32_t vtype, int64_
     return CCQ_OK;
 }
 
+void launch_write(const EncArgs& A, const EncWs& w, hipStream_t s) {
+    if (A.vtype == CCQ_I32) hipLaunchKernelGGL(k_enc_write<int32_t>, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    else hipLaunchKernelGGL(k_enc_write<int64_t>, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+}
+
 // count + scan for one mode; returns the two flag totals (synchronises)
 ccq_status enc_count(EncArgs& A, const EncWs& w, hipStream_t s, int64_t* t0, int64_t* t1) {
     A.cnt = w.cnt;
     A.off = w.off;
     A.n_wc = w.n_wc;
-    hipLaunchKernelGGL(k_enc_count, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    if (A.vtype == CCQ_I32) hipLaunchKernelGGL(k_enc_count<int32_t>, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    else hipLaunchKernelGGL(k_enc_count<int64_t>, dim3(w.grid), dim3(kEncThreads), 0, s, A);
     hipLaunchKernelGGL(k_enc_scan_part, dim3((unsigned)w.n_parts, 2), dim3(kEncThreads), 0, s, w.cnt, w.n_wc, w.part,
                        w.n_parts);
     hipLaunchKernelGGL(k_enc_scan_parts, dim3(1, 2), dim3(kEncThreads), 0, s, w.part, w.n_parts);
@@ -449,7 +461,8 @@ ccq_status ccq_encode_choose(ccq_context* ctx, const void* values, int32_t value
     }
     const EncWs w = enc_ws(ws, n_rows);
     hipLaunchKernelGGL(k_enc_stats_init, dim3(1), dim3(1), 0, s, w.stats);
-    hipLaunchKernelGGL(k_enc_stats, dim3(w.grid), dim3(kEncThreads), 0, s, values, value_type, n_rows,
+    hipLaunchKernelGGL(value_type == CCQ_I32 ? k_enc_stats<int32_t> : k_enc_stats<int64_t>, dim3(w.grid),
+                       dim3(kEncThreads), 0, s, values, value_type, n_rows,
                        w.stats);
     EncStats st;
     hipError_t e = hipMemcpyAsync(&st, w.stats, sizeof st, hipMemcpyDeviceToHost, s);
@@ -549,7 +562,7 @@ ccq_status ccq_plain_to_rle(ccq_context* ctx, const void* values, int32_t value_
     if (!run_values || !run_ends) return fail(CCQ_E_INVALID, "output arrays missing");
     A.run_values = run_values;
     A.run_ends = run_ends;
-    hipLaunchKernelGGL(k_enc_write, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    launch_write(A, w, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "encode write");
     return ok();
@@ -585,7 +598,7 @@ ccq_status ccq_plain_to_rle_index(ccq_context* ctx, const void* values, int32_t 
     A.run_ends = run_ends;
     A.idx_pos = idx_positions;
     A.idx_vals = idx_values;
-    hipLaunchKernelGGL(k_enc_write, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    launch_write(A, w, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "encode write");
     return ok();
@@ -625,7 +638,7 @@ ccq_status ccq_plain_to_plain_index(ccq_context* ctx, const void* values, int32_
     if (points && (!idx_positions || !idx_values)) return fail(CCQ_E_INVALID, "output arrays missing");
     A.idx_pos = idx_positions;
     A.idx_vals = idx_values;
-    if (points) hipLaunchKernelGGL(k_enc_write, dim3(w.grid), dim3(kEncThreads), 0, s, A);
+    if (points) launch_write(A, w, s);
     const int64_t lanes = (n_rows + 31) / 32;
     hipLaunchKernelGGL(k_enc_pack, dim3((unsigned)((lanes + kEncThreads - 1) / kEncThreads)), dim3(kEncThreads), 0, s,
                        values, value_type, n_rows, base, bit_width, packed, need);
