@@ -1111,6 +1111,19 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         int64_t lg = 0;
         if (used < avail) lg = (int64_t)((avail - used) / cell_row) & ~int64_t(3);
         lg = std::min<int64_t>(lg, G);
+        // Occupancy before coverage: when a bit-packed key's table would keep
+        // the workgroup alone on its CU, the table keeps only as many groups
+        // as let two workgroups share the CU (if that is at least
+        // kLdsShareMin), and the groups above add to the global table.  (In
+        // a batch, one such plan left whole would hold its whole launch to
+        // one workgroup per CU.)
+        // Results do not change.  Dictionary codes numbered
+        // by frequency keep their hot groups in LDS (measured: the c4 batch
+        // 355 -> 235 ms); with codes in random order about half the rows
+        // would add to the global table, about as fast as one workgroup per CU.
+        const size_t avail2 = t->ctx->lds_per_block / 2 - (size_t)kernel_static_lds(0, 0);
+        const int64_t lg2 = avail2 > used ? (int64_t)((avail2 - used) / cell_row) & ~int64_t(3) : 0;
+        if (bp_keyed && lg > kLdsShareGroups && lg2 >= kLdsShareMin) lg = std::min<int64_t>(lg, lg2);
         if (!bp_keyed && (size_t)G * cell_row > (size_t)kLdsTableBytes) lg = 0;
         if (lg > 0 && rows_per_wg < ((int64_t)1 << 31)) {
             P.table_lds = 1;

@@ -26,6 +26,8 @@ constexpr int kMaxAggs = 8;
 constexpr int kLutMaxBits = 14;        // bit-packed columns up to this width get a code table
 constexpr int64_t kMaxGroups = int64_t(1) << 27;
 constexpr int kLdsTableBytes = 16384;  // group tables up to this size live in LDS
+constexpr int64_t kLdsShareGroups = 4096;   // generic row path: tables of at most this many groups stay whole,
+constexpr int64_t kLdsShareMin = 1024;      // and larger ones keep at least this many to share the CU
 constexpr int kMaxStagedRuns = 1536;  // staged runs per wave slice, all RLE columns together
 constexpr int kSegSlots = 64;         // group segments merged per tile in LDS
 constexpr int kFastBigBytes = 65536;   // fast row path: largest uint32 count table in dynamic LDS
