@@ -258,15 +258,18 @@ struct BatchGroup {
 // more than kBatchLdsSplit bytes of LDS), fast row path of width 14 or 20,
 // each of those with a large table (1-4), the staged paths' full instance
 // (6; w0 = -1: composite columns, MIN / MAX / expressions, wide plans), the
-// common generic row path (7, and 8 with large LDS; w0 = -2).  Each instance
+// common generic row path (7; 8 with large LDS, two workgroups per CU; 9
+// above kBatchLdsHalf, one workgroup per CU, so such plans do not hold the
+// others' launch to one; w0 = -2).  Each instance
 // is compiled for its own path, so one path's registers cost no other.
 // Variant 5 runs the staged paths' kernel too, for plans that need more
 // than kBatchLdsSplit bytes of LDS per workgroup (large group tables in
 // LDS), so they do not lower the occupancy of the other staged plans'
 // launch.
-constexpr int kVariants = 9;
+constexpr int kVariants = 10;
 constexpr int kMaxInstances = 3 * kVariants;     // KMAX in {2, 4, 8}
 constexpr int kBatchLdsSplit = 48 * 1024;
+constexpr int kBatchLdsHalf = 80 * 1024;    // above this, one workgroup per CU
 inline int kernel_w0(const DevPlan& p) {
     if (p.w0 > 0) return p.w0;
     if (p.n_comp > 0 || p.n_ext > 0 || p.n_bp > kSmallBp || p.n_sums > kSmallSums) return -1;
@@ -274,11 +277,11 @@ inline int kernel_w0(const DevPlan& p) {
 }
 inline int variant_of(int w0, int big, int lds_bytes) {
     if (w0 == -1) return 6;
-    if (w0 == -2) return lds_bytes > kBatchLdsSplit ? 8 : 7;
+    if (w0 == -2) return lds_bytes > kBatchLdsHalf ? 9 : lds_bytes > kBatchLdsSplit ? 8 : 7;
     return w0 == 0 ? (lds_bytes > kBatchLdsSplit ? 5 : 0) : (w0 == 14 ? 1 : 2) + (big ? 2 : 0);
 }
 inline int variant_w0(int v) {
-    return v == 6 ? -1 : (v == 7 || v == 8) ? -2 : v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20;
+    return v == 6 ? -1 : (v == 7 || v == 8 || v == 9) ? -2 : v == 0 || v == 5 ? 0 : (v == 1 || v == 3) ? 14 : 20;
 }
 inline int variant_big(int v) { return v == 3 || v == 4 ? 1 : 0; }
 
