@@ -442,6 +442,11 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
     // is tested against the bit-packed part
     bool row_clause = false;
     std::vector<std::pair<int, Intervals>> bp_or;
+    // an OR clause over RLE columns and one Index column: the Index part's
+    // column and intervals (the clause is the row clause, applied to the row
+    // mask once the Index points are known)
+    int idx_or_col = -1;
+    Intervals idx_or_iv;
     int false_col = -1;    // a clause no row can pass: the query is false
     for (const Clause& cl : clauses) {
         std::vector<size_t> live;
@@ -464,12 +469,28 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             continue;
         }
         bool mixed = false;
+        int n_index = 0, index_j = -1;
         for (size_t j : live) {
             if (is_comp(cl.cols[j]))
                 return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes no composite column", cl.id);
-            if (t->cols[cl.cols[j]].encoding == CCQ_INDEX)
-                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: an OR across columns takes no INDEX column", cl.id);
+            if (t->cols[cl.cols[j]].encoding == CCQ_INDEX) {
+                ++n_index;
+                index_j = (int)j;
+            }
             mixed = mixed || t->cols[cl.cols[j]].encoding == CCQ_BITPACKED;
+        }
+        if (n_index > 0) {
+            // RLE columns OR one Index column (Table 4, RLE mask OR Index mask)
+            if (n_index > 1 || mixed)
+                return fail(CCQ_E_UNSUPPORTED,
+                            "OR clause %d: an OR across columns takes at most one INDEX column, with RLE columns only",
+                            cl.id);
+            if (row_clause)
+                return fail(CCQ_E_UNSUPPORTED, "OR clause %d: at most one OR clause may name INDEX or bit-packed "
+                                               "columns beside RLE ones", cl.id);
+            row_clause = true;
+            idx_or_col = cl.cols[index_j];
+            idx_or_iv = cl.iv[index_j];
         }
         if (mixed) {
             if (row_clause)
@@ -479,6 +500,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         }
         std::vector<size_t> rle_live;
         for (size_t j : live) {
+            if (t->cols[cl.cols[j]].encoding == CCQ_INDEX) continue;
             if (t->cols[cl.cols[j]].encoding == CCQ_RLE) {
                 rle_live.push_back(j);
             } else {
@@ -493,7 +515,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
             o.f.iv = cl.iv[rle_live[n]];
             fold_classify(o.f);
             o.or_next = n + 1 < rle_live.size();
-            o.row_clause = mixed;
+            o.row_clause = mixed || n_index > 0;
             or_slots.push_back(o);
         }
     }
@@ -506,7 +528,9 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         return fail(CCQ_E_UNSUPPORTED, "at most %d RLE column uses per query (one per column, plus one per OR clause naming it)", kMaxRle);
     if ((int)bp_cols.size() > kMaxBp)
         return fail(CCQ_E_UNSUPPORTED, "at most %d bit-packed columns per query", kMaxBp);
-    if ((int)idx_cols.size() > kMaxIdx) return fail(CCQ_E_UNSUPPORTED, "at most %d Index columns per query", kMaxIdx);
+    if ((int)idx_cols.size() + (idx_or_col >= 0 ? 1 : 0) > kMaxIdx)
+        return fail(CCQ_E_UNSUPPORTED, "at most %d Index columns per query (an OR clause's Index column counts once "
+                                       "more)", kMaxIdx);
     if ((int)comp_cols.size() > kMaxComp)
         return fail(CCQ_E_UNSUPPORTED, "at most %d composite columns per query", kMaxComp);
     for (auto& f : fold) fold_classify(f);
@@ -531,7 +555,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
 
     P.k_rle = (int)(rle_cols.size() + or_slots.size());
     P.n_bp = (int)bp_cols.size();
-    P.n_idx = (int)idx_cols.size();
+    P.n_idx = (int)idx_cols.size() + (idx_or_col >= 0 ? 1 : 0);
     // a column's folded predicate in the form the kernels test
     auto put_pred = [&](const Fold& f, int32_t& pred, int64_t& lo, int64_t& hi, const int64_t*& set,
                         int32_t& set_len) {
@@ -576,7 +600,7 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         put_pred(f, r.pred, r.lo, r.hi, r.set, r.set_len);
     }
     bool idx_pred = false;
-    for (int s = 0; s < P.n_idx; ++s) {
+    for (int s = 0; s < (int)idx_cols.size(); ++s) {
         const ccq_column_desc& c = t->cols[idx_cols[s]];
         IdxCol& x = P.idx[s];
         x.pos = c.positions;
@@ -590,6 +614,26 @@ ccq_status compile_plan(const ccq_table* t, const ccq_query_desc* q, Compiled& o
         put_pred(f, x.pred, x.lo, x.hi, x.set, x.set_len);
         x.zero_pass = fold_pass(f, 0) ? 1 : 0;
         idx_pred = idx_pred || x.pred != kPredNone;
+    }
+    if (idx_or_col >= 0) {
+        // the OR clause's Index part: a slot of its own, its mask ORed with the
+        // clause's RLE part (the row clause word) before the row mask takes it
+        const ccq_column_desc& c = t->cols[idx_or_col];
+        IdxCol& x = P.idx[P.n_idx - 1];
+        x.pos = c.positions;
+        x.vals = c.values;
+        x.n = c.n_entries;
+        x.ptype = c.position_type;
+        x.vtype = c.value_type;
+        x.sum_slot = -1;
+        Fold f;
+        f.constrained = true;
+        f.iv = idx_or_iv;
+        fold_classify(f);
+        put_pred(f, x.pred, x.lo, x.hi, x.set, x.set_len);
+        x.zero_pass = fold_pass(f, 0) ? 1 : 0;
+        x.or_rcl = 1;
+        idx_pred = true;
     }
 
     // keys: mixed radix; bit-packed keys up to kLutMaxBits bits get dense

@@ -688,7 +688,17 @@ __device__ __forceinline__ uint32_t idx_pred_mask(const DevPlan& P, const WaveLd
         const uint32_t x = T[lane];
         T[lane] = 0;
         wave_lds_sync();
-        pm &= ic.zero_pass ? ~x : x;
+        const uint32_t m = ic.zero_pass ? ~x : x;
+        if (ic.or_rcl && W.rcl) {
+            // an OR clause's Index part: the clause holds where its RLE part
+            // (the row clause word) or this mask does; the row test that reads
+            // the word afterwards then passes every row
+            pm &= W.rcl[lane] | m;
+            W.rcl[lane] = 0xFFFFFFFFu;
+            wave_lds_sync();
+        } else {
+            pm &= m;
+        }
     }
     return pm;
 }

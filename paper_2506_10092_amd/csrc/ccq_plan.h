@@ -115,6 +115,9 @@ struct IdxCol {
     const int64_t* set;     // kPredSet / kPredIntervals, as for RLE columns (device)
     int32_t set_len;
     int32_t zero_pass;      // 1 when the value 0 passes the predicate
+    int32_t or_rcl;         // 1: this mask is an OR clause's Index part, ORed with the clause's RLE
+                            // part (the row clause word) before the row mask takes it
+    int32_t pad_or_;
 };
 
 // A composite column (Section 3.2: RLE + Index, Plain + Index): its base

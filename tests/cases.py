@@ -116,6 +116,40 @@ def tiny_query_with_or(rng, n, wd):
     return q
 
 
+def _index_literal(rng):
+    """A predicate on the Index column s (unlisted rows hold 0): a range or
+    an IN-list, with or without 0, plain or negated."""
+    op = ["range", "in", "not_range", "not_in"][int(rng.integers(0, 4))]
+    if op.endswith("range"):
+        lo = int(rng.integers(-120, 60))
+        return ("s", op, lo, lo + int(rng.integers(0, 150)))
+    vals = set(int(x) for x in rng.integers(-100, 100, size=int(rng.integers(0, 6))))
+    if rng.random() < 0.4:
+        vals.add(0)
+    return ("s", op, sorted(vals))
+
+
+def tiny_query_with_rle_index_or(rng, n, wd):
+    """tiny_query_with_not plus one OR clause over one or two RLE columns and
+    the Index column s (RLE mask OR Index mask, Table 4), at times beside
+    OR clauses over RLE columns alone and a predicate on s; about half the
+    queries name no bit-packed column (run mode), the rest do (row mode)."""
+    q = tiny_query_with_not(rng, n, wd)
+    if rng.random() < 0.5:
+        q["preds"] = [p for p in q["preds"] if p[0] not in ("d", "p")]
+        q["keys"] = [k for k in q["keys"] if k[0] not in ("d", "p")]
+        q["aggs"] = [a for a in q["aggs"] if a[-1] not in ("d", "p")]
+    cols = ["r%d" % int(rng.integers(0, 3)) for _ in range(int(rng.integers(1, 3)))]
+    clause = [_rle_literal(rng, c) for c in cols] + [_index_literal(rng)]
+    clauses = [[clause[i] for i in rng.permutation(len(clause))]]
+    if rng.random() < 0.4:
+        clauses.append([_rle_literal(rng, "r%d" % int(rng.integers(0, 3))) for _ in range(2)])
+    if rng.random() < 0.3:
+        q["preds"] = q["preds"] + [_index_literal(rng)]
+    q["or"] = clauses
+    return q
+
+
 def tiny_query_with_index_pred(rng, n, wd):
     """tiny_query_with_not plus one or two predicates on the Index column s
     (unlisted rows hold 0): ranges and IN-lists with and without 0, plain or

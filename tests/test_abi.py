@@ -82,10 +82,17 @@ def test_host_only_context_checks_plans():
     ({"window": (0, 1001)}, ccq.E_INVALID),
     ({"window": (10, 5)}, ccq.E_INVALID),
     ({"keys": [("a", 0, 4), ("a", 1, 4)]}, ccq.E_UNSUPPORTED),
-    # two OR clauses spanning RLE and bit-packed columns; OR across an Index column
+    # two OR clauses spanning RLE and bit-packed columns; an OR over an Index
+    # and a bit-packed column; two OR clauses over RLE and Index columns; one
+    # of those beside an RLE x bit-packed clause
     ({"or": [[("a", "range", 0, 2), ("d", "in", [1])], [("m", "range", 0, 2), ("p", "range", 0, 5)]]},
      ccq.E_UNSUPPORTED),
-    ({"or": [[("s", "range", 0, 2), ("a", "in", [1])]]}, ccq.E_UNSUPPORTED),
+    ({"or": [[("s", "range", 0, 2), ("a", "in", [1]), ("d", "in", [1])]]}, ccq.E_UNSUPPORTED),
+    ({"or": [[("s", "range", 0, 2), ("d", "in", [1])]]}, ccq.E_UNSUPPORTED),
+    ({"or": [[("s", "range", 0, 2), ("a", "in", [1])], [("s", "range", 5, 9), ("m", "in", [5])]]},
+     ccq.E_UNSUPPORTED),
+    ({"or": [[("s", "range", 0, 2), ("a", "in", [1])], [("a", "range", 0, 2), ("d", "in", [1])]]},
+     ccq.E_UNSUPPORTED),
     # five two-column OR clauses need ten RLE column uses (at most eight)
     ({"or": [[("a", "range", 0, 2 + i), ("m", "range", 0, 5)] for i in range(5)]}, ccq.E_UNSUPPORTED),
     ({"or": [[]]}, ccq.E_INVALID),
@@ -107,7 +114,8 @@ def test_plan_check_rejects(bad, code):
 def test_or_clauses_fold_or_take_rle_slots():
     """An OR clause over one column folds into that column (any encoding);
     clauses that always hold drop; clauses over RLE columns are accepted up
-    to eight RLE column uses."""
+    to eight RLE column uses, and one clause may add a bit-packed column or
+    an Index column to its RLE columns."""
     tb = _host_table(_cols(), 1000)
     base = {"preds": [], "keys": [("d", 0, 1 << 14)], "aggs": [("count",)], "window": (0, 1000)}
     ok = [
@@ -118,6 +126,8 @@ def test_or_clauses_fold_or_take_rle_slots():
         [[("a", "in", []), ("d", "in", [3])]],            # one live predicate: folds into d
         [[("a", "range", 0, 2), ("d", "in", [3])]],       # RLE OR bit-packed: the row clause
         [[("d", "in", [3]), ("p", "range", 0, 9)], [("a", "range", 0, 2), ("m", "in", [5])]],
+        [[("s", "range", 1, 2), ("a", "in", [1])]],       # RLE OR Index: the row clause
+        [[("a", "range", 0, 2), ("m", "in", [5]), ("s", "not_in", [0])], [("a", "in", [2]), ("m", "in", [5])]],
     ]
     for clauses in ok:
         ccq.plan_check(tb, dict(base, preds=[("a", "range", 1, 3)], **{"or": clauses}))

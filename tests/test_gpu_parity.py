@@ -408,6 +408,44 @@ def test_or_across_rle_and_bitpacked_columns(ctx):
             check(ctx, t, qq)
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_tiny_random_tables_with_rle_index_or(ctx, seed):
+    from tests.cases import tiny_query_with_rle_index_or
+    rng = np.random.default_rng(7900 + seed)
+    n = int(rng.integers(1, 5000))
+    t, wd = tiny_table(rng, n)
+    for _ in range(3):
+        q = tiny_query_with_rle_index_or(rng, n, wd)
+        say("tiny RLE-Index OR seed", seed, "n", n, "query", q)
+        check(ctx, t, q)
+
+
+def test_or_across_rle_and_index_columns(ctx):
+    """One OR clause over RLE columns and the Index column (Table 4, RLE mask
+    OR Index mask; unlisted rows hold 0): in run mode (no bit-packed column)
+    and on the generic row path, with a predicate 0 fails and one 0 passes,
+    beside an OR clause over RLE columns alone, in windows."""
+    n = 2_000_003
+    t = datagen.config_c2(seed=99, n_rows=n, columns=("r0", "r1", "s", "d", "p"))
+    in_codes = t["query"]["preds"][2][2]
+    queries = [
+        {"preds": [("r1", "range", 0, 50000)], "keys": [], "aggs": [("sum", "s"), ("sum", "r0"), ("count",)],
+         "or": [[("r0", "range", 0, 4000), ("s", "range", 1, 300_000)]]},
+        {"preds": [], "keys": [("r1", 12, 16)], "aggs": [("sum", "s"), ("count",)],
+         "or": [[("r0", "range", 60000, 65536), ("s", "not_range", 100, 200_000)]]},
+        {"preds": [("d", "in", in_codes)], "keys": [("d", 0, 10000)], "aggs": [("sum", "s"), ("count",)],
+         "or": [[("r0", "range", 0, 20000), ("r1", "in", [1, 2, 3]), ("s", "range", 1000, 500_000)]]},
+        {"preds": [("p", "range", -200_000, 400_000)], "keys": [], "aggs": [("sum", "p"), ("sum", "s"), ("count",)],
+         "or": [[("r0", "range", 0, 30000), ("r1", "range", 0, 30000)],
+                [("s", "in", [0]), ("r1", "range", 40000, 65536)]]},
+    ]
+    for q in queries:
+        for window in ((0, n), (4097, n - 31)):
+            qq = dict(q, window=window)
+            say("RLE-Index OR query", qq["preds"], qq["or"], window)
+            check(ctx, t, qq)
+
+
 def test_index_predicates_run_mode_and_row_mode(ctx):
     """Predicates on the Index column (1% of rows listed, values >= 1, 0
     elsewhere): one that 0 fails (only listed rows can qualify: idx_in_rle),

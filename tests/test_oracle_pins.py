@@ -485,6 +485,21 @@ def test_or_clauses_match_brute_force_and_sqlite(seed):
 
 
 
+@pytest.mark.parametrize("seed", range(30))
+def test_rle_index_or_clauses_match_brute_force_and_sqlite(seed):
+    """An OR clause over RLE columns and the Index column (unlisted rows
+    hold 0), in run mode and beside bit-packed columns."""
+    from tests.cases import tiny_query_with_rle_index_or
+    rng = np.random.default_rng(9800 + seed)
+    n = int(rng.integers(1, 300))
+    t, wd = _tiny_table(rng, n)
+    for _ in range(4):
+        q = tiny_query_with_rle_index_or(rng, n, wd)
+        got = _norm(oracle.run(t, q, n_threads=1 + seed % 3))
+        assert got == _norm(brute.run(t, q)), q
+        assert got == _norm(brute.run_sqlite(t, q)), q
+
+
 # ---- predicates on Index columns: Algorithm 4 (idx_in_idx) against row
 # sets; the oracle's per-row Index predicates against brute force and SQL
 
