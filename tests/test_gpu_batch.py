@@ -33,7 +33,13 @@ def setup():
                                  [("r0", "range", 0, 30000), ("r1", "range", 0, 10000)]]}),
            # an OR clause over RLE and bit-packed columns; a predicate on the Index column
            dict(qs[6], **{"or": [[("r1", "range", 0, 20000), ("d", "in", [1, 2, 3, 4, 5])]]}),
-           dict(qs[7], preds=qs[7]["preds"] + [("s", "not_range", 1, 500_000)])]
+           dict(qs[7], preds=qs[7]["preds"] + [("s", "not_range", 1, 500_000)]),
+           # OR clauses over RLE columns and the Index column, in run mode and row mode
+           {"preds": [("r2", "range", 0, 40000)], "keys": [], "aggs": [("count",), ("sum", "s"), ("sum", "r0")],
+            "or": [[("r0", "range", 0, 5000), ("s", "range", 1, 200_000)]], "window": (1000, n - 5)},
+           {"preds": [("d", "in", list(range(0, 10000, 7)))], "keys": [("d", 0, 10000)],
+            "aggs": [("count",), ("sum", "s")],
+            "or": [[("r1", "range", 0, 10000), ("r0", "in", [1, 2]), ("s", "not_in", [0])]], "window": (0, n)}]
     ctx = ccq.Context(0)
     table = ccq.Table(ctx, n, ccq.to_device(t["columns"]))
     plans = [ccq.Plan(table, q) for q in qs]
