@@ -429,7 +429,7 @@ ccq_status ccq_tune_cache_load(ccq_context* ctx, const char* path, int64_t* n_en
         float ms = 0;
         char extra = 0;
         const int n = sscanf(line, "%" SCNx64 " %" SCNd32 " %f %c", &key, &tpi, &ms, &extra);
-        if (n != 3 || tpi < 1 || tpi >= kMaxTilesPerItem || !(ms >= 0)) {
+        if (n != 3 || tpi < 1 || tpi > kMaxTilesPerItem || !(ms >= 0)) {
             bad = true;
             break;
         }

@@ -285,15 +285,16 @@ def test_tune_cache_file_round_trip(tmp_path):
     assert ctx.tune_cache_save(path) == 0
     assert open(path).read().splitlines() == ["ccq-tune-cache 1"]
     with open(path, "a") as f:
-        f.write("00000000000000ab 32 12.5\n0123456789abcdef 512 355.25\n")
-    assert ctx.tune_cache_load(path) == 2
+        f.write("00000000000000ab 32 12.5\n0123456789abcdef 512 355.25\n0000000000000001 524288 1.5\n")
+    assert ctx.tune_cache_load(path) == 3                      # up to 2^19 tiles per item
     out = str(tmp_path / "out.txt")
-    assert ctx.tune_cache_save(out) == 2
+    assert ctx.tune_cache_save(out) == 3
     lines = open(out).read().splitlines()
     assert lines[0] == "ccq-tune-cache 1"
-    assert sorted(lines[1:]) == sorted(["00000000000000ab 32 12.5", "0123456789abcdef 512 355.25"])
+    assert sorted(lines[1:]) == sorted(["00000000000000ab 32 12.5", "0123456789abcdef 512 355.25",
+                                        "0000000000000001 524288 1.5"])
     for bad in ("not a cache\n", "ccq-tune-cache 1\nzz 1 2\n", "ccq-tune-cache 1\n00ab 0 1.0\n",
-                "ccq-tune-cache 1\n00ab 8 1.0 extra\n"):
+                "ccq-tune-cache 1\n00ab 8 1.0 extra\n", "ccq-tune-cache 1\n00ab 524289 1.0\n"):
         p = tmp_path / "bad.txt"
         p.write_text(bad)
         other = ccq.Context(ccq.HOST_ONLY)
