@@ -136,7 +136,10 @@ typedef struct {
  * unites, NOT complements.  An OR clause over one column takes any
  * encoding.  An OR clause over several columns names RLE columns, except
  * that one clause per query may also name bit-packed columns (Table 4, RLE
- * mask OR Plain mask); no Index column.  At most 8 RLE column uses per
+ * mask OR Plain mask) or, instead, exactly one Index column (Table 4, RLE
+ * mask OR Index mask; the column holds 0 at its unlisted rows).  Such an
+ * Index column takes one of the query's two Index column slots beyond any
+ * it takes for its other predicates or SUMs.  At most 8 RLE column uses per
  * query, counting each column once for the clause-0 predicates, keys and
  * SUMs and once per clause over several columns that names it.  Otherwise
  * CCQ_E_UNSUPPORTED. */
