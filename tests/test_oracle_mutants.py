@@ -25,6 +25,8 @@ MUTANTS = {
     "rle_value_of_next_run": ("int64_t stop = std::min(c.run_ends[i], r1);\n            int64_t v = value_at(c, i);",
                               "int64_t stop = std::min(c.run_ends[i], r1);\n"
                               "            int64_t v = value_at(c, i + 1 < c.n ? i + 1 : i);"),
+    "index_unlisted_rows_one": ("for (int64_t k = 0; k < len; k++) out[k] = 0;\n        for (int64_t i = first_point_at_or_after(c, r0)",
+                                "for (int64_t k = 0; k < len; k++) out[k] = 1;\n        for (int64_t i = first_point_at_or_after(c, r0)"),
     "index_value_shifted": ("out[position_at(c, i) - r0] = value_at(c, i);",
                             "out[position_at(c, i) - r0] = value_at(c, i > 0 ? i - 1 : i);"),
     "bitpacked_drops_base": ("out[r - r0] = c.base + (int64_t)code;", "out[r - r0] = (int64_t)code;"),
